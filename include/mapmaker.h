@@ -1,0 +1,200 @@
+/*
+ * mapmaker.h -- C ABI of the MI355X (gfx950) GLS map-making library.
+ *
+ * The library solves the generalised-least-squares map-making problem of
+ * arXiv:2501.16122, Sec. II: with time-ordered data d (eq. (1)), the pointing
+ * matrix P whose row t holds 1, cos 2psi_t, sin 2psi_t at the I, Q, U columns
+ * of the pixel seen at sample t (eq. (2), (8)), and a noise covariance N,
+ * the map is
+ *
+ *     x = (P^T N^-1 P)^-1 P^T N^-1 d           (eq. (5)),
+ *
+ * found by preconditioned conjugate gradient on A x = b with
+ * A = P^T N^-1 P and b = P^T N^-1 d (eq. (6)) and the block-Jacobi
+ * preconditioner M = (P^T diag(N)^-1 P)^-1 made of per-pixel 3x3 inverses
+ * (eq. (7)).  The operators are lazy (Sec. III-A): building a handle
+ * precomputes the pointing elements and preconditioner once, and each apply
+ * call only streams the timeline.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: MM_OK (0) on success; MM_NOTCONVERGED (> 0) when a solve ran out
+ *   of iterations (its outputs are still written); negative codes are errors
+ *   and leave outputs undefined.  mm_last_error() returns a thread-local
+ *   message for the last failing call of this thread.
+ * - Memory ownership follows Sec. III-A: the caller allocates and frees every
+ *   array.  Pointers named *_host are host memory read during the call;
+ *   every other pointer is device memory on the current HIP device.  Derived
+ *   state lives in a caller-provided device workspace sized by the matching
+ *   *_workspace_size call; the library allocates no device memory of its own.
+ *   A handle borrows the caller's device arrays (pix, psi, workspace) for its
+ *   whole lifetime: keep them alive until *_destroy.
+ * - Streams: `stream` is a hipStream_t (NULL = default stream).  Calls are
+ *   stream-ordered and asynchronous unless marked "blocking".
+ * - Layout: the timeline is detector-major (detector d owns samples
+ *   [det_offsets[d], det_offsets[d+1])); pixel indices are int32 in
+ *   [0, n_pix); maps over the kept pixels are interleaved I, Q, U
+ *   (f64[3 * n_kept], eq. (8)); full-grid maps are f64[3 * n_pix].
+ * - Precision: `dtype` is the storage type of psi and of every timeline
+ *   (MM_F64 or MM_F32).  `arith` selects the arithmetic of an operator's
+ *   timeline-domain work (MM_F64 or MM_F32); pixel-domain vectors, bin sums
+ *   and all PCG dot products are always FP64.
+ */
+#ifndef MAPMAKER_H
+#define MAPMAKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MM_OK = 0,
+  MM_NOTCONVERGED = 1,
+  MM_EINVAL = -1,      /* bad argument, shape or pixel index            */
+  MM_ENOSPC = -2,      /* workspace smaller than the size query asked for */
+  MM_EHIP = -3,        /* a HIP runtime call failed                      */
+  MM_EBREAKDOWN = -4   /* PCG breakdown: p^T A p <= 0 or non-finite       */
+};
+
+enum { MM_F64 = 0, MM_F32 = 1 };
+
+typedef struct mm_pointing_s* mm_pointing_t;
+typedef struct mm_noise_s* mm_noise_t;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* mm_last_error(void);
+
+/* ABI revision of this header (bumped on incompatible change). */
+int mm_abi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Pointing (the precomputation of Sec. III-A / "ProcessTimeSamples", and the
+ * preconditioner blocks of eq. (7)).
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes that mm_pointing_build needs for a timeline of
+ * n_samples samples over n_det detectors and a grid of n_pix pixels. */
+int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, size_t* bytes);
+
+/* Build the pointing handle (blocking: synchronises `stream` once to read
+ * the number of kept pixels and the pixel-range check).
+ *   pix          int32[n_samples] device, pixel of each sample
+ *   psi          f64 or f32 [n_samples] device (dtype), angle psi_t of eq. (2)
+ *   det_offsets_host  int64[n_det + 1], 0 = first, n_samples = last
+ *   det_weight_host   f64[n_det], diag(N)^-1 per detector (1/sigma_d^2) used
+ *                     for the preconditioner blocks of eq. (7)
+ *   min_hits, cond_max  a pixel is masked (dropped from the unknowns, its
+ *                     samples get a zero row of P) when it has fewer than
+ *                     min_hits samples or its 3x3 block has 2-norm condition
+ *                     number > cond_max (+inf when singular)
+ * Kept pixels are numbered in ascending pixel order.  A pixel index outside
+ * [0, n_pix) fails with MM_EINVAL and no handle. */
+int mm_pointing_build(const int32_t* pix, const void* psi, int32_t dtype, int64_t n_samples,
+                      const int64_t* det_offsets_host, int32_t n_det, const double* det_weight_host,
+                      int32_t n_pix, int32_t min_hits, double cond_max,
+                      void* workspace, size_t ws_bytes, void* stream, mm_pointing_t* out);
+
+/* Sizes of a built handle (host outputs; any pointer may be NULL). */
+int mm_pointing_info(mm_pointing_t pt, int32_t* n_kept, int64_t* n_samples, int32_t* n_pix,
+                     int32_t* n_det, int32_t* dtype);
+
+/* Copy the integer products of the build (any pointer may be NULL):
+ *   hits int32[n_pix], mask uint8[n_pix] (1 = masked),
+ *   compact int32[n_pix] (-1 = masked), kept int32[n_kept],
+ *   minv f64[9 * n_kept] (row-major 3x3 inverse blocks, eq. (7)). */
+int mm_pointing_export(mm_pointing_t pt, int32_t* hits, uint8_t* mask, int32_t* compact,
+                       int32_t* kept, double* minv, void* stream);
+
+/* Free the host-side handle; the caller frees its own arrays and workspace. */
+int mm_pointing_destroy(mm_pointing_t pt);
+
+/* ------------------------------------------------------------------------
+ * Noise models N^-1 (eq. (5)).  White: diagonal, 1/sigma_d^2 per detector.
+ * Band-Toeplitz: on each stationary chunk [chunk_offsets[c],
+ * chunk_offsets[c+1]) the finite section z_i = sum_{|i-j| < lambda}
+ * coeff[f][|i-j|] y_j with f = chunk_filter[c]; chunks do not couple and
+ * samples outside every chunk get z = 0.  Applied by overlap-save FFTs.
+ * ------------------------------------------------------------------------ */
+
+int mm_noise_white_workspace_size(int32_t n_det, size_t* bytes);
+int mm_noise_white(const double* det_weight_host, int32_t n_det, void* workspace, size_t ws_bytes,
+                   void* stream, mm_noise_t* out);
+
+/* 1 <= lambda <= 4096; chunks must be ordered, non-overlapping and must not
+ * cross a detector start (checked against the pointing at apply time). */
+int mm_noise_toeplitz_workspace_size(int32_t lambda, int32_t n_filt, const int64_t* chunk_offsets_host,
+                                     int64_t n_chunks, size_t* bytes);
+int mm_noise_toeplitz(const double* coeff_host, int32_t lambda, int32_t n_filt,
+                      const int64_t* chunk_offsets_host, const int32_t* chunk_filter_host,
+                      int64_t n_chunks, void* workspace, size_t ws_bytes, void* stream,
+                      mm_noise_t* out);
+int mm_noise_destroy(mm_noise_t nz);
+
+/* ------------------------------------------------------------------------
+ * Operators (eq. (3), (6), (7)).  x, q, r, z are f64[3 * n_kept]; timelines
+ * are dtype[n_samples] of the pointing's dtype.  Outputs are overwritten.
+ * ------------------------------------------------------------------------ */
+
+/* tod = P x  (zero on samples of masked pixels). */
+int mm_apply_P(mm_pointing_t pt, const double* x, void* tod, int32_t arith, void* stream);
+/* q = P^T tod. */
+int mm_apply_PT(mm_pointing_t pt, const void* tod, double* q, int32_t arith, void* stream);
+/* tod_out = N^-1 tod_in (tod_out must not alias tod_in). */
+int mm_apply_Ninv(mm_noise_t nz, mm_pointing_t pt, const void* tod_in, void* tod_out, int32_t arith,
+                  void* stream);
+/* q = P^T N^-1 P x in one fused pass: the timeline-length intermediate stays
+ * on chip (registers for white noise, LDS for band-Toeplitz). */
+int mm_apply_A(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, void* stream);
+/* b = P^T N^-1 tod (the right-hand side of eq. (6)), fused likewise. */
+int mm_rhs(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* b, int32_t arith, void* stream);
+/* z = M r with the 3x3 inverse blocks of eq. (7). */
+int mm_apply_M(mm_pointing_t pt, const double* r, double* z, void* stream);
+/* map_full f64[3 * n_pix] = x at kept pixels, 0 at masked ones. */
+int mm_expand_map(mm_pointing_t pt, const double* x, double* map_full, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Solve (eq. (5)/(6) by PCG, Sec. II).  Blocking.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  double tol;           /* stop at ||r_k|| / ||b|| <= tol (recursive residual); default 1e-10 */
+  int32_t max_iter;     /* iteration cap per PCG run; default 2000                         */
+  int32_t fixed_iter;   /* > 0: run exactly this many iterations (no early stop)          */
+  int32_t check_every;  /* host polls convergence every this many iterations; default 8   */
+  int32_t mixed;        /* 0: FP64 operator; 1: FP32 inner solves + FP64 refinement      */
+  int32_t max_outer;    /* mixed: refinement steps cap; default 10                        */
+  double inner_tol;     /* mixed: inner relative tolerance; default 1e-5                 */
+} mm_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* PCG iterations (summed over inner solves)         */
+  int32_t outer_iters;  /* refinement steps (1 for the FP64 solve)          */
+  int32_t converged;    /* 1 if the tolerance was met                        */
+  int32_t breakdown;    /* 1 if PCG broke down                               */
+  double rel_resid;     /* last recursive residual ||r|| / ||b||            */
+  double true_rel_resid;/* ||b - A x|| / ||b|| recomputed in FP64 at exit    */
+} mm_solve_info;
+
+/* Fill opts with the defaults above. */
+int mm_solve_opts_default(mm_solve_opts* opts);
+
+int mm_solve_workspace_size(mm_pointing_t pt, mm_noise_t nz, const mm_solve_opts* opts, size_t* bytes);
+
+/* Solve for the map from the timeline `tod` (dtype of the pointing).
+ *   map_out   f64[3 * n_pix] device, full grid (0 at masked pixels), may be NULL
+ *   x_out     f64[3 * n_kept] device, compact solution, may be NULL
+ *   history_host  f64[history_len] host, ||r_k||/||b|| for k = 0.. (may be NULL)
+ * Returns MM_OK, MM_NOTCONVERGED or an error (MM_EBREAKDOWN keeps the last
+ * good iterate in the outputs). */
+int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, double* x_out,
+             const mm_solve_opts* opts, mm_solve_info* info, double* history_host, int32_t history_len,
+             void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAPMAKER_H */

@@ -1,0 +1,378 @@
+"""Thin ctypes binding of libmapmaker (the C ABI in include/mapmaker.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every computation runs in the library's HIP kernels.
+There is no fallback: if the shared library is missing, importing the
+functions below raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmapmaker.so")
+
+MM_OK, MM_NOTCONVERGED = 0, 1
+MM_EINVAL, MM_ENOSPC, MM_EHIP, MM_EBREAKDOWN = -1, -2, -3, -4
+MM_F64, MM_F32 = 0, 1
+
+_c = ctypes
+_vp = _c.c_void_p
+_i32, _i64, _f64, _sz = _c.c_int32, _c.c_int64, _c.c_double, _c.c_size_t
+_pi32 = _c.POINTER(_c.c_int32)
+_pi64 = _c.POINTER(_c.c_int64)
+_pf64 = _c.POINTER(_c.c_double)
+_psz = _c.POINTER(_c.c_size_t)
+
+
+class SolveOpts(_c.Structure):
+    _fields_ = [("tol", _f64), ("max_iter", _i32), ("fixed_iter", _i32), ("check_every", _i32),
+                ("mixed", _i32), ("max_outer", _i32), ("inner_tol", _f64)]
+
+
+class SolveInfo(_c.Structure):
+    _fields_ = [("iters", _i32), ("outer_iters", _i32), ("converged", _i32), ("breakdown", _i32),
+                ("rel_resid", _f64), ("true_rel_resid", _f64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# name -> (restype, argtypes); every symbol include/mapmaker.h declares
+SIGNATURES = {
+    "mm_last_error": (_c.c_char_p, []),
+    "mm_abi_version": (_c.c_int, []),
+    "mm_pointing_workspace_size": (_c.c_int, [_i64, _i32, _i32, _psz]),
+    "mm_pointing_build": (_c.c_int, [_vp, _vp, _i32, _i64, _pi64, _i32, _pf64, _i32, _i32, _f64, _vp, _sz, _vp,
+                                     _c.POINTER(_vp)]),
+    "mm_pointing_info": (_c.c_int, [_vp, _pi32, _pi64, _pi32, _pi32, _pi32]),
+    "mm_pointing_export": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mm_pointing_destroy": (_c.c_int, [_vp]),
+    "mm_noise_white_workspace_size": (_c.c_int, [_i32, _psz]),
+    "mm_noise_white": (_c.c_int, [_pf64, _i32, _vp, _sz, _vp, _c.POINTER(_vp)]),
+    "mm_noise_toeplitz_workspace_size": (_c.c_int, [_i32, _i32, _pi64, _i64, _psz]),
+    "mm_noise_toeplitz": (_c.c_int, [_pf64, _i32, _i32, _pi64, _pi32, _i64, _vp, _sz, _vp, _c.POINTER(_vp)]),
+    "mm_noise_destroy": (_c.c_int, [_vp]),
+    "mm_apply_P": (_c.c_int, [_vp, _vp, _vp, _i32, _vp]),
+    "mm_apply_PT": (_c.c_int, [_vp, _vp, _vp, _i32, _vp]),
+    "mm_apply_Ninv": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "mm_apply_A": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "mm_rhs": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "mm_apply_M": (_c.c_int, [_vp, _vp, _vp, _vp]),
+    "mm_expand_map": (_c.c_int, [_vp, _vp, _vp, _vp]),
+    "mm_solve_opts_default": (_c.c_int, [_c.POINTER(SolveOpts)]),
+    "mm_solve_workspace_size": (_c.c_int, [_vp, _vp, _c.POINTER(SolveOpts), _psz]),
+    "mm_solve": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.POINTER(SolveOpts), _c.POINTER(SolveInfo), _pf64, _i32,
+                            _vp, _sz, _vp]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmapmaker.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2501_16122_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class MapMakerError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmapmaker error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc, allow=(MM_OK,)):
+    if rc in allow:
+        return rc
+    msg = load().mm_last_error()
+    raise MapMakerError(rc, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return MM_F64
+    if t.dtype == torch.float32:
+        return MM_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _dev_check(t, dtype=None, numel=None, name="tensor"):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+def _arith(a) -> int:
+    if a in ("f64", MM_F64, None):
+        return MM_F64
+    if a in ("f32", MM_F32):
+        return MM_F32
+    raise ValueError(f"bad arith {a!r}")
+
+
+class Pointing:
+    """Handle over the precomputed pointing (hits, masks, 3x3 inverse blocks).
+
+    Borrows ``pix`` and ``psi`` (device tensors) for its lifetime and owns a
+    device workspace tensor."""
+
+    def __init__(self, pix, psi, det_offsets, det_weight, n_pix, min_hits=3, cond_max=1e3, stream=None):
+        torch = _torch()
+        lib = load()
+        _dev_check(pix, torch.int32, name="pix")
+        _dev_check(psi, name="psi")
+        self.dtype = _dtype_code(psi)
+        n = pix.numel()
+        if psi.numel() != n:
+            raise ValueError("pix and psi differ in length")
+        offs = np.ascontiguousarray(det_offsets, dtype=np.int64)
+        w = np.ascontiguousarray(det_weight, dtype=np.float64)
+        n_det = offs.size - 1
+        sz = _c.c_size_t()
+        _check(lib.mm_pointing_workspace_size(n, n_det, int(n_pix), _c.byref(sz)))
+        self.workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=pix.device)
+        h = _vp()
+        _check(lib.mm_pointing_build(_ptr(pix), _ptr(psi), self.dtype, n, offs.ctypes.data_as(_pi64), n_det,
+                                     w.ctypes.data_as(_pf64), int(n_pix), int(min_hits), float(cond_max),
+                                     _ptr(self.workspace), sz.value, _stream(stream), _c.byref(h)))
+        self.handle = h
+        self._keep = (pix, psi)
+        self.n_samples, self.n_pix, self.n_det = n, int(n_pix), n_det
+        nk = _c.c_int32()
+        _check(lib.mm_pointing_info(h, _c.byref(nk), None, None, None, None))
+        self.n_kept = nk.value
+        self.device = pix.device
+        self.tod_dtype = psi.dtype
+
+    def export(self, stream=None):
+        torch = _torch()
+        dev = self.device
+        hits = torch.empty(self.n_pix, dtype=torch.int32, device=dev)
+        mask = torch.empty(self.n_pix, dtype=torch.uint8, device=dev)
+        compact = torch.empty(self.n_pix, dtype=torch.int32, device=dev)
+        kept = torch.empty(max(1, self.n_kept), dtype=torch.int32, device=dev)
+        minv = torch.empty(max(1, 9 * self.n_kept), dtype=torch.float64, device=dev)
+        _check(load().mm_pointing_export(self.handle, _ptr(hits), _ptr(mask), _ptr(compact), _ptr(kept), _ptr(minv),
+                                         _stream(stream)))
+        return {"hits": hits, "mask": mask, "compact": compact, "kept": kept[:self.n_kept],
+                "minv": minv[:9 * self.n_kept].view(-1, 3, 3)}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().mm_pointing_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Noise:
+    """N^-1: white (per-detector weights) or band-Toeplitz per chunk."""
+
+    def __init__(self, handle, workspace, kind):
+        self.handle, self.workspace, self.kind = handle, workspace, kind
+
+    @classmethod
+    def white(cls, det_weight, device, stream=None):
+        torch = _torch()
+        lib = load()
+        w = np.ascontiguousarray(det_weight, dtype=np.float64)
+        sz = _c.c_size_t()
+        _check(lib.mm_noise_white_workspace_size(w.size, _c.byref(sz)))
+        ws = torch.empty(sz.value, dtype=torch.uint8, device=device)
+        h = _vp()
+        _check(lib.mm_noise_white(w.ctypes.data_as(_pf64), w.size, _ptr(ws), sz.value, _stream(stream), _c.byref(h)))
+        return cls(h, ws, "white")
+
+    @classmethod
+    def toeplitz(cls, coeff, chunk_offsets, device, chunk_filter=None, stream=None):
+        torch = _torch()
+        lib = load()
+        c = np.ascontiguousarray(np.atleast_2d(coeff), dtype=np.float64)
+        offs = np.ascontiguousarray(chunk_offsets, dtype=np.int64)
+        n_chunks = offs.size - 1
+        filt = None
+        if chunk_filter is not None:
+            filt = np.ascontiguousarray(chunk_filter, dtype=np.int32)
+        sz = _c.c_size_t()
+        _check(lib.mm_noise_toeplitz_workspace_size(c.shape[1], c.shape[0], offs.ctypes.data_as(_pi64), n_chunks,
+                                                    _c.byref(sz)))
+        ws = torch.empty(sz.value, dtype=torch.uint8, device=device)
+        h = _vp()
+        _check(lib.mm_noise_toeplitz(c.ctypes.data_as(_pf64), c.shape[1], c.shape[0], offs.ctypes.data_as(_pi64),
+                                     None if filt is None else filt.ctypes.data_as(_pi32), n_chunks, _ptr(ws),
+                                     sz.value, _stream(stream), _c.byref(h)))
+        return cls(h, ws, "toeplitz")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().mm_noise_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _vec(pt: Pointing, x, name):
+    torch = _torch()
+    _dev_check(x, torch.float64, 3 * pt.n_kept, name)
+
+
+def _tod(pt: Pointing, t, name):
+    _dev_check(t, pt.tod_dtype, pt.n_samples, name)
+
+
+def apply_P(pt: Pointing, x, tod=None, arith="f64", stream=None):
+    torch = _torch()
+    _vec(pt, x, "x")
+    if tod is None:
+        tod = torch.empty(pt.n_samples, dtype=pt.tod_dtype, device=pt.device)
+    _tod(pt, tod, "tod")
+    _check(load().mm_apply_P(pt.handle, _ptr(x), _ptr(tod), _arith(arith), _stream(stream)))
+    return tod
+
+
+def apply_PT(pt: Pointing, tod, q=None, arith="f64", stream=None):
+    torch = _torch()
+    _tod(pt, tod, "tod")
+    if q is None:
+        q = torch.empty(3 * pt.n_kept, dtype=torch.float64, device=pt.device)
+    _vec(pt, q, "q")
+    _check(load().mm_apply_PT(pt.handle, _ptr(tod), _ptr(q), _arith(arith), _stream(stream)))
+    return q
+
+
+def apply_Ninv(nz: Noise, pt: Pointing, tod_in, tod_out=None, arith="f64", stream=None):
+    torch = _torch()
+    _tod(pt, tod_in, "tod_in")
+    if tod_out is None:
+        tod_out = torch.empty_like(tod_in)
+    _tod(pt, tod_out, "tod_out")
+    _check(load().mm_apply_Ninv(nz.handle, pt.handle, _ptr(tod_in), _ptr(tod_out), _arith(arith), _stream(stream)))
+    return tod_out
+
+
+def apply_A(pt: Pointing, nz: Noise, x, q=None, arith="f64", stream=None):
+    torch = _torch()
+    _vec(pt, x, "x")
+    if q is None:
+        q = torch.empty(3 * pt.n_kept, dtype=torch.float64, device=pt.device)
+    _vec(pt, q, "q")
+    _check(load().mm_apply_A(pt.handle, nz.handle, _ptr(x), _ptr(q), _arith(arith), _stream(stream)))
+    return q
+
+
+def rhs(pt: Pointing, nz: Noise, tod, b=None, arith="f64", stream=None):
+    torch = _torch()
+    _tod(pt, tod, "tod")
+    if b is None:
+        b = torch.empty(3 * pt.n_kept, dtype=torch.float64, device=pt.device)
+    _vec(pt, b, "b")
+    _check(load().mm_rhs(pt.handle, nz.handle, _ptr(tod), _ptr(b), _arith(arith), _stream(stream)))
+    return b
+
+
+def apply_M(pt: Pointing, r, z=None, stream=None):
+    torch = _torch()
+    _vec(pt, r, "r")
+    if z is None:
+        z = torch.empty_like(r)
+    _vec(pt, z, "z")
+    _check(load().mm_apply_M(pt.handle, _ptr(r), _ptr(z), _stream(stream)))
+    return z
+
+
+def expand_map(pt: Pointing, x, out=None, stream=None):
+    torch = _torch()
+    _vec(pt, x, "x")
+    if out is None:
+        out = torch.empty(3 * pt.n_pix, dtype=torch.float64, device=pt.device)
+    _dev_check(out, torch.float64, 3 * pt.n_pix, "map")
+    _check(load().mm_expand_map(pt.handle, _ptr(x), _ptr(out), _stream(stream)))
+    return out
+
+
+def solve_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    _check(load().mm_solve_opts_default(_c.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Solver:
+    """Reusable solve workspace for one (pointing, noise) pair."""
+
+    def __init__(self, pt: Pointing, nz: Noise, **opts):
+        torch = _torch()
+        self.pt, self.nz = pt, nz
+        self.opts = solve_opts(**opts)
+        sz = _c.c_size_t()
+        _check(load().mm_solve_workspace_size(pt.handle, nz.handle, _c.byref(self.opts), _c.byref(sz)))
+        self.workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=pt.device)
+        self.hist_len = max(self.opts.max_iter, self.opts.fixed_iter, self.opts.max_outer) + 1
+
+    def solve(self, tod, map_out=None, x_out=None, stream=None, history=False):
+        torch = _torch()
+        pt = self.pt
+        _tod(pt, tod, "tod")
+        if map_out is None:
+            map_out = torch.empty(3 * pt.n_pix, dtype=torch.float64, device=pt.device)
+        if x_out is None:
+            x_out = torch.empty(max(1, 3 * pt.n_kept), dtype=torch.float64, device=pt.device)
+        info = SolveInfo()
+        hist = np.zeros(self.hist_len) if history else None
+        rc = load().mm_solve(pt.handle, self.nz.handle, _ptr(tod), _ptr(map_out), _ptr(x_out),
+                             _c.byref(self.opts), _c.byref(info),
+                             None if hist is None else hist.ctypes.data_as(_pf64),
+                             0 if hist is None else hist.size, _ptr(self.workspace), self.workspace.numel(),
+                             _stream(stream))
+        _check(rc, allow=(MM_OK, MM_NOTCONVERGED))
+        out = {"map": map_out, "x": x_out[:3 * pt.n_kept], "info": info.as_dict(), "status": rc}
+        if hist is not None:
+            n = (info.iters + 1) if not self.opts.mixed else info.outer_iters
+            out["history"] = hist[:n]
+        return out

@@ -1,0 +1,561 @@
+// C ABI of libmapmaker: argument checking, workspace carving and the host
+// side of the PCG solve.  Every step of the computation runs in the HIP
+// kernels of the other translation units; this file only enqueues them.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <new>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string("HIP error in ") + what + ": " + hipGetErrorString(e));
+  return MM_EHIP;
+}
+
+namespace {
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool valid_dtype(int d) { return d == MM_F64 || d == MM_F32; }
+
+// Workspace layout of a pointing handle (also used for the size query).
+struct PtLayout {
+  int32_t* hits;
+  uint8_t* mask;
+  int32_t* compact;
+  int32_t* kept;
+  double* blocks;
+  double* minv;
+  int32_t* sample_k;
+  double* det_w;
+  PtTile* tiles;
+  int32_t* scan_tmp;
+  int32_t* flags;
+};
+
+int64_t count_tiles(const int64_t* offs, int32_t n_det) {
+  int64_t n = 0;
+  for (int32_t d = 0; d < n_det; ++d) n += (offs[d + 1] - offs[d] + kTileSamples - 1) / kTileSamples;
+  return n;
+}
+
+size_t carve_pointing(Carver& cv, int64_t n_samples, int32_t n_det, int32_t n_pix, int64_t n_tiles, PtLayout* L) {
+  const int64_t nb_scan = (n_pix + 1023) / 1024;
+  L->hits = cv.take<int32_t>(n_pix);
+  L->mask = cv.take<uint8_t>(n_pix);
+  L->compact = cv.take<int32_t>(n_pix);
+  L->kept = cv.take<int32_t>(n_pix);
+  L->blocks = cv.take<double>(6 * (size_t)n_pix);
+  L->minv = cv.take<double>(6 * (size_t)n_pix);
+  L->sample_k = cv.take<int32_t>(n_samples);
+  L->det_w = cv.take<double>(n_det);
+  L->tiles = cv.take<PtTile>(n_tiles);
+  L->scan_tmp = cv.take<int32_t>(nb_scan + 1);
+  L->flags = cv.take<int32_t>(4);
+  return cv.used;
+}
+
+int check_pointing(mm_pointing_t pt) {
+  if (pt == nullptr) return fail(MM_EINVAL, "null pointing handle");
+  return MM_OK;
+}
+
+int check_noise_vs_pointing(const mm_noise_s* nz, const mm_pointing_s* pt) {
+  if (nz == nullptr) return fail(MM_EINVAL, "null noise handle");
+  if (nz->kind == 0) {
+    if (nz->n_det != pt->n_det) return fail(MM_EINVAL, "white noise has a different detector count");
+    return MM_OK;
+  }
+  if (nz->chunk_offsets.back() > pt->n_samples) return fail(MM_EINVAL, "noise chunks extend past the timeline");
+  // no chunk may straddle a detector start
+  size_t d = 1;
+  for (int64_t c = 0; c < nz->n_chunks; ++c) {
+    const int64_t a = nz->chunk_offsets[c], b = nz->chunk_offsets[c + 1];
+    while (d < pt->det_offsets.size() && pt->det_offsets[d] <= a) ++d;
+    if (d < pt->det_offsets.size() && pt->det_offsets[d] < b)
+      return fail(MM_EINVAL, "a noise chunk crosses a detector start");
+  }
+  return MM_OK;
+}
+
+int apply_A_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, double* q, int arith,
+                 const int32_t* done, hipStream_t s) {
+  if (nz->kind == 0) return launch_fused_white(pt, nz->det_w, x, q, arith, done, s);
+  return launch_fused_toeplitz(pt, nz, x, nullptr, q, arith, done, s);
+}
+
+int rhs_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const void* tod, double* b, int arith, hipStream_t s) {
+  int rc = launch_fill(b, 3 * (int64_t)pt->n_kept, 0.0, s);
+  if (rc) return rc;
+  if (nz->kind == 0) return launch_rhs_white(pt, nz->det_w, tod, b, arith, s);
+  return launch_fused_toeplitz(pt, nz, nullptr, tod, b, arith, nullptr, s);
+}
+
+}  // namespace
+}  // namespace mm
+
+using namespace mm;
+
+extern "C" {
+
+const char* mm_last_error(void) { return g_last_error.c_str(); }
+
+int mm_abi_version(void) { return 1; }
+
+int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, size_t* bytes) {
+  if (!bytes || n_samples < 0 || n_det <= 0 || n_pix <= 0) return fail(MM_EINVAL, "bad pointing sizes");
+  // worst case tile count: every detector may add one partial tile
+  const int64_t n_tiles = n_samples / kTileSamples + n_det;
+  Carver cv(nullptr, 0);
+  PtLayout L;
+  *bytes = carve_pointing(cv, n_samples, n_det, n_pix, n_tiles, &L);
+  return MM_OK;
+}
+
+int mm_pointing_build(const int32_t* pix, const void* psi, int32_t dtype, int64_t n_samples,
+                      const int64_t* det_offsets_host, int32_t n_det, const double* det_weight_host, int32_t n_pix,
+                      int32_t min_hits, double cond_max, void* workspace, size_t ws_bytes, void* stream,
+                      mm_pointing_t* out) {
+  if (!out) return fail(MM_EINVAL, "null output handle pointer");
+  *out = nullptr;
+  if (!valid_dtype(dtype)) return fail(MM_EINVAL, "dtype must be MM_F64 or MM_F32");
+  if (n_samples < 0 || n_det <= 0 || n_pix <= 0) return fail(MM_EINVAL, "bad sizes");
+  if (n_samples > 0 && (!pix || !psi)) return fail(MM_EINVAL, "null pix or psi");
+  if (!det_offsets_host || !det_weight_host || !workspace) return fail(MM_EINVAL, "null argument");
+  if (det_offsets_host[0] != 0 || det_offsets_host[n_det] != n_samples)
+    return fail(MM_EINVAL, "det_offsets must start at 0 and end at n_samples");
+  for (int32_t d = 0; d < n_det; ++d) {
+    if (det_offsets_host[d + 1] < det_offsets_host[d]) return fail(MM_EINVAL, "det_offsets must be non-decreasing");
+    if (!(det_weight_host[d] >= 0.0) || !std::isfinite(det_weight_host[d]))
+      return fail(MM_EINVAL, "detector weights must be finite and >= 0");
+  }
+  size_t need = 0;
+  mm_pointing_workspace_size(n_samples, n_det, n_pix, &need);
+  if (ws_bytes < need) return fail(MM_ENOSPC, "pointing workspace too small");
+  hipStream_t s = as_stream(stream);
+
+  auto* pt = new (std::nothrow) mm_pointing_s();
+  if (!pt) return fail(MM_EINVAL, "out of host memory");
+  pt->dtype = dtype;
+  pt->n_samples = n_samples;
+  pt->n_det = n_det;
+  pt->n_pix = n_pix;
+  pt->pix = pix;
+  pt->psi = psi;
+  pt->det_offsets.assign(det_offsets_host, det_offsets_host + n_det + 1);
+  pt->det_weight.assign(det_weight_host, det_weight_host + n_det);
+  (void)hipGetDevice(&pt->device);
+
+  std::vector<PtTile> tiles;
+  for (int32_t d = 0; d < n_det; ++d)
+    for (int64_t t = det_offsets_host[d]; t < det_offsets_host[d + 1]; t += kTileSamples) {
+      const int64_t len = std::min<int64_t>(kTileSamples, det_offsets_host[d + 1] - t);
+      tiles.push_back(PtTile{t, (int32_t)len, d, 0, -1});
+    }
+  pt->n_tiles = (int64_t)tiles.size();
+  Carver cv(workspace, ws_bytes);
+  PtLayout L;
+  carve_pointing(cv, n_samples, n_det, n_pix, pt->n_tiles, &L);
+  pt->hits = L.hits;
+  pt->mask = L.mask;
+  pt->compact = L.compact;
+  pt->kept = L.kept;
+  pt->blocks = L.blocks;
+  pt->minv = L.minv;
+  pt->sample_k = L.sample_k;
+  pt->det_w = L.det_w;
+  pt->tiles = L.tiles;
+  pt->scan_tmp = L.scan_tmp;
+  pt->flags = L.flags;
+
+  auto bail = [&](int rc) {
+    delete pt;
+    return rc;
+  };
+  hipError_t e;
+  if (!tiles.empty() &&
+      (e = hipMemcpyAsync(pt->tiles, tiles.data(), tiles.size() * sizeof(PtTile), hipMemcpyHostToDevice, s)) !=
+          hipSuccess)
+    return bail(hip_fail(e, "upload tiles"));
+  if ((e = hipMemcpyAsync(pt->det_w, det_weight_host, sizeof(double) * n_det, hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return bail(hip_fail(e, "upload weights"));
+  int rc = launch_pointing_build(pt, min_hits, cond_max, s);
+  if (rc) return bail(rc);
+  int32_t flags[2] = {0, 0};
+  if ((e = hipMemcpyAsync(flags, pt->flags, sizeof(flags), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return bail(hip_fail(e, "read build flags"));
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "build sync"));
+  if (flags[0]) return bail(fail(MM_EINVAL, "pixel index outside [0, n_pix)"));
+  pt->n_kept = flags[1];
+  *out = pt;
+  return MM_OK;
+}
+
+int mm_pointing_info(mm_pointing_t pt, int32_t* n_kept, int64_t* n_samples, int32_t* n_pix, int32_t* n_det,
+                     int32_t* dtype) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (n_kept) *n_kept = pt->n_kept;
+  if (n_samples) *n_samples = pt->n_samples;
+  if (n_pix) *n_pix = pt->n_pix;
+  if (n_det) *n_det = pt->n_det;
+  if (dtype) *dtype = pt->dtype;
+  return MM_OK;
+}
+
+int mm_pointing_export(mm_pointing_t pt, int32_t* hits, uint8_t* mask, int32_t* compact, int32_t* kept, double* minv,
+                       void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  return launch_export(pt, hits, mask, compact, kept, minv, as_stream(stream));
+}
+
+int mm_pointing_destroy(mm_pointing_t pt) {
+  delete pt;
+  return MM_OK;
+}
+
+int mm_noise_white_workspace_size(int32_t n_det, size_t* bytes) {
+  if (!bytes || n_det <= 0) return fail(MM_EINVAL, "bad n_det");
+  *bytes = sizeof(double) * (size_t)n_det;
+  return MM_OK;
+}
+
+int mm_noise_white(const double* det_weight_host, int32_t n_det, void* workspace, size_t ws_bytes, void* stream,
+                   mm_noise_t* out) {
+  if (!out) return fail(MM_EINVAL, "null output handle pointer");
+  *out = nullptr;
+  if (!det_weight_host || n_det <= 0 || !workspace) return fail(MM_EINVAL, "bad white-noise arguments");
+  if (ws_bytes < sizeof(double) * (size_t)n_det) return fail(MM_ENOSPC, "noise workspace too small");
+  for (int32_t d = 0; d < n_det; ++d)
+    if (!(det_weight_host[d] >= 0.0) || !std::isfinite(det_weight_host[d]))
+      return fail(MM_EINVAL, "detector weights must be finite and >= 0");
+  auto* nz = new (std::nothrow) mm_noise_s();
+  if (!nz) return fail(MM_EINVAL, "out of host memory");
+  nz->kind = 0;
+  nz->n_det = n_det;
+  nz->det_w = static_cast<double*>(workspace);
+  (void)hipGetDevice(&nz->device);
+  hipError_t e = hipMemcpyAsync(nz->det_w, det_weight_host, sizeof(double) * n_det, hipMemcpyHostToDevice,
+                                as_stream(stream));
+  if (e == hipSuccess) e = hipStreamSynchronize(as_stream(stream));
+  if (e != hipSuccess) {
+    delete nz;
+    return hip_fail(e, "upload white-noise weights");
+  }
+  *out = nz;
+  return MM_OK;
+}
+
+static int check_chunks(const int64_t* offs, int64_t n_chunks) {
+  if (!offs || n_chunks < 0) return fail(MM_EINVAL, "bad chunk offsets");
+  if (offs[0] < 0) return fail(MM_EINVAL, "chunk offsets must be >= 0");
+  for (int64_t c = 0; c < n_chunks; ++c)
+    if (offs[c + 1] < offs[c]) return fail(MM_EINVAL, "chunk offsets must be non-decreasing");
+  return MM_OK;
+}
+
+int mm_noise_toeplitz_workspace_size(int32_t lambda, int32_t n_filt, const int64_t* chunk_offsets_host,
+                                     int64_t n_chunks, size_t* bytes) {
+  if (!bytes || lambda < 1 || lambda > kMaxLambda || n_filt < 1) return fail(MM_EINVAL, "bad Toeplitz sizes");
+  if (int rc = check_chunks(chunk_offsets_host, n_chunks)) return rc;
+  mm_noise_s tmp;
+  tmp.kind = 1;
+  tmp.lambda = lambda;
+  tmp.n_filt = n_filt;
+  tmp.n_chunks = n_chunks;
+  tmp.chunk_offsets.assign(chunk_offsets_host, chunk_offsets_host + n_chunks + 1);
+  tmp.chunk_filter.assign(n_chunks, 0);
+  return prepare_toeplitz_tables(&tmp, nullptr, nullptr, 0, nullptr, bytes);
+}
+
+int mm_noise_toeplitz(const double* coeff_host, int32_t lambda, int32_t n_filt, const int64_t* chunk_offsets_host,
+                      const int32_t* chunk_filter_host, int64_t n_chunks, void* workspace, size_t ws_bytes,
+                      void* stream, mm_noise_t* out) {
+  if (!out) return fail(MM_EINVAL, "null output handle pointer");
+  *out = nullptr;
+  if (!coeff_host || !workspace || lambda < 1 || lambda > kMaxLambda || n_filt < 1)
+    return fail(MM_EINVAL, "bad Toeplitz arguments (1 <= lambda <= 4096)");
+  if (int rc = check_chunks(chunk_offsets_host, n_chunks)) return rc;
+  for (int64_t i = 0; i < (int64_t)n_filt * lambda; ++i)
+    if (!std::isfinite(coeff_host[i])) return fail(MM_EINVAL, "non-finite Toeplitz coefficient");
+  auto* nz = new (std::nothrow) mm_noise_s();
+  if (!nz) return fail(MM_EINVAL, "out of host memory");
+  nz->kind = 1;
+  nz->lambda = lambda;
+  nz->n_filt = n_filt;
+  nz->n_chunks = n_chunks;
+  nz->chunk_offsets.assign(chunk_offsets_host, chunk_offsets_host + n_chunks + 1);
+  nz->chunk_filter.resize(n_chunks);
+  for (int64_t c = 0; c < n_chunks; ++c) {
+    const int32_t f = chunk_filter_host ? chunk_filter_host[c] : 0;
+    if (f < 0 || f >= n_filt) {
+      delete nz;
+      return fail(MM_EINVAL, "chunk_filter out of range");
+    }
+    nz->chunk_filter[c] = f;
+  }
+  (void)hipGetDevice(&nz->device);
+  int rc = prepare_toeplitz_tables(nz, coeff_host, workspace, ws_bytes, as_stream(stream), nullptr);
+  if (rc) {
+    delete nz;
+    return rc;
+  }
+  *out = nz;
+  return MM_OK;
+}
+
+int mm_noise_destroy(mm_noise_t nz) {
+  delete nz;
+  return MM_OK;
+}
+
+int mm_apply_P(mm_pointing_t pt, const double* x, void* tod, int32_t arith, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (!valid_dtype(arith)) return fail(MM_EINVAL, "bad arith");
+  if ((pt->n_kept && !x) || (pt->n_samples && !tod)) return fail(MM_EINVAL, "null vector");
+  return launch_apply_P(pt, x, tod, arith, as_stream(stream));
+}
+
+int mm_apply_PT(mm_pointing_t pt, const void* tod, double* q, int32_t arith, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (!valid_dtype(arith)) return fail(MM_EINVAL, "bad arith");
+  if ((pt->n_kept && !q) || (pt->n_samples && !tod)) return fail(MM_EINVAL, "null vector");
+  hipStream_t s = as_stream(stream);
+  if (int rc = launch_fill(q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
+  return launch_apply_PT(pt, tod, q, arith, s);
+}
+
+int mm_apply_Ninv(mm_noise_t nz, mm_pointing_t pt, const void* tod_in, void* tod_out, int32_t arith, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
+  if (!valid_dtype(arith)) return fail(MM_EINVAL, "bad arith");
+  if (pt->n_samples && (!tod_in || !tod_out)) return fail(MM_EINVAL, "null timeline");
+  if (tod_in == tod_out && pt->n_samples) return fail(MM_EINVAL, "tod_out must not alias tod_in");
+  hipStream_t s = as_stream(stream);
+  if (nz->kind == 0) return launch_ninv_white(pt, nz->det_w, tod_in, tod_out, arith, s);
+  // samples outside every chunk are zero
+  const size_t esz = pt->dtype == MM_F64 ? 8 : 4;
+  MM_HIP(hipMemsetAsync(tod_out, 0, esz * (size_t)pt->n_samples, s));
+  return launch_ninv_toeplitz(pt, nz, tod_in, tod_out, arith, s);
+}
+
+int mm_apply_A(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
+  if (!valid_dtype(arith)) return fail(MM_EINVAL, "bad arith");
+  if (pt->n_kept && (!x || !q)) return fail(MM_EINVAL, "null vector");
+  hipStream_t s = as_stream(stream);
+  if (int rc = launch_fill(q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
+  return apply_A_impl(pt, nz, x, q, arith, nullptr, s);
+}
+
+int mm_rhs(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* b, int32_t arith, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
+  if (!valid_dtype(arith)) return fail(MM_EINVAL, "bad arith");
+  if ((pt->n_kept && !b) || (pt->n_samples && !tod)) return fail(MM_EINVAL, "null vector");
+  return rhs_impl(pt, nz, tod, b, arith, as_stream(stream));
+}
+
+int mm_apply_M(mm_pointing_t pt, const double* r, double* z, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (pt->n_kept && (!r || !z)) return fail(MM_EINVAL, "null vector");
+  return launch_apply_M(pt, r, z, as_stream(stream));
+}
+
+int mm_expand_map(mm_pointing_t pt, const double* x, double* map_full, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (!map_full || (pt->n_kept && !x)) return fail(MM_EINVAL, "null vector");
+  return launch_expand(pt, x, map_full, as_stream(stream));
+}
+
+int mm_solve_opts_default(mm_solve_opts* o) {
+  if (!o) return fail(MM_EINVAL, "null opts");
+  o->tol = 1e-10;
+  o->max_iter = 2000;
+  o->fixed_iter = 0;
+  o->check_every = 8;
+  o->mixed = 0;
+  o->max_outer = 10;
+  o->inner_tol = 1e-5;
+  return MM_OK;
+}
+
+namespace {
+
+struct SolveLayout {
+  PcgBufs B;
+  double* xt;   // mixed: accumulated solution
+  double* rt;   // mixed: outer residual
+  double* b64;  // mixed: FP64 right-hand side
+};
+
+size_t carve_solve(Carver& cv, int32_t n_kept, int32_t hist_len, SolveLayout* L) {
+  const size_t n3 = 3 * (size_t)n_kept;
+  L->B.x = cv.take<double>(n3);
+  L->B.r = cv.take<double>(n3);
+  L->B.z = cv.take<double>(n3);
+  L->B.p = cv.take<double>(n3);
+  L->B.q = cv.take<double>(n3);
+  L->B.b = cv.take<double>(n3);
+  L->xt = cv.take<double>(n3);
+  L->rt = cv.take<double>(n3);
+  L->b64 = cv.take<double>(n3);
+  L->B.partials = cv.take<double>(2 * kPcgBlocks);
+  L->B.st = cv.take<PcgState>(1);
+  L->B.hist = cv.take<double>(hist_len);
+  L->B.hist_len = hist_len;
+  return cv.used;
+}
+
+int32_t hist_len_for(const mm_solve_opts& o) {
+  const int32_t n = o.fixed_iter > 0 ? o.fixed_iter : o.max_iter;
+  return std::max<int32_t>(1, n + 1);
+}
+
+// Run one PCG on B.b (already in place) with operator arithmetic `arith`.
+int run_pcg(const mm_pointing_s* pt, const mm_noise_s* nz, PcgBufs& B, int arith, double tol, int32_t max_iter,
+            int32_t fixed_iter, int32_t check_every, PcgState* host_st, hipStream_t s) {
+  if (int rc = launch_pcg_init(pt, B, tol, max_iter, fixed_iter, s)) return rc;
+  const int32_t cap = fixed_iter > 0 ? fixed_iter : max_iter;
+  int32_t issued = 0;
+  for (;;) {
+    MM_HIP(hipMemcpyAsync(host_st, B.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    MM_HIP(hipStreamSynchronize(s));
+    if (host_st->done || issued >= cap) break;
+    const int32_t chunk = std::min(check_every, cap - issued);
+    for (int32_t i = 0; i < chunk; ++i) {
+      if (int rc = apply_A_impl(pt, nz, B.p, B.q, arith, &B.st->done, s)) return rc;
+      if (int rc = launch_pcg_iteration_tail(pt, B, s)) return rc;
+    }
+    issued += chunk;
+  }
+  return MM_OK;
+}
+
+// ||b - A x|| / ||b|| in FP64 arithmetic; uses B.q as scratch.
+int true_residual(const mm_pointing_s* pt, const mm_noise_s* nz, PcgBufs& B, const double* b, const double* x,
+                  double* out_rel, PcgState* host_st, hipStream_t s) {
+  if (int rc = launch_fill(B.q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
+  if (int rc = apply_A_impl(pt, nz, x, B.q, MM_F64, nullptr, s)) return rc;
+  MM_HIP(hipMemsetAsync(&B.st->counter, 0, sizeof(uint32_t), s));
+  if (int rc = launch_diff_norm(pt, b, B.q, B, s)) return rc;
+  MM_HIP(hipMemcpyAsync(host_st, B.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  MM_HIP(hipStreamSynchronize(s));
+  *out_rel = host_st->scratch1 > 0 ? std::sqrt(host_st->scratch0 / host_st->scratch1) : 0.0;
+  return MM_OK;
+}
+
+}  // namespace
+
+int mm_solve_workspace_size(mm_pointing_t pt, mm_noise_t nz, const mm_solve_opts* opts, size_t* bytes) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (!nz || !bytes) return fail(MM_EINVAL, "null argument");
+  mm_solve_opts o;
+  mm_solve_opts_default(&o);
+  if (opts) o = *opts;
+  Carver cv(nullptr, 0);
+  SolveLayout L;
+  *bytes = carve_solve(cv, pt->n_kept, hist_len_for(o), &L);
+  return MM_OK;
+}
+
+int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, double* x_out,
+             const mm_solve_opts* opts, mm_solve_info* info, double* history_host, int32_t history_len,
+             void* workspace, size_t ws_bytes, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
+  if (pt->n_samples && !tod) return fail(MM_EINVAL, "null timeline");
+  if (!workspace) return fail(MM_EINVAL, "null workspace");
+  mm_solve_opts o;
+  mm_solve_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0.0) || o.max_iter < 0 || o.check_every < 1 || o.max_outer < 1 || !(o.inner_tol > 0.0))
+    return fail(MM_EINVAL, "bad solve options");
+  hipStream_t s = as_stream(stream);
+  Carver cv(workspace, ws_bytes);
+  SolveLayout L;
+  carve_solve(cv, pt->n_kept, hist_len_for(o), &L);
+  if (!cv.fits()) return fail(MM_ENOSPC, "solve workspace too small");
+  PcgBufs& B = L.B;
+  PcgState hs{};
+  mm_solve_info inf{};
+  double true_rel = 0.0;
+  const double* xfinal = B.x;
+
+  if (pt->n_kept == 0) {
+    if (map_out) MM_HIP(hipMemsetAsync(map_out, 0, sizeof(double) * 3 * (size_t)pt->n_pix, s));
+    MM_HIP(hipStreamSynchronize(s));
+    inf.converged = 1;
+    if (info) *info = inf;
+    return MM_OK;
+  }
+
+  if (!o.mixed) {
+    if (int rc = rhs_impl(pt, nz, tod, B.b, MM_F64, s)) return rc;
+    if (int rc = run_pcg(pt, nz, B, MM_F64, o.tol, o.max_iter, o.fixed_iter, o.check_every, &hs, s)) return rc;
+    inf.iters = hs.iter;
+    inf.outer_iters = 1;
+    inf.converged = hs.converged;
+    inf.breakdown = hs.breakdown;
+    inf.rel_resid = hs.rel;
+    if (history_host && history_len > 0) {
+      const int32_t n = std::min(history_len, std::min(B.hist_len, hs.iter + 1));
+      MM_HIP(hipMemcpy(history_host, B.hist, sizeof(double) * n, hipMemcpyDeviceToHost));
+    }
+    if (int rc = true_residual(pt, nz, B, B.b, B.x, &true_rel, &hs, s)) return rc;
+  } else {
+    // FP64 right-hand side, then refinement: inner FP32-operator PCG on the
+    // FP64 residual, FP64 update, FP64 residual b - A x.
+    if (int rc = rhs_impl(pt, nz, tod, L.b64, MM_F64, s)) return rc;
+    if (int rc = launch_fill(L.xt, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
+    MM_HIP(hipMemcpyAsync(L.rt, L.b64, sizeof(double) * 3 * (size_t)pt->n_kept, hipMemcpyDeviceToDevice, s));
+    double rel = 1.0;
+    int32_t hist_at = 0;
+    inf.converged = 0;
+    for (int32_t outer = 1; outer <= o.max_outer; ++outer) {
+      MM_HIP(hipMemcpyAsync(B.b, L.rt, sizeof(double) * 3 * (size_t)pt->n_kept, hipMemcpyDeviceToDevice, s));
+      if (int rc = run_pcg(pt, nz, B, MM_F32, o.inner_tol, o.max_iter, 0, o.check_every, &hs, s)) return rc;
+      inf.iters += hs.iter;
+      inf.outer_iters = outer;
+      if (hs.breakdown) {
+        inf.breakdown = 1;
+        break;
+      }
+      if (int rc = launch_add(pt, L.xt, B.x, s)) return rc;
+      if (int rc = true_residual(pt, nz, B, L.b64, L.xt, &rel, &hs, s)) return rc;
+      if (history_host && hist_at < history_len) history_host[hist_at++] = rel;
+      if (int rc = launch_sub(pt, L.b64, B.q, L.rt, s)) return rc;
+      if (rel <= o.tol) {
+        inf.converged = 1;
+        break;
+      }
+    }
+    inf.rel_resid = rel;
+    true_rel = rel;
+    xfinal = L.xt;
+  }
+  inf.true_rel_resid = true_rel;
+  if (map_out)
+    if (int rc = launch_expand(pt, xfinal, map_out, s)) return rc;
+  if (x_out) MM_HIP(hipMemcpyAsync(x_out, xfinal, sizeof(double) * 3 * (size_t)pt->n_kept, hipMemcpyDeviceToDevice, s));
+  MM_HIP(hipStreamSynchronize(s));
+  if (info) *info = inf;
+  if (inf.breakdown) return fail(MM_EBREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite value)");
+  if (!inf.converged && o.fixed_iter <= 0) return MM_NOTCONVERGED;
+  return MM_OK;
+}
+
+}  // extern "C"

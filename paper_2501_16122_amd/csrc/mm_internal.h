@@ -1,0 +1,204 @@
+// Internal declarations shared by the HIP translation units of libmapmaker.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mapmaker.h"
+
+namespace mm {
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define MM_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return mm::hip_fail(e_, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// geometry of the timeline-domain work units
+// ---------------------------------------------------------------------------
+
+// A pointing tile: up to kTileSamples consecutive samples of one detector.
+// kmin/kmax bound the compact pixel indices of its kept samples (kmax < kmin
+// when it has none); the hot kernels bin into LDS slots k - kmin.
+constexpr int kTileSamples = 4096;
+struct PtTile {
+  int64_t start;
+  int32_t len;
+  int32_t det;
+  int32_t kmin;
+  int32_t kmax;
+};
+static_assert(sizeof(PtTile) == 24, "PtTile layout");
+
+// An overlap-save tile of the band-Toeplitz N^-1: it produces outputs
+// [out_start, out_end) of one chunk [chunk_start, chunk_end) from the input
+// window [out_start - (lambda - 1), out_start - (lambda - 1) + L).
+struct FftTile {
+  int64_t out_start;
+  int64_t out_end;
+  int64_t chunk_start;
+  int64_t chunk_end;
+  int32_t filter;
+  int32_t pad_;
+};
+static_assert(sizeof(FftTile) == 40, "FftTile layout");
+
+// Real-signal length L and complex FFT length N = L/2 per arithmetic.
+// FP64: L = 2^14 (8192 complex doubles = 128 KiB of LDS);
+// FP32: L = 2^15 (16384 complex floats = 128 KiB of LDS).
+constexpr int kFftN64 = 8192;
+constexpr int kFftN32 = 16384;
+constexpr int kMaxLambda = 4096;
+
+// Carves aligned sub-buffers out of one caller workspace.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  size_t cap;
+  Carver(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <class T>
+  T* take(size_t n) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + n * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+  bool fits() const { return used <= cap; }
+};
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+}  // namespace mm
+
+struct mm_pointing_s {
+  int32_t dtype = MM_F64;
+  int64_t n_samples = 0;
+  int32_t n_det = 0;
+  int32_t n_pix = 0;
+  int32_t n_kept = 0;
+  int device = 0;
+  const int32_t* pix = nullptr;
+  const void* psi = nullptr;
+  std::vector<int64_t> det_offsets;
+  std::vector<double> det_weight;
+  // device state carved from the caller's workspace
+  int32_t* hits = nullptr;       // [n_pix]
+  uint8_t* mask = nullptr;       // [n_pix]
+  int32_t* compact = nullptr;    // [n_pix]
+  int32_t* kept = nullptr;       // [n_pix] (first n_kept used)
+  double* blocks = nullptr;      // [6 * n_pix] upper triangles of P^T diag(N)^-1 P
+  double* minv = nullptr;        // [6 * n_pix] upper triangles of the inverses (compact order)
+  int32_t* sample_k = nullptr;   // [n_samples] compact index per sample, -1 = masked
+  double* det_w = nullptr;       // [n_det]
+  mm::PtTile* tiles = nullptr;   // [n_tiles]
+  int64_t n_tiles = 0;
+  int32_t* scan_tmp = nullptr;   // [n_scan_blocks + 1]
+  int32_t* flags = nullptr;      // [4]: 0 = bad pixel seen, 1 = n_kept
+};
+
+struct mm_noise_s {
+  int kind = 0;  // 0 = white, 1 = band-Toeplitz
+  int device = 0;
+  // white
+  int32_t n_det = 0;
+  double* det_w = nullptr;
+  // band-Toeplitz
+  int32_t lambda = 0;
+  int32_t n_filt = 0;
+  int64_t n_chunks = 0;
+  std::vector<int64_t> chunk_offsets;
+  std::vector<int32_t> chunk_filter;
+  // per arithmetic (0 = FP64, 1 = FP32): tiles, spectral weights, twiddles
+  mm::FftTile* tiles[2] = {nullptr, nullptr};
+  int64_t n_tiles[2] = {0, 0};
+  void* ab[2] = {nullptr, nullptr};  // [n_filt][N] pairs (alpha_k, beta_k)
+  void* tw[2] = {nullptr, nullptr};  // [N] exp(-2 pi i k / N)
+};
+
+namespace mm {
+
+// ---------------------------------------------------------------------------
+// kernel launchers (each defined in the .hip file that holds its kernel)
+// ---------------------------------------------------------------------------
+int launch_pointing_build(mm_pointing_s* pt, int32_t min_hits, double cond_max, hipStream_t s);
+int launch_export(const mm_pointing_s* pt, int32_t* hits, uint8_t* mask, int32_t* compact,
+                  int32_t* kept, double* minv, hipStream_t s);
+
+// timeline-domain operators (white / diagonal parts)
+int launch_apply_P(const mm_pointing_s* pt, const double* x, void* tod, int arith, hipStream_t s);
+int launch_apply_PT(const mm_pointing_s* pt, const void* tod, double* q, int arith, hipStream_t s);
+int launch_ninv_white(const mm_pointing_s* pt, const double* det_w, const void* in, void* out, int arith,
+                      hipStream_t s);
+// q += P^T diag(w) P x (q must hold the accumulation start, usually 0).
+// `done` may be null; when it points to a nonzero int the kernel does nothing.
+int launch_fused_white(const mm_pointing_s* pt, const double* det_w, const double* x, double* q, int arith,
+                       const int32_t* done, hipStream_t s);
+// q += P^T diag(w) tod
+int launch_rhs_white(const mm_pointing_s* pt, const double* det_w, const void* tod, double* q, int arith,
+                     hipStream_t s);
+
+// band-Toeplitz
+int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
+                         hipStream_t s);
+int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
+                          double* q, int arith, const int32_t* done, hipStream_t s);
+int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, size_t ws_bytes,
+                            hipStream_t s, size_t* bytes_needed);
+
+// pixel domain
+int launch_apply_M(const mm_pointing_s* pt, const double* r, double* z, hipStream_t s);
+int launch_expand(const mm_pointing_s* pt, const double* x, double* full, hipStream_t s);
+int launch_fill(double* p, int64_t n, double v, hipStream_t s);
+
+// PCG
+struct PcgState {
+  double rho;
+  double alpha;
+  double beta;
+  double bnorm;
+  double rel;
+  double tol;
+  double scratch0;
+  double scratch1;
+  int32_t iter;
+  int32_t done;
+  int32_t breakdown;
+  int32_t converged;
+  int32_t max_iter;
+  int32_t fixed_iter;
+  uint32_t counter;
+  int32_t pad_;
+};
+constexpr int kPcgBlocks = 512;   // fixed grid of the vector kernels (deterministic sums)
+constexpr int kPcgThreads = 256;
+
+struct PcgBufs {
+  double *x, *r, *z, *p, *q, *b;
+  double* partials;   // [2 * kPcgBlocks]
+  PcgState* st;
+  double* hist;       // [hist_len]
+  int32_t hist_len;
+};
+int launch_pcg_init(const mm_pointing_s* pt, PcgBufs& B, double tol, int32_t max_iter, int32_t fixed_iter,
+                    hipStream_t s);
+int launch_pcg_iteration_tail(const mm_pointing_s* pt, PcgBufs& B, hipStream_t s);
+// out_norm2[0] = ||a - b||^2, out_norm2[1] = ||a||^2 (into st->scratch0/1)
+int launch_diff_norm(const mm_pointing_s* pt, const double* a, const double* b, PcgBufs& B, hipStream_t s);
+// y = a - b
+int launch_sub(const mm_pointing_s* pt, const double* a, const double* b, double* y, hipStream_t s);
+// y += a
+int launch_add(const mm_pointing_s* pt, double* y, const double* a, hipStream_t s);
+
+}  // namespace mm

@@ -1,0 +1,301 @@
+// Timeline-domain operators for the pointing matrix of eq. (2)/(8) and the
+// diagonal (white) N^-1, plus the fused q = P^T diag(w) P x of eq. (6).
+//
+// Every kernel streams the per-sample compact index (int32) and angle psi
+// (FP64 or FP32) once, coalesced; the map x (IQU interleaved, 24 B/pixel)
+// is gathered through the caches.  P^T accumulates each tile's samples into
+// LDS bins over the tile's compact-index window (FP64 LDS atomics), then adds
+// each touched bin to the global vector with one FP64 atomic per component.
+#include "mm_internal.h"
+#include "sincos2.h"
+
+namespace mm {
+namespace {
+
+constexpr int kOpThreads = 256;
+constexpr int kBinSlots = 2048;  // LDS bins per tile: 3 * 2048 doubles = 48 KiB
+
+// y = x[3k] + c x[3k+1] + s x[3k+2] in arithmetic C
+template <class C>
+__device__ __forceinline__ C project(const double* __restrict__ x, int32_t k, C c, C s) {
+  const double* xk = x + 3 * (int64_t)k;
+  return C(xk[0]) + c * C(xk[1]) + s * C(xk[2]);
+}
+
+template <class S, class C>
+__global__ __launch_bounds__(kOpThreads) void k_apply_P(const int32_t* __restrict__ sample_k,
+                                                        const S* __restrict__ psi, const double* __restrict__ x,
+                                                        S* __restrict__ tod, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const int32_t k = sample_k[t];
+    C y = C(0);
+    if (k >= 0) {
+      C c, s;
+      sincos2<C>(psi[t], &c, &s);
+      y = project<C>(x, k, c, s);
+    }
+    tod[t] = S(y);
+  }
+}
+
+// Flush the tile's LDS bins into q (one atomic per nonzero component).
+__device__ __forceinline__ void flush_bins(const double* __restrict__ bins, int nb, int32_t kmin,
+                                           double* __restrict__ q) {
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    const double v0 = bins[i], v1 = bins[kBinSlots + i], v2 = bins[2 * kBinSlots + i];
+    double* qk = q + 3 * (int64_t)(kmin + i);
+    if (v0 != 0.0) atomicAdd(qk + 0, v0);
+    if (v1 != 0.0) atomicAdd(qk + 1, v1);
+    if (v2 != 0.0) atomicAdd(qk + 2, v2);
+  }
+}
+
+__device__ __forceinline__ void bin_add(double* __restrict__ bins, int nb, int32_t kmin, int32_t k, double z,
+                                        double zc, double zs, double* __restrict__ q) {
+  const int32_t rel = k - kmin;
+  if (rel < nb) {
+    atomicAdd(&bins[rel], z);
+    atomicAdd(&bins[kBinSlots + rel], zc);
+    atomicAdd(&bins[2 * kBinSlots + rel], zs);
+  } else {
+    double* qk = q + 3 * (int64_t)k;
+    atomicAdd(qk + 0, z);
+    atomicAdd(qk + 1, zc);
+    atomicAdd(qk + 2, zs);
+  }
+}
+
+__device__ __forceinline__ int zero_bins(double* bins, const PtTile& tl) {
+  const int span = tl.kmax - tl.kmin + 1;
+  const int nb = span < 0 ? 0 : (span < kBinSlots ? span : kBinSlots);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    bins[i] = 0.0;
+    bins[kBinSlots + i] = 0.0;
+    bins[2 * kBinSlots + i] = 0.0;
+  }
+  __syncthreads();
+  return nb;
+}
+
+// q += P^T (w_det * tod)   (w = 1 for plain P^T)
+template <class S, class C, bool kWeighted>
+__global__ __launch_bounds__(kOpThreads) void k_bin_tod(const PtTile* __restrict__ tiles,
+                                                        const int32_t* __restrict__ sample_k,
+                                                        const S* __restrict__ psi, const S* __restrict__ tod,
+                                                        const double* __restrict__ det_w, double* __restrict__ q) {
+  __shared__ double bins[3 * kBinSlots];
+  const PtTile tl = tiles[blockIdx.x];
+  if (tl.kmax < tl.kmin) return;
+  const int nb = zero_bins(bins, tl);
+  const C w = kWeighted ? C(det_w[tl.det]) : C(1);
+  for (int i = threadIdx.x; i < tl.len; i += blockDim.x) {
+    const int64_t t = tl.start + i;
+    const int32_t k = sample_k[t];
+    if (k < 0) continue;
+    C c, s;
+    sincos2<C>(psi[t], &c, &s);
+    const C z = w * C(tod[t]);
+    bin_add(bins, nb, tl.kmin, k, double(z), double(z * c), double(z * s), q);
+  }
+  __syncthreads();
+  flush_bins(bins, nb, tl.kmin, q);
+}
+
+// q += P^T diag(w) P x: the timeline value never leaves registers.
+template <class S, class C>
+__global__ __launch_bounds__(kOpThreads) void k_fused_white(const PtTile* __restrict__ tiles,
+                                                            const int32_t* __restrict__ sample_k,
+                                                            const S* __restrict__ psi,
+                                                            const double* __restrict__ det_w,
+                                                            const double* __restrict__ x, double* __restrict__ q,
+                                                            const int32_t* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  __shared__ double bins[3 * kBinSlots];
+  const PtTile tl = tiles[blockIdx.x];
+  if (tl.kmax < tl.kmin) return;
+  const int nb = zero_bins(bins, tl);
+  const C w = C(det_w[tl.det]);
+  for (int i = threadIdx.x; i < tl.len; i += blockDim.x) {
+    const int64_t t = tl.start + i;
+    const int32_t k = sample_k[t];
+    if (k < 0) continue;
+    C c, s;
+    sincos2<C>(psi[t], &c, &s);
+    const C z = w * project<C>(x, k, c, s);
+    bin_add(bins, nb, tl.kmin, k, double(z), double(z * c), double(z * s), q);
+  }
+  __syncthreads();
+  flush_bins(bins, nb, tl.kmin, q);
+}
+
+template <class S, class C>
+__global__ __launch_bounds__(kOpThreads) void k_ninv_white(const PtTile* __restrict__ tiles,
+                                                           const double* __restrict__ det_w,
+                                                           const S* __restrict__ in, S* __restrict__ out) {
+  const PtTile tl = tiles[blockIdx.x];
+  const C w = C(det_w[tl.det]);
+  for (int i = threadIdx.x; i < tl.len; i += blockDim.x) {
+    const int64_t t = tl.start + i;
+    out[t] = S(w * C(in[t]));
+  }
+}
+
+__global__ void k_apply_M(const double* __restrict__ minv, const double* __restrict__ r, double* __restrict__ z,
+                          int32_t n_kept) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_kept) return;
+  const double* m = minv + 6 * k;
+  const double r0 = r[3 * k], r1 = r[3 * k + 1], r2 = r[3 * k + 2];
+  z[3 * k + 0] = m[0] * r0 + m[1] * r1 + m[2] * r2;
+  z[3 * k + 1] = m[1] * r0 + m[3] * r1 + m[4] * r2;
+  z[3 * k + 2] = m[2] * r0 + m[4] * r1 + m[5] * r2;
+}
+
+__global__ void k_expand(const int32_t* __restrict__ compact, const double* __restrict__ x,
+                         double* __restrict__ full, int32_t n_pix) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pix) return;
+  const int32_t k = compact[p];
+  full[3 * p + 0] = k >= 0 ? x[3 * (int64_t)k + 0] : 0.0;
+  full[3 * p + 1] = k >= 0 ? x[3 * (int64_t)k + 1] : 0.0;
+  full[3 * p + 2] = k >= 0 ? x[3 * (int64_t)k + 2] : 0.0;
+}
+
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+inline int grid_for(int64_t n, int threads) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g > 65536) g = 65536;
+  return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+int launch_apply_P(const mm_pointing_s* pt, const double* x, void* tod, int arith, hipStream_t s) {
+  const int64_t n = pt->n_samples;
+  if (n == 0) return MM_OK;
+  const dim3 g(grid_for(n, kOpThreads)), b(kOpThreads);
+  if (pt->dtype == MM_F64) {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_apply_P<double, double>), g, b, 0, s, pt->sample_k, (const double*)pt->psi, x,
+                         (double*)tod, n);
+    else
+      hipLaunchKernelGGL((k_apply_P<double, float>), g, b, 0, s, pt->sample_k, (const double*)pt->psi, x,
+                         (double*)tod, n);
+  } else {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_apply_P<float, double>), g, b, 0, s, pt->sample_k, (const float*)pt->psi, x,
+                         (float*)tod, n);
+    else
+      hipLaunchKernelGGL((k_apply_P<float, float>), g, b, 0, s, pt->sample_k, (const float*)pt->psi, x,
+                         (float*)tod, n);
+  }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+template <bool kW>
+static int launch_bin(const mm_pointing_s* pt, const double* det_w, const void* tod, double* q, int arith,
+                      hipStream_t s) {
+  if (pt->n_tiles == 0) return MM_OK;
+  const dim3 g(pt->n_tiles), b(kOpThreads);
+  if (pt->dtype == MM_F64) {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_bin_tod<double, double, kW>), g, b, 0, s, pt->tiles, pt->sample_k,
+                         (const double*)pt->psi, (const double*)tod, det_w, q);
+    else
+      hipLaunchKernelGGL((k_bin_tod<double, float, kW>), g, b, 0, s, pt->tiles, pt->sample_k,
+                         (const double*)pt->psi, (const double*)tod, det_w, q);
+  } else {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_bin_tod<float, double, kW>), g, b, 0, s, pt->tiles, pt->sample_k,
+                         (const float*)pt->psi, (const float*)tod, det_w, q);
+    else
+      hipLaunchKernelGGL((k_bin_tod<float, float, kW>), g, b, 0, s, pt->tiles, pt->sample_k,
+                         (const float*)pt->psi, (const float*)tod, det_w, q);
+  }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_apply_PT(const mm_pointing_s* pt, const void* tod, double* q, int arith, hipStream_t s) {
+  return launch_bin<false>(pt, nullptr, tod, q, arith, s);
+}
+
+int launch_rhs_white(const mm_pointing_s* pt, const double* det_w, const void* tod, double* q, int arith,
+                     hipStream_t s) {
+  return launch_bin<true>(pt, det_w, tod, q, arith, s);
+}
+
+int launch_fused_white(const mm_pointing_s* pt, const double* det_w, const double* x, double* q, int arith,
+                       const int32_t* done, hipStream_t s) {
+  if (pt->n_tiles == 0) return MM_OK;
+  const dim3 g(pt->n_tiles), b(kOpThreads);
+  if (pt->dtype == MM_F64) {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_fused_white<double, double>), g, b, 0, s, pt->tiles, pt->sample_k,
+                         (const double*)pt->psi, det_w, x, q, done);
+    else
+      hipLaunchKernelGGL((k_fused_white<double, float>), g, b, 0, s, pt->tiles, pt->sample_k,
+                         (const double*)pt->psi, det_w, x, q, done);
+  } else {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_fused_white<float, double>), g, b, 0, s, pt->tiles, pt->sample_k,
+                         (const float*)pt->psi, det_w, x, q, done);
+    else
+      hipLaunchKernelGGL((k_fused_white<float, float>), g, b, 0, s, pt->tiles, pt->sample_k,
+                         (const float*)pt->psi, det_w, x, q, done);
+  }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_ninv_white(const mm_pointing_s* pt, const double* det_w, const void* in, void* out, int arith,
+                      hipStream_t s) {
+  if (pt->n_tiles == 0) return MM_OK;
+  const dim3 g(pt->n_tiles), b(kOpThreads);
+  if (pt->dtype == MM_F64) {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_ninv_white<double, double>), g, b, 0, s, pt->tiles, det_w, (const double*)in,
+                         (double*)out);
+    else
+      hipLaunchKernelGGL((k_ninv_white<double, float>), g, b, 0, s, pt->tiles, det_w, (const double*)in,
+                         (double*)out);
+  } else {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_ninv_white<float, double>), g, b, 0, s, pt->tiles, det_w, (const float*)in,
+                         (float*)out);
+    else
+      hipLaunchKernelGGL((k_ninv_white<float, float>), g, b, 0, s, pt->tiles, det_w, (const float*)in,
+                         (float*)out);
+  }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_apply_M(const mm_pointing_s* pt, const double* r, double* z, hipStream_t s) {
+  if (pt->n_kept == 0) return MM_OK;
+  hipLaunchKernelGGL(k_apply_M, dim3((pt->n_kept + 255) / 256), dim3(256), 0, s, pt->minv, r, z, pt->n_kept);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_expand(const mm_pointing_s* pt, const double* x, double* full, hipStream_t s) {
+  if (pt->n_pix == 0) return MM_OK;
+  hipLaunchKernelGGL(k_expand, dim3((pt->n_pix + 255) / 256), dim3(256), 0, s, pt->compact, x, full, pt->n_pix);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n == 0) return MM_OK;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+}  // namespace mm

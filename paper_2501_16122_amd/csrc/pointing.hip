@@ -1,0 +1,337 @@
+// Pointing build: hits, the 3x3 blocks of P^T diag(N)^-1 P (eq. (7)), their
+// 2-norm conditioning, the mask, the ascending compaction of kept pixels and
+// the inverse blocks of the preconditioner; then the per-sample compact index
+// and each tile's compact-index window used by the hot kernels.
+#include <climits>
+
+#pragma clang fp contract(off)
+
+#include "mm_internal.h"
+#include "sincos2.h"
+
+namespace mm {
+namespace {
+
+constexpr int kBuildThreads = 256;
+constexpr int kBuildBins = 1024;  // LDS pixel bins per tile: 1024 * (4 + 6*8) B = 52 KiB
+
+
+template <class T>
+__device__ T block_reduce(T v, T* sh, bool is_min) {
+  // 64-wide wavefronts: reduce inside the wave, then across waves in LDS.
+  for (int off = 32; off > 0; off >>= 1) {
+    T o = __shfl_down(v, off, 64);
+    v = is_min ? (o < v ? o : v) : (o > v ? o : v);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T r = sh[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = is_min ? (sh[i] < r ? sh[i] : r) : (sh[i] > r ? sh[i] : r);
+    sh[0] = r;
+  }
+  __syncthreads();
+  T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// K1: per tile, bin hits and w * (1, c, s, cc, cs, ss) of every sample into
+// LDS slots over the tile's pixel range, then add the slots to the global
+// sums with one atomic per touched pixel; samples beyond the LDS window go
+// straight to global atomics.  An out-of-range pixel sets flags[0].
+template <class S>
+__global__ __launch_bounds__(kBuildThreads) void k_pointing_hist(const PtTile* __restrict__ tiles,
+                                                                 const int32_t* __restrict__ pix,
+                                                                 const S* __restrict__ psi,
+                                                                 const double* __restrict__ det_w, int32_t n_pix,
+                                                                 int32_t* __restrict__ hits,
+                                                                 double* __restrict__ blocks,
+                                                                 int32_t* __restrict__ flags) {
+  __shared__ int32_t s_hits[kBuildBins];
+  __shared__ double s_acc[6 * kBuildBins];
+  __shared__ int32_t s_red[16];
+  const PtTile tl = tiles[blockIdx.x];
+  int32_t lo = INT_MAX, hi = INT_MIN;
+  for (int i = threadIdx.x; i < tl.len; i += blockDim.x) {
+    int32_t p = pix[tl.start + i];
+    lo = p < lo ? p : lo;
+    hi = p > hi ? p : hi;
+  }
+  lo = block_reduce<int32_t>(lo, s_red, true);
+  hi = block_reduce<int32_t>(hi, s_red, false);
+  if (lo < 0 || hi >= n_pix) {
+    if (threadIdx.x == 0) atomicOr(&flags[0], 1);
+  }
+  const int32_t base = lo < 0 ? 0 : lo;
+  for (int i = threadIdx.x; i < kBuildBins; i += blockDim.x) {
+    s_hits[i] = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s_acc[j * kBuildBins + i] = 0.0;
+  }
+  __syncthreads();
+  const double w = det_w[tl.det];
+  for (int i = threadIdx.x; i < tl.len; i += blockDim.x) {
+    const int64_t t = tl.start + i;
+    const int32_t p = pix[t];
+    if (p < 0 || p >= n_pix) continue;
+    double c, s;
+    sincos2<double>(psi[t], &c, &s);
+    const double v[6] = {w, w * c, w * s, w * c * c, w * c * s, w * s * s};
+    const int32_t rel = p - base;
+    if (rel < kBuildBins) {
+      atomicAdd(&s_hits[rel], 1);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) atomicAdd(&s_acc[j * kBuildBins + rel], v[j]);
+    } else {
+      atomicAdd(&hits[p], 1);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) atomicAdd(&blocks[6 * (int64_t)p + j], v[j]);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBuildBins; i += blockDim.x) {
+    const int32_t h = s_hits[i];
+    if (h == 0) continue;
+    const int64_t p = base + i;
+    atomicAdd(&hits[p], h);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) atomicAdd(&blocks[6 * p + j], s_acc[j * kBuildBins + i]);
+  }
+}
+
+// Eigenvalues of a symmetric 3x3 matrix by cyclic Jacobi rotations
+// (Rutishauser's stable form); the diagonal converges to the eigenvalues.
+__device__ void sym3_eigvals(const double b[6], double ev[3]) {
+  double a00 = b[0], a01 = b[1], a02 = b[2], a11 = b[3], a12 = b[4], a22 = b[5];
+  for (int sweep = 0; sweep < 32; ++sweep) {
+    const double off = fabs(a01) + fabs(a02) + fabs(a12);
+    const double diag = fabs(a00) + fabs(a11) + fabs(a22);
+    if (off <= 1e-300 || off <= 1e-18 * diag) break;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      // rotate in plane (p, q) = (0,1), (0,2), (1,2)
+      double app, aqq, apq;
+      if (r == 0) { app = a00; aqq = a11; apq = a01; }
+      else if (r == 1) { app = a00; aqq = a22; apq = a02; }
+      else { app = a11; aqq = a22; apq = a12; }
+      if (apq == 0.0) continue;
+      const double theta = (aqq - app) / (2.0 * apq);
+      const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      const double napp = app - t * apq, naqq = aqq + t * apq;
+      if (r == 0) {
+        const double x = a02, y = a12;  // entries (0,2), (1,2)
+        a02 = c * x - s * y;
+        a12 = s * x + c * y;
+        a00 = napp; a11 = naqq; a01 = 0.0;
+      } else if (r == 1) {
+        const double x = a01, y = a12;  // (0,1), (2,1)
+        a01 = c * x - s * y;
+        a12 = s * x + c * y;
+        a00 = napp; a22 = naqq; a02 = 0.0;
+      } else {
+        const double x = a01, y = a02;  // (1,0), (2,0)
+        a01 = c * x - s * y;
+        a02 = s * x + c * y;
+        a11 = napp; a22 = naqq; a12 = 0.0;
+      }
+    }
+  }
+  ev[0] = a00; ev[1] = a11; ev[2] = a22;
+}
+
+// K2a: per pixel, the keep decision (hits >= min_hits and cond <= cond_max)
+// and the per-block count of kept pixels.
+constexpr int kScanBlock = 1024;  // pixels per scan block (4 per thread)
+
+__global__ __launch_bounds__(256) void k_pixel_keep(const int32_t* __restrict__ hits,
+                                                    const double* __restrict__ blocks, int32_t n_pix,
+                                                    int32_t min_hits, double cond_max,
+                                                    uint8_t* __restrict__ mask, int32_t* __restrict__ block_counts) {
+  __shared__ int32_t s_cnt[4];
+  int32_t cnt = 0;
+  for (int j = 0; j < 4; ++j) {
+    const int64_t p = (int64_t)blockIdx.x * kScanBlock + j * 256 + threadIdx.x;
+    if (p >= n_pix) continue;
+    bool keep = false;
+    if (hits[p] >= min_hits) {
+      double b[6], ev[3];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) b[i] = blocks[6 * p + i];
+      sym3_eigvals(b, ev);
+      double lo = fmin(ev[0], fmin(ev[1], ev[2]));
+      double hi = fmax(ev[0], fmax(ev[1], ev[2]));
+      const double cond = lo > 0.0 ? hi / lo : INFINITY;
+      keep = cond <= cond_max;  // NaN -> masked
+    }
+    mask[p] = keep ? 0 : 1;
+    cnt += keep ? 1 : 0;
+  }
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
+  if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) block_counts[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+}
+
+// K2b: exclusive scan of the block counts (one workgroup; sequential carry
+// over strides of 1024) and the total number of kept pixels.
+__global__ __launch_bounds__(1024) void k_scan_counts(int32_t* __restrict__ counts, int32_t n,
+                                                      int32_t* __restrict__ total) {
+  __shared__ int32_t sh[1024];
+  int32_t carry = 0;
+  for (int base = 0; base < n; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int32_t v = i < n ? counts[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int32_t o = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += o;
+      __syncthreads();
+    }
+    if (i < n) counts[i] = carry + sh[threadIdx.x] - v;
+    const int32_t blk_total = sh[1023];
+    __syncthreads();
+    carry += blk_total;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+// K2c: compact index of every pixel (ascending), the kept list and the
+// closed-form inverse (adjugate / determinant) of each kept block.
+__global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ mask,
+                                                 const int32_t* __restrict__ block_offsets,
+                                                 const double* __restrict__ blocks, int32_t n_pix,
+                                                 int32_t* __restrict__ compact, int32_t* __restrict__ kept,
+                                                 double* __restrict__ minv) {
+  __shared__ int32_t sh[kScanBlock];
+  for (int j = 0; j < 4; ++j) {
+    const int64_t p = (int64_t)blockIdx.x * kScanBlock + j * 256 + threadIdx.x;
+    sh[j * 256 + threadIdx.x] = (p < n_pix && mask[p] == 0) ? 1 : 0;
+  }
+  __syncthreads();
+  // inclusive scan over 1024 flags (Hillis-Steele, 4 per thread)
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    int32_t o[4];
+    for (int j = 0; j < 4; ++j) {
+      const int i = j * 256 + threadIdx.x;
+      o[j] = i >= off ? sh[i - off] : 0;
+    }
+    __syncthreads();
+    for (int j = 0; j < 4; ++j) sh[j * 256 + threadIdx.x] += o[j];
+    __syncthreads();
+  }
+  const int32_t boff = block_offsets[blockIdx.x];
+  for (int j = 0; j < 4; ++j) {
+    const int i = j * 256 + threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * kScanBlock + i;
+    if (p >= n_pix) continue;
+    if (mask[p]) {
+      compact[p] = -1;
+      continue;
+    }
+    const int32_t k = boff + sh[i] - 1;
+    compact[p] = k;
+    kept[k] = (int32_t)p;
+    const double a = blocks[6 * p + 0], b = blocks[6 * p + 1], c = blocks[6 * p + 2];
+    const double d = blocks[6 * p + 3], e = blocks[6 * p + 4], f = blocks[6 * p + 5];
+    // [[a b c] [b d e] [c e f]]
+    const double A = d * f - e * e, B = c * e - b * f, C = b * e - c * d;
+    const double det = a * A + b * B + c * C;
+    const double inv = 1.0 / det;
+    minv[6 * (int64_t)k + 0] = A * inv;
+    minv[6 * (int64_t)k + 1] = B * inv;
+    minv[6 * (int64_t)k + 2] = C * inv;
+    minv[6 * (int64_t)k + 3] = (a * f - c * c) * inv;
+    minv[6 * (int64_t)k + 4] = (b * c - a * e) * inv;
+    minv[6 * (int64_t)k + 5] = (a * d - b * b) * inv;
+  }
+}
+
+// Per-sample compact index and, per tile, the window [kmin, kmax] of the
+// compact indices of its kept samples.
+__global__ __launch_bounds__(256) void k_sample_index(PtTile* __restrict__ tiles, const int32_t* __restrict__ pix,
+                                                      const int32_t* __restrict__ compact, int32_t n_pix,
+                                                      int32_t* __restrict__ sample_k) {
+  __shared__ int32_t s_red[16];
+  PtTile tl = tiles[blockIdx.x];
+  int32_t lo = INT_MAX, hi = -1;
+  for (int i = threadIdx.x; i < tl.len; i += blockDim.x) {
+    const int64_t t = tl.start + i;
+    const int32_t p = pix[t];
+    const int32_t k = (p >= 0 && p < n_pix) ? compact[p] : -1;
+    sample_k[t] = k;
+    if (k >= 0) {
+      lo = k < lo ? k : lo;
+      hi = k > hi ? k : hi;
+    }
+  }
+  lo = block_reduce<int32_t>(lo, s_red, true);
+  hi = block_reduce<int32_t>(hi, s_red, false);
+  if (threadIdx.x == 0) {
+    tiles[blockIdx.x].kmin = lo;
+    tiles[blockIdx.x].kmax = hi;
+  }
+}
+
+__global__ void k_export_minv(const double* __restrict__ minv6, int32_t n_kept, double* __restrict__ out9) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_kept) return;
+  const double* m = minv6 + 6 * k;
+  double* o = out9 + 9 * k;
+  o[0] = m[0]; o[1] = m[1]; o[2] = m[2];
+  o[3] = m[1]; o[4] = m[3]; o[5] = m[4];
+  o[6] = m[2]; o[7] = m[4]; o[8] = m[5];
+}
+
+}  // namespace
+
+int launch_pointing_build(mm_pointing_s* pt, int32_t min_hits, double cond_max, hipStream_t s) {
+  const int64_t nb_scan = (pt->n_pix + kScanBlock - 1) / kScanBlock;
+  MM_HIP(hipMemsetAsync(pt->hits, 0, sizeof(int32_t) * pt->n_pix, s));
+  MM_HIP(hipMemsetAsync(pt->blocks, 0, sizeof(double) * 6 * (size_t)pt->n_pix, s));
+  MM_HIP(hipMemsetAsync(pt->flags, 0, sizeof(int32_t) * 4, s));
+  if (pt->n_tiles > 0) {
+    if (pt->dtype == MM_F64)
+      hipLaunchKernelGGL(k_pointing_hist<double>, dim3(pt->n_tiles), dim3(kBuildThreads), 0, s, pt->tiles, pt->pix,
+                         static_cast<const double*>(pt->psi), pt->det_w, pt->n_pix, pt->hits, pt->blocks, pt->flags);
+    else
+      hipLaunchKernelGGL(k_pointing_hist<float>, dim3(pt->n_tiles), dim3(kBuildThreads), 0, s, pt->tiles, pt->pix,
+                         static_cast<const float*>(pt->psi), pt->det_w, pt->n_pix, pt->hits, pt->blocks, pt->flags);
+    MM_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_pixel_keep, dim3(nb_scan), dim3(256), 0, s, pt->hits, pt->blocks, pt->n_pix, min_hits, cond_max,
+                     pt->mask, pt->scan_tmp);
+  MM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, pt->scan_tmp, (int32_t)nb_scan, &pt->flags[1]);
+  MM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_compact, dim3(nb_scan), dim3(256), 0, s, pt->mask, pt->scan_tmp, pt->blocks, pt->n_pix,
+                     pt->compact, pt->kept, pt->minv);
+  MM_HIP(hipGetLastError());
+  if (pt->n_tiles > 0) {
+    hipLaunchKernelGGL(k_sample_index, dim3(pt->n_tiles), dim3(256), 0, s, pt->tiles, pt->pix, pt->compact,
+                       pt->n_pix, pt->sample_k);
+    MM_HIP(hipGetLastError());
+  }
+  return MM_OK;
+}
+
+int launch_export(const mm_pointing_s* pt, int32_t* hits, uint8_t* mask, int32_t* compact, int32_t* kept,
+                  double* minv, hipStream_t s) {
+  if (hits) MM_HIP(hipMemcpyAsync(hits, pt->hits, sizeof(int32_t) * pt->n_pix, hipMemcpyDeviceToDevice, s));
+  if (mask) MM_HIP(hipMemcpyAsync(mask, pt->mask, pt->n_pix, hipMemcpyDeviceToDevice, s));
+  if (compact) MM_HIP(hipMemcpyAsync(compact, pt->compact, sizeof(int32_t) * pt->n_pix, hipMemcpyDeviceToDevice, s));
+  if (kept && pt->n_kept)
+    MM_HIP(hipMemcpyAsync(kept, pt->kept, sizeof(int32_t) * pt->n_kept, hipMemcpyDeviceToDevice, s));
+  if (minv && pt->n_kept) {
+    hipLaunchKernelGGL(k_export_minv, dim3((pt->n_kept + 255) / 256), dim3(256), 0, s, pt->minv, pt->n_kept, minv);
+    MM_HIP(hipGetLastError());
+  }
+  return MM_OK;
+}
+
+}  // namespace mm

@@ -1,0 +1,118 @@
+// (cos 2psi, sin 2psi) of eq. (2) from a stored angle psi (FP64 or FP32) in a
+// chosen arithmetic C.
+//
+// Argument reduction x = 2 psi = j pi/2 + r, |r| <= pi/4, in FP64 with pi/2
+// split into three parts (Cody & Waite, "Software Manual for the Elementary
+// Functions", 1980): the first two carry 33 significant bits, so j*A and j*B
+// are exact for |j| < 2^20 and the reduction error stays near one ulp of r
+// for |x| < kReduceMax.  sin r and cos r come from their Taylor series in
+// Horner form (truncation below 1e-19 relative on |r| <= pi/4 in FP64, below
+// 2e-9 in FP32), and the quadrant j mod 4 permutes and negates them.  Larger
+// or non-finite arguments go to the device library in a separate,
+// non-inlined function, which keeps the hot loops' register use small.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mm {
+
+namespace sc {
+constexpr double kPio2A = 1.5707963267341256;       // 0x1.921fb544p+0
+constexpr double kPio2B = 6.077100506303966e-11;    // 0x1.0b4611a6p-34
+constexpr double kPio2C = 2.0222662487959506e-21;   // 0x1.3198a2e037073p-69
+constexpr double kTwoOverPi = 0.63661977236758134308;
+constexpr double kReduceMax = 1.0e5;
+
+__device__ __noinline__ void sincos_fallback(double x, double* s, double* c) { sincos(x, s, c); }
+
+// x = j pi/2 + r; returns r and j mod 4
+__device__ __forceinline__ double reduce(double x, int* q) {
+  const double j = rint(x * kTwoOverPi);
+  double r = fma(-j, kPio2A, x);
+  r = fma(-j, kPio2B, r);
+  r = fma(-j, kPio2C, r);
+  *q = (int)(long long)j & 3;
+  return r;
+}
+
+template <class C>
+__device__ __forceinline__ void quadrant(int q, C sr, C cr, C* s, C* c) {
+  const C s0 = (q & 1) ? cr : sr;
+  const C c0 = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -s0 : s0;
+  *c = ((q + 1) & 2) ? -c0 : c0;
+}
+
+__device__ __forceinline__ void poly_f64(double r, double* sr, double* cr) {
+  const double u = r * r;
+  double ps = 2.8114572543455206e-15;        // 1/17!
+  ps = fma(ps, u, -7.647163731819816e-13);   // -1/15!
+  ps = fma(ps, u, 1.6059043836821613e-10);   // 1/13!
+  ps = fma(ps, u, -2.505210838544172e-08);   // -1/11!
+  ps = fma(ps, u, 2.7557319223985893e-06);   // 1/9!
+  ps = fma(ps, u, -0.0001984126984126984);   // -1/7!
+  ps = fma(ps, u, 0.008333333333333333);     // 1/5!
+  ps = fma(ps, u, -0.16666666666666666);     // -1/3!
+  *sr = fma(r * u, ps, r);
+  double pc = -1.5619206968586225e-16;       // -1/18!
+  pc = fma(pc, u, 4.779477332387385e-14);    // 1/16!
+  pc = fma(pc, u, -1.1470745597729725e-11);  // -1/14!
+  pc = fma(pc, u, 2.08767569878681e-09);     // 1/12!
+  pc = fma(pc, u, -2.755731922398589e-07);   // -1/10!
+  pc = fma(pc, u, 2.48015873015873e-05);     // 1/8!
+  pc = fma(pc, u, -0.001388888888888889);    // -1/6!
+  pc = fma(pc, u, 0.041666666666666664);     // 1/4!
+  pc = fma(pc, u, -0.5);                     // -1/2!
+  *cr = fma(u, pc, 1.0);
+}
+
+__device__ __forceinline__ void poly_f32(float r, float* sr, float* cr) {
+  const float u = r * r;
+  float ps = 2.7557319e-06f;          // 1/9!
+  ps = fmaf(ps, u, -1.9841270e-04f);  // -1/7!
+  ps = fmaf(ps, u, 8.3333333e-03f);   // 1/5!
+  ps = fmaf(ps, u, -1.6666667e-01f);  // -1/3!
+  *sr = fmaf(r * u, ps, r);
+  float pc = -2.7557319e-07f;         // -1/10!
+  pc = fmaf(pc, u, 2.4801587e-05f);   // 1/8!
+  pc = fmaf(pc, u, -1.3888889e-03f);  // -1/6!
+  pc = fmaf(pc, u, 4.1666667e-02f);   // 1/4!
+  pc = fmaf(pc, u, -0.5f);            // -1/2!
+  *cr = fmaf(u, pc, 1.0f);
+}
+}  // namespace sc
+
+// sin and cos of an FP64 argument
+__device__ __forceinline__ void sincos_x(double x, double* s, double* c) {
+  if (!(fabs(x) < sc::kReduceMax)) {
+    sc::sincos_fallback(x, s, c);
+    return;
+  }
+  int q;
+  const double r = sc::reduce(x, &q);
+  double sr, cr;
+  sc::poly_f64(r, &sr, &cr);
+  sc::quadrant<double>(q, sr, cr, s, c);
+}
+
+// sin and cos of an FP64 argument, evaluated to FP32 accuracy
+__device__ __forceinline__ void sincos_x(double x, float* s, float* c) {
+  if (!(fabs(x) < sc::kReduceMax)) {
+    double sd, cd;
+    sc::sincos_fallback(x, &sd, &cd);
+    *s = float(sd);
+    *c = float(cd);
+    return;
+  }
+  int q;
+  const float r = float(sc::reduce(x, &q));
+  float sr, cr;
+  sc::poly_f32(r, &sr, &cr);
+  sc::quadrant<float>(q, sr, cr, s, c);
+}
+
+template <class C, class S>
+__device__ __forceinline__ void sincos2(S psi, C* c, C* s) {
+  sincos_x(2.0 * double(psi), s, c);
+}
+
+}  // namespace mm
