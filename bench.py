@@ -1,0 +1,258 @@
+#!/usr/bin/env python
+"""Benchmark: GLS map-making PCG on one MI355X.
+
+One step = one complete map from device-resident inputs: build the pointing
+(hits, 3x3 blocks, masks, compaction, preconditioner), form b = P^T N^-1 d,
+run PCG to ||r||/||b|| <= 1e-10, and expand the map to the full grid.
+
+Workload: 512x512 grid (262144 pixels x IQU), 64 detectors x 2^22 samples
+(2^28 samples), 1/f noise, band-Toeplitz N^-1 with 4096 lags on stationary
+chunks of 2^20 samples, FP64.  Inputs are synthetic and seeded (the
+package's ``synth`` module); d = P m + n is formed on the device.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TOD samples/s per PCG iter + time-to-map @1e-10 (FP64 vs FP32-refined); p99"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# source files of the dominant kernel (the fused band-Toeplitz A); a stored
+# counter summary is used only while these are unchanged
+KERNEL_SOURCES = ["paper_2501_16122_amd/csrc/toeplitz.hip", "paper_2501_16122_amd/csrc/fft_lds.h",
+                  "paper_2501_16122_amd/csrc/sincos2.h"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_toeplitz_fused_f64_gls512.counters.json")
+
+
+def log(msg):
+    sys.stderr.write(f"[bench {time.strftime('%H:%M:%S')}] {msg}\n")
+    sys.stderr.flush()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def fft_flops_per_launch(w, n_fft=8192):
+    """Algorithmic flops of one fused P^T T P launch: per overlap-save tile
+    two complex N-point FFTs at 5 N log2 N, the bin-pair spectral multiply
+    (8 N), and per timeline sample of the tile window P (4) and, per valid
+    sample, P^T (6)."""
+    L = 2 * n_fft
+    V = L - 2 * (w.lam - 1)
+    tiles_per_chunk = -(-w.chunk // V)
+    n_chunks = w.n_samples // w.chunk
+    tiles = tiles_per_chunk * n_chunks
+    per_tile = 2 * 5 * n_fft * np.log2(n_fft) + 8 * n_fft + 4 * L
+    return tiles * per_tile + 6 * w.n_samples
+
+
+def stored_traffic():
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, pix, psi, d, n_det_sample):
+    """The FP64 oracle on the first n_det_sample detectors of the same
+    workload, single process: build + per-iteration time of A = P^T N^-1 P."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        return _cpu_baseline(w, pix, psi, d, n_det_sample)
+
+
+def _cpu_baseline(w, pix, psi, d, n_det_sample):
+    import oracle.mapmaking as oracle
+    from paper_2501_16122_amd import synth
+    ns = n_det_sample * w.n_samp
+    ws = w.replace(n_det=n_det_sample)
+    t0 = time.perf_counter()
+    opt = oracle.build_pointing(pix[:ns], psi[:ns], synth.det_offsets(ws), synth.det_weight(ws), w.n_pix)
+    t_build = time.perf_counter() - t0
+    nz = oracle.toeplitz_noise(synth.toeplitz_coeff(ws), synth.chunk_offsets(ws))
+    b = oracle.rhs(opt, nz, d[:ns])
+    reps = 3
+    x = b.copy()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        q = oracle.apply_A(opt, nz, x)
+        x = oracle.apply_M(opt, q)
+    t_iter = (time.perf_counter() - t0) / reps
+    return {"value": ns / t_iter, "unit": "TOD samples/s per PCG iteration", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_det_sample} of {w.n_det} detectors ({ns} samples) of the same workload; "
+                      f"{reps} applications of A = P^T N^-1 P (+ M), single process, 1 thread; "
+                      f"oracle build of that sample {t_build:.2f} s",
+            "ms_per_iter": 1e3 * t_iter, "host_cpu_count": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gls", choices=["gls", "shard", "binned"])
+    ap.add_argument("--fp32-steps", type=int, default=3, help="timed FP32-refined steps (0 = skip)")
+    ap.add_argument("--cpu-det", type=int, default=2, help="detectors in the oracle sample (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sample-sharded design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2501_16122_amd import binding as b
+    from paper_2501_16122_amd import synth
+
+    b.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    w = {"gls": synth.C2_GLS, "shard": synth.C2_SHARD, "binned": synth.C1_BINNED}[args.workload]
+    log(f"workload {w.name}: {w.n_samples} samples, {w.n_pix} pixels")
+
+    t0 = time.perf_counter()
+    pix, psi = synth.pointing(w)
+    noise = synth.noise(w)
+    m = synth.sky(w)
+    log(f"generated inputs in {time.perf_counter() - t0:.1f} s")
+    offs, wdet = synth.det_offsets(w), synth.det_weight(w)
+
+    t_pix = torch.from_numpy(pix).to(dev)
+    t_psi = torch.from_numpy(psi).to(dev)
+    t_noise = torch.from_numpy(noise).to(dev)
+    t_m = torch.from_numpy(m).to(dev)
+    if w.toeplitz:
+        coeff, chunks = synth.toeplitz_coeff(w), synth.chunk_offsets(w)
+        nz = b.Noise.toeplitz(coeff, chunks, dev)
+    else:
+        nz = b.Noise.white(wdet, dev)
+    # d = P m + n on the device (P over the kept pixels)
+    pt0 = b.Pointing(t_pix, t_psi, offs, wdet, w.n_pix, w.min_hits, w.cond_max)
+    kept = pt0.export()["kept"].long()
+    t_d = b.apply_P(pt0, t_m[kept].reshape(-1).contiguous())
+    t_d += t_noise
+    del t_noise
+    torch.cuda.synchronize()
+    log(f"inputs resident on the device; {pt0.n_kept} kept pixels")
+
+    def step(psi_t, d_t, mixed):
+        pt = b.Pointing(t_pix, psi_t, offs, wdet, w.n_pix, w.min_hits, w.cond_max)
+        if w.toeplitz:
+            pt.attach_weights()  # precomputed (cos 2psi, sin 2psi), part of the build
+        s = b.Solver(pt, nz, tol=1e-10, mixed=mixed, timing=1, check_every=8)
+        out = s.solve(d_t)
+        return out["info"]
+
+    for i in range(args.warmup):
+        info = step(t_psi, t_d, 0)
+        log(f"warmup {i}: iters {info['iters']} rel {info['rel_resid']:.2e}")
+    torch.cuda.synchronize()
+    infos, times = [], []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        infos.append(step(t_psi, t_d, 0))
+        times.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    iters = sum(i["iters"] for i in infos)
+    log(f"timed {args.steps} FP64 steps in {t_total:.3f} s, {iters} PCG iterations")
+
+    op_ms = sum(i["op_ms"] for i in infos)
+    op_n = sum(i["op_launches"] for i in infos)
+    kernel_ms = op_ms / max(op_n, 1)
+    # streamed per sample: int32 compact index + FP64 (cos 2psi, sin 2psi) for
+    # the band-Toeplitz operator; int32 index + FP64 psi for the white one
+    alg_bytes = (20.0 if w.toeplitz else 12.0) * w.n_samples
+    achieved_gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(),
+            "kernel": "k_toeplitz<double,double,gather,scatter> (fused P^T N^-1 P)" if w.toeplitz
+            else "k_fused_white<double,double>",
+            "kernel_ms_avg": round(kernel_ms, 4), "launches": op_n,
+            "algorithmic_bytes_per_launch": alg_bytes}
+    if w.toeplitz:
+        flops = fft_flops_per_launch(w)
+        tf = flops / (kernel_ms * 1e-3) / 1e12
+        roof["fp64_tflops"] = round(tf, 2)
+        roof["fp64_frac"] = round(tf / FP64_PEAK_TFLOPS, 4)
+        roof["algorithmic_flops_per_launch"] = flops
+
+    iter_p50 = float(np.median([i["iter_ms_p50"] for i in infos]))
+    iter_p99 = float(np.max([i["iter_ms_p99"] for i in infos]))
+    result = {
+        "metric": METRIC,
+        "value": round(w.n_samples * iters / t_total, 1),
+        "unit": "TOD samples/s per PCG iteration",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_total / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded scan, sky and 1/f noise)",
+        "config": {"workload": w.name, "grid": f"{w.width}x{w.height}", "n_det": w.n_det,
+                   "samples_per_det": w.n_samp, "n_samples": w.n_samples,
+                   "noise": (f"1/f, band-Toeplitz N^-1 lambda={w.lam}, chunks {w.chunk}" if w.toeplitz
+                             else "white"), "tol": 1e-10, "parallelism": "single GPU"},
+        "time_to_map_ms": {"p50": round(1e3 * float(np.median(times)), 3),
+                           "p99": round(1e3 * float(np.percentile(times, 99)), 3)},
+        "pcg_iters_per_solve": iters / args.steps,
+        "iter_ms": {"p50": round(iter_p50, 4), "p99": round(iter_p99, 4)},
+        "samples_per_s_per_iter_p50": round(w.n_samples / (iter_p50 * 1e-3), 1),
+        "final_true_rel_resid": max(i["true_rel_resid"] for i in infos),
+        "roofline": roof,
+    }
+
+    if args.fp32_steps > 0:
+        psi32 = t_psi.float()
+        d32 = t_d.float()
+        torch.cuda.synchronize()
+        step(psi32, d32, 1)
+        f_times, f_infos = [], []
+        torch.cuda.synchronize()
+        for i in range(args.fp32_steps):
+            ts = time.perf_counter()
+            f_infos.append(step(psi32, d32, 1))
+            f_times.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        ftm = float(np.median(f_times))
+        result["fp32_refined"] = {
+            "time_to_map_ms": {"p50": round(1e3 * ftm, 3), "p99": round(1e3 * float(np.percentile(f_times, 99)), 3)},
+            "inner_iters": f_infos[-1]["iters"], "outer_iters": f_infos[-1]["outer_iters"],
+            "final_true_rel_resid": max(i["true_rel_resid"] for i in f_infos),
+            "speedup_vs_fp64": round(float(np.median(times)) / ftm, 3),
+            "note": "psi and d rounded to FP32 once; inner PCG with FP32 timeline arithmetic, FP64 refinement"}
+        log(f"FP32-refined: {1e3 * ftm:.1f} ms per map")
+
+    if args.cpu_det > 0:
+        t0 = time.perf_counter()
+        d_host = t_d.cpu().numpy()
+        result["cpu_baseline"] = cpu_baseline(w, pix, psi, d_host, min(args.cpu_det, w.n_det))
+        log(f"cpu baseline in {time.perf_counter() - t0:.1f} s")
+
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

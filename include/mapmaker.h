@@ -91,7 +91,8 @@ int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, 
  *                     min_hits samples or its 3x3 block has 2-norm condition
  *                     number > cond_max (+inf when singular)
  * Kept pixels are numbered in ascending pixel order.  A pixel index outside
- * [0, n_pix) fails with MM_EINVAL and no handle. */
+ * [0, n_pix), or an angle that is not finite or has |2 psi| >= 4e8, fails
+ * with MM_EINVAL and no handle. */
 int mm_pointing_build(const int32_t* pix, const void* psi, int32_t dtype, int64_t n_samples,
                       const int64_t* det_offsets_host, int32_t n_det, const double* det_weight_host,
                       int32_t n_pix, int32_t min_hits, double cond_max,
@@ -107,6 +108,15 @@ int mm_pointing_info(mm_pointing_t pt, int32_t* n_kept, int64_t* n_samples, int3
  *   minv f64[9 * n_kept] (row-major 3x3 inverse blocks, eq. (7)). */
 int mm_pointing_export(mm_pointing_t pt, int32_t* hits, uint8_t* mask, int32_t* compact,
                        int32_t* kept, double* minv, void* stream);
+
+/* Precompute the pointing elements (cos 2psi_t, sin 2psi_t) of eq. (8) once
+ * (Sec. III-A) into caller memory and let the band-Toeplitz operators stream
+ * them instead of evaluating sin/cos from psi three times per sample:
+ *   weights   dtype[2 * n_samples] device, interleaved (cos, sin) per sample,
+ *             same dtype as psi; borrowed until detached or destroyed
+ * Stored weights serve arithmetic no finer than their dtype (FP32 weights are
+ * not used by FP64 arithmetic).  weights = NULL detaches.  Stream-ordered. */
+int mm_pointing_attach_weights(mm_pointing_t pt, void* weights, void* stream);
 
 /* Free the host-side handle; the caller frees its own arrays and workspace. */
 int mm_pointing_destroy(mm_pointing_t pt);
@@ -167,6 +177,8 @@ typedef struct {
   int32_t mixed;        /* 0: FP64 operator; 1: FP32 inner solves + FP64 refinement      */
   int32_t max_outer;    /* mixed: refinement steps cap; default 10                        */
   double inner_tol;     /* mixed: inner relative tolerance; default 1e-5                 */
+  int32_t timing;       /* 1: time each iteration and its A kernel with HIP events       */
+  int32_t reserved_;
 } mm_solve_opts;
 
 typedef struct {
@@ -176,6 +188,12 @@ typedef struct {
   int32_t breakdown;    /* 1 if PCG broke down                               */
   double rel_resid;     /* last recursive residual ||r|| / ||b||            */
   double true_rel_resid;/* ||b - A x|| / ||b|| recomputed in FP64 at exit    */
+  /* filled when opts.timing = 1 (iterations that did work only):           */
+  double op_ms;         /* summed duration of the A = P^T N^-1 P kernel      */
+  int32_t op_launches;  /* launches summed in op_ms                          */
+  int32_t reserved_;
+  double iter_ms_p50;   /* median duration of one PCG iteration              */
+  double iter_ms_p99;   /* 99th percentile of the same                       */
 } mm_solve_info;
 
 /* Fill opts with the defaults above. */

@@ -31,12 +31,14 @@ _psz = _c.POINTER(_c.c_size_t)
 
 class SolveOpts(_c.Structure):
     _fields_ = [("tol", _f64), ("max_iter", _i32), ("fixed_iter", _i32), ("check_every", _i32),
-                ("mixed", _i32), ("max_outer", _i32), ("inner_tol", _f64)]
+                ("mixed", _i32), ("max_outer", _i32), ("inner_tol", _f64), ("timing", _i32),
+                ("reserved_", _i32)]
 
 
 class SolveInfo(_c.Structure):
     _fields_ = [("iters", _i32), ("outer_iters", _i32), ("converged", _i32), ("breakdown", _i32),
-                ("rel_resid", _f64), ("true_rel_resid", _f64)]
+                ("rel_resid", _f64), ("true_rel_resid", _f64), ("op_ms", _f64), ("op_launches", _i32),
+                ("reserved_", _i32), ("iter_ms_p50", _f64), ("iter_ms_p99", _f64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -51,6 +53,7 @@ SIGNATURES = {
                                      _c.POINTER(_vp)]),
     "mm_pointing_info": (_c.c_int, [_vp, _pi32, _pi64, _pi32, _pi32, _pi32]),
     "mm_pointing_export": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mm_pointing_attach_weights": (_c.c_int, [_vp, _vp, _vp]),
     "mm_pointing_destroy": (_c.c_int, [_vp]),
     "mm_noise_white_workspace_size": (_c.c_int, [_i32, _psz]),
     "mm_noise_white": (_c.c_int, [_pf64, _i32, _vp, _sz, _vp, _c.POINTER(_vp)]),
@@ -191,6 +194,18 @@ class Pointing:
                                          _stream(stream)))
         return {"hits": hits, "mask": mask, "compact": compact, "kept": kept[:self.n_kept],
                 "minv": minv[:9 * self.n_kept].view(-1, 3, 3)}
+
+    def attach_weights(self, stream=None):
+        """Precompute (cos 2psi, sin 2psi) per sample into a device tensor the
+        handle keeps; the band-Toeplitz operators then stream it."""
+        torch = _torch()
+        self.weights = torch.empty(2 * max(1, self.n_samples), dtype=self.tod_dtype, device=self.device)
+        _check(load().mm_pointing_attach_weights(self.handle, _ptr(self.weights), _stream(stream)))
+        return self.weights
+
+    def detach_weights(self):
+        _check(load().mm_pointing_attach_weights(self.handle, None, None))
+        self.weights = None
 
     def close(self):
         if getattr(self, "handle", None):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <new>
+#include <vector>
 
 #include "mm_internal.h"
 
@@ -198,7 +199,8 @@ int mm_pointing_build(const int32_t* pix, const void* psi, int32_t dtype, int64_
   if ((e = hipMemcpyAsync(flags, pt->flags, sizeof(flags), hipMemcpyDeviceToHost, s)) != hipSuccess)
     return bail(hip_fail(e, "read build flags"));
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "build sync"));
-  if (flags[0]) return bail(fail(MM_EINVAL, "pixel index outside [0, n_pix)"));
+  if (flags[0] & 1) return bail(fail(MM_EINVAL, "pixel index outside [0, n_pix)"));
+  if (flags[0] & 2) return bail(fail(MM_EINVAL, "psi not finite or |2 psi| >= 4e8"));
   pt->n_kept = flags[1];
   *out = pt;
   return MM_OK;
@@ -219,6 +221,17 @@ int mm_pointing_export(mm_pointing_t pt, int32_t* hits, uint8_t* mask, int32_t* 
                        void* stream) {
   if (int rc = check_pointing(pt)) return rc;
   return launch_export(pt, hits, mask, compact, kept, minv, as_stream(stream));
+}
+
+int mm_pointing_attach_weights(mm_pointing_t pt, void* weights, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (weights == nullptr) {
+    pt->weights = nullptr;
+    return MM_OK;
+  }
+  if (int rc = launch_compute_weights(pt, weights, as_stream(stream))) return rc;
+  pt->weights = weights;
+  return MM_OK;
 }
 
 int mm_pointing_destroy(mm_pointing_t pt) {
@@ -390,6 +403,8 @@ int mm_solve_opts_default(mm_solve_opts* o) {
   o->mixed = 0;
   o->max_outer = 10;
   o->inner_tol = 1e-5;
+  o->timing = 0;
+  o->reserved_ = 0;
   return MM_OK;
 }
 
@@ -425,24 +440,68 @@ int32_t hist_len_for(const mm_solve_opts& o) {
   return std::max<int32_t>(1, n + 1);
 }
 
+// HIP-event timing of PCG iterations (opts.timing).
+struct IterTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // per slot: iteration start, A end; plus one closing event
+  std::vector<double> iter_ms;
+  double op_ms = 0.0;
+  int32_t op_launches = 0;
+  ~IterTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  int init(int32_t slots) {
+    ev.resize(2 * (size_t)slots + 1, nullptr);
+    for (auto& e : ev) MM_HIP(hipEventCreate(&e));
+    return MM_OK;
+  }
+};
+
 // Run one PCG on B.b (already in place) with operator arithmetic `arith`.
 int run_pcg(const mm_pointing_s* pt, const mm_noise_s* nz, PcgBufs& B, int arith, double tol, int32_t max_iter,
-            int32_t fixed_iter, int32_t check_every, PcgState* host_st, hipStream_t s) {
+            int32_t fixed_iter, int32_t check_every, PcgState* host_st, IterTimer* tm, hipStream_t s) {
   if (int rc = launch_pcg_init(pt, B, tol, max_iter, fixed_iter, s)) return rc;
   const int32_t cap = fixed_iter > 0 ? fixed_iter : max_iter;
   int32_t issued = 0;
+  int32_t last_chunk = 0;
   for (;;) {
     MM_HIP(hipMemcpyAsync(host_st, B.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     MM_HIP(hipStreamSynchronize(s));
+    if (tm && tm->on && last_chunk > 0) {
+      // iterations issued - last_chunk + i did work iff their index < host_st->iter
+      const int32_t first = issued - last_chunk;
+      for (int32_t i = 0; i < last_chunk; ++i) {
+        if (first + i >= host_st->iter) break;
+        float a = 0.f, it = 0.f;
+        MM_HIP(hipEventElapsedTime(&a, tm->ev[2 * i], tm->ev[2 * i + 1]));
+        MM_HIP(hipEventElapsedTime(&it, tm->ev[2 * i], tm->ev[2 * i + 2]));
+        tm->op_ms += a;
+        tm->op_launches += 1;
+        tm->iter_ms.push_back(it);
+      }
+    }
     if (host_st->done || issued >= cap) break;
     const int32_t chunk = std::min(check_every, cap - issued);
     for (int32_t i = 0; i < chunk; ++i) {
+      if (tm && tm->on) MM_HIP(hipEventRecord(tm->ev[2 * i], s));
       if (int rc = apply_A_impl(pt, nz, B.p, B.q, arith, &B.st->done, s)) return rc;
+      if (tm && tm->on) MM_HIP(hipEventRecord(tm->ev[2 * i + 1], s));
       if (int rc = launch_pcg_iteration_tail(pt, B, s)) return rc;
     }
+    if (tm && tm->on) MM_HIP(hipEventRecord(tm->ev[2 * chunk], s));
     issued += chunk;
+    last_chunk = chunk;
   }
   return MM_OK;
+}
+
+double percentile(std::vector<double> v, double p) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double pos = p * (double)(v.size() - 1);
+  const size_t i = (size_t)pos;
+  const double f = pos - (double)i;
+  return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
 }
 
 // ||b - A x|| / ||b|| in FP64 arithmetic; uses B.q as scratch.
@@ -492,6 +551,11 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
   PcgBufs& B = L.B;
   PcgState hs{};
   mm_solve_info inf{};
+  IterTimer tm;
+  if (o.timing) {
+    tm.on = true;
+    if (int rc = tm.init(o.check_every)) return rc;
+  }
   double true_rel = 0.0;
   const double* xfinal = B.x;
 
@@ -505,7 +569,8 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
 
   if (!o.mixed) {
     if (int rc = rhs_impl(pt, nz, tod, B.b, MM_F64, s)) return rc;
-    if (int rc = run_pcg(pt, nz, B, MM_F64, o.tol, o.max_iter, o.fixed_iter, o.check_every, &hs, s)) return rc;
+    if (int rc = run_pcg(pt, nz, B, MM_F64, o.tol, o.max_iter, o.fixed_iter, o.check_every, &hs, &tm, s))
+      return rc;
     inf.iters = hs.iter;
     inf.outer_iters = 1;
     inf.converged = hs.converged;
@@ -527,7 +592,8 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
     inf.converged = 0;
     for (int32_t outer = 1; outer <= o.max_outer; ++outer) {
       MM_HIP(hipMemcpyAsync(B.b, L.rt, sizeof(double) * 3 * (size_t)pt->n_kept, hipMemcpyDeviceToDevice, s));
-      if (int rc = run_pcg(pt, nz, B, MM_F32, o.inner_tol, o.max_iter, 0, o.check_every, &hs, s)) return rc;
+      if (int rc = run_pcg(pt, nz, B, MM_F32, o.inner_tol, o.max_iter, 0, o.check_every, &hs, &tm, s))
+        return rc;
       inf.iters += hs.iter;
       inf.outer_iters = outer;
       if (hs.breakdown) {
@@ -548,6 +614,12 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
     xfinal = L.xt;
   }
   inf.true_rel_resid = true_rel;
+  if (tm.on) {
+    inf.op_ms = tm.op_ms;
+    inf.op_launches = tm.op_launches;
+    inf.iter_ms_p50 = percentile(tm.iter_ms, 0.5);
+    inf.iter_ms_p99 = percentile(tm.iter_ms, 0.99);
+  }
   if (map_out)
     if (int rc = launch_expand(pt, xfinal, map_out, s)) return rc;
   if (x_out) MM_HIP(hipMemcpyAsync(x_out, xfinal, sizeof(double) * 3 * (size_t)pt->n_kept, hipMemcpyDeviceToDevice, s));

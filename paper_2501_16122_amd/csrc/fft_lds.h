@@ -65,6 +65,17 @@ __device__ __forceinline__ cpx<C> rot64(cpx<C> a, int idx) {
     if (qq == 2) return {-a.x, -a.y};  // * (-1)
     return {-a.y, a.x};                // * (+i)
   }
+  if (r == 8) {
+    // eighth turns: rotate by -+pi/4 with two multiplies, then by the
+    // remaining quarter turns ((-i)^q forward, i^q inverse)
+    const C h = C(0.70710678118654757);
+    const cpx<C> t = kFwd ? cpx<C>{(a.x + a.y) * h, (a.y - a.x) * h} : cpx<C>{(a.x - a.y) * h, (a.x + a.y) * h};
+    const int qt = kFwd ? (4 - q) & 3 : q;  // number of +i rotations
+    if (qt == 0) return t;
+    if (qt == 1) return {-t.y, t.x};
+    if (qt == 2) return {-t.x, -t.y};
+    return {t.y, -t.x};
+  }
   C c = C(kCos64[r]), s = C(kCos64[16 - r]);
   // rotate (c, s) by q quarter turns: angle 2 pi idx / 64
   C cc, ss;

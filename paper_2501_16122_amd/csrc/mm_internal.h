@@ -91,6 +91,8 @@ struct mm_pointing_s {
   int device = 0;
   const int32_t* pix = nullptr;
   const void* psi = nullptr;
+  // optional precomputed (cos 2psi, sin 2psi) per sample, dtype pairs
+  const void* weights = nullptr;
   std::vector<int64_t> det_offsets;
   std::vector<double> det_weight;
   // device state carved from the caller's workspace
@@ -133,6 +135,7 @@ namespace mm {
 // kernel launchers (each defined in the .hip file that holds its kernel)
 // ---------------------------------------------------------------------------
 int launch_pointing_build(mm_pointing_s* pt, int32_t min_hits, double cond_max, hipStream_t s);
+int launch_compute_weights(const mm_pointing_s* pt, void* weights, hipStream_t s);
 int launch_export(const mm_pointing_s* pt, int32_t* hits, uint8_t* mask, int32_t* compact,
                   int32_t* kept, double* minv, hipStream_t s);
 

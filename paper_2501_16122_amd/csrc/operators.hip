@@ -141,6 +141,18 @@ __global__ __launch_bounds__(kOpThreads) void k_ninv_white(const PtTile* __restr
   }
 }
 
+// (cos 2psi_t, sin 2psi_t) of every sample, stored as a pair of S
+template <class S>
+__global__ __launch_bounds__(kOpThreads) void k_weights(const S* __restrict__ psi, S* __restrict__ w, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    S c, s;
+    sincos2<S>(psi[t], &c, &s);
+    w[2 * t] = c;
+    w[2 * t + 1] = s;
+  }
+}
+
 __global__ void k_apply_M(const double* __restrict__ minv, const double* __restrict__ r, double* __restrict__ z,
                           int32_t n_kept) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -273,6 +285,18 @@ int launch_ninv_white(const mm_pointing_s* pt, const double* det_w, const void* 
       hipLaunchKernelGGL((k_ninv_white<float, float>), g, b, 0, s, pt->tiles, det_w, (const float*)in,
                          (float*)out);
   }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_compute_weights(const mm_pointing_s* pt, void* weights, hipStream_t s) {
+  const int64_t n = pt->n_samples;
+  if (n == 0) return MM_OK;
+  const dim3 g(grid_for(n, kOpThreads)), b(kOpThreads);
+  if (pt->dtype == MM_F64)
+    hipLaunchKernelGGL(k_weights<double>, g, b, 0, s, (const double*)pt->psi, (double*)weights, n);
+  else
+    hipLaunchKernelGGL(k_weights<float>, g, b, 0, s, (const float*)pt->psi, (float*)weights, n);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }

@@ -77,6 +77,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_pointing_hist(const PtTile* _
     const int64_t t = tl.start + i;
     const int32_t p = pix[t];
     if (p < 0 || p >= n_pix) continue;
+    if (!(fabs(2.0 * double(psi[t])) < sc::kReduceMax)) {  // also NaN / inf
+      atomicOr(&flags[0], 2);
+      continue;
+    }
     double c, s;
     sincos2<double>(psi[t], &c, &s);
     const double v[6] = {w, w * c, w * s, w * c * c, w * c * s, w * s * s};

@@ -2,27 +2,26 @@
 // chosen arithmetic C.
 //
 // Argument reduction x = 2 psi = j pi/2 + r, |r| <= pi/4, in FP64 with pi/2
-// split into three parts (Cody & Waite, "Software Manual for the Elementary
-// Functions", 1980): the first two carry 33 significant bits, so j*A and j*B
-// are exact for |j| < 2^20 and the reduction error stays near one ulp of r
-// for |x| < kReduceMax.  sin r and cos r come from their Taylor series in
-// Horner form (truncation below 1e-19 relative on |r| <= pi/4 in FP64, below
-// 2e-9 in FP32), and the quadrant j mod 4 permutes and negates them.  Larger
-// or non-finite arguments go to the device library in a separate,
-// non-inlined function, which keeps the hot loops' register use small.
+// split into four parts (Cody & Waite, "Software Manual for the Elementary
+// Functions", 1980): the first three carry 25 significant bits, so j times
+// each of them is exact for |j| < 2^28, and the reduction error stays near
+// one ulp of r for |x| < kReduceMax.  sin r and cos r come from their Taylor
+// series in Horner form (truncation below 1e-19 relative on |r| <= pi/4 in
+// FP64, below 2e-9 in FP32), and the quadrant j mod 4 permutes and negates
+// them.  There is no slow path: the pointing build rejects angles with
+// |2 psi| >= kReduceMax (or non-finite), so every kernel stays call-free.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace mm {
 
 namespace sc {
-constexpr double kPio2A = 1.5707963267341256;       // 0x1.921fb544p+0
-constexpr double kPio2B = 6.077100506303966e-11;    // 0x1.0b4611a6p-34
-constexpr double kPio2C = 2.0222662487959506e-21;   // 0x1.3198a2e037073p-69
+constexpr double kPio2A = 1.5707963109016418;      // 0x1.921fb5p+0
+constexpr double kPio2B = 1.5893254712295857e-08;  // 0x1.110b46p-26
+constexpr double kPio2C = 6.123233932053594e-17;   // 0x1.1a6263p-54
+constexpr double kPio2D = 6.36831716351095e-25;    // 0x1.8a2e03707344ap-81
 constexpr double kTwoOverPi = 0.63661977236758134308;
-constexpr double kReduceMax = 1.0e5;
-
-__device__ __noinline__ void sincos_fallback(double x, double* s, double* c) { sincos(x, s, c); }
+constexpr double kReduceMax = 4.0e8;  // < 2^28 * pi/2
 
 // x = j pi/2 + r; returns r and j mod 4
 __device__ __forceinline__ double reduce(double x, int* q) {
@@ -30,6 +29,7 @@ __device__ __forceinline__ double reduce(double x, int* q) {
   double r = fma(-j, kPio2A, x);
   r = fma(-j, kPio2B, r);
   r = fma(-j, kPio2C, r);
+  r = fma(-j, kPio2D, r);
   *q = (int)(long long)j & 3;
   return r;
 }
@@ -81,12 +81,8 @@ __device__ __forceinline__ void poly_f32(float r, float* sr, float* cr) {
 }
 }  // namespace sc
 
-// sin and cos of an FP64 argument
+// sin and cos of an FP64 argument with |x| < kReduceMax
 __device__ __forceinline__ void sincos_x(double x, double* s, double* c) {
-  if (!(fabs(x) < sc::kReduceMax)) {
-    sc::sincos_fallback(x, s, c);
-    return;
-  }
   int q;
   const double r = sc::reduce(x, &q);
   double sr, cr;
@@ -94,15 +90,8 @@ __device__ __forceinline__ void sincos_x(double x, double* s, double* c) {
   sc::quadrant<double>(q, sr, cr, s, c);
 }
 
-// sin and cos of an FP64 argument, evaluated to FP32 accuracy
+// the same to FP32 accuracy
 __device__ __forceinline__ void sincos_x(double x, float* s, float* c) {
-  if (!(fabs(x) < sc::kReduceMax)) {
-    double sd, cd;
-    sc::sincos_fallback(x, &sd, &cd);
-    *s = float(sd);
-    *c = float(cd);
-    return;
-  }
   int q;
   const float r = float(sc::reduce(x, &q));
   float sr, cr;

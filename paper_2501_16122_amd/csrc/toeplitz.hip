@@ -28,24 +28,31 @@
 namespace mm {
 namespace {
 
-constexpr int kFftThreads = 256;
+constexpr int kFftThreads = 512;
 
+// Radix plans.  FP64: N = 8192 = 16*16*16*2 (the radix-2 stages folded into
+// the spectral step), 16 elements per thread;
+// FP32: N = 16384 = 32*32*16, 32 elements per thread.  The inverse runs the
+// radices in reverse order; its first pass also applies the spectral weights.
 template <class C>
 struct Plan;
-// FP64: N = 8192 = 32 * 16 * 16, 32 elements per thread.
 template <>
 struct Plan<double> {
-  static constexpr int N = kFftN64, R1 = 32, R2 = 16, R3 = 16;
+  static constexpr int N = kFftN64;
+  static constexpr int kGatherBatch = 8;   // entries (sample pairs) per load batch
+  static constexpr int kScatterBatch = 4;
 };
-// FP32: N = 16384 = 32 * 32 * 16, 64 elements per thread.
 template <>
 struct Plan<float> {
-  static constexpr int N = kFftN32, R1 = 32, R2 = 32, R3 = 16;
+  static constexpr int N = kFftN32;
+  static constexpr int kGatherBatch = 8;
+  static constexpr int kScatterBatch = 4;
 };
 
 constexpr int kLdsBytes = lds_elems<kFftN64>() * 16;  // same for both plans
 static_assert(lds_elems<kFftN32>() * 8 == kLdsBytes, "plans share one LDS size");
 constexpr int kTBinSlots = (kLdsBytes / 24) & ~63;    // bins reuse the FFT buffer
+constexpr int kXPixels = kLdsBytes / 32;                // staged map pixels (4-double stride)
 
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
   for (int off = 32; off > 0; off >>= 1) {
@@ -63,141 +70,336 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
   return v;
 }
 
+// Remaining passes of a plan: compute the pass held in registers, exchange
+// through LDS, load the next pass's inputs, recurse.
+template <class C, int N, int T, bool kFwd, int Ns, int R>
+__device__ __forceinline__ void passes(cpx<C>* buf, cpx<C>* v, const cpx<C>* __restrict__ tw) {
+  pass_compute<C, N, T, R, Ns, kFwd>(v, tw);
+}
+template <class C, int N, int T, bool kFwd, int Ns, int R, int R2, int... Rest>
+__device__ __forceinline__ void passes(cpx<C>* buf, cpx<C>* v, const cpx<C>* __restrict__ tw) {
+  pass_compute<C, N, T, R, Ns, kFwd>(v, tw);
+  __syncthreads();
+  pass_store<C, N, T, R, Ns>(buf, v);
+  __syncthreads();
+  pass_load<C, N, T, R2>(buf, v);
+  passes<C, N, T, kFwd, Ns * R, R2, Rest...>(buf, v, tw);
+}
+
+// X_k = alpha_k Z_k + i beta_k conj(Z_{N-k}) for the inputs of the first
+// inverse pass (radix R): slot b*R + m holds k = tid + b*T + m*N/R.
+template <class C, int N, int T, int R>
+__device__ __forceinline__ void spectral_load(const cpx<C>* buf, const cpx<C>* __restrict__ abf, cpx<C>* v) {
+  constexpr int BPT = N / T / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int j = threadIdx.x + b * T;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int k = j + m * (N / R);
+      const cpx<C> z = buf[lds_pad(k)];
+      const cpx<C> zr = buf[lds_pad((N - k) & (N - 1))];
+      const cpx<C> w = abf[k];  // (alpha_k, beta_k)
+      // alpha (zx + i zy) + i beta (zrx - i zry) = (alpha zx + beta zry) + i (alpha zy + beta zrx)
+      v[b * R + m] = cpx<C>{w.x * z.x + w.y * zr.y, w.x * z.y + w.y * zr.x};
+      if (((b * R + m) & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// FP64 plan: after forward passes 16, 16, 16 the buffer holds Y, the two
+// interleaved N/2-point DFTs (even / odd elements) of the packed tile.  One
+// LDS round trip over bin quadruples (j, j + H, m, m + H), m = H - j, H = N/2,
+// then performs the last forward radix-2 butterfly
+//   Z_k = Y_k + w^k Y_{k+H},  Z_{k+H} = Y_k - w^k Y_{k+H}   (w = e^{-2 pi i/N}),
+// the spectral weights X_k = alpha_k Z_k + i beta_k conj(Z_{N-k}), and the
+// first inverse radix-2 pass  out_{2k} = X_k + X_{k+H},  out_{2k+1} = X_k - X_{k+H}.
+__device__ __forceinline__ cpx<double> spec(cpx<double> ab, cpx<double> z, cpx<double> zr) {
+  return {ab.x * z.x + ab.y * zr.y, ab.x * z.y + ab.y * zr.x};
+}
+
+template <int N, int T>
+__device__ __forceinline__ void middle_r2(cpx<double>* buf, const cpx<double>* __restrict__ abf,
+                                          const cpx<double>* __restrict__ tw) {
+  constexpr int H = N / 2, Q = H / 2, PPT = Q / T;
+  static_assert(PPT * T == Q, "quadruples must tile the threads");
+  const int tid = threadIdx.x;
+  cpx<double> o[PPT][4];
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int j = 1 + tid + T * r;  // 1..Q; j = Q is its own mirror
+    const int m = H - j;
+    const cpx<double> a = buf[lds_pad(j)], b = buf[lds_pad(j + H)];
+    const cpx<double> c = buf[lds_pad(m)], d = buf[lds_pad(m + H)];
+    const cpx<double> wb = cmul(tw[j], b), wd = cmul(tw[m], d);
+    const cpx<double> zj = cadd(a, wb), zj2 = csub(a, wb), zm = cadd(c, wd), zm2 = csub(c, wd);
+    const cpx<double> xj = spec(abf[j], zj, zm2), xjh = spec(abf[j + H], zj2, zm);
+    const cpx<double> xm = spec(abf[m], zm, zj2), xmh = spec(abf[m + H], zm2, zj);
+    o[r][0] = cadd(xj, xjh);
+    o[r][1] = csub(xj, xjh);
+    o[r][2] = cadd(xm, xmh);
+    o[r][3] = csub(xm, xmh);
+  }
+  cpx<double> o0 = {0, 0}, o1 = {0, 0};
+  if (tid == 0) {  // k = 0 pairs with itself and with H
+    const cpx<double> a = buf[0], b = buf[lds_pad(H)];
+    const cpx<double> z0 = cadd(a, b), zh = csub(a, b);
+    const cpx<double> x0 = spec(abf[0], z0, z0), xh = spec(abf[H], zh, zh);
+    o0 = cadd(x0, xh);
+    o1 = csub(x0, xh);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int j = 1 + tid + T * r;
+    const int m = H - j;
+    buf[lds_pad(2 * j)] = o[r][0];
+    buf[lds_pad(2 * j + 1)] = o[r][1];
+    buf[lds_pad(2 * m)] = o[r][2];
+    buf[lds_pad(2 * m + 1)] = o[r][3];
+  }
+  if (tid == 0) {
+    buf[0] = o0;
+    buf[lds_pad(1)] = o1;
+  }
+  __syncthreads();
+}
+
+template <class C>
+struct Fft;
+template <>
+struct Fft<double> {
+  static constexpr int RIn = 16, ROut = 16;  // first forward / last inverse radix
+  template <int N, int T>
+  static __device__ __forceinline__ void forward(cpx<double>* buf, cpx<double>* v, const cpx<double>* tw) {
+    passes<double, N, T, true, 1, 16, 16, 16>(buf, v, tw);
+    __syncthreads();
+    pass_store<double, N, T, 16, 256>(buf, v);  // Y: two interleaved N/2-point DFTs
+    __syncthreads();
+  }
+  template <int N, int T>
+  static __device__ __forceinline__ void inverse(cpx<double>* buf, const cpx<double>* abf, cpx<double>* v,
+                                                 const cpx<double>* tw) {
+    middle_r2<N, T>(buf, abf, tw);
+    pass_load<double, N, T, 16>(buf, v);
+    passes<double, N, T, false, 2, 16, 16, 16>(buf, v, tw);
+  }
+};
+template <>
+struct Fft<float> {
+  static constexpr int RIn = 32, ROut = 32;
+  template <int N, int T>
+  static __device__ __forceinline__ void forward(cpx<float>* buf, cpx<float>* v, const cpx<float>* tw) {
+    passes<float, N, T, true, 1, 32, 32, 16>(buf, v, tw);
+    __syncthreads();
+    pass_store<float, N, T, 16, N / 16>(buf, v);
+    __syncthreads();
+  }
+  template <int N, int T>
+  static __device__ __forceinline__ void inverse(cpx<float>* buf, const cpx<float>* abf, cpx<float>* v,
+                                                 const cpx<float>* tw) {
+    spectral_load<float, N, T, 16>(buf, abf, v);
+    passes<float, N, T, false, 1, 16, 32, 32>(buf, v, tw);
+  }
+};
+
+// (cos 2psi_t, sin 2psi_t) in arithmetic C: from the stored pair when kW,
+// else from psi.
+template <class C, class S, int kW>
+struct Angle {
+  using type = typename std::conditional<kW == 1, cpx<S>, S>::type;
+  static __device__ __forceinline__ type load(const S* __restrict__ psi, const cpx<S>* __restrict__ w, int64_t t) {
+    if constexpr (kW == 1) return w[t];
+    else return psi[t];
+  }
+  static __device__ __forceinline__ type zero() {
+    if constexpr (kW == 1) return cpx<S>{S(0), S(0)};
+    else return S(0);
+  }
+  static __device__ __forceinline__ void eval(type a, C* c, C* s) {
+    if constexpr (kW == 1) {
+      *c = C(a.x);
+      *s = C(a.y);
+    } else {
+      sincos2<C>(a, c, s);
+    }
+  }
+};
+
 // kIn: 0 = timeline input tod_in; 1 = gather P x.
 // kOut: 0 = timeline output tod_out; 1 = scatter q += P^T z.
-template <class S, class C, int kIn, int kOut>
-__global__ __launch_bounds__(kFftThreads) void k_toeplitz(const FftTile* __restrict__ tiles, int32_t lambda,
+// kW: 1 = stream the precomputed (cos 2psi, sin 2psi) pairs instead of psi.
+template <class S, class C, int kIn, int kOut, int kW>
+__global__ __launch_bounds__(kFftThreads) void k_toeplitz(const FftTile* __restrict__ tiles, int64_t n_tiles,
+                                                          int32_t lambda,
                                                           const cpx<C>* __restrict__ ab,
                                                           const cpx<C>* __restrict__ tw,
                                                           const int32_t* __restrict__ sample_k,
-                                                          const S* __restrict__ psi, const double* __restrict__ x,
+                                                          const S* __restrict__ psi,
+                                                          const cpx<S>* __restrict__ wts, const double* __restrict__ x,
                                                           const S* __restrict__ tod_in, S* __restrict__ tod_out,
                                                           double* __restrict__ q, const int32_t* __restrict__ done) {
   using P = Plan<C>;
-  constexpr int N = P::N, T = kFftThreads, E = N / T;
-  constexpr int L = 2 * N;
+  using F = Fft<C>;
+  using A = Angle<C, S, kW>;
+  constexpr int N = P::N, T = kFftThreads, E = N / T, L = 2 * N, G = P::kGatherBatch, GS = P::kScatterBatch;
+  static_assert(E % G == 0, "gather batches must tile the elements");
   if (done != nullptr && *done) return;
   __shared__ cpx<C> buf[lds_elems<N>()];
-  __shared__ int32_t s_red[8];
+  __shared__ int32_t s_red[4 * (kFftThreads / 64)];
 
-  const FftTile tl = tiles[blockIdx.x];
-  const int64_t in0 = tl.out_start - (lambda - 1);
-  const int32_t vlo = lambda - 1;                                   // first valid position
-  const int32_t vhi = vlo + (int32_t)(tl.out_end - tl.out_start);  // one past the last
+  // XCD-aware mapping: workgroups go round-robin over the 8 XCDs, so give
+  // XCD x a contiguous run of tiles; neighbouring tiles (which share their
+  // overlap-save halos) then run close together on one L2.
+  const int64_t per_xcd = (n_tiles + 7) / 8;
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (tile >= n_tiles) return;
+  const FftTile tl = tiles[tile];
+  const int64_t in0 = tl.out_start - (lambda - 1);  // timeline index of window position 0
+  const int32_t vlo = lambda - 1;                    // valid (non-wrapping) outputs: [vlo, vhi)
+  const int32_t vhi = vlo + (int32_t)(tl.out_end - tl.out_start);
+  // window positions inside the chunk: [ilo, ihi)
+  const int32_t ilo = (int32_t)(tl.chunk_start > in0 ? tl.chunk_start - in0 : 0);
+  const int32_t ihi = (int32_t)(tl.chunk_end - in0 < L ? tl.chunk_end - in0 : L);
   const int tid = threadIdx.x;
 
-  // ---- load the window into LDS in natural order: complex entry n packs
-  // samples 2n and 2n+1 (zero outside the chunk or on masked pixels)
-  int32_t kmin = INT32_MAX, kmax = -1;
-#pragma unroll 2
-  for (int n = tid; n < N; n += T) {
-    C u[2];
+  // ---- input: element e of this thread packs window samples 2n, 2n+1 with
+  // n = tid + T e, which is where the first forward pass wants it
+  cpx<C> v[E];
+  int32_t kmin = INT32_MAX, kmax = -1;  // compact-index window of the valid outputs
+  // With 16 elements per thread the compact indices stay in registers from
+  // the gather to the scatter (no reload); with 32 they would not fit.
+  constexpr bool kKeepK = kIn == 1 && kOut == 1 && E <= 16;
+  int32_t kk[2 * E];
+  if constexpr (kIn == 1) {
+    // (1) compact index of every window sample of this thread, one batch
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int pos = 2 * n + h;
-      const int64_t t = in0 + pos;
-      C val = C(0);
-      if (t >= tl.chunk_start && t < tl.chunk_end) {
-        if (kIn == 0) {
-          val = C(tod_in[t]);
-        } else {
-          const int32_t k = sample_k[t];
-          if (k >= 0) {
-            C c, s;
-            sincos2<C>(psi[t], &c, &s);
-            const double* xk = x + 3 * (int64_t)k;
-            val = C(xk[0]) + c * C(xk[1]) + s * C(xk[2]);
-          }
-          if (kOut == 1 && k >= 0 && pos >= vlo && pos < vhi) {
-            kmin = k < kmin ? k : kmin;
-            kmax = k > kmax ? k : kmax;
-          }
-        }
-        if (kIn == 0 && kOut == 1 && pos >= vlo && pos < vhi) {
-          const int32_t k = sample_k[t];
-          if (k >= 0) {
-            kmin = k < kmin ? k : kmin;
-            kmax = k > kmax ? k : kmax;
-          }
+    for (int i = 0; i < 2 * E; ++i) {
+      const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
+      kk[i] = (pos >= ilo && pos < ihi) ? sample_k[in0 + pos] : -1;
+    }
+    int32_t amin = INT32_MAX, amax = -1;  // window of every kept sample (map staging)
+#pragma unroll
+    for (int i = 0; i < 2 * E; ++i) {
+      const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
+      if (kk[i] >= 0) {
+        amin = kk[i] < amin ? kk[i] : amin;
+        amax = kk[i] > amax ? kk[i] : amax;
+        if (kOut == 1 && pos >= vlo && pos < vhi) {
+          kmin = kk[i] < kmin ? kk[i] : kmin;
+          kmax = kk[i] > kmax ? kk[i] : kmax;
         }
       }
-      u[h] = val;
     }
-    buf[lds_pad(n)] = cpx<C>{u[0], u[1]};
-  }
-  if (kOut == 1) {
+    amin = wave_min(amin);
+    amax = wave_max(amax);
     kmin = wave_min(kmin);
     kmax = wave_max(kmax);
+    constexpr int W = T / 64;
     if ((tid & 63) == 0) {
       s_red[tid >> 6] = kmin;
-      s_red[4 + (tid >> 6)] = kmax;
+      s_red[W + (tid >> 6)] = kmax;
+      s_red[2 * W + (tid >> 6)] = amin;
+      s_red[3 * W + (tid >> 6)] = amax;
     }
-  }
-  __syncthreads();
-
-  // ---- forward FFT: passes R1, R2, R3 (spans 1, R1, R1 R2)
-  cpx<C> v[E];
-  pass_load<C, N, T, P::R1>(buf, v);
-  pass_compute<C, N, T, P::R1, 1, true>(v, tw);
-  __syncthreads();
-  pass_store<C, N, T, P::R1, 1>(buf, v);
-  __syncthreads();
-  pass_load<C, N, T, P::R2>(buf, v);
-  pass_compute<C, N, T, P::R2, P::R1, true>(v, tw);
-  __syncthreads();
-  pass_store<C, N, T, P::R2, P::R1>(buf, v);
-  __syncthreads();
-  pass_load<C, N, T, P::R3>(buf, v);
-  pass_compute<C, N, T, P::R3, P::R1 * P::R2, true>(v, tw);
-  __syncthreads();
-  pass_store<C, N, T, P::R3, P::R1 * P::R2>(buf, v);
-  __syncthreads();
-
-  // ---- spectral multiply fused into the first inverse pass (radix R3):
-  // X_k = alpha_k Z_k + i beta_k conj(Z_{N-k})
-  {
-    constexpr int BPT = E / P::R3;
-    const cpx<C>* abf = ab + (int64_t)tl.filter * N;
+    __syncthreads();
+    amin = s_red[2 * W];
+    amax = s_red[3 * W];
 #pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-      const int j = tid + b * T;
+    for (int w = 1; w < W; ++w) {
+      amin = s_red[2 * W + w] < amin ? s_red[2 * W + w] : amin;
+      amax = s_red[3 * W + w] > amax ? s_red[3 * W + w] : amax;
+    }
+    // (2) stage the map over [amin, amax] in LDS with coalesced loads when it
+    // fits (the FFT buffer is free until the first pass)
+    double* xs = reinterpret_cast<double*>(buf);
+    const int xspan = amax - amin + 1;
+    const bool staged = amax >= amin && xspan <= kXPixels;
+    if (staged) {
+      // pixel p of the window at xs[4p .. 4p+2]: 32-byte stride keeps the
+      // (I, Q) pair 16-byte aligned for one LDS read
+      const double* xw = x + 3 * (int64_t)amin;
+      for (int i = tid; i < 3 * xspan; i += T) {
+        const int p = i / 3;
+        xs[4 * p + (i - 3 * p)] = xw[i];
+      }
+    }
+    __syncthreads();
+    // (3) pointing weights in batches, P x from the staged map
 #pragma unroll
-      for (int m = 0; m < P::R3; ++m) {
-        const int k = j + m * (N / P::R3);
-        const cpx<C> z = buf[lds_pad(k)];
-        const cpx<C> zr = buf[lds_pad((N - k) & (N - 1))];
-        const cpx<C> w = abf[k];  // (alpha_k, beta_k)
-        // alpha (zx + i zy) + i beta (zrx - i zry) = (alpha zx + beta zry) + i (alpha zy + beta zrx)
-        v[b * P::R3 + m] = cpx<C>{w.x * z.x + w.y * zr.y, w.x * z.y + w.y * zr.x};
-        if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    for (int e0 = 0; e0 < E; e0 += G) {
+      __builtin_amdgcn_sched_barrier(0);  // one batch of loads in flight at a time
+      typename A::type ps[2 * G];
+#pragma unroll
+      for (int i = 0; i < 2 * G; ++i) {
+        const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
+        ps[i] = kk[2 * e0 + i] >= 0 ? A::load(psi, wts, in0 + pos) : A::zero();
+      }
+#pragma unroll
+      for (int i = 0; i < 2 * G; ++i) {
+        const int32_t k = kk[2 * e0 + i];
+        C val = C(0);
+        if (k >= 0) {
+          C c, s;
+          A::eval(ps[i], &c, &s);
+          const double* xk = staged ? xs + 4 * (k - amin) : x + 3 * (int64_t)k;
+          val = C(xk[0]) + c * C(xk[1]) + s * C(xk[2]);
+        }
+        cpx<C>& slot = v[slot_of<N, T, F::RIn>(e0 + i / 2)];
+        if (i & 1) slot.y = val;
+        else slot.x = val;
+      }
+    }
+    __syncthreads();  // the FFT reuses the staging area
+  } else {
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += G) {
+      __builtin_amdgcn_sched_barrier(0);
+      int32_t kt[2 * G];
+      S tv[2 * G];
+#pragma unroll
+      for (int i = 0; i < 2 * G; ++i) {
+        const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
+        const bool in = pos >= ilo && pos < ihi;
+        const int64_t t = in0 + pos;
+        if (kOut == 1) kt[i] = (in && pos >= vlo && pos < vhi) ? sample_k[t] : -1;
+        tv[i] = in ? tod_in[t] : S(0);
+      }
+#pragma unroll
+      for (int i = 0; i < 2 * G; ++i) {
+        if (kOut == 1 && kt[i] >= 0) {
+          kmin = kt[i] < kmin ? kt[i] : kmin;
+          kmax = kt[i] > kmax ? kt[i] : kmax;
+        }
+        cpx<C>& slot = v[slot_of<N, T, F::RIn>(e0 + i / 2)];
+        if (i & 1) slot.y = C(tv[i]);
+        else slot.x = C(tv[i]);
+      }
+    }
+    if (kOut == 1) {
+      kmin = wave_min(kmin);
+      kmax = wave_max(kmax);
+      if ((tid & 63) == 0) {
+        s_red[tid >> 6] = kmin;
+        s_red[T / 64 + (tid >> 6)] = kmax;
       }
     }
   }
-  pass_compute<C, N, T, P::R3, 1, false>(v, tw);
-  __syncthreads();
-  pass_store<C, N, T, P::R3, 1>(buf, v);
-  __syncthreads();
-  pass_load<C, N, T, P::R2>(buf, v);
-  pass_compute<C, N, T, P::R2, P::R3, false>(v, tw);
-  __syncthreads();
-  pass_store<C, N, T, P::R2, P::R3>(buf, v);
-  __syncthreads();
-  pass_load<C, N, T, P::R1>(buf, v);
-  pass_compute<C, N, T, P::R1, P::R3 * P::R2, false>(v, tw);
-  // v now holds, for element e, the outputs at samples 2n, 2n+1, n = tid + T e
+
+  // ---- forward FFT (natural order into LDS), spectral multiply fused into
+  // the first inverse pass, inverse FFT (outputs stay in registers)
+  F::template forward<N, T>(buf, v, tw);
+  F::template inverse<N, T>(buf, ab + (int64_t)tl.filter * N, v, tw);
+  // v[slot_of<ROut>(e)] now holds the outputs at window samples 2n, 2n+1,
+  // n = tid + T e
 
   if (kOut == 0) {
-    __syncthreads();
-    pass_store<C, N, T, P::R1, P::R3 * P::R2>(buf, v);  // natural order
-    __syncthreads();
-#pragma unroll 2
-    for (int n = tid; n < N; n += T) {
-      const cpx<C> o = buf[lds_pad(n)];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int pos = 2 * n + h;
-        if (pos >= vlo && pos < vhi) tod_out[in0 + pos] = S(h == 0 ? o.x : o.y);
-      }
+    for (int e = 0; e < E; ++e) {
+      const int n = tid + T * e;
+      const cpx<C> o = v[slot_of<N, T, F::ROut>(e)];
+      if (2 * n >= vlo && 2 * n < vhi) tod_out[in0 + 2 * n] = S(o.x);
+      if (2 * n + 1 >= vlo && 2 * n + 1 < vhi) tod_out[in0 + 2 * n + 1] = S(o.y);
     }
     return;
   }
@@ -205,52 +407,65 @@ __global__ __launch_bounds__(kFftThreads) void k_toeplitz(const FftTile* __restr
   // ---- P^T scatter through LDS bins over the tile's compact-index window
   __syncthreads();  // every thread is done reading buf
   kmin = s_red[0];
-  kmax = s_red[4];
+  kmax = s_red[T / 64];
 #pragma unroll
-  for (int w = 1; w < 4; ++w) {
+  for (int w = 1; w < T / 64; ++w) {
     kmin = s_red[w] < kmin ? s_red[w] : kmin;
-    kmax = s_red[4 + w] > kmax ? s_red[4 + w] : kmax;
+    kmax = s_red[T / 64 + w] > kmax ? s_red[T / 64 + w] : kmax;
   }
   if (kmax < kmin) return;
   double* bins = reinterpret_cast<double*>(buf);
   const int span = kmax - kmin + 1;
-  const int nb = span < kTBinSlots ? span : kTBinSlots;
-  for (int i = tid; i < nb; i += T) {
-    bins[i] = 0.0;
-    bins[kTBinSlots + i] = 0.0;
-    bins[2 * kTBinSlots + i] = 0.0;
+  // Uniform per tile: bin in LDS when the window fits, else add straight
+  // into q (only for scans whose tile footprint exceeds kTBinSlots pixels).
+  const bool use_lds = span <= kTBinSlots;
+  if (use_lds) {
+    for (int i = tid; i < span; i += T) {
+      bins[i] = 0.0;
+      bins[kTBinSlots + i] = 0.0;
+      bins[2 * kTBinSlots + i] = 0.0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  double* dst = use_lds ? nullptr : q;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int n = tid + T * e;
-    const cpx<C> o = v[slot_of<N, T, P::R1>(e)];
-    if ((e & 3) == 0) __builtin_amdgcn_sched_barrier(0);
+  for (int e0 = 0; e0 < E; e0 += GS) {
+    __builtin_amdgcn_sched_barrier(0);  // keep one batch of loads in flight at a time
+    int32_t ks[2 * GS];
+    typename A::type ps[2 * GS];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int pos = 2 * n + h;
-      if (pos < vlo || pos >= vhi) continue;
+    for (int i = 0; i < 2 * GS; ++i) {
+      const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
+      const bool valid = pos >= vlo && pos < vhi;
       const int64_t t = in0 + pos;
-      const int32_t k = sample_k[t];
-      if (k < 0) continue;
+      if constexpr (kKeepK) ks[i] = valid ? kk[2 * e0 + i] : -1;
+      else ks[i] = valid ? sample_k[t] : -1;
+      ps[i] = ks[i] >= 0 ? A::load(psi, wts, t) : A::zero();
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * GS; ++i) {
+      const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
+      const C z = (i & 1) ? o.y : o.x;
       C c, s;
-      sincos2<C>(psi[t], &c, &s);
-      const C z = h == 0 ? o.x : o.y;
-      const int32_t rel = k - kmin;
-      if (rel < nb) {
-        atomicAdd(&bins[rel], double(z));
-        atomicAdd(&bins[kTBinSlots + rel], double(z * c));
-        atomicAdd(&bins[2 * kTBinSlots + rel], double(z * s));
-      } else {
-        double* qk = q + 3 * (int64_t)k;
-        atomicAdd(qk + 0, double(z));
-        atomicAdd(qk + 1, double(z * c));
-        atomicAdd(qk + 2, double(z * s));
+      A::eval(ps[i], &c, &s);
+      if (ks[i] >= 0) {
+        if (use_lds) {
+          const int32_t rel = ks[i] - kmin;
+          atomicAdd(&bins[rel], double(z));
+          atomicAdd(&bins[kTBinSlots + rel], double(z * c));
+          atomicAdd(&bins[2 * kTBinSlots + rel], double(z * s));
+        } else {
+          double* qk = dst + 3 * (int64_t)ks[i];
+          atomicAdd(qk + 0, double(z));
+          atomicAdd(qk + 1, double(z * c));
+          atomicAdd(qk + 2, double(z * s));
+        }
       }
     }
   }
+  if (!use_lds) return;
   __syncthreads();
-  for (int i = tid; i < nb; i += T) {
+  for (int i = tid; i < span; i += T) {
     const double v0 = bins[i], v1 = bins[kTBinSlots + i], v2 = bins[2 * kTBinSlots + i];
     double* qk = q + 3 * (int64_t)(kmin + i);
     if (v0 != 0.0) atomicAdd(qk + 0, v0);
@@ -259,28 +474,39 @@ __global__ __launch_bounds__(kFftThreads) void k_toeplitz(const FftTile* __restr
   }
 }
 
-template <class S, class C, int kIn, int kOut>
+template <class S, class C, int kIn, int kOut, int kW>
 int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod_in, void* tod_out,
              double* q, const int32_t* done, hipStream_t s) {
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
-  hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut>), dim3(nz->n_tiles[a]), dim3(kFftThreads), 0, s, nz->tiles[a],
-                     nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
-                     pt ? pt->sample_k : nullptr, pt ? (const S*)pt->psi : nullptr, x, (const S*)tod_in,
-                     (S*)tod_out, q, done);
+  const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8);
+  hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW>), dim3(grid), dim3(kFftThreads), 0, s, nz->tiles[a],
+                     nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
+                     pt ? pt->sample_k : nullptr, pt ? (const S*)pt->psi : nullptr,
+                     pt ? (const cpx<S>*)pt->weights : nullptr, x, (const S*)tod_in, (S*)tod_out, q, done);
   MM_HIP(hipGetLastError());
   return MM_OK;
+}
+
+// Stored weights serve an arithmetic no finer than their storage.
+inline bool use_weights(const mm_pointing_s* pt, int arith) {
+  return pt != nullptr && pt->weights != nullptr && (arith == MM_F32 || pt->dtype == MM_F64);
 }
 
 template <int kIn, int kOut>
 int dispatch(const mm_pointing_s* pt, const mm_noise_s* nz, int dtype, int arith, const double* x,
              const void* tod_in, void* tod_out, double* q, const int32_t* done, hipStream_t s) {
+  const bool w = kOut == 1 && use_weights(pt, arith);
   if (dtype == MM_F64) {
-    if (arith == MM_F64) return launch_t<double, double, kIn, kOut>(pt, nz, x, tod_in, tod_out, q, done, s);
-    return launch_t<double, float, kIn, kOut>(pt, nz, x, tod_in, tod_out, q, done, s);
+    if (arith == MM_F64)
+      return w ? launch_t<double, double, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, done, s)
+               : launch_t<double, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, done, s);
+    return w ? launch_t<double, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, done, s)
+             : launch_t<double, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, done, s);
   }
-  if (arith == MM_F64) return launch_t<float, double, kIn, kOut>(pt, nz, x, tod_in, tod_out, q, done, s);
-  return launch_t<float, float, kIn, kOut>(pt, nz, x, tod_in, tod_out, q, done, s);
+  if (arith == MM_F64) return launch_t<float, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, done, s);
+  return w ? launch_t<float, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, done, s)
+           : launch_t<float, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, done, s);
 }
 
 }  // namespace

@@ -133,6 +133,16 @@ def test_build_rejects_bad_pixel():
     assert ei.value.code == b.MM_EINVAL
 
 
+def test_build_rejects_bad_angle():
+    b = _b()
+    pix = torch.tensor([0, 1, 1], dtype=torch.int32, device=DEV)
+    for bad in (float("nan"), float("inf"), 3e8):
+        psi = torch.tensor([0.1, bad, 0.2], dtype=torch.float64, device=DEV)
+        with pytest.raises(b.MapMakerError) as ei:
+            b.Pointing(pix, psi, [0, 3], [1.0], 5)
+        assert ei.value.code == b.MM_EINVAL
+
+
 def test_P_PT_white_ninv(ragged):
     b = _b()
     P = ragged
@@ -267,3 +277,24 @@ def test_toeplitz_solve_fixed_iterations(ragged):
     assert out2["info"]["converged"] == 1
     assert abs(out2["info"]["iters"] - k) <= 1
     assert out2["info"]["true_rel_resid"] < 1e-9
+
+
+def test_fused_toeplitz_with_stored_weights(ragged):
+    # the precomputed (cos, sin) path gives the same operator
+    b = _b()
+    P = ragged
+    x = np.random.default_rng(15).normal(size=3 * P.opt.n_kept)
+    tx = torch.from_numpy(x).to(DEV)
+    q0 = b.apply_A(P.pt, P.nz, tx).cpu().numpy()
+    P.pt.attach_weights()
+    try:
+        w = P.pt.weights.cpu().numpy().reshape(-1, 2)
+        assert np.max(np.abs(w[:, 0] - P.opt.cos2)) < 1e-15
+        assert np.max(np.abs(w[:, 1] - P.opt.sin2)) < 1e-15
+        q1 = b.apply_A(P.pt, P.nz, tx).cpu().numpy()
+        bb = b.rhs(P.pt, P.nz, P.t_d).cpu().numpy()
+    finally:
+        P.pt.detach_weights()
+    assert rel_err(q1, oracle.apply_A(P.opt, P.noise, x)) < 1e-12
+    assert rel_err(q1, q0) < 1e-13
+    assert rel_err(bb, oracle.rhs(P.opt, P.noise, P.d)) < 1e-12
