@@ -28,31 +28,33 @@
 namespace mm {
 namespace {
 
-constexpr int kFftThreads = 512;
-
-// Radix plans.  FP64: N = 8192 = 16*16*16*2 (the radix-2 stages folded into
-// the spectral step), 16 elements per thread;
-// FP32: N = 16384 = 32*32*16, 32 elements per thread.  The inverse runs the
-// radices in reverse order; its first pass also applies the spectral weights.
+// Radix plans.
+// FP64: N = 8192 = 16*16*16*2 (the radix-2 stages folded into the spectral
+//   step), 512 threads x 16 elements, 136 KiB of LDS: one workgroup per CU.
+// FP32: N = 16384 = 32*32*16, 512 threads x 32 elements, 136 KiB of LDS;
+//   the longer tile keeps 75% of each window valid at lambda = 4096 (an
+//   8192-point FP32 plan with two workgroups per CU measured slower).
 template <class C>
 struct Plan;
 template <>
 struct Plan<double> {
-  static constexpr int N = kFftN64;
+  static constexpr int N = kFftN64, T = 512, kMinBlocks = 1;
   static constexpr int kGatherBatch = 8;   // entries (sample pairs) per load batch
   static constexpr int kScatterBatch = 4;
 };
 template <>
 struct Plan<float> {
-  static constexpr int N = kFftN32;
+  static constexpr int N = kFftN32, T = 512, kMinBlocks = 1;
   static constexpr int kGatherBatch = 8;
   static constexpr int kScatterBatch = 4;
 };
 
-constexpr int kLdsBytes = lds_elems<kFftN64>() * 16;  // same for both plans
-static_assert(lds_elems<kFftN32>() * 8 == kLdsBytes, "plans share one LDS size");
-constexpr int kTBinSlots = (kLdsBytes / 24) & ~63;    // bins reuse the FFT buffer
-constexpr int kXPixels = kLdsBytes / 32;                // staged map pixels (4-double stride)
+template <class C>
+struct Lds {
+  static constexpr int kBytes = lds_elems<Plan<C>::N>() * (int)sizeof(cpx<C>);
+  static constexpr int kBinSlots = (kBytes / 24) & ~63;  // P^T bins reuse the FFT buffer
+  static constexpr int kXPixels = kBytes / 32;           // staged map pixels (4-double stride)
+};
 
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
   for (int off = 32; off > 0; off >>= 1) {
@@ -192,7 +194,7 @@ struct Fft<float> {
   static __device__ __forceinline__ void forward(cpx<float>* buf, cpx<float>* v, const cpx<float>* tw) {
     passes<float, N, T, true, 1, 32, 32, 16>(buf, v, tw);
     __syncthreads();
-    pass_store<float, N, T, 16, N / 16>(buf, v);
+    pass_store<float, N, T, 16, N / 16>(buf, v);  // natural order
     __syncthreads();
   }
   template <int N, int T>
@@ -230,7 +232,8 @@ struct Angle {
 // kOut: 0 = timeline output tod_out; 1 = scatter q += P^T z.
 // kW: 1 = stream the precomputed (cos 2psi, sin 2psi) pairs instead of psi.
 template <class S, class C, int kIn, int kOut, int kW>
-__global__ __launch_bounds__(kFftThreads) void k_toeplitz(const FftTile* __restrict__ tiles, int64_t n_tiles,
+__global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(const FftTile* __restrict__ tiles,
+                                                                              int64_t n_tiles,
                                                           int32_t lambda,
                                                           const cpx<C>* __restrict__ ab,
                                                           const cpx<C>* __restrict__ tw,
@@ -242,11 +245,12 @@ __global__ __launch_bounds__(kFftThreads) void k_toeplitz(const FftTile* __restr
   using P = Plan<C>;
   using F = Fft<C>;
   using A = Angle<C, S, kW>;
-  constexpr int N = P::N, T = kFftThreads, E = N / T, L = 2 * N, G = P::kGatherBatch, GS = P::kScatterBatch;
+  constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch, GS = P::kScatterBatch;
+  constexpr int kTBinSlots = Lds<C>::kBinSlots, kXPixels = Lds<C>::kXPixels;
   static_assert(E % G == 0, "gather batches must tile the elements");
   if (done != nullptr && *done) return;
   __shared__ cpx<C> buf[lds_elems<N>()];
-  __shared__ int32_t s_red[4 * (kFftThreads / 64)];
+  __shared__ int32_t s_red[4 * (P::T / 64)];
 
   // XCD-aware mapping: workgroups go round-robin over the 8 XCDs, so give
   // XCD x a contiguous run of tiles; neighbouring tiles (which share their
@@ -480,7 +484,7 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
   const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8);
-  hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW>), dim3(grid), dim3(kFftThreads), 0, s, nz->tiles[a],
+  hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
                      nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
                      pt ? pt->sample_k : nullptr, pt ? (const S*)pt->psi : nullptr,
                      pt ? (const cpx<S>*)pt->weights : nullptr, x, (const S*)tod_in, (S*)tod_out, q, done);
