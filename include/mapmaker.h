@@ -160,6 +160,11 @@ int mm_apply_Ninv(mm_noise_t nz, mm_pointing_t pt, const void* tod_in, void* tod
 int mm_apply_A(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, void* stream);
 /* b = P^T N^-1 tod (the right-hand side of eq. (6)), fused likewise. */
 int mm_rhs(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* b, int32_t arith, void* stream);
+/* Q = A X for n_rhs vectors at once (X, Q: f64[n_rhs][3 * n_kept]); the
+ * right-hand sides of one tile run side by side, so the pointing is streamed
+ * from memory once for all of them. */
+int mm_apply_A_multi(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const double* x, double* q, int32_t arith,
+                     void* stream);
 /* z = M r with the 3x3 inverse blocks of eq. (7). */
 int mm_apply_M(mm_pointing_t pt, const double* r, double* z, void* stream);
 /* map_full f64[3 * n_pix] = x at kept pixels, 0 at masked ones. */
@@ -210,6 +215,44 @@ int mm_solve_workspace_size(mm_pointing_t pt, mm_noise_t nz, const mm_solve_opts
 int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, double* x_out,
              const mm_solve_opts* opts, mm_solve_info* info, double* history_host, int32_t history_len,
              void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Resumable solves: one or several right-hand sides sharing a pointing and a
+ * noise model (detector splits, Monte Carlo noise realisations), advanced in
+ * asynchronous steps so that many solves can be in flight at once.
+ * ------------------------------------------------------------------------ */
+
+typedef struct mm_solver_s* mm_solver_t;
+
+int mm_solver_workspace_size(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const mm_solve_opts* opts,
+                             size_t* bytes);
+
+/* Form b = P^T N^-1 d (FP64) for each timeline of `tod` (dtype[n_rhs][n_samples])
+ * and start PCG, asynchronously on `stream`, which the solver keeps using.
+ * The workspace is borrowed until mm_solver_destroy. */
+int mm_solver_create(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const void* tod, const mm_solve_opts* opts,
+                     void* workspace, size_t ws_bytes, void* stream, mm_solver_t* out);
+
+/* Enqueue up to k more PCG iterations (a pending outer refinement step first)
+ * and an asynchronous copy of the solver state to host memory.  Never blocks;
+ * the kernels of a right-hand side that is done return at once. */
+int mm_solver_step(mm_solver_t sv, int32_t k);
+
+/* Non-blocking: *done = 1 once every right-hand side has converged, broken
+ * down or reached its caps, as of the last step whose state copy has landed;
+ * *in_flight (may be NULL) = 1 while the latest step's copy has not landed;
+ * info (n_rhs entries, may be NULL) reports the last landed state. */
+int mm_solver_poll(mm_solver_t sv, int32_t* done, int32_t* in_flight, mm_solve_info* info);
+
+/* Blocking: true FP64 residual, then the full-grid maps (f64[n_rhs][3 * n_pix],
+ * may be NULL) and compact solutions (f64[n_rhs][3 * n_kept], may be NULL).
+ * history_host receives right-hand side 0's residual history (inner, or the
+ * outer FP64 one for mixed solves).  Returns like mm_solve. */
+int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_info* info, double* history_host,
+                     int32_t history_len);
+
+/* Free the host side (pinned state copy, events); the caller frees the workspace. */
+int mm_solver_destroy(mm_solver_t sv);
 
 #ifdef __cplusplus
 }

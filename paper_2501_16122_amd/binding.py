@@ -65,12 +65,19 @@ SIGNATURES = {
     "mm_apply_Ninv": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
     "mm_apply_A": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
     "mm_rhs": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "mm_apply_A_multi": (_c.c_int, [_vp, _vp, _i32, _vp, _vp, _i32, _vp]),
     "mm_apply_M": (_c.c_int, [_vp, _vp, _vp, _vp]),
     "mm_expand_map": (_c.c_int, [_vp, _vp, _vp, _vp]),
     "mm_solve_opts_default": (_c.c_int, [_c.POINTER(SolveOpts)]),
     "mm_solve_workspace_size": (_c.c_int, [_vp, _vp, _c.POINTER(SolveOpts), _psz]),
     "mm_solve": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.POINTER(SolveOpts), _c.POINTER(SolveInfo), _pf64, _i32,
                             _vp, _sz, _vp]),
+    "mm_solver_workspace_size": (_c.c_int, [_vp, _vp, _i32, _c.POINTER(SolveOpts), _psz]),
+    "mm_solver_create": (_c.c_int, [_vp, _vp, _i32, _vp, _c.POINTER(SolveOpts), _vp, _sz, _vp, _c.POINTER(_vp)]),
+    "mm_solver_step": (_c.c_int, [_vp, _i32]),
+    "mm_solver_poll": (_c.c_int, [_vp, _pi32, _pi32, _c.POINTER(SolveInfo)]),
+    "mm_solver_finish": (_c.c_int, [_vp, _vp, _vp, _c.POINTER(SolveInfo), _pf64, _i32]),
+    "mm_solver_destroy": (_c.c_int, [_vp]),
 }
 
 _lib = None
@@ -328,6 +335,18 @@ def rhs(pt: Pointing, nz: Noise, tod, b=None, arith="f64", stream=None):
     return b
 
 
+def apply_A_multi(pt: Pointing, nz: Noise, x, q=None, arith="f64", stream=None):
+    """Q = A X for X of shape (n_rhs, 3 n_kept) in one launch."""
+    torch = _torch()
+    n_rhs = x.shape[0]
+    _dev_check(x, torch.float64, n_rhs * 3 * pt.n_kept, "x")
+    if q is None:
+        q = torch.empty_like(x)
+    _dev_check(q, torch.float64, n_rhs * 3 * pt.n_kept, "q")
+    _check(load().mm_apply_A_multi(pt.handle, nz.handle, n_rhs, _ptr(x), _ptr(q), _arith(arith), _stream(stream)))
+    return q
+
+
 def apply_M(pt: Pointing, r, z=None, stream=None):
     torch = _torch()
     _vec(pt, r, "r")
@@ -388,6 +407,73 @@ class Solver:
         _check(rc, allow=(MM_OK, MM_NOTCONVERGED))
         out = {"map": map_out, "x": x_out[:3 * pt.n_kept], "info": info.as_dict(), "status": rc}
         if hist is not None:
-            n = (info.iters + 1) if not self.opts.mixed else info.outer_iters
+            n = (info.iters + 1) if not self.opts.mixed else info.outer_iters + 1
             out["history"] = hist[:n]
         return out
+
+
+class AsyncSolver:
+    """A resumable solve of n_rhs timelines (tod: (n_rhs, n_samples), or one
+    timeline) sharing ``pt`` and ``nz``; advanced by ``step`` on its own
+    stream, polled without blocking, finished by ``finish``."""
+
+    def __init__(self, pt: Pointing, nz: Noise, tod, stream=None, **opts):
+        torch = _torch()
+        lib = load()
+        self.pt, self.nz = pt, nz
+        self.n_rhs = 1 if tod.dim() == 1 else tod.shape[0]
+        _dev_check(tod, pt.tod_dtype, self.n_rhs * pt.n_samples, "tod")
+        self.opts = solve_opts(**opts)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        sz = _c.c_size_t()
+        _check(lib.mm_solver_workspace_size(pt.handle, nz.handle, self.n_rhs, _c.byref(self.opts), _c.byref(sz)))
+        self.workspace_bytes = sz.value
+        self.workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=pt.device)
+        self._tod = tod
+        h = _vp()
+        _check(lib.mm_solver_create(pt.handle, nz.handle, self.n_rhs, _ptr(tod), _c.byref(self.opts),
+                                    _ptr(self.workspace), sz.value, self.stream.cuda_stream, _c.byref(h)))
+        self.handle = h
+        self.done = False
+
+    def step(self, k=None):
+        _check(load().mm_solver_step(self.handle, int(self.opts.check_every if k is None else k)))
+
+    def poll(self, with_info=False):
+        """(done, in_flight[, infos]) without blocking."""
+        done = _c.c_int32()
+        flight = _c.c_int32()
+        infos = (SolveInfo * self.n_rhs)() if with_info else None
+        _check(load().mm_solver_poll(self.handle, _c.byref(done), _c.byref(flight), infos))
+        self.done = bool(done.value)
+        if with_info:
+            return self.done, bool(flight.value), [i.as_dict() for i in infos]
+        return self.done, bool(flight.value)
+
+    def finish(self, history=False):
+        torch = _torch()
+        pt = self.pt
+        maps = torch.empty((self.n_rhs, 3 * pt.n_pix), dtype=torch.float64, device=pt.device)
+        xs = torch.empty((self.n_rhs, max(1, 3 * pt.n_kept)), dtype=torch.float64, device=pt.device)
+        infos = (SolveInfo * self.n_rhs)()
+        hl = max(self.opts.max_iter, self.opts.fixed_iter, self.opts.max_outer) + 1
+        hist = np.zeros(hl) if history else None
+        rc = load().mm_solver_finish(self.handle, _ptr(maps), _ptr(xs), infos,
+                                     None if hist is None else hist.ctypes.data_as(_pf64), 0 if hist is None else hl)
+        _check(rc, allow=(MM_OK, MM_NOTCONVERGED))
+        out = {"maps": maps, "x": xs[:, :3 * pt.n_kept], "info": [i.as_dict() for i in infos], "status": rc}
+        if hist is not None:
+            i0 = out["info"][0]
+            out["history"] = hist[: (i0["outer_iters"] + 1 if self.opts.mixed else i0["iters"] + 1)]
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().mm_solver_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

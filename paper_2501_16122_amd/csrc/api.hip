@@ -68,6 +68,21 @@ size_t carve_pointing(Carver& cv, int64_t n_samples, int32_t n_det, int32_t n_pi
   return cv.used;
 }
 
+}  // namespace
+
+int apply_A_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, double* q, int arith,
+                 const RhsBatch& rb, hipStream_t s) {
+  if (nz->kind == 0) return launch_fused_white(pt, nz->det_w, x, q, arith, rb, s);
+  return launch_fused_toeplitz(pt, nz, x, nullptr, q, arith, rb, s);
+}
+
+int rhs_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const void* tod, double* b, int arith, hipStream_t s) {
+  int rc = launch_fill(b, 3 * (int64_t)pt->n_kept, 0.0, s);
+  if (rc) return rc;
+  if (nz->kind == 0) return launch_rhs_white(pt, nz->det_w, tod, b, arith, s);
+  return launch_fused_toeplitz(pt, nz, nullptr, tod, b, arith, RhsBatch{}, s);
+}
+
 int check_pointing(mm_pointing_t pt) {
   if (pt == nullptr) return fail(MM_EINVAL, "null pointing handle");
   return MM_OK;
@@ -91,20 +106,6 @@ int check_noise_vs_pointing(const mm_noise_s* nz, const mm_pointing_s* pt) {
   return MM_OK;
 }
 
-int apply_A_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, double* q, int arith,
-                 const int32_t* done, hipStream_t s) {
-  if (nz->kind == 0) return launch_fused_white(pt, nz->det_w, x, q, arith, done, s);
-  return launch_fused_toeplitz(pt, nz, x, nullptr, q, arith, done, s);
-}
-
-int rhs_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const void* tod, double* b, int arith, hipStream_t s) {
-  int rc = launch_fill(b, 3 * (int64_t)pt->n_kept, 0.0, s);
-  if (rc) return rc;
-  if (nz->kind == 0) return launch_rhs_white(pt, nz->det_w, tod, b, arith, s);
-  return launch_fused_toeplitz(pt, nz, nullptr, tod, b, arith, nullptr, s);
-}
-
-}  // namespace
 }  // namespace mm
 
 using namespace mm;
@@ -371,7 +372,22 @@ int mm_apply_A(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int3
   if (pt->n_kept && (!x || !q)) return fail(MM_EINVAL, "null vector");
   hipStream_t s = as_stream(stream);
   if (int rc = launch_fill(q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
-  return apply_A_impl(pt, nz, x, q, arith, nullptr, s);
+  return apply_A_impl(pt, nz, x, q, arith, RhsBatch{}, s);
+}
+
+int mm_apply_A_multi(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const double* x, double* q, int32_t arith,
+                     void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
+  if (!valid_dtype(arith) || n_rhs < 1) return fail(MM_EINVAL, "bad arith or n_rhs");
+  if (pt->n_kept && (!x || !q)) return fail(MM_EINVAL, "null vector");
+  hipStream_t s = as_stream(stream);
+  const int64_t n3 = 3 * (int64_t)pt->n_kept;
+  if (int rc = launch_fill(q, n3 * n_rhs, 0.0, s)) return rc;
+  RhsBatch rb;
+  rb.nrhs = n_rhs;
+  rb.vstride = n3;
+  return apply_A_impl(pt, nz, x, q, arith, rb, s);
 }
 
 int mm_rhs(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* b, int32_t arith, void* stream) {
@@ -392,242 +408,6 @@ int mm_expand_map(mm_pointing_t pt, const double* x, double* map_full, void* str
   if (int rc = check_pointing(pt)) return rc;
   if (!map_full || (pt->n_kept && !x)) return fail(MM_EINVAL, "null vector");
   return launch_expand(pt, x, map_full, as_stream(stream));
-}
-
-int mm_solve_opts_default(mm_solve_opts* o) {
-  if (!o) return fail(MM_EINVAL, "null opts");
-  o->tol = 1e-10;
-  o->max_iter = 2000;
-  o->fixed_iter = 0;
-  o->check_every = 8;
-  o->mixed = 0;
-  o->max_outer = 10;
-  o->inner_tol = 1e-5;
-  o->timing = 0;
-  o->reserved_ = 0;
-  return MM_OK;
-}
-
-namespace {
-
-struct SolveLayout {
-  PcgBufs B;
-  double* xt;   // mixed: accumulated solution
-  double* rt;   // mixed: outer residual
-  double* b64;  // mixed: FP64 right-hand side
-};
-
-size_t carve_solve(Carver& cv, int32_t n_kept, int32_t hist_len, SolveLayout* L) {
-  const size_t n3 = 3 * (size_t)n_kept;
-  L->B.x = cv.take<double>(n3);
-  L->B.r = cv.take<double>(n3);
-  L->B.z = cv.take<double>(n3);
-  L->B.p = cv.take<double>(n3);
-  L->B.q = cv.take<double>(n3);
-  L->B.b = cv.take<double>(n3);
-  L->xt = cv.take<double>(n3);
-  L->rt = cv.take<double>(n3);
-  L->b64 = cv.take<double>(n3);
-  L->B.partials = cv.take<double>(2 * kPcgBlocks);
-  L->B.st = cv.take<PcgState>(1);
-  L->B.hist = cv.take<double>(hist_len);
-  L->B.hist_len = hist_len;
-  return cv.used;
-}
-
-int32_t hist_len_for(const mm_solve_opts& o) {
-  const int32_t n = o.fixed_iter > 0 ? o.fixed_iter : o.max_iter;
-  return std::max<int32_t>(1, n + 1);
-}
-
-// HIP-event timing of PCG iterations (opts.timing).
-struct IterTimer {
-  bool on = false;
-  std::vector<hipEvent_t> ev;  // per slot: iteration start, A end; plus one closing event
-  std::vector<double> iter_ms;
-  double op_ms = 0.0;
-  int32_t op_launches = 0;
-  ~IterTimer() {
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-  }
-  int init(int32_t slots) {
-    ev.resize(2 * (size_t)slots + 1, nullptr);
-    for (auto& e : ev) MM_HIP(hipEventCreate(&e));
-    return MM_OK;
-  }
-};
-
-// Run one PCG on B.b (already in place) with operator arithmetic `arith`.
-int run_pcg(const mm_pointing_s* pt, const mm_noise_s* nz, PcgBufs& B, int arith, double tol, int32_t max_iter,
-            int32_t fixed_iter, int32_t check_every, PcgState* host_st, IterTimer* tm, hipStream_t s) {
-  if (int rc = launch_pcg_init(pt, B, tol, max_iter, fixed_iter, s)) return rc;
-  const int32_t cap = fixed_iter > 0 ? fixed_iter : max_iter;
-  int32_t issued = 0;
-  int32_t last_chunk = 0;
-  for (;;) {
-    MM_HIP(hipMemcpyAsync(host_st, B.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-    MM_HIP(hipStreamSynchronize(s));
-    if (tm && tm->on && last_chunk > 0) {
-      // iterations issued - last_chunk + i did work iff their index < host_st->iter
-      const int32_t first = issued - last_chunk;
-      for (int32_t i = 0; i < last_chunk; ++i) {
-        if (first + i >= host_st->iter) break;
-        float a = 0.f, it = 0.f;
-        MM_HIP(hipEventElapsedTime(&a, tm->ev[2 * i], tm->ev[2 * i + 1]));
-        MM_HIP(hipEventElapsedTime(&it, tm->ev[2 * i], tm->ev[2 * i + 2]));
-        tm->op_ms += a;
-        tm->op_launches += 1;
-        tm->iter_ms.push_back(it);
-      }
-    }
-    if (host_st->done || issued >= cap) break;
-    const int32_t chunk = std::min(check_every, cap - issued);
-    for (int32_t i = 0; i < chunk; ++i) {
-      if (tm && tm->on) MM_HIP(hipEventRecord(tm->ev[2 * i], s));
-      if (int rc = apply_A_impl(pt, nz, B.p, B.q, arith, &B.st->done, s)) return rc;
-      if (tm && tm->on) MM_HIP(hipEventRecord(tm->ev[2 * i + 1], s));
-      if (int rc = launch_pcg_iteration_tail(pt, B, s)) return rc;
-    }
-    if (tm && tm->on) MM_HIP(hipEventRecord(tm->ev[2 * chunk], s));
-    issued += chunk;
-    last_chunk = chunk;
-  }
-  return MM_OK;
-}
-
-double percentile(std::vector<double> v, double p) {
-  if (v.empty()) return 0.0;
-  std::sort(v.begin(), v.end());
-  const double pos = p * (double)(v.size() - 1);
-  const size_t i = (size_t)pos;
-  const double f = pos - (double)i;
-  return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
-}
-
-// ||b - A x|| / ||b|| in FP64 arithmetic; uses B.q as scratch.
-int true_residual(const mm_pointing_s* pt, const mm_noise_s* nz, PcgBufs& B, const double* b, const double* x,
-                  double* out_rel, PcgState* host_st, hipStream_t s) {
-  if (int rc = launch_fill(B.q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
-  if (int rc = apply_A_impl(pt, nz, x, B.q, MM_F64, nullptr, s)) return rc;
-  MM_HIP(hipMemsetAsync(&B.st->counter, 0, sizeof(uint32_t), s));
-  if (int rc = launch_diff_norm(pt, b, B.q, B, s)) return rc;
-  MM_HIP(hipMemcpyAsync(host_st, B.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-  MM_HIP(hipStreamSynchronize(s));
-  *out_rel = host_st->scratch1 > 0 ? std::sqrt(host_st->scratch0 / host_st->scratch1) : 0.0;
-  return MM_OK;
-}
-
-}  // namespace
-
-int mm_solve_workspace_size(mm_pointing_t pt, mm_noise_t nz, const mm_solve_opts* opts, size_t* bytes) {
-  if (int rc = check_pointing(pt)) return rc;
-  if (!nz || !bytes) return fail(MM_EINVAL, "null argument");
-  mm_solve_opts o;
-  mm_solve_opts_default(&o);
-  if (opts) o = *opts;
-  Carver cv(nullptr, 0);
-  SolveLayout L;
-  *bytes = carve_solve(cv, pt->n_kept, hist_len_for(o), &L);
-  return MM_OK;
-}
-
-int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, double* x_out,
-             const mm_solve_opts* opts, mm_solve_info* info, double* history_host, int32_t history_len,
-             void* workspace, size_t ws_bytes, void* stream) {
-  if (int rc = check_pointing(pt)) return rc;
-  if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
-  if (pt->n_samples && !tod) return fail(MM_EINVAL, "null timeline");
-  if (!workspace) return fail(MM_EINVAL, "null workspace");
-  mm_solve_opts o;
-  mm_solve_opts_default(&o);
-  if (opts) o = *opts;
-  if (!(o.tol >= 0.0) || o.max_iter < 0 || o.check_every < 1 || o.max_outer < 1 || !(o.inner_tol > 0.0))
-    return fail(MM_EINVAL, "bad solve options");
-  hipStream_t s = as_stream(stream);
-  Carver cv(workspace, ws_bytes);
-  SolveLayout L;
-  carve_solve(cv, pt->n_kept, hist_len_for(o), &L);
-  if (!cv.fits()) return fail(MM_ENOSPC, "solve workspace too small");
-  PcgBufs& B = L.B;
-  PcgState hs{};
-  mm_solve_info inf{};
-  IterTimer tm;
-  if (o.timing) {
-    tm.on = true;
-    if (int rc = tm.init(o.check_every)) return rc;
-  }
-  double true_rel = 0.0;
-  const double* xfinal = B.x;
-
-  if (pt->n_kept == 0) {
-    if (map_out) MM_HIP(hipMemsetAsync(map_out, 0, sizeof(double) * 3 * (size_t)pt->n_pix, s));
-    MM_HIP(hipStreamSynchronize(s));
-    inf.converged = 1;
-    if (info) *info = inf;
-    return MM_OK;
-  }
-
-  if (!o.mixed) {
-    if (int rc = rhs_impl(pt, nz, tod, B.b, MM_F64, s)) return rc;
-    if (int rc = run_pcg(pt, nz, B, MM_F64, o.tol, o.max_iter, o.fixed_iter, o.check_every, &hs, &tm, s))
-      return rc;
-    inf.iters = hs.iter;
-    inf.outer_iters = 1;
-    inf.converged = hs.converged;
-    inf.breakdown = hs.breakdown;
-    inf.rel_resid = hs.rel;
-    if (history_host && history_len > 0) {
-      const int32_t n = std::min(history_len, std::min(B.hist_len, hs.iter + 1));
-      MM_HIP(hipMemcpy(history_host, B.hist, sizeof(double) * n, hipMemcpyDeviceToHost));
-    }
-    if (int rc = true_residual(pt, nz, B, B.b, B.x, &true_rel, &hs, s)) return rc;
-  } else {
-    // FP64 right-hand side, then refinement: inner FP32-operator PCG on the
-    // FP64 residual, FP64 update, FP64 residual b - A x.
-    if (int rc = rhs_impl(pt, nz, tod, L.b64, MM_F64, s)) return rc;
-    if (int rc = launch_fill(L.xt, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
-    MM_HIP(hipMemcpyAsync(L.rt, L.b64, sizeof(double) * 3 * (size_t)pt->n_kept, hipMemcpyDeviceToDevice, s));
-    double rel = 1.0;
-    int32_t hist_at = 0;
-    inf.converged = 0;
-    for (int32_t outer = 1; outer <= o.max_outer; ++outer) {
-      MM_HIP(hipMemcpyAsync(B.b, L.rt, sizeof(double) * 3 * (size_t)pt->n_kept, hipMemcpyDeviceToDevice, s));
-      if (int rc = run_pcg(pt, nz, B, MM_F32, o.inner_tol, o.max_iter, 0, o.check_every, &hs, &tm, s))
-        return rc;
-      inf.iters += hs.iter;
-      inf.outer_iters = outer;
-      if (hs.breakdown) {
-        inf.breakdown = 1;
-        break;
-      }
-      if (int rc = launch_add(pt, L.xt, B.x, s)) return rc;
-      if (int rc = true_residual(pt, nz, B, L.b64, L.xt, &rel, &hs, s)) return rc;
-      if (history_host && hist_at < history_len) history_host[hist_at++] = rel;
-      if (int rc = launch_sub(pt, L.b64, B.q, L.rt, s)) return rc;
-      if (rel <= o.tol) {
-        inf.converged = 1;
-        break;
-      }
-    }
-    inf.rel_resid = rel;
-    true_rel = rel;
-    xfinal = L.xt;
-  }
-  inf.true_rel_resid = true_rel;
-  if (tm.on) {
-    inf.op_ms = tm.op_ms;
-    inf.op_launches = tm.op_launches;
-    inf.iter_ms_p50 = percentile(tm.iter_ms, 0.5);
-    inf.iter_ms_p99 = percentile(tm.iter_ms, 0.99);
-  }
-  if (map_out)
-    if (int rc = launch_expand(pt, xfinal, map_out, s)) return rc;
-  if (x_out) MM_HIP(hipMemcpyAsync(x_out, xfinal, sizeof(double) * 3 * (size_t)pt->n_kept, hipMemcpyDeviceToDevice, s));
-  MM_HIP(hipStreamSynchronize(s));
-  if (info) *info = inf;
-  if (inf.breakdown) return fail(MM_EBREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite value)");
-  if (!inf.converged && o.fixed_iter <= 0) return MM_NOTCONVERGED;
-  return MM_OK;
 }
 
 }  // extern "C"

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -144,10 +145,19 @@ int launch_apply_P(const mm_pointing_s* pt, const double* x, void* tod, int arit
 int launch_apply_PT(const mm_pointing_s* pt, const void* tod, double* q, int arith, hipStream_t s);
 int launch_ninv_white(const mm_pointing_s* pt, const double* det_w, const void* in, void* out, int arith,
                       hipStream_t s);
+// Right-hand-side batching of the fused operators: nrhs vectors at stride
+// vstride (x and q), and per right-hand side a "done" flag at done[r *
+// done_stride] (null: never done); a right-hand side whose flag is set is
+// skipped.
+struct RhsBatch {
+  int32_t nrhs = 1;
+  int64_t vstride = 0;
+  const int32_t* done = nullptr;
+  int32_t done_stride = 0;
+};
 // q += P^T diag(w) P x (q must hold the accumulation start, usually 0).
-// `done` may be null; when it points to a nonzero int the kernel does nothing.
 int launch_fused_white(const mm_pointing_s* pt, const double* det_w, const double* x, double* q, int arith,
-                       const int32_t* done, hipStream_t s);
+                       const RhsBatch& rb, hipStream_t s);
 // q += P^T diag(w) tod
 int launch_rhs_white(const mm_pointing_s* pt, const double* det_w, const void* tod, double* q, int arith,
                      hipStream_t s);
@@ -156,9 +166,16 @@ int launch_rhs_white(const mm_pointing_s* pt, const double* det_w, const void* t
 int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
                          hipStream_t s);
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
-                          double* q, int arith, const int32_t* done, hipStream_t s);
+                          double* q, int arith, const RhsBatch& rb, hipStream_t s);
 int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, size_t ws_bytes,
                             hipStream_t s, size_t* bytes_needed);
+
+// operator helpers shared by the C entry points and the solver
+int apply_A_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, double* q, int arith,
+                 const RhsBatch& rb, hipStream_t s);
+int rhs_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const void* tod, double* b, int arith, hipStream_t s);
+int check_pointing(mm_pointing_t pt);
+int check_noise_vs_pointing(const mm_noise_s* nz, const mm_pointing_s* pt);
 
 // pixel domain
 int launch_apply_M(const mm_pointing_s* pt, const double* r, double* z, hipStream_t s);
@@ -186,22 +203,55 @@ struct PcgState {
 };
 constexpr int kPcgBlocks = 512;   // fixed grid of the vector kernels (deterministic sums)
 constexpr int kPcgThreads = 256;
+constexpr int32_t kPcgDoneStride = (int32_t)(sizeof(PcgState) / sizeof(int32_t));
 
-struct PcgBufs {
-  double *x, *r, *z, *p, *q, *b;
-  double* partials;   // [2 * kPcgBlocks]
-  PcgState* st;
-  double* hist;       // [hist_len]
+// Vectors of nrhs right-hand sides at stride vstride; state/partials/history
+// per right-hand side (kernels use blockIdx.y as the right-hand-side index).
+struct PcgArgs {
+  double *x, *r, *z, *p, *q;
+  const double* b;
+  double* partials;  // [nrhs][2 * kPcgBlocks]
+  PcgState* st;      // [nrhs]
+  double* hist;      // [nrhs][hist_len]
+  int64_t vstride;
+  int32_t n_kept;
   int32_t hist_len;
 };
-int launch_pcg_init(const mm_pointing_s* pt, PcgBufs& B, double tol, int32_t max_iter, int32_t fixed_iter,
-                    hipStream_t s);
-int launch_pcg_iteration_tail(const mm_pointing_s* pt, PcgBufs& B, hipStream_t s);
-// out_norm2[0] = ||a - b||^2, out_norm2[1] = ||a||^2 (into st->scratch0/1)
-int launch_diff_norm(const mm_pointing_s* pt, const double* a, const double* b, PcgBufs& B, hipStream_t s);
-// y = a - b
-int launch_sub(const mm_pointing_s* pt, const double* a, const double* b, double* y, hipStream_t s);
-// y += a
-int launch_add(const mm_pointing_s* pt, double* y, const double* a, hipStream_t s);
+
+// Outer FP64 refinement state per right-hand side.
+struct OuterState {
+  double bnorm;
+  double rel;
+  int32_t iters;        // outer steps taken
+  int32_t inner_total;  // inner PCG iterations of finished inner solves
+  int32_t converged;
+  int32_t done;
+  int32_t skip;         // 1: no outer step pending for this right-hand side
+  int32_t breakdown;
+  uint32_t counter;
+  int32_t pad_;
+};
+constexpr int32_t kOuterSkipOffset = (int32_t)(offsetof(OuterState, skip) / sizeof(int32_t));
+constexpr int32_t kOuterStride = (int32_t)(sizeof(OuterState) / sizeof(int32_t));
+
+struct OuterArgs {
+  double *xt, *rt;
+  const double* b64;
+  double* partials;  // [nrhs][2 * kPcgBlocks]
+  OuterState* os;    // [nrhs]
+  double* hist;      // [nrhs][hist_len]
+  int64_t vstride;
+  int32_t hist_len;
+  int32_t pad_;
+};
+
+int launch_pcg_init(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, double tol, int32_t max_iter,
+                    int32_t fixed_iter, const OuterState* gate, hipStream_t s);
+int launch_pcg_iteration_tail(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, hipStream_t s);
+// per right-hand side: st->scratch0 = ||x - y||^2, st->scratch1 = ||x||^2
+int launch_diff_norm(const PcgArgs& a, int nrhs, const double* x, const double* y, hipStream_t s);
+int launch_outer_init(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s);
+int launch_outer_add(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s);
+int launch_outer_end(const OuterArgs& o, const PcgArgs& a, int nrhs, double tol, int32_t max_outer, hipStream_t s);
 
 }  // namespace mm

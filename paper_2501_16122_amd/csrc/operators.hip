@@ -103,14 +103,17 @@ __global__ __launch_bounds__(kOpThreads) void k_bin_tod(const PtTile* __restrict
 }
 
 // q += P^T diag(w) P x: the timeline value never leaves registers.
+// blockIdx.y selects the right-hand side.
 template <class S, class C>
 __global__ __launch_bounds__(kOpThreads) void k_fused_white(const PtTile* __restrict__ tiles,
                                                             const int32_t* __restrict__ sample_k,
                                                             const S* __restrict__ psi,
                                                             const double* __restrict__ det_w,
                                                             const double* __restrict__ x, double* __restrict__ q,
-                                                            const int32_t* __restrict__ done) {
-  if (done != nullptr && *done) return;
+                                                            RhsBatch rb) {
+  if (rb.done != nullptr && rb.done[(int64_t)blockIdx.y * rb.done_stride]) return;
+  x += blockIdx.y * rb.vstride;
+  q += blockIdx.y * rb.vstride;
   __shared__ double bins[3 * kBinSlots];
   const PtTile tl = tiles[blockIdx.x];
   if (tl.kmax < tl.kmin) return;
@@ -244,23 +247,23 @@ int launch_rhs_white(const mm_pointing_s* pt, const double* det_w, const void* t
 }
 
 int launch_fused_white(const mm_pointing_s* pt, const double* det_w, const double* x, double* q, int arith,
-                       const int32_t* done, hipStream_t s) {
+                       const RhsBatch& rb, hipStream_t s) {
   if (pt->n_tiles == 0) return MM_OK;
-  const dim3 g(pt->n_tiles), b(kOpThreads);
+  const dim3 g(pt->n_tiles, rb.nrhs), b(kOpThreads);
   if (pt->dtype == MM_F64) {
     if (arith == MM_F64)
       hipLaunchKernelGGL((k_fused_white<double, double>), g, b, 0, s, pt->tiles, pt->sample_k,
-                         (const double*)pt->psi, det_w, x, q, done);
+                         (const double*)pt->psi, det_w, x, q, rb);
     else
       hipLaunchKernelGGL((k_fused_white<double, float>), g, b, 0, s, pt->tiles, pt->sample_k,
-                         (const double*)pt->psi, det_w, x, q, done);
+                         (const double*)pt->psi, det_w, x, q, rb);
   } else {
     if (arith == MM_F64)
       hipLaunchKernelGGL((k_fused_white<float, double>), g, b, 0, s, pt->tiles, pt->sample_k,
-                         (const float*)pt->psi, det_w, x, q, done);
+                         (const float*)pt->psi, det_w, x, q, rb);
     else
       hipLaunchKernelGGL((k_fused_white<float, float>), g, b, 0, s, pt->tiles, pt->sample_k,
-                         (const float*)pt->psi, det_w, x, q, done);
+                         (const float*)pt->psi, det_w, x, q, rb);
   }
   MM_HIP(hipGetLastError());
   return MM_OK;

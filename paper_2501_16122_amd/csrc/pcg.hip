@@ -1,13 +1,17 @@
 // Pixel-domain steps of preconditioned conjugate gradient (Sec. II; the
 // textbook iteration, Saad, "Iterative Methods for Sparse Linear Systems",
-// Alg. 9.1) with the block-Jacobi M of eq. (7).
+// Alg. 9.1) with the block-Jacobi M of eq. (7), and the outer FP64
+// refinement around an FP32-operator PCG.
 //
-// Scalars (rho, alpha, beta, ||b||, the iteration count and a "done" flag)
-// live in device memory, so a chunk of iterations is enqueued without host
-// round trips; every kernel returns at once when "done" is set.  Dot products
-// are deterministic: a fixed grid of kPcgBlocks blocks with a fixed pixel
-// assignment writes per-block partials, and the last block to finish (an
-// atomic ticket) sums them in a fixed order.
+// Every kernel runs one y-slice (blockIdx.y) per right-hand side; slice r
+// uses the vectors at offset r * vstride, state st[r], partials
+// [r * 2 * kPcgBlocks, ...) and history [r * hist_len, ...).  Scalars (rho,
+// alpha, beta, ||b||, the iteration count, a "done" flag) live in device
+// memory, so chunks of iterations are enqueued without host round trips and
+// every kernel of a slice returns at once when that slice is done.  Dot
+// products are deterministic: a fixed grid of kPcgBlocks blocks with a fixed
+// pixel assignment writes per-block partials and the last block to finish
+// (an atomic ticket) sums them in a fixed order.
 #include "mm_internal.h"
 
 namespace mm {
@@ -39,7 +43,7 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
 }
 
 // Write this block's two partials; returns true in every thread of the last
-// block, whose thread 0 then holds the grid totals in (a, b).
+// block of the slice, whose thread 0 then holds the slice totals in (a, b).
 __device__ bool grid_sum2(double& a, double& b, double* partials, uint32_t* counter, double* sh, bool* s_last) {
   block_sum2(a, b, sh);
   if (threadIdx.x == 0) {
@@ -74,30 +78,46 @@ __device__ __forceinline__ void apply_m3(const double* __restrict__ m, double r0
   z2 = m[2] * r0 + m[4] * r1 + m[5] * r2;
 }
 
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_init(int32_t n_kept, const double* __restrict__ minv,
-                                                          const double* __restrict__ b, double* __restrict__ x,
-                                                          double* __restrict__ r, double* __restrict__ z,
-                                                          double* __restrict__ p, double* __restrict__ q,
-                                                          double* __restrict__ partials, PcgState* st,
-                                                          double* __restrict__ hist, int32_t hist_len, double tol,
-                                                          int32_t max_iter, int32_t fixed_iter) {
+struct Slice {
+  double *x, *r, *z, *p, *q;
+  const double* b;
+  double* partials;
+  PcgState* st;
+  double* hist;
+};
+
+__device__ __forceinline__ Slice slice(const PcgArgs& a) {
+  const int64_t o = (int64_t)blockIdx.y * a.vstride;
+  return Slice{a.x + o, a.r + o, a.z + o, a.p + o, a.q + o, a.b + o,
+               a.partials + (int64_t)blockIdx.y * 2 * kPcgBlocks, a.st + blockIdx.y,
+               a.hist + (int64_t)blockIdx.y * a.hist_len};
+}
+
+// x = 0, r = b, z = M r, p = z, q = 0, rho = r.z, ||b||.  Skipped for a
+// slice whose gate (outer "done" flag) is set.
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_init(PcgArgs a, const double* __restrict__ minv, double tol,
+                                                          int32_t max_iter, int32_t fixed_iter,
+                                                          const OuterState* gate) {
+  if (gate != nullptr && (gate[blockIdx.y].done || gate[blockIdx.y].skip)) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
+  Slice S = slice(a);
   double bb = 0.0, rz = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_kept; k += (int64_t)gridDim.x * blockDim.x) {
-    const double b0 = b[3 * k], b1 = b[3 * k + 1], b2 = b[3 * k + 2];
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
+    const double b0 = S.b[3 * k], b1 = S.b[3 * k + 1], b2 = S.b[3 * k + 2];
     double z0, z1, z2;
     apply_m3(minv + 6 * k, b0, b1, b2, z0, z1, z2);
-    x[3 * k] = 0.0; x[3 * k + 1] = 0.0; x[3 * k + 2] = 0.0;
-    r[3 * k] = b0; r[3 * k + 1] = b1; r[3 * k + 2] = b2;
-    z[3 * k] = z0; z[3 * k + 1] = z1; z[3 * k + 2] = z2;
-    p[3 * k] = z0; p[3 * k + 1] = z1; p[3 * k + 2] = z2;
-    q[3 * k] = 0.0; q[3 * k + 1] = 0.0; q[3 * k + 2] = 0.0;
+    S.x[3 * k] = 0.0; S.x[3 * k + 1] = 0.0; S.x[3 * k + 2] = 0.0;
+    S.r[3 * k] = b0; S.r[3 * k + 1] = b1; S.r[3 * k + 2] = b2;
+    S.z[3 * k] = z0; S.z[3 * k + 1] = z1; S.z[3 * k + 2] = z2;
+    S.p[3 * k] = z0; S.p[3 * k + 1] = z1; S.p[3 * k + 2] = z2;
+    S.q[3 * k] = 0.0; S.q[3 * k + 1] = 0.0; S.q[3 * k + 2] = 0.0;
     bb += b0 * b0 + b1 * b1 + b2 * b2;
     rz += b0 * z0 + b1 * z1 + b2 * z2;
   }
-  if (!grid_sum2(bb, rz, partials, &st->counter, sh, &s_last)) return;
+  if (!grid_sum2(bb, rz, S.partials, &S.st->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
+    PcgState* st = S.st;
     const double bnorm = sqrt(bb);
     const double rel = bnorm > 0.0 ? 1.0 : 0.0;
     st->rho = rz;
@@ -113,64 +133,59 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_init(int32_t n_kept, const 
     const bool met = rel <= tol;
     st->converged = met ? 1 : 0;
     st->done = (bnorm == 0.0 || (fixed_iter <= 0 && met) || (fixed_iter <= 0 && max_iter <= 0)) ? 1 : 0;
-    if (fixed_iter > 0 && bnorm == 0.0) st->done = 1;
-    if (hist_len > 0) hist[0] = rel;
+    if (a.hist_len > 0) S.hist[0] = rel;
   }
 }
 
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_alpha(int32_t n_kept, const double* __restrict__ p,
-                                                           const double* __restrict__ q,
-                                                           double* __restrict__ partials, PcgState* st) {
-  if (st->done) return;
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_alpha(PcgArgs a) {
+  Slice S = slice(a);
+  if (S.st->done) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   double pq = 0.0, unused = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)a.n_kept;
        i += (int64_t)gridDim.x * blockDim.x)
-    pq += p[i] * q[i];
-  if (!grid_sum2(pq, unused, partials, &st->counter, sh, &s_last)) return;
+    pq += S.p[i] * S.q[i];
+  if (!grid_sum2(pq, unused, S.partials, &S.st->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
     if (!(pq > 0.0) || isinf(pq)) {
-      st->breakdown = 1;
-      st->done = 1;
+      S.st->breakdown = 1;
+      S.st->done = 1;
     } else {
-      st->alpha = st->rho / pq;
+      S.st->alpha = S.st->rho / pq;
     }
   }
 }
 
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_update(int32_t n_kept, const double* __restrict__ minv,
-                                                            double* __restrict__ x, double* __restrict__ r,
-                                                            double* __restrict__ z, const double* __restrict__ p,
-                                                            const double* __restrict__ q,
-                                                            double* __restrict__ partials, PcgState* st,
-                                                            double* __restrict__ hist, int32_t hist_len) {
-  if (st->done) return;
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_update(PcgArgs a, const double* __restrict__ minv) {
+  Slice S = slice(a);
+  if (S.st->done) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
-  const double alpha = st->alpha;
+  const double alpha = S.st->alpha;
   double rr = 0.0, rz = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_kept; k += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
     double rv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      x[3 * k + c] += alpha * p[3 * k + c];
-      rv[c] = r[3 * k + c] - alpha * q[3 * k + c];
-      r[3 * k + c] = rv[c];
+      S.x[3 * k + c] += alpha * S.p[3 * k + c];
+      rv[c] = S.r[3 * k + c] - alpha * S.q[3 * k + c];
+      S.r[3 * k + c] = rv[c];
     }
     double z0, z1, z2;
     apply_m3(minv + 6 * k, rv[0], rv[1], rv[2], z0, z1, z2);
-    z[3 * k] = z0; z[3 * k + 1] = z1; z[3 * k + 2] = z2;
+    S.z[3 * k] = z0; S.z[3 * k + 1] = z1; S.z[3 * k + 2] = z2;
     rr += rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
     rz += rv[0] * z0 + rv[1] * z1 + rv[2] * z2;
   }
-  if (!grid_sum2(rr, rz, partials, &st->counter, sh, &s_last)) return;
+  if (!grid_sum2(rr, rz, S.partials, &S.st->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
+    PcgState* st = S.st;
     const int it = st->iter + 1;
     st->iter = it;
     const double rel = sqrt(rr) / st->bnorm;
     st->rel = rel;
-    if (it < hist_len) hist[it] = rel;
+    if (it < a.hist_len) S.hist[it] = rel;
     if (!isfinite(rel)) {
       st->breakdown = 1;
       st->done = 1;
@@ -190,82 +205,164 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_update(int32_t n_kept, cons
   }
 }
 
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_direction(int32_t n_kept, const double* __restrict__ z,
-                                                               double* __restrict__ p, double* __restrict__ q,
-                                                               const PcgState* st) {
-  if (st->done) return;
-  const double beta = st->beta;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)n_kept;
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_direction(PcgArgs a) {
+  Slice S = slice(a);
+  if (S.st->done) return;
+  const double beta = S.st->beta;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)a.n_kept;
        i += (int64_t)gridDim.x * blockDim.x) {
-    p[i] = z[i] + beta * p[i];
-    q[i] = 0.0;
+    S.p[i] = S.z[i] + beta * S.p[i];
+    S.q[i] = 0.0;
   }
 }
 
-// scratch0 = ||a - b||^2, scratch1 = ||a||^2
-__global__ __launch_bounds__(kPcgThreads) void k_diff_norm(int64_t n, const double* __restrict__ a,
-                                                           const double* __restrict__ b,
-                                                           double* __restrict__ partials, PcgState* st) {
+// ---- outer FP64 refinement (per slice) ------------------------------------
+// init: xt = 0, rt = b64, ||b64||; the inner state starts "done" so that
+// nothing runs for a slice until its first inner solve is initialised.
+__global__ __launch_bounds__(kPcgThreads) void k_outer_init(OuterArgs o, PcgArgs a) {
   __shared__ double sh[16];
   __shared__ bool s_last;
-  double dd = 0.0, aa = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double d = a[i] - b[i];
-    dd += d * d;
-    aa += a[i] * a[i];
+  const int64_t off = (int64_t)blockIdx.y * o.vstride;
+  const int64_t n3 = 3 * (int64_t)a.n_kept;
+  OuterState* os = o.os + blockIdx.y;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.st[blockIdx.y].done = 1;
+    a.st[blockIdx.y].iter = 0;
+    a.st[blockIdx.y].breakdown = 0;
   }
-  if (!grid_sum2(dd, aa, partials, &st->counter, sh, &s_last)) return;
+  double bb = 0.0, unused = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = o.b64[off + i];
+    o.xt[off + i] = 0.0;
+    o.rt[off + i] = v;
+    bb += v * v;
+  }
+  if (!grid_sum2(bb, unused, o.partials + (int64_t)blockIdx.y * 2 * kPcgBlocks, &os->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
-    st->scratch0 = dd;
-    st->scratch1 = aa;
+    os->bnorm = sqrt(bb);
+    os->rel = os->bnorm > 0.0 ? 1.0 : 0.0;
+    os->iters = 0;
+    os->inner_total = 0;
+    os->converged = os->bnorm == 0.0 ? 1 : 0;
+    os->done = os->bnorm == 0.0 ? 1 : 0;
+    os->skip = 0;  // the first inner solve may start
+    os->breakdown = 0;
   }
 }
 
-__global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = a[i] - b[i];
+// A slice whose inner solve has ended and whose outer loop is still open
+// takes an outer step: xt += x; q := 0 (A64 xt accumulates into q next).
+__global__ __launch_bounds__(kPcgThreads) void k_outer_add(OuterArgs o, PcgArgs a) {
+  const int64_t off = (int64_t)blockIdx.y * o.vstride;
+  OuterState* os = o.os + blockIdx.y;
+  const PcgState* st = a.st + blockIdx.y;
+  const bool act = st->done && !os->done;
+  if (!act) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) os->skip = 1;
+    return;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)a.n_kept;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    o.xt[off + i] += a.x[off + i];
+    a.q[off + i] = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    os->skip = 0;
+    os->inner_total += st->iter;
+    if (st->breakdown) os->breakdown = 1;
+  }
 }
 
-__global__ void k_add(int64_t n, double* __restrict__ y, const double* __restrict__ a) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] += a[i];
+// rt = b64 - q (q = A64 xt), ||rt|| / ||b64||, the outer stopping test.
+__global__ __launch_bounds__(kPcgThreads) void k_outer_end(OuterArgs o, PcgArgs a, double tol, int32_t max_outer) {
+  OuterState* os = o.os + blockIdx.y;
+  if (os->skip) return;
+  __shared__ double sh[16];
+  __shared__ bool s_last;
+  const int64_t off = (int64_t)blockIdx.y * o.vstride;
+  double rr = 0.0, unused = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)a.n_kept;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = o.b64[off + i] - a.q[off + i];
+    o.rt[off + i] = v;
+    rr += v * v;
+  }
+  if (!grid_sum2(rr, unused, o.partials + (int64_t)blockIdx.y * 2 * kPcgBlocks, &os->counter, sh, &s_last)) return;
+  if (threadIdx.x == 0) {
+    const int it = os->iters + 1;
+    os->iters = it;
+    const double rel = sqrt(rr) / os->bnorm;
+    os->rel = rel;
+    if (it < o.hist_len) o.hist[(int64_t)blockIdx.y * o.hist_len + it] = rel;
+    if (rel <= tol) {
+      os->converged = 1;
+      os->done = 1;
+    } else if (it >= max_outer || os->breakdown || !isfinite(rel)) {
+      os->done = 1;
+    }
+  }
+}
+
+// scratch0 = ||a - b||^2, scratch1 = ||a||^2 per slice
+__global__ __launch_bounds__(kPcgThreads) void k_diff_norm(PcgArgs A, const double* __restrict__ a,
+                                                           const double* __restrict__ b) {
+  __shared__ double sh[16];
+  __shared__ bool s_last;
+  Slice S = slice(A);
+  const int64_t off = (int64_t)blockIdx.y * A.vstride;
+  double dd = 0.0, aa = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)A.n_kept;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = a[off + i] - b[off + i];
+    dd += d * d;
+    aa += a[off + i] * a[off + i];
+  }
+  if (!grid_sum2(dd, aa, S.partials, &S.st->counter, sh, &s_last)) return;
+  if (threadIdx.x == 0) {
+    S.st->scratch0 = dd;
+    S.st->scratch1 = aa;
+  }
 }
 
 }  // namespace
 
-int launch_pcg_init(const mm_pointing_s* pt, PcgBufs& B, double tol, int32_t max_iter, int32_t fixed_iter,
-                    hipStream_t s) {
-  MM_HIP(hipMemsetAsync(&B.st->counter, 0, sizeof(uint32_t), s));
-  hipLaunchKernelGGL(k_pcg_init, dim3(kPcgBlocks), dim3(kPcgThreads), 0, s, pt->n_kept, pt->minv, B.b, B.x, B.r, B.z,
-                     B.p, B.q, B.partials, B.st, B.hist, B.hist_len, tol, max_iter, fixed_iter);
+int launch_pcg_init(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, double tol, int32_t max_iter,
+                    int32_t fixed_iter, const OuterState* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a, pt->minv, tol, max_iter,
+                     fixed_iter, gate);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
-int launch_pcg_iteration_tail(const mm_pointing_s* pt, PcgBufs& B, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(kPcgBlocks), dim3(kPcgThreads), 0, s, pt->n_kept, B.p, B.q, B.partials, B.st);
-  hipLaunchKernelGGL(k_pcg_update, dim3(kPcgBlocks), dim3(kPcgThreads), 0, s, pt->n_kept, pt->minv, B.x, B.r, B.z,
-                     B.p, B.q, B.partials, B.st, B.hist, B.hist_len);
-  hipLaunchKernelGGL(k_pcg_direction, dim3(kPcgBlocks), dim3(kPcgThreads), 0, s, pt->n_kept, B.z, B.p, B.q, B.st);
+int launch_pcg_iteration_tail(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a);
+  hipLaunchKernelGGL(k_pcg_update, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a, pt->minv);
+  hipLaunchKernelGGL(k_pcg_direction, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
-int launch_diff_norm(const mm_pointing_s* pt, const double* a, const double* b, PcgBufs& B, hipStream_t s) {
-  hipLaunchKernelGGL(k_diff_norm, dim3(kPcgBlocks), dim3(kPcgThreads), 0, s, 3 * (int64_t)pt->n_kept, a, b,
-                     B.partials, B.st);
+int launch_diff_norm(const PcgArgs& a, int nrhs, const double* x, const double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_diff_norm, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a, x, y);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
-int launch_sub(const mm_pointing_s* pt, const double* a, const double* b, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub, dim3(kPcgBlocks), dim3(kPcgThreads), 0, s, 3 * (int64_t)pt->n_kept, a, b, y);
+int launch_outer_init(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_init, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, o, a);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
-int launch_add(const mm_pointing_s* pt, double* y, const double* a, hipStream_t s) {
-  hipLaunchKernelGGL(k_add, dim3(kPcgBlocks), dim3(kPcgThreads), 0, s, 3 * (int64_t)pt->n_kept, y, a);
+int launch_outer_add(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_add, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, o, a);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_outer_end(const OuterArgs& o, const PcgArgs& a, int nrhs, double tol, int32_t max_outer,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_end, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, o, a, tol, max_outer);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }

@@ -1,0 +1,435 @@
+// Resumable PCG solver (Sec. II) for one or several right-hand sides that
+// share a pointing and a noise model, with optional FP32-operator inner
+// solves under FP64 iterative refinement; mm_solve is its blocking form.
+//
+// The whole state machine runs on the device: a step enqueues (when the last
+// poll saw a finished inner solve) one outer refinement step -- x += dx,
+// r = b - A64 x, the outer stopping test, a gated re-initialisation of the
+// inner PCG -- then k inner iterations whose kernels return at once for a
+// right-hand side that is done, then an asynchronous copy of the per-RHS
+// state to pinned host memory.  Polling only queries an event, so a serving
+// loop can keep many solvers in flight on their own streams.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "mm_internal.h"
+
+using namespace mm;
+
+namespace {
+
+double percentile(std::vector<double> v, double p) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double pos = p * (double)(v.size() - 1);
+  const size_t i = (size_t)pos;
+  const double f = pos - (double)i;
+  return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+}
+
+struct Layout {
+  PcgArgs A;
+  OuterArgs O;
+  double* b64;
+  double* b;
+};
+
+int32_t inner_hist_len(const mm_solve_opts& o) { return std::max<int32_t>(1, (o.fixed_iter > 0 ? o.fixed_iter : o.max_iter) + 1); }
+int32_t outer_hist_len(const mm_solve_opts& o) { return std::max<int32_t>(1, o.max_outer + 1); }
+
+size_t carve(Carver& cv, int32_t n_kept, int32_t nrhs, const mm_solve_opts& o, Layout* L) {
+  const size_t n3 = 3 * (size_t)n_kept, nv = n3 * nrhs;
+  PcgArgs& A = L->A;
+  A.x = cv.take<double>(nv);
+  A.r = cv.take<double>(nv);
+  A.z = cv.take<double>(nv);
+  A.p = cv.take<double>(nv);
+  A.q = cv.take<double>(nv);
+  L->b = cv.take<double>(nv);
+  A.partials = cv.take<double>(2 * (size_t)kPcgBlocks * nrhs);
+  A.st = cv.take<PcgState>(nrhs);
+  A.hist_len = inner_hist_len(o);
+  A.hist = cv.take<double>((size_t)A.hist_len * nrhs);
+  A.vstride = (int64_t)n3;
+  A.n_kept = n_kept;
+  A.b = L->b;
+  OuterArgs& O = L->O;
+  O.xt = cv.take<double>(nv);
+  O.rt = cv.take<double>(nv);
+  L->b64 = cv.take<double>(nv);
+  O.b64 = L->b64;
+  O.partials = cv.take<double>(2 * (size_t)kPcgBlocks * nrhs);
+  O.os = cv.take<OuterState>(nrhs);
+  O.hist_len = outer_hist_len(o);
+  O.hist = cv.take<double>((size_t)O.hist_len * nrhs);
+  O.vstride = (int64_t)n3;
+  O.pad_ = 0;
+  return cv.used;
+}
+
+int check_opts(const mm_solve_opts& o) {
+  if (!(o.tol >= 0.0) || o.max_iter < 0 || o.check_every < 1 || o.max_outer < 1 || !(o.inner_tol > 0.0))
+    return fail(MM_EINVAL, "bad solve options");
+  if (o.mixed && o.fixed_iter > 0) return fail(MM_EINVAL, "fixed_iter is not available with mixed precision");
+  return MM_OK;
+}
+
+}  // namespace
+
+struct mm_solver_s {
+  const mm_pointing_s* pt = nullptr;
+  const mm_noise_s* nz = nullptr;
+  mm_solve_opts o{};
+  hipStream_t s = nullptr;
+  int32_t nrhs = 1;
+  int64_t n3 = 0;
+  Layout L{};
+  bool mixed = false;
+  bool outer_pending = false;  // the last poll saw a finished inner solve
+  bool step_pending = false;   // a state copy is in flight
+  hipEvent_t ev = nullptr;
+  PcgState* h_st = nullptr;    // pinned mirrors
+  OuterState* h_os = nullptr;
+  std::vector<PcgState> st;    // last known
+  std::vector<OuterState> os;
+  // optional timing of iterations and of the A kernel
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  int32_t tev_used = 0;
+  int64_t work_seen = 0;
+  std::vector<double> iter_ms;
+  double op_ms = 0.0;
+  int32_t op_launches = 0;
+
+  ~mm_solver_s() {
+    if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t e : tev) (void)hipEventDestroy(e);
+    if (h_st) (void)hipHostFree(h_st);
+    if (h_os) (void)hipHostFree(h_os);
+  }
+
+  int64_t work_total() const {
+    // inner iterations that did work, summed over right-hand sides
+    int64_t w = 0;
+    for (int r = 0; r < nrhs; ++r) w += mixed ? (int64_t)os[r].inner_total + st[r].iter : st[r].iter;
+    return w;
+  }
+
+  bool all_done() const {
+    for (int r = 0; r < nrhs; ++r)
+      if (!(mixed ? os[r].done : st[r].done)) return false;
+    return true;
+  }
+
+  int step(int32_t k) {
+    if (mixed && outer_pending) {
+      // outer step for every right-hand side whose inner solve has ended
+      if (int rc = launch_outer_add(L.O, L.A, nrhs, s)) return rc;
+      RhsBatch rb;
+      rb.nrhs = nrhs;
+      rb.vstride = n3;
+      rb.done = &L.O.os[0].skip;
+      rb.done_stride = kOuterStride;
+      if (int rc = apply_A_impl(pt, nz, L.O.xt, L.A.q, MM_F64, rb, s)) return rc;
+      if (int rc = launch_outer_end(L.O, L.A, nrhs, o.tol, o.max_outer, s)) return rc;
+      if (int rc = launch_pcg_init(pt, L.A, nrhs, o.inner_tol, o.max_iter, 0, L.O.os, s)) return rc;
+      outer_pending = false;
+    }
+    RhsBatch rb;
+    rb.nrhs = nrhs;
+    rb.vstride = n3;
+    rb.done = &L.A.st[0].done;
+    rb.done_stride = kPcgDoneStride;
+    const int arith = mixed ? MM_F32 : MM_F64;
+    if (timing && (int32_t)tev.size() < 2 * k + 1) {
+      for (hipEvent_t e : tev) (void)hipEventDestroy(e);
+      tev.assign(2 * (size_t)k + 1, nullptr);
+      for (auto& e : tev) MM_HIP(hipEventCreate(&e));
+    }
+    for (int32_t i = 0; i < k; ++i) {
+      if (timing) MM_HIP(hipEventRecord(tev[2 * i], s));
+      if (int rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s)) return rc;
+      if (timing) MM_HIP(hipEventRecord(tev[2 * i + 1], s));
+      if (int rc = launch_pcg_iteration_tail(pt, L.A, nrhs, s)) return rc;
+    }
+    if (timing) MM_HIP(hipEventRecord(tev[2 * k], s));
+    tev_used = timing ? k : 0;
+    MM_HIP(hipMemcpyAsync(h_st, L.A.st, sizeof(PcgState) * nrhs, hipMemcpyDeviceToHost, s));
+    if (mixed) MM_HIP(hipMemcpyAsync(h_os, L.O.os, sizeof(OuterState) * nrhs, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipEventRecord(ev, s));
+    step_pending = true;
+    return MM_OK;
+  }
+
+  int poll(int32_t* done) {
+    if (step_pending) {
+      const hipError_t q = hipEventQuery(ev);
+      if (q == hipErrorNotReady) {
+        *done = 0;
+        return MM_OK;
+      }
+      if (q != hipSuccess) return hip_fail(q, "solver event");
+      std::copy(h_st, h_st + nrhs, st.begin());
+      if (mixed) std::copy(h_os, h_os + nrhs, os.begin());
+      step_pending = false;
+      if (timing && tev_used > 0) {
+        // the first (work - work_seen) iterations of the last step did work
+        const int64_t w = work_total() - work_seen;
+        for (int32_t i = 0; i < tev_used && i < w; ++i) {
+          float a = 0.f, it = 0.f;
+          MM_HIP(hipEventElapsedTime(&a, tev[2 * i], tev[2 * i + 1]));
+          MM_HIP(hipEventElapsedTime(&it, tev[2 * i], tev[2 * i + 2]));
+          op_ms += a;
+          op_launches += 1;
+          iter_ms.push_back(it);
+        }
+        work_seen = work_total();
+        tev_used = 0;
+      }
+      if (mixed) {
+        for (int r = 0; r < nrhs; ++r)
+          if (st[r].done && !os[r].done) outer_pending = true;
+      }
+    }
+    *done = all_done() ? 1 : 0;
+    return MM_OK;
+  }
+
+  void fill_info(int r, mm_solve_info* inf) const {
+    *inf = mm_solve_info{};
+    if (mixed) {
+      inf->iters = os[r].inner_total;
+      inf->outer_iters = os[r].iters;
+      inf->converged = os[r].converged;
+      inf->breakdown = os[r].breakdown;
+      inf->rel_resid = os[r].rel;
+      inf->true_rel_resid = os[r].rel;
+    } else {
+      inf->iters = st[r].iter;
+      inf->outer_iters = 1;
+      inf->converged = st[r].converged;
+      inf->breakdown = st[r].breakdown;
+      inf->rel_resid = st[r].rel;
+    }
+    if (timing) {
+      inf->op_ms = op_ms;
+      inf->op_launches = op_launches;
+      inf->iter_ms_p50 = percentile(iter_ms, 0.5);
+      inf->iter_ms_p99 = percentile(iter_ms, 0.99);
+    }
+  }
+};
+
+extern "C" {
+
+int mm_solve_opts_default(mm_solve_opts* o) {
+  if (!o) return fail(MM_EINVAL, "null opts");
+  o->tol = 1e-10;
+  o->max_iter = 2000;
+  o->fixed_iter = 0;
+  o->check_every = 8;
+  o->mixed = 0;
+  o->max_outer = 10;
+  o->inner_tol = 1e-5;
+  o->timing = 0;
+  o->reserved_ = 0;
+  return MM_OK;
+}
+
+int mm_solver_workspace_size(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const mm_solve_opts* opts,
+                             size_t* bytes) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (!nz || !bytes || n_rhs < 1) return fail(MM_EINVAL, "bad solver workspace query");
+  mm_solve_opts o;
+  mm_solve_opts_default(&o);
+  if (opts) o = *opts;
+  Carver cv(nullptr, 0);
+  Layout L;
+  *bytes = carve(cv, pt->n_kept, n_rhs, o, &L);
+  return MM_OK;
+}
+
+int mm_solve_workspace_size(mm_pointing_t pt, mm_noise_t nz, const mm_solve_opts* opts, size_t* bytes) {
+  return mm_solver_workspace_size(pt, nz, 1, opts, bytes);
+}
+
+int mm_solver_create(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const void* tod, const mm_solve_opts* opts,
+                     void* workspace, size_t ws_bytes, void* stream, mm_solver_t* out) {
+  if (!out) return fail(MM_EINVAL, "null output handle pointer");
+  *out = nullptr;
+  if (int rc = check_pointing(pt)) return rc;
+  if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
+  if (n_rhs < 1) return fail(MM_EINVAL, "n_rhs must be >= 1");
+  if (pt->n_samples && !tod) return fail(MM_EINVAL, "null timeline");
+  if (!workspace) return fail(MM_EINVAL, "null workspace");
+  if (pt->n_kept == 0) return fail(MM_EINVAL, "no kept pixels to solve for");
+  mm_solve_opts o;
+  mm_solve_opts_default(&o);
+  if (opts) o = *opts;
+  if (int rc = check_opts(o)) return rc;
+  auto* sv = new (std::nothrow) mm_solver_s();
+  if (!sv) return fail(MM_EINVAL, "out of host memory");
+  sv->pt = pt;
+  sv->nz = nz;
+  sv->o = o;
+  sv->s = reinterpret_cast<hipStream_t>(stream);
+  sv->nrhs = n_rhs;
+  sv->n3 = 3 * (int64_t)pt->n_kept;
+  sv->mixed = o.mixed != 0;
+  sv->timing = o.timing != 0;
+  sv->st.assign(n_rhs, PcgState{});
+  sv->os.assign(n_rhs, OuterState{});
+  Carver cv(workspace, ws_bytes);
+  carve(cv, pt->n_kept, n_rhs, o, &sv->L);
+  auto bail = [&](int rc) {
+    delete sv;
+    return rc;
+  };
+  if (!cv.fits()) return bail(fail(MM_ENOSPC, "solver workspace too small"));
+  hipError_t e;
+  if ((e = hipHostMalloc((void**)&sv->h_st, sizeof(PcgState) * n_rhs, hipHostMallocDefault)) != hipSuccess)
+    return bail(hip_fail(e, "pinned state"));
+  if ((e = hipHostMalloc((void**)&sv->h_os, sizeof(OuterState) * n_rhs, hipHostMallocDefault)) != hipSuccess)
+    return bail(hip_fail(e, "pinned state"));
+  if ((e = hipEventCreateWithFlags(&sv->ev, hipEventDisableTiming)) != hipSuccess)
+    return bail(hip_fail(e, "solver event"));
+  // zero the per-RHS states: their reduction tickets must start at 0
+  if ((e = hipMemsetAsync(sv->L.A.st, 0, sizeof(PcgState) * n_rhs, sv->s)) != hipSuccess)
+    return bail(hip_fail(e, "state init"));
+  if ((e = hipMemsetAsync(sv->L.O.os, 0, sizeof(OuterState) * n_rhs, sv->s)) != hipSuccess)
+    return bail(hip_fail(e, "state init"));
+  const size_t esz = pt->dtype == MM_F64 ? 8 : 4;
+  double* rhs_dst = sv->mixed ? sv->L.b64 : sv->L.b;
+  for (int32_t r = 0; r < n_rhs; ++r) {
+    const char* t = static_cast<const char*>(tod) + (size_t)r * esz * (size_t)pt->n_samples;
+    if (int rc = rhs_impl(pt, nz, t, rhs_dst + r * sv->n3, MM_F64, sv->s)) return bail(rc);
+  }
+  if (sv->mixed) {
+    sv->L.A.b = sv->L.O.rt;  // inner solves run on the outer residual
+    if (int rc = launch_outer_init(sv->L.O, sv->L.A, n_rhs, sv->s)) return bail(rc);
+    if (int rc = launch_pcg_init(pt, sv->L.A, n_rhs, o.inner_tol, o.max_iter, 0, sv->L.O.os, sv->s))
+      return bail(rc);
+  } else {
+    if (int rc = launch_pcg_init(pt, sv->L.A, n_rhs, o.tol, o.max_iter, o.fixed_iter, nullptr, sv->s))
+      return bail(rc);
+  }
+  *out = sv;
+  return MM_OK;
+}
+
+int mm_solver_step(mm_solver_t sv, int32_t k) {
+  if (!sv || k < 0) return fail(MM_EINVAL, "bad solver step");
+  return sv->step(k);
+}
+
+int mm_solver_poll(mm_solver_t sv, int32_t* done, int32_t* in_flight, mm_solve_info* info) {
+  if (!sv || !done) return fail(MM_EINVAL, "bad solver poll");
+  if (int rc = sv->poll(done)) return rc;
+  if (in_flight) *in_flight = sv->step_pending ? 1 : 0;
+  if (info)
+    for (int r = 0; r < sv->nrhs; ++r) sv->fill_info(r, &info[r]);
+  return MM_OK;
+}
+
+int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_info* info, double* history_host,
+                     int32_t history_len) {
+  if (!sv) return fail(MM_EINVAL, "null solver");
+  const mm_pointing_s* pt = sv->pt;
+  hipStream_t s = sv->s;
+  MM_HIP(hipStreamSynchronize(s));
+  int32_t done = 0;
+  if (int rc = sv->poll(&done)) return rc;
+  std::vector<double> true_rel(sv->nrhs, 0.0);
+  const double* xf = sv->mixed ? sv->L.O.xt : sv->L.A.x;
+  if (!sv->mixed) {
+    // ||b - A x|| / ||b|| in FP64 arithmetic
+    RhsBatch rb;
+    rb.nrhs = sv->nrhs;
+    rb.vstride = sv->n3;
+    if (int rc = launch_fill(sv->L.A.q, sv->n3 * sv->nrhs, 0.0, s)) return rc;
+    if (int rc = apply_A_impl(pt, sv->nz, sv->L.A.x, sv->L.A.q, MM_F64, rb, s)) return rc;
+    if (int rc = launch_diff_norm(sv->L.A, sv->nrhs, sv->L.b, sv->L.A.q, s)) return rc;
+    MM_HIP(hipMemcpyAsync(sv->h_st, sv->L.A.st, sizeof(PcgState) * sv->nrhs, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < sv->nrhs; ++r)
+      true_rel[r] = sv->h_st[r].scratch1 > 0 ? std::sqrt(sv->h_st[r].scratch0 / sv->h_st[r].scratch1) : 0.0;
+  }
+  for (int r = 0; r < sv->nrhs; ++r) {
+    if (maps_out)
+      if (int rc = launch_expand(pt, xf + r * sv->n3, maps_out + r * 3 * (int64_t)pt->n_pix, s)) return rc;
+  }
+  if (x_out) MM_HIP(hipMemcpyAsync(x_out, xf, sizeof(double) * sv->n3 * sv->nrhs, hipMemcpyDeviceToDevice, s));
+  MM_HIP(hipStreamSynchronize(s));
+  if (history_host && history_len > 0) {
+    // right-hand side 0: inner residual history, or the outer one (mixed);
+    // a plain copy, since the destination is pageable caller memory
+    const double* h = sv->mixed ? sv->L.O.hist : sv->L.A.hist;
+    const int32_t avail = sv->mixed ? std::min(sv->L.O.hist_len, sv->os[0].iters + 1)
+                                    : std::min(sv->L.A.hist_len, sv->st[0].iter + 1);
+    const int32_t n = std::min(history_len, avail);
+    if (n > 0) MM_HIP(hipMemcpy(history_host, h, sizeof(double) * n, hipMemcpyDeviceToHost));
+  }
+  if (history_host && history_len > 0 && sv->mixed) history_host[0] = sv->os[0].bnorm > 0 ? 1.0 : 0.0;
+  bool breakdown = false, converged = true;
+  for (int r = 0; r < sv->nrhs; ++r) {
+    mm_solve_info inf;
+    sv->fill_info(r, &inf);
+    if (!sv->mixed) inf.true_rel_resid = true_rel[r];
+    breakdown = breakdown || inf.breakdown;
+    converged = converged && inf.converged;
+    if (info) info[r] = inf;
+  }
+  if (breakdown) return fail(MM_EBREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite value)");
+  if (!converged && !(sv->o.fixed_iter > 0 && !sv->mixed)) return MM_NOTCONVERGED;
+  return MM_OK;
+}
+
+int mm_solver_destroy(mm_solver_t sv) {
+  delete sv;
+  return MM_OK;
+}
+
+int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, double* x_out,
+             const mm_solve_opts* opts, mm_solve_info* info, double* history_host, int32_t history_len,
+             void* workspace, size_t ws_bytes, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  mm_solve_opts o;
+  mm_solve_opts_default(&o);
+  if (opts) o = *opts;
+  if (int rc = check_opts(o)) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (pt->n_kept == 0) {
+    if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
+    if (map_out) MM_HIP(hipMemsetAsync(map_out, 0, sizeof(double) * 3 * (size_t)pt->n_pix, s));
+    MM_HIP(hipStreamSynchronize(s));
+    if (info) {
+      *info = mm_solve_info{};
+      info->converged = 1;
+    }
+    return MM_OK;
+  }
+  mm_solver_t sv = nullptr;
+  if (int rc = mm_solver_create(pt, nz, 1, tod, &o, workspace, ws_bytes, stream, &sv)) return rc;
+  // upper bound on steps: every inner solve is capped, so is the outer loop
+  // (an outer step costs one extra step)
+  const int64_t per_inner = (int64_t)(o.fixed_iter > 0 ? o.fixed_iter : o.max_iter) / o.check_every + 3;
+  const int64_t max_steps = per_inner * (o.mixed ? o.max_outer : 1) + 4;
+  int32_t done = 0;
+  int rc = MM_OK;
+  for (int64_t i = 0; i < max_steps && !done; ++i) {
+    if ((rc = sv->step(o.check_every))) break;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "solve sync");
+      break;
+    }
+    if ((rc = sv->poll(&done))) break;
+  }
+  if (rc == MM_OK) rc = mm_solver_finish(sv, map_out, x_out, info, history_host, history_len);
+  mm_solver_destroy(sv);
+  return rc;
+}
+
+}  // extern "C"

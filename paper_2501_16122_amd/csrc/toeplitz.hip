@@ -241,23 +241,28 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(co
                                                           const S* __restrict__ psi,
                                                           const cpx<S>* __restrict__ wts, const double* __restrict__ x,
                                                           const S* __restrict__ tod_in, S* __restrict__ tod_out,
-                                                          double* __restrict__ q, const int32_t* __restrict__ done) {
+                                                          double* __restrict__ q, RhsBatch rb) {
   using P = Plan<C>;
   using F = Fft<C>;
   using A = Angle<C, S, kW>;
   constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch, GS = P::kScatterBatch;
   constexpr int kTBinSlots = Lds<C>::kBinSlots, kXPixels = Lds<C>::kXPixels;
   static_assert(E % G == 0, "gather batches must tile the elements");
-  if (done != nullptr && *done) return;
   __shared__ cpx<C> buf[lds_elems<N>()];
   __shared__ int32_t s_red[4 * (P::T / 64)];
 
   // XCD-aware mapping: workgroups go round-robin over the 8 XCDs, so give
   // XCD x a contiguous run of tiles; neighbouring tiles (which share their
-  // overlap-save halos) then run close together on one L2.
+  // overlap-save halos) then run close together on one L2, and the right-hand
+  // sides of one tile are adjacent, so its pointing is read from HBM once.
   const int64_t per_xcd = (n_tiles + 7) / 8;
-  const int64_t tile = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int64_t local = blockIdx.x / 8;
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * per_xcd + local / rb.nrhs;
+  const int rhs = (int)(local % rb.nrhs);
   if (tile >= n_tiles) return;
+  if (rb.done != nullptr && rb.done[(int64_t)rhs * rb.done_stride]) return;
+  if (x != nullptr) x += rhs * rb.vstride;
+  q += rhs * rb.vstride;
   const FftTile tl = tiles[tile];
   const int64_t in0 = tl.out_start - (lambda - 1);  // timeline index of window position 0
   const int32_t vlo = lambda - 1;                    // valid (non-wrapping) outputs: [vlo, vhi)
@@ -480,14 +485,14 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(co
 
 template <class S, class C, int kIn, int kOut, int kW>
 int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod_in, void* tod_out,
-             double* q, const int32_t* done, hipStream_t s) {
+             double* q, const RhsBatch& rb, hipStream_t s) {
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
-  const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8);
+  const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8) * rb.nrhs;
   hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
                      nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
                      pt ? pt->sample_k : nullptr, pt ? (const S*)pt->psi : nullptr,
-                     pt ? (const cpx<S>*)pt->weights : nullptr, x, (const S*)tod_in, (S*)tod_out, q, done);
+                     pt ? (const cpx<S>*)pt->weights : nullptr, x, (const S*)tod_in, (S*)tod_out, q, rb);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
@@ -499,31 +504,31 @@ inline bool use_weights(const mm_pointing_s* pt, int arith) {
 
 template <int kIn, int kOut>
 int dispatch(const mm_pointing_s* pt, const mm_noise_s* nz, int dtype, int arith, const double* x,
-             const void* tod_in, void* tod_out, double* q, const int32_t* done, hipStream_t s) {
+             const void* tod_in, void* tod_out, double* q, const RhsBatch& rb, hipStream_t s) {
   const bool w = kOut == 1 && use_weights(pt, arith);
   if (dtype == MM_F64) {
     if (arith == MM_F64)
-      return w ? launch_t<double, double, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, done, s)
-               : launch_t<double, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, done, s);
-    return w ? launch_t<double, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, done, s)
-             : launch_t<double, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, done, s);
+      return w ? launch_t<double, double, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s)
+               : launch_t<double, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s);
+    return w ? launch_t<double, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s)
+             : launch_t<double, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s);
   }
-  if (arith == MM_F64) return launch_t<float, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, done, s);
-  return w ? launch_t<float, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, done, s)
-           : launch_t<float, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, done, s);
+  if (arith == MM_F64) return launch_t<float, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s);
+  return w ? launch_t<float, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s)
+           : launch_t<float, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s);
 }
 
 }  // namespace
 
 int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
                          hipStream_t s) {
-  return dispatch<0, 0>(pt, nz, pt->dtype, arith, nullptr, in, out, nullptr, nullptr, s);
+  return dispatch<0, 0>(pt, nz, pt->dtype, arith, nullptr, in, out, nullptr, RhsBatch{}, s);
 }
 
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
-                          double* q, int arith, const int32_t* done, hipStream_t s) {
-  if (x != nullptr) return dispatch<1, 1>(pt, nz, pt->dtype, arith, x, nullptr, nullptr, q, done, s);
-  return dispatch<0, 1>(pt, nz, pt->dtype, arith, nullptr, tod, nullptr, q, done, s);
+                          double* q, int arith, const RhsBatch& rb, hipStream_t s) {
+  if (x != nullptr) return dispatch<1, 1>(pt, nz, pt->dtype, arith, x, nullptr, nullptr, q, rb, s);
+  return dispatch<0, 1>(pt, nz, pt->dtype, arith, nullptr, tod, nullptr, q, rb, s);
 }
 
 // Host side: overlap-save tiles per arithmetic, the spectral weights

@@ -1,0 +1,230 @@
+"""Continuous-batching server for map-making solves on one GPU.
+
+Requests (each a complete map-making problem: pointing, timeline, noise
+model) arrive over time.  The server admits a request as soon as a slot is
+free and its device footprint fits the memory budget, uploads its arrays,
+builds its pointing (and precomputed pointing weights) and noise handles,
+and starts a resumable solver on a stream of its own.  Every scheduler tick
+enqueues one chunk of iterations for every active solve, so the work of
+different requests overlaps on the device; solves whose state copy shows
+convergence are finished (true residual, full-grid map), their memory is
+released, and waiting requests are admitted in their place.
+
+All computation runs in libmapmaker's kernels; this module only schedules.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+from typing import Callable, Optional
+
+import numpy as np
+
+from . import binding as b
+from . import synth
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds after the start of the run
+    workload: synth.Workload
+    # host inputs (filled by ``materialize``)
+    pix: Optional[np.ndarray] = None
+    psi: Optional[np.ndarray] = None
+    d: Optional[np.ndarray] = None
+    coeff: Optional[np.ndarray] = None
+    chunks: Optional[np.ndarray] = None
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    map: np.ndarray                # f64[n_pix, 3]
+    info: dict
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def footprint_bytes(w: synth.Workload, opts: b.SolveOpts, weights: bool) -> int:
+    """Upper bound of the device memory one request holds while in flight."""
+    lib = b.load()
+    esz = 4 if w.precision == "f32" else 8
+    n = w.n_samples
+    total = n * (4 + esz + esz)                      # pix, psi, d
+    if weights:
+        total += 2 * n * esz
+    sz = b._c.c_size_t()
+    b._check(lib.mm_pointing_workspace_size(n, w.n_det, w.n_pix, b._c.byref(sz)))
+    total += sz.value
+    if w.toeplitz:
+        offs = synth.chunk_offsets(w)
+        b._check(lib.mm_noise_toeplitz_workspace_size(w.lam, 1, offs.ctypes.data_as(b._pi64), offs.size - 1,
+                                                      b._c.byref(sz)))
+        total += sz.value
+    else:
+        total += 8 * w.n_det
+    # solver vectors with every pixel kept (upper bound)
+    n3 = 3 * w.n_pix
+    hist = max(opts.max_iter, opts.fixed_iter) + opts.max_outer + 2
+    total += 9 * n3 * 8 + 4 * 2 * 512 * 8 + 8 * hist + 4096
+    return int(total)
+
+
+def materialize(req: Request, make_d: Callable) -> Request:
+    """Draw the request's seeded inputs on the host.  ``make_d(w, pix, psi)``
+    forms the timeline (the caller chooses how; tests use the oracle)."""
+    w = req.workload
+    pix, psi = synth.pointing(w)
+    req.pix = pix
+    req.psi = synth.storage(w, psi)
+    req.d = synth.storage(w, make_d(w, pix, req.psi))
+    if w.toeplitz:
+        req.coeff = synth.toeplitz_coeff(w)
+        req.chunks = synth.chunk_offsets(w)
+    return req
+
+
+class _Slot:
+    def __init__(self, req: Request, dev, stream, opts, use_weights, now):
+        import torch
+        w = req.workload
+        self.req = req
+        self.admitted = now
+        with torch.cuda.stream(stream):
+            self.t_pix = torch.from_numpy(req.pix).to(dev, non_blocking=False)
+            self.t_psi = torch.from_numpy(req.psi).to(dev, non_blocking=False)
+            self.t_d = torch.from_numpy(req.d).to(dev, non_blocking=False)
+            self.pt = b.Pointing(self.t_pix, self.t_psi, synth.det_offsets(w), synth.det_weight(w), w.n_pix,
+                                 w.min_hits, w.cond_max, stream=stream)
+            if w.toeplitz:
+                if use_weights:
+                    self.pt.attach_weights(stream=stream)
+                self.nz = b.Noise.toeplitz(req.coeff, req.chunks, dev, stream=stream)
+            else:
+                self.nz = b.Noise.white(synth.det_weight(w), dev, stream=stream)
+            self.solver = b.AsyncSolver(self.pt, self.nz, self.t_d, stream=stream, **opts)
+
+    def release(self):
+        self.solver.close()
+        self.pt.close()
+        self.nz.close()
+        del self.t_pix, self.t_psi, self.t_d
+
+
+class Server:
+    """Admit, advance and retire map-making solves with overlapping work."""
+
+    def __init__(self, device="cuda:0", hbm_budget: Optional[int] = None, max_slots: int = 8, k_chunk: int = 8,
+                 n_streams: int = 8, use_weights: bool = True, **solve_opts):
+        import torch
+        self.dev = torch.device(device)
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.dev)
+            hbm_budget = int(0.9 * free)
+        self.budget = hbm_budget
+        self.max_slots = max_slots
+        self.k_chunk = k_chunk
+        self.opts = dict(tol=1e-10, mixed=1, check_every=k_chunk)
+        self.opts.update(solve_opts)
+        self._sopts = b.solve_opts(**self.opts)
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_streams)]
+        self.use_weights = use_weights
+        self.pending: collections.deque = collections.deque()
+        self.active: list = []
+        self.in_use = 0
+        self.results: list = []
+        self.peak_slots = 0
+        self.peak_bytes = 0
+
+    def submit(self, req: Request):
+        self.pending.append(req)
+
+    def _fp(self, req: Request) -> int:
+        return footprint_bytes(req.workload, self._sopts, self.use_weights and req.workload.toeplitz)
+
+    def _admit(self, now: float, t0: float):
+        while self.pending and len(self.active) < self.max_slots:
+            req = self.pending[0]
+            if req.arrival > now - t0:
+                break
+            fp = self._fp(req)
+            if fp > self.budget:
+                raise MemoryError(f"request {req.rid} needs {fp} bytes, more than the whole budget")
+            if self.in_use + fp > self.budget:
+                break  # wait for memory to free up
+            self.pending.popleft()
+            stream = self.streams[req.rid % len(self.streams)]
+            slot = _Slot(req, self.dev, stream, self.opts, self.use_weights, now - t0)
+            slot.fp = fp
+            slot.depth = 0
+            self.in_use += fp
+            self.active.append(slot)
+            self.peak_slots = max(self.peak_slots, len(self.active))
+            self.peak_bytes = max(self.peak_bytes, self.in_use)
+
+    def run(self, requests=None, realtime=True, on_result=None):
+        """Serve ``requests`` (sorted by arrival); returns the results in
+        completion order.  With realtime=False arrival times are ignored and
+        every request is admitted as soon as it fits."""
+        for r in sorted(requests or [], key=lambda r: r.arrival):
+            if not realtime:
+                r.arrival = 0.0
+            self.submit(r)
+        t0 = time.perf_counter()
+        while self.pending or self.active:
+            now = time.perf_counter()
+            self._admit(now, t0)
+            if not self.active:
+                # nothing admitted yet: wait for the next arrival
+                nxt = self.pending[0].arrival - (time.perf_counter() - t0)
+                if nxt > 0:
+                    time.sleep(min(nxt, 0.01))
+                continue
+            progressed = False
+            still = []
+            for slot in self.active:
+                done, in_flight = slot.solver.poll()
+                if done:
+                    out = slot.solver.finish()
+                    w = slot.req.workload
+                    res = Result(slot.req.rid, out["maps"][0].cpu().numpy().reshape(w.n_pix, 3), out["info"][0],
+                                 slot.req.arrival, slot.admitted, time.perf_counter() - t0)
+                    self.in_use -= slot.fp
+                    slot.release()
+                    self.results.append(res)
+                    progressed = True
+                    if on_result:
+                        on_result(res)
+                    continue
+                still.append(slot)
+                if not in_flight:
+                    slot.depth = 0
+                if slot.depth < 2:  # at most two chunks queued per solve
+                    slot.solver.step(self.k_chunk)
+                    slot.depth += 1
+                    progressed = True
+            self.active = still
+            if not progressed:
+                time.sleep(0.0002)
+        return self.results
+
+
+def poisson_requests(n: int, rate: float, sizes: Callable[[np.random.Generator, int], synth.Workload],
+                     seed_id: int = 5) -> list:
+    """n requests with exponential inter-arrival times (mean 1/rate s) and
+    workloads drawn by ``sizes(rng, i)`` (seeded, stream 4)."""
+    rng = np.random.default_rng(np.random.SeedSequence([synth.ROOT_SEED, seed_id, synth.STREAM_SERVE]))
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    return [Request(i, float(t[i]), sizes(rng, i)) for i in range(n)]
+
+
+def log_uniform_int(rng: np.random.Generator, lo: float, hi: float) -> int:
+    return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
