@@ -15,6 +15,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -108,6 +109,144 @@ def _cpu_baseline(w, pix, psi, d, n_det_sample):
             "ms_per_iter": 1e3 * t_iter, "host_cpu_count": os.cpu_count()}
 
 
+def _solve_blocking(b, pt, nz, tod, **opts):
+    s = b.AsyncSolver(pt, nz, tod, **opts)
+    while True:
+        s.step()
+        s.stream.synchronize()
+        done, _ = s.poll()
+        if done:
+            break
+    out = s.finish()
+    s.close()
+    return out
+
+
+def multi_rhs_section(torch, b, synth, dev, n_rhs=8):
+    """8 noise realisations sharing one pointing, solved together (one A
+    launch per iteration streams the pointing once for all of them) vs one
+    realisation alone; FP32 storage, FP64 refinement to 1e-10."""
+    w = synth.C4_MULTI
+    t0 = time.perf_counter()
+    pix, psi = synth.pointing(w)
+    m = synth.sky(w)
+    t_pix = torch.from_numpy(pix).to(dev)
+    t_psi = torch.from_numpy(psi).to(dev).float()
+    pt = b.Pointing(t_pix, t_psi, synth.det_offsets(w), synth.det_weight(w), w.n_pix)
+    pt.attach_weights()
+    nz = b.Noise.toeplitz(synth.toeplitz_coeff(w), synth.chunk_offsets(w), dev)
+    kept = pt.export()["kept"].long()
+    sig = b.apply_P(pt, torch.from_numpy(m).to(dev)[kept].reshape(-1).contiguous())  # FP32 P m
+    tods = torch.empty((n_rhs, w.n_samples), dtype=torch.float32, device=dev)
+    for r in range(n_rhs):
+        nr = synth.noise(w.replace(config_id=w.config_id * 100 + r))
+        tods[r] = sig + torch.from_numpy(nr).to(dev).float()
+    del sig
+    torch.cuda.synchronize()
+    log(f"multi-RHS inputs ready in {time.perf_counter() - t0:.1f} s")
+    opts = dict(tol=1e-10, mixed=1, check_every=8, max_outer=10)
+    _solve_blocking(b, pt, nz, tods[0].contiguous(), **opts)  # warm-up
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    one = _solve_blocking(b, pt, nz, tods[0].contiguous(), **opts)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - ts
+    ts = time.perf_counter()
+    multi = _solve_blocking(b, pt, nz, tods, **opts)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - ts
+    return {"workload": w.name, "n_rhs": n_rhs, "n_samples": w.n_samples,
+            "time_to_maps_ms": round(1e3 * t_multi, 2), "time_to_one_map_ms": round(1e3 * t_one, 2),
+            "speedup_vs_separate_solves": round(n_rhs * t_one / t_multi, 3),
+            "inner_iters": [i["iters"] for i in multi["info"]],
+            "final_true_rel_resid_max": max(i["true_rel_resid"] for i in multi["info"]),
+            "note": "FP32 storage and inner operator, FP64 refinement to 1e-10; speedup = n_rhs x (one "
+                    "realisation alone) / (all realisations together)"}
+
+
+def serving_section(torch, b, synth, dev, n_req=24, rate=20.0):
+    """A seeded Poisson stream of map-making requests of mixed sizes and
+    noise models through the continuous-batching server (FP32 storage, FP64
+    refinement to 1e-10) vs the same requests as serial plain FP64 solves."""
+    from paper_2501_16122_amd import serve
+
+    def sizes(rng, i):
+        side = serve.log_uniform_int(rng, 64, 512)
+        n_det = serve.log_uniform_int(rng, 4, 32)
+        n_samp = serve.log_uniform_int(rng, 1 << 18, 1 << 21)
+        toep = rng.uniform() < 0.5
+        return synth.Workload(f"req{i}", 5000 + i, side, side, n_det, n_samp, t_psi=1000.0,
+                              noise="oneoverf" if toep else "white", chunk=(1 << 18) if toep else 0,
+                              lam=4096 if toep else 0, precision="f32")
+
+    def make_d(w, pix, psi):
+        tp = torch.from_numpy(pix).to(dev)
+        ts = torch.from_numpy(np.asarray(psi, dtype=np.float64)).to(dev)
+        pt = b.Pointing(tp, ts, synth.det_offsets(w), synth.det_weight(w), w.n_pix)
+        kept = pt.export()["kept"].long()
+        y = b.apply_P(pt, torch.from_numpy(synth.sky(w)).to(dev)[kept].reshape(-1).contiguous())
+        d = y.cpu().numpy() + synth.noise(w)
+        pt.close()
+        return d
+
+    t0 = time.perf_counter()
+    reqs = [serve.materialize(r, make_d) for r in serve.poisson_requests(n_req, rate, sizes, seed_id=5)]
+    arrivals = np.array([r.arrival for r in reqs])
+    n_samples = sum(r.workload.n_samples for r in reqs)
+    log(f"serving: {n_req} requests, {n_samples} samples, inputs in {time.perf_counter() - t0:.1f} s")
+
+    # serial plain FP64: each request alone, upload + build + solve + map to host
+    torch.cuda.synchronize()
+    service = []
+    for r in reqs:
+        ts = time.perf_counter()
+        w = r.workload
+        tp = torch.from_numpy(r.pix).to(dev)
+        tsi = torch.from_numpy(r.psi.astype(np.float64)).to(dev)
+        td = torch.from_numpy(r.d.astype(np.float64)).to(dev)
+        pt = b.Pointing(tp, tsi, synth.det_offsets(w), synth.det_weight(w), w.n_pix)
+        if w.toeplitz:
+            pt.attach_weights()
+            nz = b.Noise.toeplitz(r.coeff, r.chunks, dev)
+        else:
+            nz = b.Noise.white(synth.det_weight(w), dev)
+        b.Solver(pt, nz, tol=1e-10).solve(td)["map"].cpu()
+        pt.close()
+        nz.close()
+        service.append(time.perf_counter() - ts)
+    # the same arrivals served first-come first-served by that serial solver
+    fin, serial_lat = 0.0, []
+    for a, sv in zip(arrivals, service):
+        fin = max(fin, a) + sv
+        serial_lat.append(fin - a)
+    serial_lat = np.array(serial_lat)
+
+    # capacity: every request queued at t = 0
+    srv = serve.Server(dev, max_slots=8, k_chunk=8)
+    ts = time.perf_counter()
+    res = srv.run([dataclasses.replace(r) for r in reqs], realtime=False)
+    t_cap = time.perf_counter() - ts
+    ok_cap = all(x.info["converged"] == 1 for x in res)
+    # latency under the Poisson arrivals, in real time
+    srv = serve.Server(dev, max_slots=8, k_chunk=8)
+    res = srv.run(reqs, realtime=True)
+    lat = np.array([x.latency for x in res])
+
+    def pct(v):
+        return {"p50": round(1e3 * float(np.median(v)), 2), "p99": round(1e3 * float(np.percentile(v, 99)), 2)}
+
+    return {"requests": n_req, "arrival_rate_per_s": rate, "samples_total": n_samples,
+            "solves_per_s": round(n_req / t_cap, 3), "latency_ms": pct(lat),
+            "peak_concurrent_solves": srv.peak_slots,
+            "all_converged": ok_cap and all(x.info["converged"] == 1 for x in res),
+            "serial_plain_fp64_solves_per_s": round(n_req / float(np.sum(service)), 3),
+            "serial_plain_fp64_latency_ms": pct(serial_lat),
+            "note": "solves/s: all requests queued at once (FP32 storage, FP64 refinement to 1e-10, up to 8 "
+                    "overlapping solves); latency: the seeded Poisson arrivals in real time. Serial baseline: "
+                    "each request alone as a plain FP64 solve (upload, build, solve, map to host); its latency "
+                    "is that solver serving the same arrivals first-come first-served"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,10 +255,12 @@ def main():
     ap.add_argument("--workload", default="gls", choices=["gls", "shard", "binned"])
     ap.add_argument("--fp32-steps", type=int, default=3, help="timed FP32-refined steps (0 = skip)")
     ap.add_argument("--cpu-det", type=int, default=2, help="detectors in the oracle sample (0 = skip)")
+    ap.add_argument("--multi-rhs", type=int, default=8, help="realisations in the multi-RHS measurement (0 = skip)")
+    ap.add_argument("--serve", type=int, default=24, help="requests in the serving measurement (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sample-sharded design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: single-GPU only (asked for --gpus {args.gpus}); sharding the timeline across "
+              "GPUs with one all-reduce of P^T N^-1 P p per iteration is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -156,6 +297,7 @@ def main():
     t_d += t_noise
     del t_noise
     torch.cuda.synchronize()
+    d_host = t_d.cpu().numpy() if args.cpu_det > 0 else None
     log(f"inputs resident on the device; {pt0.n_kept} kept pixels")
 
     def step(psi_t, d_t, mixed):
@@ -245,9 +387,16 @@ def main():
             "note": "psi and d rounded to FP32 once; inner PCG with FP32 timeline arithmetic, FP64 refinement"}
         log(f"FP32-refined: {1e3 * ftm:.1f} ms per map")
 
+    if args.multi_rhs > 0:
+        torch.cuda.empty_cache()
+        result["multi_rhs"] = multi_rhs_section(torch, b, synth, dev, args.multi_rhs)
+        log(f"multi-RHS: {result['multi_rhs']['time_to_maps_ms']} ms for {args.multi_rhs} maps")
+        torch.cuda.empty_cache()
+    if args.serve > 0:
+        result["serving"] = serving_section(torch, b, synth, dev, args.serve)
+        log(f"serving: {result['serving']['solves_per_s']} solves/s")
     if args.cpu_det > 0:
         t0 = time.perf_counter()
-        d_host = t_d.cpu().numpy()
         result["cpu_baseline"] = cpu_baseline(w, pix, psi, d_host, min(args.cpu_det, w.n_det))
         log(f"cpu baseline in {time.perf_counter() - t0:.1f} s")
 

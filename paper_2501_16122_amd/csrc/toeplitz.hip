@@ -531,94 +531,4 @@ int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const d
   return dispatch<0, 1>(pt, nz, pt->dtype, arith, nullptr, tod, nullptr, q, rb, s);
 }
 
-// Host side: overlap-save tiles per arithmetic, the spectral weights
-// (alpha_k, beta_k) of every filter and the twiddle tables.
-int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, size_t ws_bytes, hipStream_t s,
-                            size_t* bytes_needed) {
-  const int lam = nz->lambda;
-  Carver cv(ws, ws_bytes);
-  const int Ns[2] = {kFftN64, kFftN32};
-  std::vector<FftTile> tiles[2];
-  for (int a = 0; a < 2; ++a) {
-    const int64_t L = 2 * (int64_t)Ns[a];
-    const int64_t V = L - 2 * (int64_t)(lam - 1);
-    for (int64_t c = 0; c < nz->n_chunks; ++c) {
-      const int64_t c0 = nz->chunk_offsets[c], c1 = nz->chunk_offsets[c + 1];
-      for (int64_t o = c0; o < c1; o += V)
-        tiles[a].push_back(FftTile{o, o + V < c1 ? o + V : c1, c0, c1, nz->chunk_filter[c], 0});
-    }
-    nz->n_tiles[a] = (int64_t)tiles[a].size();
-  }
-  FftTile* d_tiles[2];
-  for (int a = 0; a < 2; ++a) d_tiles[a] = cv.take<FftTile>(tiles[a].size());
-  void* d_ab[2];
-  void* d_tw[2];
-  d_ab[0] = cv.take<cpx<double>>((size_t)nz->n_filt * kFftN64);
-  d_ab[1] = cv.take<cpx<float>>((size_t)nz->n_filt * kFftN32);
-  d_tw[0] = cv.take<cpx<double>>(kFftN64);
-  d_tw[1] = cv.take<cpx<float>>(kFftN32);
-  if (bytes_needed) *bytes_needed = cv.used;
-  if (ws == nullptr) return MM_OK;
-  if (!cv.fits()) return fail(MM_ENOSPC, "noise workspace too small");
-
-  std::vector<cpx<double>> ab64((size_t)nz->n_filt * kFftN64), tw64(kFftN64);
-  std::vector<cpx<float>> ab32((size_t)nz->n_filt * kFftN32), tw32(kFftN32);
-  for (int a = 0; a < 2; ++a) {
-    const int N = Ns[a];
-    const int64_t L = 2 * (int64_t)N;
-    // cos(2 pi j / L) for j in [0, L)
-    std::vector<double> cosL(L);
-    for (int64_t j = 0; j < L; ++j) cosL[j] = std::cos(2.0 * M_PI * (double)j / (double)L);
-    for (int f = 0; f < nz->n_filt; ++f) {
-      const double* c = coeff_host + (size_t)f * lam;
-      // H_k = c_0 + 2 sum_{tau >= 1} c_tau cos(2 pi k tau / L), k = 0..N
-      std::vector<double> H(N + 1);
-      for (int k = 0; k <= N; ++k) {
-        long double acc = c[0];
-        int64_t idx = 0;
-        for (int tau = 1; tau < lam; ++tau) {
-          idx += k;
-          if (idx >= L) idx -= L;
-          acc += 2.0L * (long double)c[tau] * (long double)cosL[idx];
-        }
-        H[k] = (double)acc;
-      }
-      for (int k = 0; k < N; ++k) {
-        const double S = H[k] + H[N - k], D = H[k] - H[N - k];
-        const double th = 2.0 * M_PI * (double)k / (double)L;
-        const double alpha = (S - D * std::sin(th)) / (double)L;
-        const double beta = D * std::cos(th) / (double)L;
-        if (a == 0)
-          ab64[(size_t)f * N + k] = {alpha, beta};
-        else
-          ab32[(size_t)f * N + k] = {(float)alpha, (float)beta};
-      }
-    }
-    for (int k = 0; k < N; ++k) {
-      const double th = -2.0 * M_PI * (double)k / (double)N;
-      if (a == 0)
-        tw64[k] = {std::cos(th), std::sin(th)};
-      else
-        tw32[k] = {(float)std::cos(th), (float)std::sin(th)};
-    }
-  }
-  for (int a = 0; a < 2; ++a) {
-    if (!tiles[a].empty())
-      MM_HIP(hipMemcpyAsync(d_tiles[a], tiles[a].data(), tiles[a].size() * sizeof(FftTile), hipMemcpyHostToDevice,
-                            s));
-    nz->tiles[a] = d_tiles[a];
-  }
-  MM_HIP(hipMemcpyAsync(d_ab[0], ab64.data(), ab64.size() * sizeof(ab64[0]), hipMemcpyHostToDevice, s));
-  MM_HIP(hipMemcpyAsync(d_ab[1], ab32.data(), ab32.size() * sizeof(ab32[0]), hipMemcpyHostToDevice, s));
-  MM_HIP(hipMemcpyAsync(d_tw[0], tw64.data(), tw64.size() * sizeof(tw64[0]), hipMemcpyHostToDevice, s));
-  MM_HIP(hipMemcpyAsync(d_tw[1], tw32.data(), tw32.size() * sizeof(tw32[0]), hipMemcpyHostToDevice, s));
-  // the host staging vectors die on return: wait for the copies
-  MM_HIP(hipStreamSynchronize(s));
-  for (int a = 0; a < 2; ++a) {
-    nz->ab[a] = d_ab[a];
-    nz->tw[a] = d_tw[a];
-  }
-  return MM_OK;
-}
-
 }  // namespace mm

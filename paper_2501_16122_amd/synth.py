@@ -92,7 +92,12 @@ C3_PRECISION = C1_BINNED.replace(name="binned_64x64_4x2^18_white_f32", precision
 # One GPU's share of C2 under sample sharding over 8 devices (8 of 64 detectors).
 C2_SHARD = C2_GLS.replace(name="gls_512x512_8x2^22_1overf_toeplitz4096", n_det=8)
 
-CONFIGS = {w.name: w for w in (C1_BINNED, C2_GLS, C3_PRECISION, C2_SHARD)}
+# Multi-RHS form: 8 seeded noise realisations sharing one pointing (the
+# realisation index enters the noise seed), FP32 storage with FP64 refinement.
+C4_MULTI = Workload("multirhs_512x512_32x2^22_x8_1overf_toeplitz4096_f32", 4, 512, 512, 32, 1 << 22,
+                    t_psi=6000.0, noise="oneoverf", chunk=1 << 20, lam=4096, precision="f32")
+
+CONFIGS = {w.name: w for w in (C1_BINNED, C2_GLS, C3_PRECISION, C2_SHARD, C4_MULTI)}
 
 
 def _rng(config_id: int, stream: int) -> np.random.Generator:
