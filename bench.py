@@ -164,6 +164,98 @@ def multi_rhs_section(torch, b, synth, dev, n_rhs=8):
                     "realisation alone) / (all realisations together)"}
 
 
+def batched_section(torch, b, synth, dev, n_solves=16):
+    """n independent solves of uneven size advanced together by batched steps
+    (one operator launch per iteration over every member's tiles), vs the
+    same solves one after another (FP32-refined, and plain FP64)."""
+    ws = synth.batch_workloads(n_solves)
+    t0 = time.perf_counter()
+    mem = []
+    for w in ws:
+        pix, psi = synth.pointing(w)
+        noise = synth.noise(w)
+        m = synth.sky(w)
+        offs, wdet = synth.det_offsets(w), synth.det_weight(w)
+        t_pix = torch.from_numpy(pix).to(dev)
+        t_psi = torch.from_numpy(psi).to(dev).float()
+        del pix, psi
+        pt = b.Pointing(t_pix, t_psi, offs, wdet, w.n_pix)
+        kept = pt.export()["kept"].long()
+        y = b.apply_P(pt, torch.from_numpy(m).to(dev)[kept].reshape(-1).contiguous())
+        y += torch.from_numpy(noise).to(dev).float()
+        del noise
+        pt.attach_weights()
+        nz = b.Noise.toeplitz(synth.toeplitz_coeff(w), synth.chunk_offsets(w), dev)
+        mem.append((w, t_pix, t_psi, y, pt, nz))
+    torch.cuda.synchronize()
+    n_samples = sum(w.n_samples for w in ws)
+    log(f"batched: {n_solves} solves, {n_samples} samples, inputs and pointing in {time.perf_counter() - t0:.1f} s")
+    opts = dict(tol=1e-10, mixed=1, max_outer=10)
+    # warm-up of the batched kernels on the two smallest members
+    small = sorted(range(n_solves), key=lambda i: ws[i].n_samples)[:2]
+    stream = torch.cuda.current_stream()
+
+    def run_batch(idx):
+        solvers = [b.AsyncSolver(mem[i][4], mem[i][5], mem[i][3], stream=stream, **opts) for i in idx]
+        while True:
+            b.batch_step(solvers, 8)
+            stream.synchronize()
+            if all([sv.poll()[0] for sv in solvers]):
+                break
+        outs = [sv.finish() for sv in solvers]
+        for sv in solvers:
+            sv.close()
+        return outs
+
+    run_batch(small)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    outs = run_batch(range(n_solves))
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - ts
+    ts = time.perf_counter()
+    for w, t_pix, t_psi, y, pt, nz in mem:
+        b.Solver(pt, nz, **opts).solve(y)
+    torch.cuda.synchronize()
+    t_seq32 = time.perf_counter() - ts
+    # plain FP64: the same problems with FP64 storage (pointing built outside the timed solves)
+    t_seq64 = 0.0
+    iters64 = []
+    for w, t_pix, t_psi, y, pt, nz in mem:
+        psi64, d64 = t_psi.double(), y.double()
+        pt64 = b.Pointing(t_pix, psi64, synth.det_offsets(w), synth.det_weight(w), w.n_pix)
+        pt64.attach_weights()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        r = b.Solver(pt64, nz, tol=1e-10).solve(d64)
+        torch.cuda.synchronize()
+        t_seq64 += time.perf_counter() - ts
+        iters64.append(r["info"]["iters"])
+        pt64.close()
+        del psi64, d64
+    infos = [o["info"][0] for o in outs]
+    res = {"solves": n_solves, "samples_total": n_samples,
+           "members": [w.name for w in ws],
+           "time_to_all_maps_ms": round(1e3 * t_batch, 1),
+           "sequential_fp32_refined_ms": round(1e3 * t_seq32, 1),
+           "serial_plain_fp64_ms": round(1e3 * t_seq64, 1),
+           "speedup_vs_sequential_fp32_refined": round(t_seq32 / t_batch, 3),
+           "speedup_vs_serial_fp64": round(t_seq64 / t_batch, 3),
+           "inner_iters": [i["iters"] for i in infos], "outer_iters": [i["outer_iters"] for i in infos],
+           "fp64_iters": iters64,
+           "all_converged": all(i["converged"] == 1 for i in infos),
+           "final_true_rel_resid_max": max(i["true_rel_resid"] for i in infos),
+           "note": "16 uneven solves (detectors, samples per detector and grid side log-uniform), FP32 storage "
+                   "with FP64 refinement to 1e-10, advanced by batched steps of 8 iterations; the baselines "
+                   "solve the same problems one at a time; pointing builds are outside all three timings"}
+    for w, t_pix, t_psi, y, pt, nz in mem:
+        pt.close()
+        nz.close()
+    del mem
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_section(torch, b, synth, dev, n_req=24, rate=20.0):
     """A seeded Poisson stream of map-making requests of mixed sizes and
     noise models through the continuous-batching server (FP32 storage, FP64
@@ -257,6 +349,7 @@ def main():
     ap.add_argument("--cpu-det", type=int, default=2, help="detectors in the oracle sample (0 = skip)")
     ap.add_argument("--multi-rhs", type=int, default=8, help="realisations in the multi-RHS measurement (0 = skip)")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--batch", type=int, default=16, help="uneven solves in the batched measurement (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: single-GPU only (asked for --gpus {args.gpus}); sharding the timeline across "
@@ -392,6 +485,9 @@ def main():
         result["multi_rhs"] = multi_rhs_section(torch, b, synth, dev, args.multi_rhs)
         log(f"multi-RHS: {result['multi_rhs']['time_to_maps_ms']} ms for {args.multi_rhs} maps")
         torch.cuda.empty_cache()
+    if args.batch > 0:
+        result["batched"] = batched_section(torch, b, synth, dev, min(args.batch, 16))
+        log(f"batched: {result['batched']['time_to_all_maps_ms']} ms for {args.batch} maps")
     if args.serve > 0:
         result["serving"] = serving_section(torch, b, synth, dev, args.serve)
         log(f"serving: {result['serving']['solves_per_s']} solves/s")

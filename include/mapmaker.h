@@ -254,6 +254,20 @@ int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_i
 /* Free the host side (pinned state copy, events); the caller frees the workspace. */
 int mm_solver_destroy(mm_solver_t sv);
 
+/* Advance n resumable solvers together: the PCG iterations of Sec. II for
+ * several independent map-making problems in shared launches.  Each of up to
+ * k iterations is one persistent operator launch per noise kind over the
+ * tiles of every member's right-hand sides (A = P^T N^-1 P, eq. (6)) and one
+ * launch per PCG vector step over all their vectors; for mixed-precision
+ * members a pending outer refinement step runs first.  Members may differ in
+ * size, pointing, noise model and tolerances; they must share one device,
+ * the stream they were created on, the timeline dtype and the precision mode
+ * (mixed or not), and hold at most 16 right-hand sides in all (MM_EINVAL
+ * otherwise).  Asynchronous: every member records its state copy as after
+ * mm_solver_step and is polled and finished on its own.  Batched steps are
+ * not timed (opts.timing). */
+int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k);
+
 #ifdef __cplusplus
 }
 #endif

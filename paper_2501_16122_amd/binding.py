@@ -78,6 +78,7 @@ SIGNATURES = {
     "mm_solver_poll": (_c.c_int, [_vp, _pi32, _pi32, _c.POINTER(SolveInfo)]),
     "mm_solver_finish": (_c.c_int, [_vp, _vp, _vp, _c.POINTER(SolveInfo), _pf64, _i32]),
     "mm_solver_destroy": (_c.c_int, [_vp]),
+    "mm_batch_step": (_c.c_int, [_c.POINTER(_vp), _i32, _i32]),
 }
 
 _lib = None
@@ -410,6 +411,14 @@ class Solver:
             n = (info.iters + 1) if not self.opts.mixed else info.outer_iters + 1
             out["history"] = hist[:n]
         return out
+
+
+def batch_step(solvers, k=8):
+    """Advance several AsyncSolvers (same stream, dtype and precision mode,
+    at most 16 right-hand sides in all) by up to k iterations in shared
+    launches; poll and finish each one as usual."""
+    arr = (_vp * len(solvers))(*[sv.handle for sv in solvers])
+    _check(load().mm_batch_step(arr, len(solvers), int(k)))
 
 
 class AsyncSolver:

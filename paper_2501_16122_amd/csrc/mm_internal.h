@@ -245,6 +245,41 @@ struct OuterArgs {
   int32_t pad_;
 };
 
+// ---------------------------------------------------------------------------
+// Batched launches: up to kMaxBatch right-hand sides ("slots") of different
+// solves advance in shared launches.  The slot tables travel by value as
+// kernel arguments, so a batch needs no device memory of its own.
+// ---------------------------------------------------------------------------
+constexpr int kMaxBatch = 16;
+
+// One slot of a batched operator launch: the fused A of one right-hand side.
+struct OpSlot {
+  const void* tiles;        // FftTile[] of the plan (band-Toeplitz) or PtTile[] (white)
+  const void* ab;           // band-Toeplitz spectral weights of the plan
+  const void* tw;           // band-Toeplitz twiddles of the plan
+  const int32_t* sample_k;
+  const void* psi;
+  const void* wts;          // stored (cos 2psi, sin 2psi) or null
+  const double* det_w;      // white noise weights
+  const double* x;
+  double* q;
+  const int32_t* done;      // the slot is skipped while *done != 0 (null: never)
+  int32_t lambda;
+  int32_t pad_;
+};
+struct OpBatch {
+  int32_t n = 0;
+  int32_t pad_ = 0;
+  int64_t off[kMaxBatch + 1] = {};  // slot s owns work items [off[s], off[s + 1])
+  OpSlot s[kMaxBatch] = {};
+};
+static_assert(sizeof(OpBatch) <= 2048, "operator batch must stay a small kernel argument");
+
+// q += P^T N^-1 P x for every slot, one persistent launch per noise kind.
+// dtype / arith / weights must be common to all slots of the launch.
+int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, hipStream_t s);
+int launch_white_batch(const OpBatch& b, int dtype, int arith, hipStream_t s);
+
 int launch_pcg_init(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, double tol, int32_t max_iter,
                     int32_t fixed_iter, const OuterState* gate, hipStream_t s);
 int launch_pcg_iteration_tail(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, hipStream_t s);
@@ -253,5 +288,30 @@ int launch_diff_norm(const PcgArgs& a, int nrhs, const double* x, const double* 
 int launch_outer_init(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s);
 int launch_outer_add(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s);
 int launch_outer_end(const OuterArgs& o, const PcgArgs& a, int nrhs, double tol, int32_t max_outer, hipStream_t s);
+
+// One slot of a batched PCG launch: single right-hand-side views (slice 0)
+// of a solver's inner and outer state, and its preconditioner blocks.
+struct PcgSlot {
+  PcgArgs A;
+  OuterArgs O;
+  const double* minv;
+  double tol;         // outer tolerance (mixed)
+  double inner_tol;   // inner tolerance of a re-initialised inner solve
+  int32_t max_iter;   // inner iteration cap
+  int32_t max_outer;  // refinement step cap
+};
+struct PcgBatch {
+  int32_t n = 0;
+  int32_t pad_ = 0;
+  PcgSlot s[kMaxBatch] = {};
+};
+static_assert(sizeof(PcgBatch) <= 3072, "PCG batch must stay a small kernel argument");
+
+int launch_pcg_iteration_tail_batch(const PcgBatch& b, hipStream_t s);
+// the outer refinement step of every slot whose inner solve has ended:
+// xt += x, q = 0 (then q += A64 xt by an operator launch), and
+int launch_outer_add_batch(const PcgBatch& b, hipStream_t s);
+// rt = b64 - q, the outer test, and the gated re-initialisation of the inner PCG
+int launch_outer_end_batch(const PcgBatch& b, hipStream_t s);
 
 }  // namespace mm

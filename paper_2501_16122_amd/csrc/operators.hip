@@ -6,6 +6,8 @@
 // is gathered through the caches.  P^T accumulates each tile's samples into
 // LDS bins over the tile's compact-index window (FP64 LDS atomics), then adds
 // each touched bin to the global vector with one FP64 atomic per component.
+#include <algorithm>
+
 #include "mm_internal.h"
 #include "sincos2.h"
 
@@ -102,20 +104,13 @@ __global__ __launch_bounds__(kOpThreads) void k_bin_tod(const PtTile* __restrict
   flush_bins(bins, nb, tl.kmin, q);
 }
 
-// q += P^T diag(w) P x: the timeline value never leaves registers.
-// blockIdx.y selects the right-hand side.
+// q += P^T diag(w) P x over one pointing tile: the timeline value never
+// leaves registers.
 template <class S, class C>
-__global__ __launch_bounds__(kOpThreads) void k_fused_white(const PtTile* __restrict__ tiles,
-                                                            const int32_t* __restrict__ sample_k,
-                                                            const S* __restrict__ psi,
-                                                            const double* __restrict__ det_w,
-                                                            const double* __restrict__ x, double* __restrict__ q,
-                                                            RhsBatch rb) {
-  if (rb.done != nullptr && rb.done[(int64_t)blockIdx.y * rb.done_stride]) return;
-  x += blockIdx.y * rb.vstride;
-  q += blockIdx.y * rb.vstride;
+__device__ __forceinline__ void fused_white_tile(const PtTile& tl, const int32_t* __restrict__ sample_k,
+                                                 const S* __restrict__ psi, const double* __restrict__ det_w,
+                                                 const double* __restrict__ x, double* __restrict__ q) {
   __shared__ double bins[3 * kBinSlots];
-  const PtTile tl = tiles[blockIdx.x];
   if (tl.kmax < tl.kmin) return;
   const int nb = zero_bins(bins, tl);
   const C w = C(det_w[tl.det]);
@@ -130,6 +125,36 @@ __global__ __launch_bounds__(kOpThreads) void k_fused_white(const PtTile* __rest
   }
   __syncthreads();
   flush_bins(bins, nb, tl.kmin, q);
+}
+
+// one tile per workgroup; blockIdx.y selects the right-hand side
+template <class S, class C>
+__global__ __launch_bounds__(kOpThreads) void k_fused_white(const PtTile* __restrict__ tiles,
+                                                            const int32_t* __restrict__ sample_k,
+                                                            const S* __restrict__ psi,
+                                                            const double* __restrict__ det_w,
+                                                            const double* __restrict__ x, double* __restrict__ q,
+                                                            RhsBatch rb) {
+  if (rb.done != nullptr && rb.done[(int64_t)blockIdx.y * rb.done_stride]) return;
+  fused_white_tile<S, C>(tiles[blockIdx.x], sample_k, psi, det_w, x + blockIdx.y * rb.vstride,
+                         q + blockIdx.y * rb.vstride);
+}
+
+// Persistent form over the pointing tiles of several slots (right-hand sides
+// of different solves), numbered one after the other; a slot whose done
+// flag is set is skipped.
+template <class S, class C>
+__global__ __launch_bounds__(kOpThreads) void k_fused_white_batch(OpBatch b) {
+  const int64_t n_items = b.off[b.n];
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    int sl = 0;
+    for (int k = 1; k < b.n; ++k) sl = b.off[k] <= it ? k : sl;
+    const OpSlot& o = b.s[sl];
+    if (o.done == nullptr || *o.done == 0)
+      fused_white_tile<S, C>(static_cast<const PtTile*>(o.tiles)[it - b.off[sl]], o.sample_k,
+                             static_cast<const S*>(o.psi), o.det_w, o.x, o.q);
+    __syncthreads();  // the next item reuses the LDS bins
+  }
 }
 
 template <class S, class C>
@@ -264,6 +289,23 @@ int launch_fused_white(const mm_pointing_s* pt, const double* det_w, const doubl
     else
       hipLaunchKernelGGL((k_fused_white<float, float>), g, b, 0, s, pt->tiles, pt->sample_k,
                          (const float*)pt->psi, det_w, x, q, rb);
+  }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_white_batch(const OpBatch& b, int dtype, int arith, hipStream_t s) {
+  if (b.n == 0) return MM_OK;
+  const int64_t n_items = b.off[b.n];
+  if (n_items == 0) return MM_OK;
+  // up to three 48 KiB-LDS workgroups per CU on 256 CUs
+  const dim3 g((unsigned)std::min<int64_t>(n_items, 3 * 256)), blk(kOpThreads);
+  if (dtype == MM_F64) {
+    if (arith == MM_F64) hipLaunchKernelGGL((k_fused_white_batch<double, double>), g, blk, 0, s, b);
+    else hipLaunchKernelGGL((k_fused_white_batch<double, float>), g, blk, 0, s, b);
+  } else {
+    if (arith == MM_F64) hipLaunchKernelGGL((k_fused_white_batch<float, double>), g, blk, 0, s, b);
+    else hipLaunchKernelGGL((k_fused_white_batch<float, float>), g, blk, 0, s, b);
   }
   MM_HIP(hipGetLastError());
   return MM_OK;

@@ -78,32 +78,51 @@ __device__ __forceinline__ void apply_m3(const double* __restrict__ m, double r0
   z2 = m[2] * r0 + m[4] * r1 + m[5] * r2;
 }
 
+// One right-hand side: its vectors, state, partials and history.
 struct Slice {
   double *x, *r, *z, *p, *q;
   const double* b;
   double* partials;
   PcgState* st;
   double* hist;
+  int32_t n_kept;
+  int32_t hist_len;
 };
 
-__device__ __forceinline__ Slice slice(const PcgArgs& a) {
-  const int64_t o = (int64_t)blockIdx.y * a.vstride;
+__device__ __forceinline__ Slice slice(const PcgArgs& a, int y) {
+  const int64_t o = (int64_t)y * a.vstride;
   return Slice{a.x + o, a.r + o, a.z + o, a.p + o, a.q + o, a.b + o,
-               a.partials + (int64_t)blockIdx.y * 2 * kPcgBlocks, a.st + blockIdx.y,
-               a.hist + (int64_t)blockIdx.y * a.hist_len};
+               a.partials + (int64_t)y * 2 * kPcgBlocks, a.st + y, a.hist + (int64_t)y * a.hist_len,
+               a.n_kept, a.hist_len};
 }
 
-// x = 0, r = b, z = M r, p = z, q = 0, rho = r.z, ||b||.  Skipped for a
-// slice whose gate (outer "done" flag) is set.
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_init(PcgArgs a, const double* __restrict__ minv, double tol,
-                                                          int32_t max_iter, int32_t fixed_iter,
-                                                          const OuterState* gate) {
-  if (gate != nullptr && (gate[blockIdx.y].done || gate[blockIdx.y].skip)) return;
+// The outer refinement vectors and state of one right-hand side.
+struct OSlice {
+  double *xt, *rt;
+  const double* b64;
+  double* partials;
+  OuterState* os;
+  double* hist;
+  int32_t hist_len;
+};
+
+__device__ __forceinline__ OSlice oslice(const OuterArgs& o, int y) {
+  const int64_t off = (int64_t)y * o.vstride;
+  return OSlice{o.xt + off, o.rt + off, o.b64 + off, o.partials + (int64_t)y * 2 * kPcgBlocks, o.os + y,
+                o.hist + (int64_t)y * o.hist_len, o.hist_len};
+}
+
+// ---- bodies (one right-hand side each) ------------------------------------
+
+// x = 0, r = b, z = M r, p = z, q = 0, rho = r.z, ||b||.  Skipped while the
+// gate (outer state) is done or has no step pending.
+__device__ __forceinline__ void pcg_init_body(const Slice& S, const double* __restrict__ minv, double tol,
+                                              int32_t max_iter, int32_t fixed_iter, const OuterState* gate) {
+  if (gate != nullptr && (gate->done || gate->skip)) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
-  Slice S = slice(a);
   double bb = 0.0, rz = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
     const double b0 = S.b[3 * k], b1 = S.b[3 * k + 1], b2 = S.b[3 * k + 2];
     double z0, z1, z2;
     apply_m3(minv + 6 * k, b0, b1, b2, z0, z1, z2);
@@ -133,17 +152,17 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_init(PcgArgs a, const doubl
     const bool met = rel <= tol;
     st->converged = met ? 1 : 0;
     st->done = (bnorm == 0.0 || (fixed_iter <= 0 && met) || (fixed_iter <= 0 && max_iter <= 0)) ? 1 : 0;
-    if (a.hist_len > 0) S.hist[0] = rel;
+    if (S.hist_len > 0) S.hist[0] = rel;
   }
 }
 
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_alpha(PcgArgs a) {
-  Slice S = slice(a);
+// alpha = rho / p.q (breakdown if p.q <= 0 or not finite)
+__device__ __forceinline__ void pcg_alpha_body(const Slice& S) {
   if (S.st->done) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   double pq = 0.0, unused = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)a.n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)S.n_kept;
        i += (int64_t)gridDim.x * blockDim.x)
     pq += S.p[i] * S.q[i];
   if (!grid_sum2(pq, unused, S.partials, &S.st->counter, sh, &s_last)) return;
@@ -157,14 +176,14 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_alpha(PcgArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_update(PcgArgs a, const double* __restrict__ minv) {
-  Slice S = slice(a);
+// x += alpha p, r -= alpha q, z = M r, ||r||, r.z, the stopping test, beta
+__device__ __forceinline__ void pcg_update_body(const Slice& S, const double* __restrict__ minv) {
   if (S.st->done) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   const double alpha = S.st->alpha;
   double rr = 0.0, rz = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
     double rv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -185,7 +204,7 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_update(PcgArgs a, const dou
     st->iter = it;
     const double rel = sqrt(rr) / st->bnorm;
     st->rel = rel;
-    if (it < a.hist_len) S.hist[it] = rel;
+    if (it < S.hist_len) S.hist[it] = rel;
     if (!isfinite(rel)) {
       st->breakdown = 1;
       st->done = 1;
@@ -205,40 +224,39 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_update(PcgArgs a, const dou
   }
 }
 
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_direction(PcgArgs a) {
-  Slice S = slice(a);
+// p = z + beta p, q = 0 (the next operator launch accumulates into q)
+__device__ __forceinline__ void pcg_direction_body(const Slice& S) {
   if (S.st->done) return;
   const double beta = S.st->beta;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)a.n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)S.n_kept;
        i += (int64_t)gridDim.x * blockDim.x) {
     S.p[i] = S.z[i] + beta * S.p[i];
     S.q[i] = 0.0;
   }
 }
 
-// ---- outer FP64 refinement (per slice) ------------------------------------
+// ---- outer FP64 refinement ------------------------------------------------
 // init: xt = 0, rt = b64, ||b64||; the inner state starts "done" so that
-// nothing runs for a slice until its first inner solve is initialised.
-__global__ __launch_bounds__(kPcgThreads) void k_outer_init(OuterArgs o, PcgArgs a) {
+// nothing runs until the first inner solve is initialised.
+__device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S) {
   __shared__ double sh[16];
   __shared__ bool s_last;
-  const int64_t off = (int64_t)blockIdx.y * o.vstride;
-  const int64_t n3 = 3 * (int64_t)a.n_kept;
-  OuterState* os = o.os + blockIdx.y;
+  const int64_t n3 = 3 * (int64_t)S.n_kept;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.st[blockIdx.y].done = 1;
-    a.st[blockIdx.y].iter = 0;
-    a.st[blockIdx.y].breakdown = 0;
+    S.st->done = 1;
+    S.st->iter = 0;
+    S.st->breakdown = 0;
   }
   double bb = 0.0, unused = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = o.b64[off + i];
-    o.xt[off + i] = 0.0;
-    o.rt[off + i] = v;
+    const double v = O.b64[i];
+    O.xt[i] = 0.0;
+    O.rt[i] = v;
     bb += v * v;
   }
-  if (!grid_sum2(bb, unused, o.partials + (int64_t)blockIdx.y * 2 * kPcgBlocks, &os->counter, sh, &s_last)) return;
+  if (!grid_sum2(bb, unused, O.partials, &O.os->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
+    OuterState* os = O.os;
     os->bnorm = sqrt(bb);
     os->rel = os->bnorm > 0.0 ? 1.0 : 0.0;
     os->iters = 0;
@@ -250,21 +268,21 @@ __global__ __launch_bounds__(kPcgThreads) void k_outer_init(OuterArgs o, PcgArgs
   }
 }
 
-// A slice whose inner solve has ended and whose outer loop is still open
-// takes an outer step: xt += x; q := 0 (A64 xt accumulates into q next).
-__global__ __launch_bounds__(kPcgThreads) void k_outer_add(OuterArgs o, PcgArgs a) {
-  const int64_t off = (int64_t)blockIdx.y * o.vstride;
-  OuterState* os = o.os + blockIdx.y;
-  const PcgState* st = a.st + blockIdx.y;
+// A right-hand side whose inner solve has ended and whose outer loop is
+// still open takes an outer step: xt += x; q := 0 (A64 xt accumulates into
+// q next).  Any other right-hand side is marked skip.
+__device__ __forceinline__ void outer_add_body(const OSlice& O, const Slice& S) {
+  OuterState* os = O.os;
+  const PcgState* st = S.st;
   const bool act = st->done && !os->done;
   if (!act) {
     if (blockIdx.x == 0 && threadIdx.x == 0) os->skip = 1;
     return;
   }
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)a.n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)S.n_kept;
        i += (int64_t)gridDim.x * blockDim.x) {
-    o.xt[off + i] += a.x[off + i];
-    a.q[off + i] = 0.0;
+    O.xt[i] += S.x[i];
+    S.q[i] = 0.0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     os->skip = 0;
@@ -274,26 +292,25 @@ __global__ __launch_bounds__(kPcgThreads) void k_outer_add(OuterArgs o, PcgArgs 
 }
 
 // rt = b64 - q (q = A64 xt), ||rt|| / ||b64||, the outer stopping test.
-__global__ __launch_bounds__(kPcgThreads) void k_outer_end(OuterArgs o, PcgArgs a, double tol, int32_t max_outer) {
-  OuterState* os = o.os + blockIdx.y;
+__device__ __forceinline__ void outer_end_body(const OSlice& O, const Slice& S, double tol, int32_t max_outer) {
+  OuterState* os = O.os;
   if (os->skip) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
-  const int64_t off = (int64_t)blockIdx.y * o.vstride;
   double rr = 0.0, unused = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)a.n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)S.n_kept;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = o.b64[off + i] - a.q[off + i];
-    o.rt[off + i] = v;
+    const double v = O.b64[i] - S.q[i];
+    O.rt[i] = v;
     rr += v * v;
   }
-  if (!grid_sum2(rr, unused, o.partials + (int64_t)blockIdx.y * 2 * kPcgBlocks, &os->counter, sh, &s_last)) return;
+  if (!grid_sum2(rr, unused, O.partials, &os->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
     const int it = os->iters + 1;
     os->iters = it;
     const double rel = sqrt(rr) / os->bnorm;
     os->rel = rel;
-    if (it < o.hist_len) o.hist[(int64_t)blockIdx.y * o.hist_len + it] = rel;
+    if (it < O.hist_len) O.hist[it] = rel;
     if (rel <= tol) {
       os->converged = 1;
       os->done = 1;
@@ -303,12 +320,71 @@ __global__ __launch_bounds__(kPcgThreads) void k_outer_end(OuterArgs o, PcgArgs 
   }
 }
 
+// ---- kernels: one slice per blockIdx.y -------------------------------------
+// Single solver: slice blockIdx.y of one PcgArgs (a right-hand side).
+// Batch: slot blockIdx.y of a PcgBatch (slice 0 of that slot's views).
+
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_init(PcgArgs a, const double* __restrict__ minv, double tol,
+                                                          int32_t max_iter, int32_t fixed_iter,
+                                                          const OuterState* gate) {
+  pcg_init_body(slice(a, blockIdx.y), minv, tol, max_iter, fixed_iter, gate ? gate + blockIdx.y : nullptr);
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_alpha(PcgArgs a) { pcg_alpha_body(slice(a, blockIdx.y)); }
+
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_update(PcgArgs a, const double* __restrict__ minv) {
+  pcg_update_body(slice(a, blockIdx.y), minv);
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_direction(PcgArgs a) {
+  pcg_direction_body(slice(a, blockIdx.y));
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_outer_init(OuterArgs o, PcgArgs a) {
+  outer_init_body(oslice(o, blockIdx.y), slice(a, blockIdx.y));
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_outer_add(OuterArgs o, PcgArgs a) {
+  outer_add_body(oslice(o, blockIdx.y), slice(a, blockIdx.y));
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_outer_end(OuterArgs o, PcgArgs a, double tol, int32_t max_outer) {
+  outer_end_body(oslice(o, blockIdx.y), slice(a, blockIdx.y), tol, max_outer);
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_alpha_b(PcgBatch b) {
+  pcg_alpha_body(slice(b.s[blockIdx.y].A, 0));
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_update_b(PcgBatch b) {
+  pcg_update_body(slice(b.s[blockIdx.y].A, 0), b.s[blockIdx.y].minv);
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_direction_b(PcgBatch b) {
+  pcg_direction_body(slice(b.s[blockIdx.y].A, 0));
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_outer_add_b(PcgBatch b) {
+  const PcgSlot& p = b.s[blockIdx.y];
+  outer_add_body(oslice(p.O, 0), slice(p.A, 0));
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_outer_end_b(PcgBatch b) {
+  const PcgSlot& p = b.s[blockIdx.y];
+  outer_end_body(oslice(p.O, 0), slice(p.A, 0), p.tol, p.max_outer);
+}
+
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_reinit_b(PcgBatch b) {
+  const PcgSlot& p = b.s[blockIdx.y];
+  pcg_init_body(slice(p.A, 0), p.minv, p.inner_tol, p.max_iter, 0, p.O.os);
+}
+
 // scratch0 = ||a - b||^2, scratch1 = ||a||^2 per slice
 __global__ __launch_bounds__(kPcgThreads) void k_diff_norm(PcgArgs A, const double* __restrict__ a,
                                                            const double* __restrict__ b) {
   __shared__ double sh[16];
   __shared__ bool s_last;
-  Slice S = slice(A);
+  Slice S = slice(A, blockIdx.y);
   const int64_t off = (int64_t)blockIdx.y * A.vstride;
   double dd = 0.0, aa = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)A.n_kept;
@@ -363,6 +439,30 @@ int launch_outer_add(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t
 int launch_outer_end(const OuterArgs& o, const PcgArgs& a, int nrhs, double tol, int32_t max_outer,
                      hipStream_t s) {
   hipLaunchKernelGGL(k_outer_end, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, o, a, tol, max_outer);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_pcg_iteration_tail_batch(const PcgBatch& b, hipStream_t s) {
+  if (b.n == 0) return MM_OK;
+  hipLaunchKernelGGL(k_pcg_alpha_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
+  hipLaunchKernelGGL(k_pcg_update_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
+  hipLaunchKernelGGL(k_pcg_direction_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_outer_add_batch(const PcgBatch& b, hipStream_t s) {
+  if (b.n == 0) return MM_OK;
+  hipLaunchKernelGGL(k_outer_add_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+int launch_outer_end_batch(const PcgBatch& b, hipStream_t s) {
+  if (b.n == 0) return MM_OK;
+  hipLaunchKernelGGL(k_outer_end_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
+  hipLaunchKernelGGL(k_pcg_reinit_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }

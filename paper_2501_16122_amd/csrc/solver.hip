@@ -156,6 +156,11 @@ struct mm_solver_s {
     }
     if (timing) MM_HIP(hipEventRecord(tev[2 * k], s));
     tev_used = timing ? k : 0;
+    return record_state();
+  }
+
+  // asynchronous copy of the per-RHS state to the pinned mirrors
+  int record_state() {
     MM_HIP(hipMemcpyAsync(h_st, L.A.st, sizeof(PcgState) * nrhs, hipMemcpyDeviceToHost, s));
     if (mixed) MM_HIP(hipMemcpyAsync(h_os, L.O.os, sizeof(OuterState) * nrhs, hipMemcpyDeviceToHost, s));
     MM_HIP(hipEventRecord(ev, s));
@@ -388,6 +393,114 @@ int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_i
 
 int mm_solver_destroy(mm_solver_t sv) {
   delete sv;
+  return MM_OK;
+}
+
+int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
+  if (!solvers || n < 1 || k < 0) return fail(MM_EINVAL, "bad batch step");
+  const mm_solver_s* s0 = solvers[0];
+  if (!s0) return fail(MM_EINVAL, "null solver in batch");
+  int32_t slots = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const mm_solver_s* sv = solvers[i];
+    if (!sv) return fail(MM_EINVAL, "null solver in batch");
+    for (int32_t j = 0; j < i; ++j)
+      if (solvers[j] == sv) return fail(MM_EINVAL, "solver listed twice in batch");
+    if (sv->s != s0->s) return fail(MM_EINVAL, "batch members must share one stream");
+    if (sv->mixed != s0->mixed || sv->pt->dtype != s0->pt->dtype)
+      return fail(MM_EINVAL, "batch members must share the timeline dtype and precision mode");
+    if (sv->pt->device != s0->pt->device) return fail(MM_EINVAL, "batch members must share one device");
+    slots += sv->nrhs;
+  }
+  if (slots > kMaxBatch) return fail(MM_EINVAL, "more than 16 right-hand sides in one batch");
+  hipStream_t s = s0->s;
+  const bool mixed = s0->mixed;
+  const int dtype = s0->pt->dtype;
+  const int arith = mixed ? MM_F32 : MM_F64;
+  // stored weights only where every band-Toeplitz slot has usable ones
+  auto weights_ok = [&](int ar) {
+    for (int32_t i = 0; i < n; ++i) {
+      const mm_pointing_s* pt = solvers[i]->pt;
+      if (solvers[i]->nz->kind == 1 && !(pt->weights != nullptr && (ar == MM_F32 || pt->dtype == MM_F64)))
+        return false;
+    }
+    return true;
+  };
+  const bool w_in = weights_ok(arith), w_out = weights_ok(MM_F64);
+
+  PcgBatch pb;
+  OpBatch t_in, w_in_b, t_out, w_out_b;  // inner / outer operator slots, band-Toeplitz and white
+  bool pending = false;
+  auto add_op = [](OpBatch& b, const mm_solver_s* sv, int plan, const double* x, double* q, const int32_t* done) {
+    const mm_pointing_s* pt = sv->pt;
+    const mm_noise_s* nz = sv->nz;
+    OpSlot& o = b.s[b.n];
+    o = OpSlot{};
+    o.sample_k = pt->sample_k;
+    o.psi = pt->psi;
+    o.wts = pt->weights;
+    o.x = x;
+    o.q = q;
+    o.done = done;
+    int64_t items;
+    if (nz->kind == 1) {
+      o.tiles = nz->tiles[plan];
+      o.ab = nz->ab[plan];
+      o.tw = nz->tw[plan];
+      o.lambda = nz->lambda;
+      items = nz->n_tiles[plan];
+    } else {
+      o.tiles = pt->tiles;
+      o.det_w = nz->det_w;
+      items = pt->n_tiles;
+    }
+    b.off[b.n + 1] = b.off[b.n] + items;
+    b.n += 1;
+  };
+  for (int32_t i = 0; i < n; ++i) {
+    mm_solver_s* sv = solvers[i];
+    pending = pending || sv->outer_pending;
+    for (int32_t r = 0; r < sv->nrhs; ++r) {
+      const int64_t o3 = (int64_t)r * sv->n3;
+      PcgSlot& p = pb.s[pb.n++];
+      p.A = sv->L.A;
+      p.A.x += o3; p.A.r += o3; p.A.z += o3; p.A.p += o3; p.A.q += o3; p.A.b += o3;
+      p.A.partials += (int64_t)r * 2 * kPcgBlocks;
+      p.A.st += r;
+      p.A.hist += (int64_t)r * p.A.hist_len;
+      p.O = sv->L.O;
+      p.O.xt += o3; p.O.rt += o3; p.O.b64 += o3;
+      p.O.partials += (int64_t)r * 2 * kPcgBlocks;
+      p.O.os += r;
+      p.O.hist += (int64_t)r * p.O.hist_len;
+      p.minv = sv->pt->minv;
+      p.tol = sv->o.tol;
+      p.inner_tol = sv->o.inner_tol;
+      p.max_iter = sv->o.max_iter;
+      p.max_outer = sv->o.max_outer;
+      const int plan_in = arith == MM_F64 ? 0 : 1;
+      add_op(sv->nz->kind == 1 ? t_in : w_in_b, sv, plan_in, p.A.p, p.A.q, &p.A.st->done);
+      add_op(sv->nz->kind == 1 ? t_out : w_out_b, sv, 0, p.O.xt, p.A.q, &p.O.os->skip);
+    }
+  }
+  if (mixed && pending) {
+    // one outer step for every slot whose inner solve has ended (the
+    // device-side flags decide; the others are marked skip and stay put)
+    if (int rc = launch_outer_add_batch(pb, s)) return rc;
+    if (int rc = launch_toeplitz_batch(t_out, dtype, MM_F64, w_out, s)) return rc;
+    if (int rc = launch_white_batch(w_out_b, dtype, MM_F64, s)) return rc;
+    if (int rc = launch_outer_end_batch(pb, s)) return rc;
+    for (int32_t i = 0; i < n; ++i) solvers[i]->outer_pending = false;
+  }
+  for (int32_t i = 0; i < k; ++i) {
+    if (int rc = launch_toeplitz_batch(t_in, dtype, arith, w_in, s)) return rc;
+    if (int rc = launch_white_batch(w_in_b, dtype, arith, s)) return rc;
+    if (int rc = launch_pcg_iteration_tail_batch(pb, s)) return rc;
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    solvers[i]->tev_used = 0;  // batched steps are not timed
+    if (int rc = solvers[i]->record_state()) return rc;
+  }
   return MM_OK;
 }
 

@@ -17,6 +17,7 @@
 // where H is the (real, even) DFT of h, and IFFT_N(X)_n = v_{2n} + i v_{2n+1}
 // is the convolved tile.  This folds the real-FFT post- and pre-processing
 // and the spectral multiply into one pass over bin pairs (k, N-k).
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 #include <vector>
@@ -232,16 +233,11 @@ struct Angle {
 // kOut: 0 = timeline output tod_out; 1 = scatter q += P^T z.
 // kW: 1 = stream the precomputed (cos 2psi, sin 2psi) pairs instead of psi.
 template <class S, class C, int kIn, int kOut, int kW>
-__global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(const FftTile* __restrict__ tiles,
-                                                                              int64_t n_tiles,
-                                                          int32_t lambda,
-                                                          const cpx<C>* __restrict__ ab,
-                                                          const cpx<C>* __restrict__ tw,
-                                                          const int32_t* __restrict__ sample_k,
-                                                          const S* __restrict__ psi,
-                                                          const cpx<S>* __restrict__ wts, const double* __restrict__ x,
-                                                          const S* __restrict__ tod_in, S* __restrict__ tod_out,
-                                                          double* __restrict__ q, RhsBatch rb) {
+__device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda, const cpx<C>* __restrict__ abf,
+                                              const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k,
+                                              const S* __restrict__ psi, const cpx<S>* __restrict__ wts,
+                                              const double* __restrict__ x, const S* __restrict__ tod_in,
+                                              S* __restrict__ tod_out, double* __restrict__ q) {
   using P = Plan<C>;
   using F = Fft<C>;
   using A = Angle<C, S, kW>;
@@ -251,19 +247,6 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(co
   __shared__ cpx<C> buf[lds_elems<N>()];
   __shared__ int32_t s_red[4 * (P::T / 64)];
 
-  // XCD-aware mapping: workgroups go round-robin over the 8 XCDs, so give
-  // XCD x a contiguous run of tiles; neighbouring tiles (which share their
-  // overlap-save halos) then run close together on one L2, and the right-hand
-  // sides of one tile are adjacent, so its pointing is read from HBM once.
-  const int64_t per_xcd = (n_tiles + 7) / 8;
-  const int64_t local = blockIdx.x / 8;
-  const int64_t tile = (int64_t)(blockIdx.x % 8) * per_xcd + local / rb.nrhs;
-  const int rhs = (int)(local % rb.nrhs);
-  if (tile >= n_tiles) return;
-  if (rb.done != nullptr && rb.done[(int64_t)rhs * rb.done_stride]) return;
-  if (x != nullptr) x += rhs * rb.vstride;
-  q += rhs * rb.vstride;
-  const FftTile tl = tiles[tile];
   const int64_t in0 = tl.out_start - (lambda - 1);  // timeline index of window position 0
   const int32_t vlo = lambda - 1;                    // valid (non-wrapping) outputs: [vlo, vhi)
   const int32_t vhi = vlo + (int32_t)(tl.out_end - tl.out_start);
@@ -398,7 +381,7 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(co
   // ---- forward FFT (natural order into LDS), spectral multiply fused into
   // the first inverse pass, inverse FFT (outputs stay in registers)
   F::template forward<N, T>(buf, v, tw);
-  F::template inverse<N, T>(buf, ab + (int64_t)tl.filter * N, v, tw);
+  F::template inverse<N, T>(buf, abf, v, tw);
   // v[slot_of<ROut>(e)] now holds the outputs at window samples 2n, 2n+1,
   // n = tid + T e
 
@@ -483,6 +466,50 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(co
   }
 }
 
+// One tile of one right-hand side per workgroup.  XCD-aware mapping:
+// workgroups go round-robin over the 8 XCDs, so XCD x gets a contiguous run
+// of tiles; neighbouring tiles (which share their overlap-save halos) then
+// run close together on one L2, and the right-hand sides of one tile are
+// adjacent, so its pointing is read from HBM once.
+template <class S, class C, int kIn, int kOut, int kW>
+__global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(
+    const FftTile* __restrict__ tiles, int64_t n_tiles, int32_t lambda, const cpx<C>* __restrict__ ab,
+    const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
+    const cpx<S>* __restrict__ wts, const double* __restrict__ x, const S* __restrict__ tod_in,
+    S* __restrict__ tod_out, double* __restrict__ q, RhsBatch rb) {
+  const int64_t per_xcd = (n_tiles + 7) / 8;
+  const int64_t local = blockIdx.x / 8;
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * per_xcd + local / rb.nrhs;
+  const int rhs = (int)(local % rb.nrhs);
+  if (tile >= n_tiles) return;
+  if (rb.done != nullptr && rb.done[(int64_t)rhs * rb.done_stride]) return;
+  if (x != nullptr) x += rhs * rb.vstride;
+  q += rhs * rb.vstride;
+  const FftTile tl = tiles[tile];
+  toeplitz_tile<S, C, kIn, kOut, kW>(tl, lambda, ab + (int64_t)tl.filter * Plan<C>::N, tw, sample_k, psi, wts, x,
+                                     tod_in, tod_out, q);
+}
+
+// One launch over the tiles of several slots (right-hand sides of different
+// solves): the work items of all slots are numbered one after the other and
+// mapped to workgroups XCD-aware as above.  A slot whose done flag is set is
+// skipped.
+template <class S, class C, int kW>
+__global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_batch(OpBatch b) {
+  const int64_t n_items = b.off[b.n];
+  const int64_t per_xcd = (n_items + 7) / 8;
+  const int64_t it = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (it >= n_items || blockIdx.x / 8 >= per_xcd) return;
+  int sl = 0;
+  for (int k = 1; k < b.n; ++k) sl = b.off[k] <= it ? k : sl;
+  const OpSlot& o = b.s[sl];
+  if (o.done != nullptr && *o.done != 0) return;
+  const FftTile tl = static_cast<const FftTile*>(o.tiles)[it - b.off[sl]];
+  toeplitz_tile<S, C, 1, 1, kW>(tl, o.lambda, static_cast<const cpx<C>*>(o.ab) + (int64_t)tl.filter * Plan<C>::N,
+                                static_cast<const cpx<C>*>(o.tw), o.sample_k, static_cast<const S*>(o.psi),
+                                static_cast<const cpx<S>*>(o.wts), o.x, nullptr, nullptr, o.q);
+}
+
 template <class S, class C, int kIn, int kOut, int kW>
 int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod_in, void* tod_out,
              double* q, const RhsBatch& rb, hipStream_t s) {
@@ -519,6 +546,32 @@ int dispatch(const mm_pointing_s* pt, const mm_noise_s* nz, int dtype, int arith
 }
 
 }  // namespace
+
+int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, hipStream_t s) {
+  if (b.n == 0) return MM_OK;
+  const int64_t n_items = b.off[b.n];
+  if (n_items == 0) return MM_OK;
+  const dim3 grid((unsigned)(8 * ((n_items + 7) / 8)));
+  const int T = arith == MM_F64 ? Plan<double>::T : Plan<float>::T;
+  if (dtype == MM_F64) {
+    if (arith == MM_F64) {
+      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<double, double, 1>), grid, dim3(T), 0, s, b);
+      else hipLaunchKernelGGL((k_toeplitz_batch<double, double, 0>), grid, dim3(T), 0, s, b);
+    } else {
+      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<double, float, 1>), grid, dim3(T), 0, s, b);
+      else hipLaunchKernelGGL((k_toeplitz_batch<double, float, 0>), grid, dim3(T), 0, s, b);
+    }
+  } else {
+    if (arith == MM_F64) {
+      hipLaunchKernelGGL((k_toeplitz_batch<float, double, 0>), grid, dim3(T), 0, s, b);
+    } else {
+      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<float, float, 1>), grid, dim3(T), 0, s, b);
+      else hipLaunchKernelGGL((k_toeplitz_batch<float, float, 0>), grid, dim3(T), 0, s, b);
+    }
+  }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
 
 int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
                          hipStream_t s) {

@@ -100,6 +100,24 @@ C4_MULTI = Workload("multirhs_512x512_32x2^22_x8_1overf_toeplitz4096_f32", 4, 51
 CONFIGS = {w.name: w for w in (C1_BINNED, C2_GLS, C3_PRECISION, C2_SHARD, C4_MULTI)}
 
 
+def batch_workloads(n: int = 16, config_id: int = 4, det=(8, 128), samples=(1 << 20, 1 << 23),
+                    side=(128, 1024)) -> list:
+    """n independent solves of uneven size: detectors, samples per detector
+    and grid side each log-uniform over the given ranges (stream 3); 1/f
+    noise with the band-Toeplitz N^-1 of the GLS workload, FP32 storage."""
+    rng = _rng(config_id, STREAM_BATCH)
+
+    def logu(lo, hi):
+        return int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+
+    out = []
+    for i in range(n):
+        nd, ns, sd = logu(*det), logu(*samples), logu(*side)
+        out.append(Workload(f"batch{i}_{sd}x{sd}_{nd}x{ns}", config_id * 1000 + i, sd, sd, nd, ns, t_psi=6000.0,
+                            noise="oneoverf", chunk=1 << 20, lam=4096, precision="f32"))
+    return out
+
+
 def _rng(config_id: int, stream: int) -> np.random.Generator:
     return np.random.default_rng(np.random.SeedSequence([ROOT_SEED, config_id, stream]))
 

@@ -55,3 +55,8 @@ def test_host_only_calls():
     assert sz.value > 0
     assert lib.mm_noise_toeplitz_workspace_size(5000, 1, offs.ctypes.data_as(binding._pi64), 2,
                                                 ctypes.byref(sz)) == binding.MM_EINVAL
+    # batched steps validate their arguments before touching a device
+    assert lib.mm_batch_step(None, 0, 8) == binding.MM_EINVAL
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert lib.mm_batch_step(arr, 2, 8) == binding.MM_EINVAL
+    assert b"null solver" in lib.mm_last_error()

@@ -1,0 +1,151 @@
+"""Batched steps over uneven solves (different sizes, pointings, noise
+models, right-hand-side counts) in shared launches: every member's result
+equals the same solve run alone, and the oracle."""
+import numpy as np
+import pytest
+
+import oracle.mapmaking as oracle
+from paper_2501_16122_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def _b():
+    from paper_2501_16122_amd import binding
+    return binding
+
+
+# uneven members: band-Toeplitz and white, several sizes, one with 2 RHS
+MEMBERS = [
+    (synth.Workload("batch_t64_2x60000", 981, 64, 64, 2, 60000, t_psi=900.0, noise="oneoverf", chunk=20000,
+                    lam=256), 1),
+    (synth.Workload("batch_t48_3x40000", 982, 48, 48, 3, 40000, t_psi=700.0, noise="oneoverf", chunk=16384,
+                    lam=128), 1),
+    (synth.Workload("batch_w32_2x30000", 983, 32, 32, 2, 30000, t_psi=500.0), 1),
+    (synth.Workload("batch_w80_1x100000", 984, 80, 80, 1, 100000, t_psi=800.0), 1),
+    (synth.Workload("batch_t64_1x50000_x2", 985, 64, 64, 1, 50000, t_psi=600.0, noise="oneoverf", chunk=25000,
+                    lam=512), 2),
+]
+
+
+class Member:
+    def __init__(self, w, n_rhs, precision):
+        b = _b()
+        w = w.replace(precision=precision)
+        self.w = w
+        pix, psi = synth.pointing(w)
+        psi = synth.storage(w, psi)
+        offs, wdet = synth.det_offsets(w), synth.det_weight(w)
+        self.opt = oracle.build_pointing(pix, psi, offs, wdet, w.n_pix)
+        self.noise = oracle.toeplitz_noise(synth.toeplitz_coeff(w), synth.chunk_offsets(w)) if w.toeplitz else None
+        m = synth.sky(w)[self.opt.kept].reshape(-1)
+        self.ds = [synth.storage(w, oracle.apply_P(self.opt, m) + synth.noise(w.replace(config_id=w.config_id * 100 + r)))
+                   for r in range(n_rhs)]
+        self.pt = b.Pointing(torch.from_numpy(pix).to(DEV), torch.from_numpy(psi).to(DEV), offs, wdet, w.n_pix)
+        if w.toeplitz:
+            self.pt.attach_weights()
+            self.nz = b.Noise.toeplitz(synth.toeplitz_coeff(w), synth.chunk_offsets(w), DEV)
+        else:
+            self.nz = b.Noise.white(wdet, DEV)
+        self.tods = torch.from_numpy(np.stack(self.ds)).to(DEV)
+
+
+def _members(precision):
+    return [Member(w, r, precision) for w, r in MEMBERS]
+
+
+def _run_alone(mb, **opts):
+    s = _b().AsyncSolver(mb.pt, mb.nz, mb.tods if mb.tods.shape[0] > 1 else mb.tods[0].contiguous(), **opts)
+    while True:
+        s.step()
+        s.stream.synchronize()
+        if s.poll()[0]:
+            break
+    out = s.finish()
+    s.close()
+    return out
+
+
+def _run_batch(mbs, k=8, per_member=None, **opts):
+    b = _b()
+    stream = torch.cuda.current_stream()
+    solvers = [b.AsyncSolver(mb.pt, mb.nz, mb.tods if mb.tods.shape[0] > 1 else mb.tods[0].contiguous(),
+                             stream=stream, **opts, **(per_member(mb) if per_member else {})) for mb in mbs]
+    for _ in range(10000):
+        b.batch_step(solvers, k)
+        stream.synchronize()
+        if all([s.poll()[0] for s in solvers]):
+            break
+    outs = [s.finish() for s in solvers]
+    for s in solvers:
+        s.close()
+    return outs
+
+
+def _fixed(mb):
+    # white noise: M = A^-1, so one iteration is the exact solve
+    return {"fixed_iter": 23 if mb.w.toeplitz else 1}
+
+
+def test_batch_fixed_iterations_match_alone_and_oracle():
+    mbs = _members("f64")
+    outs = _run_batch(mbs, k=8, per_member=_fixed, tol=0.0)
+    for mb, out in zip(mbs, outs):
+        k = _fixed(mb)["fixed_iter"]
+        alone = _run_alone(mb, fixed_iter=k, tol=0.0)
+        for r in range(len(mb.ds)):
+            assert out["info"][r]["iters"] == k
+            x = out["x"][r].cpu().numpy()
+            # FP64 atomics add in a different order in the batch: iterates
+            # agree to rounding amplified over the iterations (~1e-12)
+            err = oracle.rel_l2_per_stokes(x, alone["x"][r].cpu().numpy())
+            assert np.all(err < 1e-10), (mb.w.name, r, err)
+            _, _, x_ref = oracle.solve(mb.opt, mb.noise, mb.ds[r].astype(np.float64), fixed_iters=k)
+            err = oracle.rel_l2_per_stokes(x, x_ref)
+            assert np.all(err < 1e-10), (mb.w.name, r, err)
+
+
+def test_batch_mixed_precision_matches_alone():
+    mbs = _members("f32")
+    opts = dict(tol=1e-12, mixed=1, max_outer=20)
+    outs = _run_batch(mbs, k=8, **opts)
+    for mb, out in zip(mbs, outs):
+        alone = _run_alone(mb, **opts)
+        for r in range(len(mb.ds)):
+            assert out["info"][r]["converged"] == 1, (mb.w.name, out["info"][r])
+            assert out["info"][r]["true_rel_resid"] <= 1e-12
+            err = oracle.rel_l2_per_stokes(out["x"][r].cpu().numpy(), alone["x"][r].cpu().numpy())
+            assert np.all(err < 1e-10), (mb.w.name, r, err)
+            hits = mb.pt.export()["hits"].cpu().numpy()
+            assert np.array_equal(hits, mb.opt.hits)
+    # two members against the oracle on the same (rounded) inputs
+    for mb, out in [(mbs[0], outs[0]), (mbs[3], outs[3])]:
+        _, _, x_ref = oracle.solve(mb.opt, mb.noise, mb.ds[0].astype(np.float64), tol=1e-13)
+        err = oracle.rel_l2_per_stokes(out["x"][0].cpu().numpy(), x_ref)
+        assert np.all(err < 1e-9), (mb.w.name, err)
+
+
+def test_batch_rejects_bad_groups():
+    b = _b()
+    m64 = Member(MEMBERS[2][0], 1, "f64")
+    m32 = Member(MEMBERS[3][0], 1, "f32")
+    stream = torch.cuda.current_stream()
+    s64 = b.AsyncSolver(m64.pt, m64.nz, m64.tods[0].contiguous(), stream=stream)
+    s32 = b.AsyncSolver(m32.pt, m32.nz, m32.tods[0].contiguous(), stream=stream, mixed=1)
+    with pytest.raises(b.MapMakerError):
+        b.batch_step([s64, s32])  # different dtype and precision mode
+    with pytest.raises(b.MapMakerError):
+        b.batch_step([s64, s64])  # listed twice
+    other = torch.cuda.Stream()
+    s_other = b.AsyncSolver(m64.pt, m64.nz, m64.tods[0].contiguous(), stream=other)
+    with pytest.raises(b.MapMakerError):
+        b.batch_step([s64, s_other])  # different streams
+    many = b.AsyncSolver(m64.pt, m64.nz, m64.tods.repeat(17, 1), stream=stream)
+    with pytest.raises(b.MapMakerError):
+        b.batch_step([many])  # 17 right-hand sides
+    torch.cuda.synchronize()
+    for s in (s64, s32, s_other, many):
+        s.close()
