@@ -104,27 +104,61 @@ __global__ __launch_bounds__(kOpThreads) void k_bin_tod(const PtTile* __restrict
   flush_bins(bins, nb, tl.kmin, q);
 }
 
-// q += P^T diag(w) P x over one pointing tile: the timeline value never
-// leaves registers.
+// q += P^T diag(w) P x over one pointing tile: each thread keeps its
+// samples' weighted values (z, z cos 2psi, z sin 2psi) in registers, and the
+// tile's compact-index window is binned in LDS in passes of kBinSlots pixels
+// (one pass unless the scan's footprint is wide).
 template <class S, class C>
 __device__ __forceinline__ void fused_white_tile(const PtTile& tl, const int32_t* __restrict__ sample_k,
                                                  const S* __restrict__ psi, const double* __restrict__ det_w,
                                                  const double* __restrict__ x, double* __restrict__ q) {
+  constexpr int J = kTileSamples / kOpThreads;
   __shared__ double bins[3 * kBinSlots];
   if (tl.kmax < tl.kmin) return;
-  const int nb = zero_bins(bins, tl);
   const C w = C(det_w[tl.det]);
-  for (int i = threadIdx.x; i < tl.len; i += blockDim.x) {
-    const int64_t t = tl.start + i;
-    const int32_t k = sample_k[t];
-    if (k < 0) continue;
-    C c, s;
-    sincos2<C>(psi[t], &c, &s);
-    const C z = w * project<C>(x, k, c, s);
-    bin_add(bins, nb, tl.kmin, k, double(z), double(z * c), double(z * s), q);
+  int32_t kv[J];
+  double v0[J], v1[J], v2[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = threadIdx.x + kOpThreads * j;
+    kv[j] = -1;
+    v0[j] = v1[j] = v2[j] = 0.0;
+    if (i < tl.len) {
+      const int64_t t = tl.start + i;
+      const int32_t k = sample_k[t];
+      if (k >= 0) {
+        C c, s;
+        sincos2<C>(psi[t], &c, &s);
+        const C z = w * project<C>(x, k, c, s);
+        kv[j] = k - tl.kmin;
+        v0[j] = double(z);
+        v1[j] = double(z * c);
+        v2[j] = double(z * s);
+      }
+    }
   }
-  __syncthreads();
-  flush_bins(bins, nb, tl.kmin, q);
+  const int span = tl.kmax - tl.kmin + 1;
+  for (int lo = 0; lo < span; lo += kBinSlots) {
+    const int nb = span - lo < kBinSlots ? span - lo : kBinSlots;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+      bins[i] = 0.0;
+      bins[kBinSlots + i] = 0.0;
+      bins[2 * kBinSlots + i] = 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int rel = kv[j] - lo;
+      if (kv[j] >= 0 && rel >= 0 && rel < nb) {
+        atomicAdd(&bins[rel], v0[j]);
+        atomicAdd(&bins[kBinSlots + rel], v1[j]);
+        atomicAdd(&bins[2 * kBinSlots + rel], v2[j]);
+      }
+    }
+    __syncthreads();
+    flush_bins(bins, nb, tl.kmin + lo, q);
+    __syncthreads();  // the next pass clears the bins
+  }
 }
 
 // one tile per workgroup; blockIdx.y selects the right-hand side

@@ -461,6 +461,9 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
     mm_solver_s* sv = solvers[i];
     pending = pending || sv->outer_pending;
     for (int32_t r = 0; r < sv->nrhs; ++r) {
+      // right-hand sides already seen finished take no slot (the device
+      // flags still guard those that finished since the last poll)
+      if (mixed ? sv->os[r].done : sv->st[r].done) continue;
       const int64_t o3 = (int64_t)r * sv->n3;
       PcgSlot& p = pb.s[pb.n++];
       p.A = sv->L.A;

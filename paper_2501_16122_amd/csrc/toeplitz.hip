@@ -211,7 +211,7 @@ struct Fft<float> {
 template <class C, class S, int kW>
 struct Angle {
   using type = typename std::conditional<kW == 1, cpx<S>, S>::type;
-  static __device__ __forceinline__ type load(const S* __restrict__ psi, const cpx<S>* __restrict__ w, int64_t t) {
+  static __device__ __forceinline__ type load(const S* __restrict__ psi, const cpx<S>* __restrict__ w, int32_t t) {
     if constexpr (kW == 1) return w[t];
     else return psi[t];
   }
@@ -253,6 +253,12 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
   // window positions inside the chunk: [ilo, ihi)
   const int32_t ilo = (int32_t)(tl.chunk_start > in0 ? tl.chunk_start - in0 : 0);
   const int32_t ihi = (int32_t)(tl.chunk_end - in0 < L ? tl.chunk_end - in0 : L);
+  // tile-based views indexed by window position (only [ilo, ihi) is read)
+  const int32_t* __restrict__ sk = sample_k != nullptr ? sample_k + in0 : nullptr;
+  const S* __restrict__ ps0 = (kW == 0 && psi != nullptr) ? psi + in0 : nullptr;
+  const cpx<S>* __restrict__ w0 = (kW == 1 && wts != nullptr) ? wts + in0 : nullptr;
+  const S* __restrict__ tin = tod_in != nullptr ? tod_in + in0 : nullptr;
+  S* __restrict__ tout = tod_out != nullptr ? tod_out + in0 : nullptr;
   const int tid = threadIdx.x;
 
   // ---- input: element e of this thread packs window samples 2n, 2n+1 with
@@ -268,7 +274,7 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
 #pragma unroll
     for (int i = 0; i < 2 * E; ++i) {
       const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
-      kk[i] = (pos >= ilo && pos < ihi) ? sample_k[in0 + pos] : -1;
+      kk[i] = (pos >= ilo && pos < ihi) ? sk[pos] : -1;
     }
     int32_t amin = INT32_MAX, amax = -1;  // window of every kept sample (map staging)
 #pragma unroll
@@ -325,7 +331,7 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
         const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
-        ps[i] = kk[2 * e0 + i] >= 0 ? A::load(psi, wts, in0 + pos) : A::zero();
+        ps[i] = kk[2 * e0 + i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
       }
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
@@ -353,9 +359,8 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
       for (int i = 0; i < 2 * G; ++i) {
         const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
         const bool in = pos >= ilo && pos < ihi;
-        const int64_t t = in0 + pos;
-        if (kOut == 1) kt[i] = (in && pos >= vlo && pos < vhi) ? sample_k[t] : -1;
-        tv[i] = in ? tod_in[t] : S(0);
+        if (kOut == 1) kt[i] = (in && pos >= vlo && pos < vhi) ? sk[pos] : -1;
+        tv[i] = in ? tin[pos] : S(0);
       }
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
@@ -390,8 +395,8 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
     for (int e = 0; e < E; ++e) {
       const int n = tid + T * e;
       const cpx<C> o = v[slot_of<N, T, F::ROut>(e)];
-      if (2 * n >= vlo && 2 * n < vhi) tod_out[in0 + 2 * n] = S(o.x);
-      if (2 * n + 1 >= vlo && 2 * n + 1 < vhi) tod_out[in0 + 2 * n + 1] = S(o.y);
+      if (2 * n >= vlo && 2 * n < vhi) tout[2 * n] = S(o.x);
+      if (2 * n + 1 >= vlo && 2 * n + 1 < vhi) tout[2 * n + 1] = S(o.y);
     }
     return;
   }
@@ -407,62 +412,61 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
   }
   if (kmax < kmin) return;
   double* bins = reinterpret_cast<double*>(buf);
-  const int span = kmax - kmin + 1;
-  // Uniform per tile: bin in LDS when the window fits, else add straight
-  // into q (only for scans whose tile footprint exceeds kTBinSlots pixels).
-  const bool use_lds = span <= kTBinSlots;
-  if (use_lds) {
-    for (int i = tid; i < span; i += T) {
+  // The window [kmin, kmax] is binned in passes of at most kTBinSlots pixels
+  // (one pass for compact scans); a pass reads the indices and weights of
+  // its own samples only, so wide windows (sparse or large grids) cost extra
+  // L2 reads instead of one global atomic per sample.
+  for (int32_t wlo = kmin; wlo <= kmax; wlo += kTBinSlots) {
+    const int nb = kmax - wlo + 1 < kTBinSlots ? kmax - wlo + 1 : kTBinSlots;
+    // opaque copy of the index view: keeps its loads inside the pass
+    // instead of 2E indices hoisted and held live across all passes
+    const int32_t* skp = sk;
+    int tidp = tid;
+    asm volatile("" : "+s"(skp), "+v"(tidp));
+    for (int i = tid; i < nb; i += T) {
       bins[i] = 0.0;
       bins[kTBinSlots + i] = 0.0;
       bins[2 * kTBinSlots + i] = 0.0;
     }
     __syncthreads();
-  }
-  double* dst = use_lds ? nullptr : q;
 #pragma unroll
-  for (int e0 = 0; e0 < E; e0 += GS) {
-    __builtin_amdgcn_sched_barrier(0);  // keep one batch of loads in flight at a time
-    int32_t ks[2 * GS];
-    typename A::type ps[2 * GS];
+    for (int e0 = 0; e0 < E; e0 += GS) {
+      __builtin_amdgcn_sched_barrier(0);  // keep one batch of loads in flight at a time
+      int32_t ks[2 * GS];
+      typename A::type ps[2 * GS];
 #pragma unroll
-    for (int i = 0; i < 2 * GS; ++i) {
-      const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
-      const bool valid = pos >= vlo && pos < vhi;
-      const int64_t t = in0 + pos;
-      if constexpr (kKeepK) ks[i] = valid ? kk[2 * e0 + i] : -1;
-      else ks[i] = valid ? sample_k[t] : -1;
-      ps[i] = ks[i] >= 0 ? A::load(psi, wts, t) : A::zero();
-    }
+      for (int i = 0; i < 2 * GS; ++i) {
+        const int pos = 2 * (tidp + T * (e0 + i / 2)) + (i & 1);
+        const bool valid = pos >= vlo && pos < vhi;
+        int32_t k;
+        if constexpr (kKeepK) k = valid ? kk[2 * e0 + i] : -1;
+        else k = valid ? skp[pos] : -1;
+        const int32_t rel = k - wlo;
+        ks[i] = (k >= 0 && rel < nb && rel >= 0) ? rel : -1;
+        ps[i] = ks[i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
+      }
 #pragma unroll
-    for (int i = 0; i < 2 * GS; ++i) {
-      const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
-      const C z = (i & 1) ? o.y : o.x;
-      C c, s;
-      A::eval(ps[i], &c, &s);
-      if (ks[i] >= 0) {
-        if (use_lds) {
-          const int32_t rel = ks[i] - kmin;
-          atomicAdd(&bins[rel], double(z));
-          atomicAdd(&bins[kTBinSlots + rel], double(z * c));
-          atomicAdd(&bins[2 * kTBinSlots + rel], double(z * s));
-        } else {
-          double* qk = dst + 3 * (int64_t)ks[i];
-          atomicAdd(qk + 0, double(z));
-          atomicAdd(qk + 1, double(z * c));
-          atomicAdd(qk + 2, double(z * s));
+      for (int i = 0; i < 2 * GS; ++i) {
+        const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
+        const C z = (i & 1) ? o.y : o.x;
+        C c, s;
+        A::eval(ps[i], &c, &s);
+        if (ks[i] >= 0) {
+          atomicAdd(&bins[ks[i]], double(z));
+          atomicAdd(&bins[kTBinSlots + ks[i]], double(z * c));
+          atomicAdd(&bins[2 * kTBinSlots + ks[i]], double(z * s));
         }
       }
     }
-  }
-  if (!use_lds) return;
-  __syncthreads();
-  for (int i = tid; i < span; i += T) {
-    const double v0 = bins[i], v1 = bins[kTBinSlots + i], v2 = bins[2 * kTBinSlots + i];
-    double* qk = q + 3 * (int64_t)(kmin + i);
-    if (v0 != 0.0) atomicAdd(qk + 0, v0);
-    if (v1 != 0.0) atomicAdd(qk + 1, v1);
-    if (v2 != 0.0) atomicAdd(qk + 2, v2);
+    __syncthreads();
+    for (int i = tid; i < nb; i += T) {
+      const double v0 = bins[i], v1 = bins[kTBinSlots + i], v2 = bins[2 * kTBinSlots + i];
+      double* qk = q + 3 * (int64_t)(wlo + i);
+      if (v0 != 0.0) atomicAdd(qk + 0, v0);
+      if (v1 != 0.0) atomicAdd(qk + 1, v1);
+      if (v2 != 0.0) atomicAdd(qk + 2, v2);
+    }
+    __syncthreads();  // the next pass clears the bins
   }
 }
 
@@ -491,20 +495,35 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(
 }
 
 // One launch over the tiles of several slots (right-hand sides of different
-// solves): the work items of all slots are numbered one after the other and
-// mapped to workgroups XCD-aware as above.  A slot whose done flag is set is
-// skipped.
+// solves).  Every slot's tiles are split into 8 contiguous parts and XCD x
+// takes part x of every slot, one after the other: each XCD then gets an
+// equal share of every solve (tiles of different solves differ in cost) and
+// still walks neighbouring tiles of one solve together.  A slot whose done
+// flag is set is skipped.
 template <class S, class C, int kW>
 __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_batch(OpBatch b) {
-  const int64_t n_items = b.off[b.n];
-  const int64_t per_xcd = (n_items + 7) / 8;
-  const int64_t it = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (it >= n_items || blockIdx.x / 8 >= per_xcd) return;
-  int sl = 0;
-  for (int k = 1; k < b.n; ++k) sl = b.off[k] <= it ? k : sl;
+  const int x = blockIdx.x % 8;
+  int64_t j = blockIdx.x / 8;  // position in XCD x's list
+  int sl = -1;
+  int64_t idx = 0;
+  for (int k = 0; k < b.n; ++k) {
+    const int64_t n = b.off[k + 1] - b.off[k];
+    const int64_t per = (n + 7) / 8;
+    const int64_t lo = x * per < n ? x * per : n;
+    const int64_t cnt = (lo + per < n ? lo + per : n) - lo;
+    if (sl < 0) {
+      if (j < cnt) {
+        sl = k;
+        idx = lo + j;
+      } else {
+        j -= cnt;
+      }
+    }
+  }
+  if (sl < 0) return;
   const OpSlot& o = b.s[sl];
   if (o.done != nullptr && *o.done != 0) return;
-  const FftTile tl = static_cast<const FftTile*>(o.tiles)[it - b.off[sl]];
+  const FftTile tl = static_cast<const FftTile*>(o.tiles)[idx];
   toeplitz_tile<S, C, 1, 1, kW>(tl, o.lambda, static_cast<const cpx<C>*>(o.ab) + (int64_t)tl.filter * Plan<C>::N,
                                 static_cast<const cpx<C>*>(o.tw), o.sample_k, static_cast<const S*>(o.psi),
                                 static_cast<const cpx<S>*>(o.wts), o.x, nullptr, nullptr, o.q);
@@ -549,9 +568,11 @@ int dispatch(const mm_pointing_s* pt, const mm_noise_s* nz, int dtype, int arith
 
 int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, hipStream_t s) {
   if (b.n == 0) return MM_OK;
-  const int64_t n_items = b.off[b.n];
-  if (n_items == 0) return MM_OK;
-  const dim3 grid((unsigned)(8 * ((n_items + 7) / 8)));
+  // XCD x's list holds up to ceil(n_s / 8) tiles of every slot s
+  int64_t per_xcd = 0;
+  for (int k = 0; k < b.n; ++k) per_xcd += (b.off[k + 1] - b.off[k] + 7) / 8;
+  if (per_xcd == 0) return MM_OK;
+  const dim3 grid((unsigned)(8 * per_xcd));
   const int T = arith == MM_F64 ? Plan<double>::T : Plan<float>::T;
   if (dtype == MM_F64) {
     if (arith == MM_F64) {

@@ -345,3 +345,30 @@ def test_precision_form_toeplitz_refined():
     # FP64 residual history decreases monotonically across outer steps
     h = out["history"]
     assert np.all(np.diff(h) < 0)
+
+
+# a sparse, wide scan: 8 detectors x 2^20 samples on a 1024^2 grid; a tile's
+# pixel window is wider than the LDS bins, so P^T bins it in several passes
+WIDE = synth.Workload("wide_1024x1024_8x2^20", 941, 1024, 1024, 8, 1 << 20, t_psi=1500.0, noise="oneoverf",
+                      chunk=1 << 18, lam=256)
+
+
+def test_fused_toeplitz_wide_window_matches_oracle():
+    b = _b()
+    P = Problem(WIDE, with_d=True).device()
+    o = P.opt
+    # the valid part of one FP64 tile (2^14 - 2*255 samples) spans more
+    # compact indices than the 5760 LDS bins, so several passes are taken
+    k = o.compact[P.pix[:(1 << 14) - 510]]
+    k = k[k >= 0]
+    assert k.max() - k.min() + 1 > 5760
+    assert 0.05 < o.mask.mean() < 0.6  # a realistic masked fraction
+    P.pt.attach_weights()
+    x = np.random.default_rng(21).normal(size=3 * o.n_kept)
+    tx = torch.from_numpy(x).to(DEV)
+    q_ref = oracle.apply_A(o, P.noise, x)
+    assert rel_err(b.apply_A(P.pt, P.nz, tx).cpu().numpy(), q_ref) < 1e-12
+    # FP32 timeline arithmetic (32768-sample tiles, more passes): FP32 rounding only
+    assert rel_err(b.apply_A(P.pt, P.nz, tx, arith="f32").cpu().numpy(), q_ref) < 1e-5
+    bb = b.rhs(P.pt, P.nz, P.t_d).cpu().numpy()
+    assert rel_err(bb, oracle.rhs(o, P.noise, P.d)) < 1e-12
