@@ -397,7 +397,7 @@ def main():
         pt = b.Pointing(t_pix, psi_t, offs, wdet, w.n_pix, w.min_hits, w.cond_max)
         if w.toeplitz:
             pt.attach_weights()  # precomputed (cos 2psi, sin 2psi), part of the build
-        s = b.Solver(pt, nz, tol=1e-10, mixed=mixed, timing=1, check_every=8)
+        s = b.Solver(pt, nz, tol=1e-10, mixed=mixed, timing=1, check_every=8, autotune=1)
         out = s.solve(d_t)
         return out["info"]
 
@@ -428,6 +428,7 @@ def main():
             "kernel": "k_toeplitz<double,double,gather,scatter> (fused P^T N^-1 P)" if w.toeplitz
             else "k_fused_white<double,double>",
             "kernel_ms_avg": round(kernel_ms, 4), "launches": op_n,
+            "op_variant": infos[-1]["op_variant"],
             "algorithmic_bytes_per_launch": alg_bytes}
     if w.toeplitz:
         flops = fft_flops_per_launch(w)

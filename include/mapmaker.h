@@ -67,7 +67,7 @@ typedef struct mm_noise_s* mm_noise_t;
 /* Message of the last failing call on this thread ("" if none). */
 const char* mm_last_error(void);
 
-/* ABI revision of this header (bumped on incompatible change). */
+/* ABI revision of this header (bumped on incompatible change): 2. */
 int mm_abi_version(void);
 
 /* ------------------------------------------------------------------------
@@ -183,6 +183,12 @@ typedef struct {
   int32_t max_outer;    /* mixed: refinement steps cap; default 10                        */
   double inner_tol;     /* mixed: inner relative tolerance; default 1e-5                 */
   int32_t timing;       /* 1: time each iteration and its A kernel with HIP events       */
+  int32_t autotune;     /* 1: time the band-Toeplitz operator variants on this problem at
+                           solver creation and keep the fastest (remembered by the noise
+                           handle per problem size); 0: use op_variant                       */
+  int32_t op_variant;   /* variant when not autotuned (default 0): bit 0 = tiles in launch
+                           order instead of the XCD-aware order, bit 1 = map read from
+                           global memory instead of staged in LDS                          */
   int32_t reserved_;
 } mm_solve_opts;
 
@@ -196,7 +202,7 @@ typedef struct {
   /* filled when opts.timing = 1 (iterations that did work only):           */
   double op_ms;         /* summed duration of the A = P^T N^-1 P kernel      */
   int32_t op_launches;  /* launches summed in op_ms                          */
-  int32_t reserved_;
+  int32_t op_variant;   /* band-Toeplitz operator variant used (see opts)    */
   double iter_ms_p50;   /* median duration of one PCG iteration              */
   double iter_ms_p99;   /* 99th percentile of the same                       */
 } mm_solve_info;

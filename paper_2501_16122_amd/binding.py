@@ -32,13 +32,13 @@ _psz = _c.POINTER(_c.c_size_t)
 class SolveOpts(_c.Structure):
     _fields_ = [("tol", _f64), ("max_iter", _i32), ("fixed_iter", _i32), ("check_every", _i32),
                 ("mixed", _i32), ("max_outer", _i32), ("inner_tol", _f64), ("timing", _i32),
-                ("reserved_", _i32)]
+                ("autotune", _i32), ("op_variant", _i32), ("reserved_", _i32)]
 
 
 class SolveInfo(_c.Structure):
     _fields_ = [("iters", _i32), ("outer_iters", _i32), ("converged", _i32), ("breakdown", _i32),
                 ("rel_resid", _f64), ("true_rel_resid", _f64), ("op_ms", _f64), ("op_launches", _i32),
-                ("reserved_", _i32), ("iter_ms_p50", _f64), ("iter_ms_p99", _f64)]
+                ("op_variant", _i32), ("iter_ms_p50", _f64), ("iter_ms_p99", _f64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

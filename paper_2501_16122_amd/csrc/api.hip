@@ -71,9 +71,9 @@ size_t carve_pointing(Carver& cv, int64_t n_samples, int32_t n_det, int32_t n_pi
 }  // namespace
 
 int apply_A_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, double* q, int arith,
-                 const RhsBatch& rb, hipStream_t s) {
+                 const RhsBatch& rb, hipStream_t s, int32_t variant) {
   if (nz->kind == 0) return launch_fused_white(pt, nz->det_w, x, q, arith, rb, s);
-  return launch_fused_toeplitz(pt, nz, x, nullptr, q, arith, rb, s);
+  return launch_fused_toeplitz(pt, nz, x, nullptr, q, arith, rb, s, variant);
 }
 
 int rhs_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const void* tod, double* b, int arith, hipStream_t s) {
@@ -114,7 +114,7 @@ extern "C" {
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
 
-int mm_abi_version(void) { return 1; }
+int mm_abi_version(void) { return 2; }
 
 int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, size_t* bytes) {
   if (!bytes || n_samples < 0 || n_det <= 0 || n_pix <= 0) return fail(MM_EINVAL, "bad pointing sizes");

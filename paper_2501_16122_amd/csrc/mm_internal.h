@@ -128,6 +128,12 @@ struct mm_noise_s {
   int64_t n_tiles[2] = {0, 0};
   void* ab[2] = {nullptr, nullptr};  // [n_filt][N] pairs (alpha_k, beta_k)
   void* tw[2] = {nullptr, nullptr};  // [N] exp(-2 pi i k / N)
+  // operator variants picked by the autotuner, per problem shape
+  struct Tuned {
+    int64_t n_samples;
+    int32_t n_kept, dtype, arith, nrhs, variant, pad_;
+  };
+  mutable std::vector<Tuned> tuned;
 };
 
 namespace mm {
@@ -165,14 +171,20 @@ int launch_rhs_white(const mm_pointing_s* pt, const double* det_w, const void* t
 // band-Toeplitz
 int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
                          hipStream_t s);
+// Variants of the fused band-Toeplitz operator (picked by the solver's
+// autotuner): bit kOpLinearOrder takes tiles in launch order instead of the
+// XCD-aware order; bit kOpNoStaging reads the map from global memory instead
+// of staging the tile's pixel window in LDS.  Every variant computes the same
+// sums (up to the order of floating-point atomics).
+constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpVariants = 4;
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
-                          double* q, int arith, const RhsBatch& rb, hipStream_t s);
+                          double* q, int arith, const RhsBatch& rb, hipStream_t s, int32_t variant = 0);
 int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, size_t ws_bytes,
                             hipStream_t s, size_t* bytes_needed);
 
 // operator helpers shared by the C entry points and the solver
 int apply_A_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, double* q, int arith,
-                 const RhsBatch& rb, hipStream_t s);
+                 const RhsBatch& rb, hipStream_t s, int32_t variant = 0);
 int rhs_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const void* tod, double* b, int arith, hipStream_t s);
 int check_pointing(mm_pointing_t pt);
 int check_noise_vs_pointing(const mm_noise_s* nz, const mm_pointing_s* pt);
@@ -265,7 +277,7 @@ struct OpSlot {
   double* q;
   const int32_t* done;      // the slot is skipped while *done != 0 (null: never)
   int32_t lambda;
-  int32_t pad_;
+  int32_t variant;          // band-Toeplitz operator variant (kOpNoStaging is honoured)
 };
 struct OpBatch {
   int32_t n = 0;

@@ -73,6 +73,7 @@ int check_opts(const mm_solve_opts& o) {
   if (!(o.tol >= 0.0) || o.max_iter < 0 || o.check_every < 1 || o.max_outer < 1 || !(o.inner_tol > 0.0))
     return fail(MM_EINVAL, "bad solve options");
   if (o.mixed && o.fixed_iter > 0) return fail(MM_EINVAL, "fixed_iter is not available with mixed precision");
+  if (o.op_variant < 0 || o.op_variant >= kOpVariants) return fail(MM_EINVAL, "op_variant out of range");
   return MM_OK;
 }
 
@@ -87,6 +88,7 @@ struct mm_solver_s {
   int64_t n3 = 0;
   Layout L{};
   bool mixed = false;
+  int32_t variant = 0;         // band-Toeplitz operator variant
   bool outer_pending = false;  // the last poll saw a finished inner solve
   bool step_pending = false;   // a state copy is in flight
   hipEvent_t ev = nullptr;
@@ -132,7 +134,7 @@ struct mm_solver_s {
       rb.vstride = n3;
       rb.done = &L.O.os[0].skip;
       rb.done_stride = kOuterStride;
-      if (int rc = apply_A_impl(pt, nz, L.O.xt, L.A.q, MM_F64, rb, s)) return rc;
+      if (int rc = apply_A_impl(pt, nz, L.O.xt, L.A.q, MM_F64, rb, s, variant)) return rc;
       if (int rc = launch_outer_end(L.O, L.A, nrhs, o.tol, o.max_outer, s)) return rc;
       if (int rc = launch_pcg_init(pt, L.A, nrhs, o.inner_tol, o.max_iter, 0, L.O.os, s)) return rc;
       outer_pending = false;
@@ -150,13 +152,63 @@ struct mm_solver_s {
     }
     for (int32_t i = 0; i < k; ++i) {
       if (timing) MM_HIP(hipEventRecord(tev[2 * i], s));
-      if (int rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s)) return rc;
+      if (int rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s, variant)) return rc;
       if (timing) MM_HIP(hipEventRecord(tev[2 * i + 1], s));
       if (int rc = launch_pcg_iteration_tail(pt, L.A, nrhs, s)) return rc;
     }
     if (timing) MM_HIP(hipEventRecord(tev[2 * k], s));
     tev_used = timing ? k : 0;
     return record_state();
+  }
+
+  // Autotuner: time each variant of the fused band-Toeplitz operator on
+  // this problem (one warm-up and two timed launches on the current search
+  // direction, into q, which is cleared afterwards) and keep the fastest.
+  // The choice is remembered by the noise handle for this problem shape.
+  int tune() {
+    const int arith = mixed ? MM_F32 : MM_F64;
+    for (const auto& t : nz->tuned)
+      if (t.n_samples == pt->n_samples && t.n_kept == pt->n_kept && t.dtype == pt->dtype && t.arith == arith &&
+          t.nrhs == nrhs) {
+        variant = t.variant;
+        return MM_OK;
+      }
+    RhsBatch rb;
+    rb.nrhs = nrhs;
+    rb.vstride = n3;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MM_HIP(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return hip_fail(e, "tuner event");
+    }
+    int rc = MM_OK;
+    float best = 0.f;
+    int32_t best_v = 0;
+    for (int32_t v = 0; v < kOpVariants && rc == MM_OK; ++v) {
+      if ((rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s, v))) break;
+      if ((e = hipEventRecord(e0, s)) != hipSuccess) { rc = hip_fail(e, "tuner event"); break; }
+      for (int r = 0; r < 2 && rc == MM_OK; ++r) rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s, v);
+      if (rc) break;
+      if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+        rc = hip_fail(e, "tuner event");
+        break;
+      }
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = hip_fail(e, "tuner event"); break; }
+      if (v == 0 || ms < best) {
+        best = ms;
+        best_v = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = launch_fill(L.A.q, n3 * nrhs, 0.0, s))) return rc;
+    variant = best_v;
+    nz->tuned.push_back(mm_noise_s::Tuned{pt->n_samples, pt->n_kept, pt->dtype, arith, nrhs, best_v, 0});
+    return MM_OK;
   }
 
   // asynchronous copy of the per-RHS state to the pinned mirrors
@@ -218,6 +270,7 @@ struct mm_solver_s {
       inf->breakdown = st[r].breakdown;
       inf->rel_resid = st[r].rel;
     }
+    inf->op_variant = variant;
     if (timing) {
       inf->op_ms = op_ms;
       inf->op_launches = op_launches;
@@ -239,6 +292,8 @@ int mm_solve_opts_default(mm_solve_opts* o) {
   o->max_outer = 10;
   o->inner_tol = 1e-5;
   o->timing = 0;
+  o->autotune = 0;
+  o->op_variant = 0;
   o->reserved_ = 0;
   return MM_OK;
 }
@@ -320,6 +375,9 @@ int mm_solver_create(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const void*
     if (int rc = launch_pcg_init(pt, sv->L.A, n_rhs, o.tol, o.max_iter, o.fixed_iter, nullptr, sv->s))
       return bail(rc);
   }
+  sv->variant = o.op_variant;
+  if (o.autotune && nz->kind == 1)
+    if (int rc = sv->tune()) return bail(rc);
   *out = sv;
   return MM_OK;
 }
@@ -354,7 +412,7 @@ int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_i
     rb.nrhs = sv->nrhs;
     rb.vstride = sv->n3;
     if (int rc = launch_fill(sv->L.A.q, sv->n3 * sv->nrhs, 0.0, s)) return rc;
-    if (int rc = apply_A_impl(pt, sv->nz, sv->L.A.x, sv->L.A.q, MM_F64, rb, s)) return rc;
+    if (int rc = apply_A_impl(pt, sv->nz, sv->L.A.x, sv->L.A.q, MM_F64, rb, s, sv->variant)) return rc;
     if (int rc = launch_diff_norm(sv->L.A, sv->nrhs, sv->L.b, sv->L.A.q, s)) return rc;
     MM_HIP(hipMemcpyAsync(sv->h_st, sv->L.A.st, sizeof(PcgState) * sv->nrhs, hipMemcpyDeviceToHost, s));
     MM_HIP(hipStreamSynchronize(s));
@@ -442,6 +500,7 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
     o.x = x;
     o.q = q;
     o.done = done;
+    o.variant = sv->variant;
     int64_t items;
     if (nz->kind == 1) {
       o.tiles = nz->tiles[plan];

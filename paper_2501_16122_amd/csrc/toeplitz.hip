@@ -237,7 +237,7 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
                                               const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k,
                                               const S* __restrict__ psi, const cpx<S>* __restrict__ wts,
                                               const double* __restrict__ x, const S* __restrict__ tod_in,
-                                              S* __restrict__ tod_out, double* __restrict__ q) {
+                                              S* __restrict__ tod_out, double* __restrict__ q, int32_t variant) {
   using P = Plan<C>;
   using F = Fft<C>;
   using A = Angle<C, S, kW>;
@@ -312,7 +312,7 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
     // fits (the FFT buffer is free until the first pass)
     double* xs = reinterpret_cast<double*>(buf);
     const int xspan = amax - amin + 1;
-    const bool staged = amax >= amin && xspan <= kXPixels;
+    const bool staged = amax >= amin && xspan <= kXPixels && (variant & kOpNoStaging) == 0;
     if (staged) {
       // pixel p of the window at xs[4p .. 4p+2]: 32-byte stride keeps the
       // (I, Q) pair 16-byte aligned for one LDS read
@@ -480,18 +480,25 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(
     const FftTile* __restrict__ tiles, int64_t n_tiles, int32_t lambda, const cpx<C>* __restrict__ ab,
     const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
     const cpx<S>* __restrict__ wts, const double* __restrict__ x, const S* __restrict__ tod_in,
-    S* __restrict__ tod_out, double* __restrict__ q, RhsBatch rb) {
-  const int64_t per_xcd = (n_tiles + 7) / 8;
-  const int64_t local = blockIdx.x / 8;
-  const int64_t tile = (int64_t)(blockIdx.x % 8) * per_xcd + local / rb.nrhs;
-  const int rhs = (int)(local % rb.nrhs);
+    S* __restrict__ tod_out, double* __restrict__ q, RhsBatch rb, int32_t variant) {
+  int64_t tile;
+  int rhs;
+  if (variant & kOpLinearOrder) {  // tiles in launch order
+    tile = blockIdx.x / rb.nrhs;
+    rhs = (int)(blockIdx.x % rb.nrhs);
+  } else {
+    const int64_t per_xcd = (n_tiles + 7) / 8;
+    const int64_t local = blockIdx.x / 8;
+    tile = (int64_t)(blockIdx.x % 8) * per_xcd + local / rb.nrhs;
+    rhs = (int)(local % rb.nrhs);
+  }
   if (tile >= n_tiles) return;
   if (rb.done != nullptr && rb.done[(int64_t)rhs * rb.done_stride]) return;
   if (x != nullptr) x += rhs * rb.vstride;
   q += rhs * rb.vstride;
   const FftTile tl = tiles[tile];
   toeplitz_tile<S, C, kIn, kOut, kW>(tl, lambda, ab + (int64_t)tl.filter * Plan<C>::N, tw, sample_k, psi, wts, x,
-                                     tod_in, tod_out, q);
+                                     tod_in, tod_out, q, variant);
 }
 
 // One launch over the tiles of several slots (right-hand sides of different
@@ -526,19 +533,19 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_ba
   const FftTile tl = static_cast<const FftTile*>(o.tiles)[idx];
   toeplitz_tile<S, C, 1, 1, kW>(tl, o.lambda, static_cast<const cpx<C>*>(o.ab) + (int64_t)tl.filter * Plan<C>::N,
                                 static_cast<const cpx<C>*>(o.tw), o.sample_k, static_cast<const S*>(o.psi),
-                                static_cast<const cpx<S>*>(o.wts), o.x, nullptr, nullptr, o.q);
+                                static_cast<const cpx<S>*>(o.wts), o.x, nullptr, nullptr, o.q, o.variant);
 }
 
 template <class S, class C, int kIn, int kOut, int kW>
 int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod_in, void* tod_out,
-             double* q, const RhsBatch& rb, hipStream_t s) {
+             double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
   const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8) * rb.nrhs;
   hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
                      nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
                      pt ? pt->sample_k : nullptr, pt ? (const S*)pt->psi : nullptr,
-                     pt ? (const cpx<S>*)pt->weights : nullptr, x, (const S*)tod_in, (S*)tod_out, q, rb);
+                     pt ? (const cpx<S>*)pt->weights : nullptr, x, (const S*)tod_in, (S*)tod_out, q, rb, variant);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
@@ -550,18 +557,18 @@ inline bool use_weights(const mm_pointing_s* pt, int arith) {
 
 template <int kIn, int kOut>
 int dispatch(const mm_pointing_s* pt, const mm_noise_s* nz, int dtype, int arith, const double* x,
-             const void* tod_in, void* tod_out, double* q, const RhsBatch& rb, hipStream_t s) {
+             const void* tod_in, void* tod_out, double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
   const bool w = kOut == 1 && use_weights(pt, arith);
   if (dtype == MM_F64) {
     if (arith == MM_F64)
-      return w ? launch_t<double, double, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s)
-               : launch_t<double, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s);
-    return w ? launch_t<double, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s)
-             : launch_t<double, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s);
+      return w ? launch_t<double, double, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s, variant)
+               : launch_t<double, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
+    return w ? launch_t<double, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s, variant)
+             : launch_t<double, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
   }
-  if (arith == MM_F64) return launch_t<float, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s);
-  return w ? launch_t<float, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s)
-           : launch_t<float, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s);
+  if (arith == MM_F64) return launch_t<float, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
+  return w ? launch_t<float, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s, variant)
+           : launch_t<float, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
 }
 
 }  // namespace
@@ -596,13 +603,13 @@ int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, 
 
 int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
                          hipStream_t s) {
-  return dispatch<0, 0>(pt, nz, pt->dtype, arith, nullptr, in, out, nullptr, RhsBatch{}, s);
+  return dispatch<0, 0>(pt, nz, pt->dtype, arith, nullptr, in, out, nullptr, RhsBatch{}, s, 0);
 }
 
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
-                          double* q, int arith, const RhsBatch& rb, hipStream_t s) {
-  if (x != nullptr) return dispatch<1, 1>(pt, nz, pt->dtype, arith, x, nullptr, nullptr, q, rb, s);
-  return dispatch<0, 1>(pt, nz, pt->dtype, arith, nullptr, tod, nullptr, q, rb, s);
+                          double* q, int arith, const RhsBatch& rb, hipStream_t s, int32_t variant) {
+  if (x != nullptr) return dispatch<1, 1>(pt, nz, pt->dtype, arith, x, nullptr, nullptr, q, rb, s, variant);
+  return dispatch<0, 1>(pt, nz, pt->dtype, arith, nullptr, tod, nullptr, q, rb, s, variant);
 }
 
 }  // namespace mm

@@ -177,3 +177,36 @@ def test_serving_poisson_stream_latencies():
     assert len(res) == 7 and all(r.info["converged"] == 1 for r in res)
     lat = np.array([r.latency for r in res])
     assert np.all(lat > 0) and np.all(np.array([r.admitted for r in res]) >= np.array([r.arrival for r in res]) - 1e-9)
+
+
+def test_operator_variants_agree_and_autotune():
+    """Every band-Toeplitz operator variant (tile order, map staging) gives
+    the same solve; the autotuner picks one of them and remembers it."""
+    b = _b()
+    pt, nz, opt, noise, ds = _device_problem(SMALL_T)
+    pt.attach_weights()
+    td = torch.from_numpy(ds[0]).to(DEV)
+    ref = b.Solver(pt, nz, tol=1e-12).solve(td)
+    for v in range(4):
+        out = b.Solver(pt, nz, tol=1e-12, op_variant=v).solve(td)
+        assert out["info"]["op_variant"] == v
+        err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), ref["x"].cpu().numpy())
+        assert np.all(err < 1e-10), (v, err)
+    tuned = b.Solver(pt, nz, tol=1e-12, autotune=1).solve(td)
+    assert 0 <= tuned["info"]["op_variant"] < 4
+    err = oracle.rel_l2_per_stokes(tuned["x"].cpu().numpy(), ref["x"].cpu().numpy())
+    assert np.all(err < 1e-10), err
+    again = b.Solver(pt, nz, tol=1e-12, autotune=1).solve(td)  # remembered by the noise handle
+    assert again["info"]["op_variant"] == tuned["info"]["op_variant"]
+    with pytest.raises(b.MapMakerError):
+        b.Solver(pt, nz, op_variant=4).solve(td)
+    # the FP32 inner operator with refinement, tuned
+    w32 = SMALL_T.replace(precision="f32")
+    pt32, nz32, opt32, noise32, ds32 = _device_problem(w32)
+    pt32.attach_weights()
+    out = b.Solver(pt32, nz32, tol=1e-12, mixed=1, max_outer=20, autotune=1).solve(
+        torch.from_numpy(ds32[0]).to(DEV))
+    assert out["info"]["converged"] == 1 and 0 <= out["info"]["op_variant"] < 4
+    _, _, x_ref = oracle.solve(opt32, noise32, ds32[0].astype(np.float64), tol=1e-13)
+    err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref)
+    assert np.all(err < 1e-9), err
