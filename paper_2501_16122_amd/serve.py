@@ -10,6 +10,11 @@ different requests overlaps on the device; solves whose state copy shows
 convergence are finished (true residual, full-grid map), their memory is
 released, and waiting requests are admitted in their place.
 
+Two ways to overlap the active solves: one stream per solve (the default),
+or batched, where every tick enqueues one shared step for all active solves
+(mm_batch_step: one operator launch per iteration over the tiles of every
+solve, one launch per PCG vector step over all of them) on a single stream.
+
 All computation runs in libmapmaker's kernels; this module only schedules.
 """
 from __future__ import annotations
@@ -123,7 +128,7 @@ class Server:
     """Admit, advance and retire map-making solves with overlapping work."""
 
     def __init__(self, device="cuda:0", hbm_budget: Optional[int] = None, max_slots: int = 8, k_chunk: int = 8,
-                 n_streams: int = 8, use_weights: bool = True, **solve_opts):
+                 n_streams: int = 8, use_weights: bool = True, batched: bool = False, **solve_opts):
         import torch
         self.dev = torch.device(device)
         if hbm_budget is None:
@@ -135,7 +140,13 @@ class Server:
         self.opts = dict(tol=1e-10, mixed=1, check_every=k_chunk)
         self.opts.update(solve_opts)
         self._sopts = b.solve_opts(**self.opts)
-        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_streams)]
+        # batched: every active solve advances in the same launches
+        # (mm_batch_step, at most 16 right-hand sides), on one stream;
+        # otherwise each solve runs on a stream of its own and the streams overlap
+        self.batched = batched
+        if batched and max_slots > 16:
+            raise ValueError("batched serving takes at most 16 slots")
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(1 if batched else n_streams)]
         self.use_weights = use_weights
         self.pending: collections.deque = collections.deque()
         self.active: list = []
@@ -143,6 +154,7 @@ class Server:
         self.results: list = []
         self.peak_slots = 0
         self.peak_bytes = 0
+        self.depth = 0  # batched mode: shared steps in flight
 
     def submit(self, req: Request):
         self.pending.append(req)
@@ -188,21 +200,16 @@ class Server:
                 if nxt > 0:
                     time.sleep(min(nxt, 0.01))
                 continue
+            if self.batched:
+                self._tick_batched(t0, on_result)
+                continue
             progressed = False
             still = []
             for slot in self.active:
                 done, in_flight = slot.solver.poll()
                 if done:
-                    out = slot.solver.finish()
-                    w = slot.req.workload
-                    res = Result(slot.req.rid, out["maps"][0].cpu().numpy().reshape(w.n_pix, 3), out["info"][0],
-                                 slot.req.arrival, slot.admitted, time.perf_counter() - t0)
-                    self.in_use -= slot.fp
-                    slot.release()
-                    self.results.append(res)
+                    self._retire(slot, t0, on_result)
                     progressed = True
-                    if on_result:
-                        on_result(res)
                     continue
                 still.append(slot)
                 if not in_flight:
@@ -215,6 +222,38 @@ class Server:
             if not progressed:
                 time.sleep(0.0002)
         return self.results
+
+    def _retire(self, slot, t0, on_result):
+        out = slot.solver.finish()
+        w = slot.req.workload
+        res = Result(slot.req.rid, out["maps"][0].cpu().numpy().reshape(w.n_pix, 3), out["info"][0],
+                     slot.req.arrival, slot.admitted, time.perf_counter() - t0)
+        self.in_use -= slot.fp
+        slot.release()
+        self.results.append(res)
+        if on_result:
+            on_result(res)
+
+    def _tick_batched(self, t0, on_result):
+        """One scheduler tick of the batched mode: retire finished solves, then
+        enqueue one shared step of k iterations for all the others (at most two
+        steps in flight)."""
+        still, in_flight = [], False
+        for slot in self.active:
+            done, flight = slot.solver.poll()
+            if done:
+                self._retire(slot, t0, on_result)
+            else:
+                still.append(slot)
+                in_flight = in_flight or flight
+        self.active = still
+        if not in_flight:
+            self.depth = 0
+        if still and self.depth < 2:
+            b.batch_step([sl.solver for sl in still], self.k_chunk)
+            self.depth += 1
+        elif still:
+            time.sleep(0.0002)
 
 
 def poisson_requests(n: int, rate: float, sizes: Callable[[np.random.Generator, int], synth.Workload],

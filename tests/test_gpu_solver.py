@@ -153,6 +153,28 @@ def test_serving_mix_equals_alone():
         assert np.all(err < 1e-9), (r.rid, err)
 
 
+def test_batched_serving_mix_equals_alone():
+    """The batched server (one shared step for all active solves) gives each
+    request the result it gets alone."""
+    from paper_2501_16122_amd import serve
+    reqs, _ = _serving_requests()
+    alone = {r.rid: r for r in serve.Server(DEV, max_slots=1, k_chunk=8, tol=1e-12, max_outer=20).run(
+        reqs, realtime=False)}
+    reqs2, _ = _serving_requests()
+    srv = serve.Server(DEV, max_slots=8, k_chunk=8, tol=1e-12, max_outer=20, batched=True)
+    mix = {r.rid: r for r in srv.run(reqs2, realtime=False)}
+    assert srv.peak_slots >= 2
+    assert sorted(alone) == sorted(mix) == list(range(7))
+    for rid in alone:
+        a, m = alone[rid], mix[rid]
+        assert m.info["converged"] == 1 and m.info["true_rel_resid"] <= 1e-12
+        mask = np.any(a.map != 0, axis=1)
+        err = oracle.rel_l2_per_stokes(m.map[mask], a.map[mask])
+        assert np.all(err < 1e-10), (rid, err)
+    with pytest.raises(ValueError):
+        serve.Server(DEV, max_slots=17, batched=True)
+
+
 def test_serving_respects_memory_budget():
     from paper_2501_16122_amd import serve
     reqs, _ = _serving_requests()
