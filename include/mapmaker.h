@@ -188,7 +188,9 @@ typedef struct {
                            handle per problem size); 0: use op_variant                       */
   int32_t op_variant;   /* variant when not autotuned (default 0): bit 0 = tiles in launch
                            order instead of the XCD-aware order, bit 1 = map read from
-                           global memory instead of staged in LDS                          */
+                           global memory instead of staged in LDS, bit 2 = shorter tiles in
+                           runs that carry the overlapping half-window from tile to tile
+                           (needs stored pointing weights; never stages)                    */
   int32_t reserved_;
 } mm_solve_opts;
 

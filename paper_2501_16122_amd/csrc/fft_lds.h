@@ -122,6 +122,15 @@ __device__ __forceinline__ void dft_reg(cpx<C>* a) {
   for (int i = 0; i < R; ++i) a[i] = t[i];
 }
 
+// Thread index as an opaque value: each pass derives its LDS addresses from
+// it afresh, so the compiler cannot hoist (and keep live, or spill) the
+// addresses of every pass when the FFT runs inside a loop over tiles.
+__device__ __forceinline__ int fft_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // LDS index with one pad element every 16, which staggers the strided
 // accesses of the passes across banks.
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
@@ -134,11 +143,12 @@ __device__ __forceinline__ void pass_compute(cpx<C>* v, const cpx<C>* __restrict
   constexpr int E = N / T;
   constexpr int BPT = E / R;
   static_assert(BPT * R == E, "radix must divide the elements per thread");
+  const int tid = fft_tid();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     cpx<C>* a = v + b * R;
     if (Ns > 1) {
-      const int j = threadIdx.x + b * T;
+      const int j = tid + b * T;
       const int k = j & (Ns - 1);
       cpx<C> w1 = tw[k * (N / (Ns * R))];
       if (!kFwd) w1.y = -w1.y;
@@ -156,9 +166,10 @@ __device__ __forceinline__ void pass_compute(cpx<C>* v, const cpx<C>* __restrict
 template <class C, int N, int T, int R, int Ns>
 __device__ __forceinline__ void pass_store(cpx<C>* buf, const cpx<C>* v) {
   constexpr int BPT = N / T / R;
+  const int tid = fft_tid();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int j = threadIdx.x + b * T;
+    const int j = tid + b * T;
     const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
 #pragma unroll
     for (int q = 0; q < R; ++q) buf[lds_pad(base + q * Ns)] = v[b * R + q];
@@ -168,9 +179,10 @@ __device__ __forceinline__ void pass_store(cpx<C>* buf, const cpx<C>* v) {
 template <class C, int N, int T, int R>
 __device__ __forceinline__ void pass_load(const cpx<C>* buf, cpx<C>* v) {
   constexpr int BPT = N / T / R;
+  const int tid = fft_tid();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int j = threadIdx.x + b * T;
+    const int j = tid + b * T;
 #pragma unroll
     for (int m = 0; m < R; ++m) v[b * R + m] = buf[lds_pad(j + m * (N / R))];
   }

@@ -56,6 +56,20 @@ struct FftTile {
 };
 static_assert(sizeof(FftTile) == 40, "FftTile layout");
 
+// Halo-carrying tiles: consecutive tiles of one chunk start kCarryStride[a]
+// samples apart, a multiple of the 1024 window positions one element of
+// every thread covers, so the gathered P x of a window's last kCarryElems
+// elements is the next window's first, in the same registers.  A segment is
+// a run of up to kSegTiles such tiles of one chunk, handled by one workgroup
+// in order.
+constexpr int kCarryElems = 8;
+constexpr int kSegTiles = 16;
+struct CarrySeg {
+  int64_t first;  // index of its first tile in the halo-carrying tile list
+  int32_t count;
+  int32_t pad_;
+};
+
 // Real-signal length L and complex FFT length N = L/2 per arithmetic.
 // FP64: L = 2^14 (8192 complex doubles = 128 KiB of LDS);
 // FP32: L = 2^15 (16384 complex floats = 128 KiB of LDS).
@@ -126,6 +140,10 @@ struct mm_noise_s {
   // per arithmetic (0 = FP64, 1 = FP32): tiles, spectral weights, twiddles
   mm::FftTile* tiles[2] = {nullptr, nullptr};
   int64_t n_tiles[2] = {0, 0};
+  // halo-carrying tiles and their segments, per arithmetic
+  mm::FftTile* ctiles[2] = {nullptr, nullptr};
+  mm::CarrySeg* csegs[2] = {nullptr, nullptr};
+  int64_t n_csegs[2] = {0, 0};
   void* ab[2] = {nullptr, nullptr};  // [n_filt][N] pairs (alpha_k, beta_k)
   void* tw[2] = {nullptr, nullptr};  // [N] exp(-2 pi i k / N)
   // operator variants picked by the autotuner, per problem shape
@@ -176,7 +194,11 @@ int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const vo
 // XCD-aware order; bit kOpNoStaging reads the map from global memory instead
 // of staging the tile's pixel window in LDS.  Every variant computes the same
 // sums (up to the order of floating-point atomics).
-constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpVariants = 4;
+// Bit kOpCarry uses the halo-carrying tiles: a workgroup walks a segment of
+// consecutive tiles and reuses the P x of the overlap instead of gathering
+// it again (never staged; tile order as bit kOpLinearOrder says; only with
+// stored pointing weights, else the plain tiles are used).
+constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpCarry = 4, kOpVariants = 8;
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
                           double* q, int arith, const RhsBatch& rb, hipStream_t s, int32_t variant = 0);
 int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, size_t ws_bytes,

@@ -88,8 +88,32 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     }
     nz->n_tiles[a] = (int64_t)tiles[a].size();
   }
+  // halo-carrying tiles (stride (E - kCarryElems) * 1024 window positions,
+  // E = N / 512 elements per thread) and their segments
+  std::vector<FftTile> ctiles[2];
+  std::vector<CarrySeg> csegs[2];
+  for (int a = 0; a < 2; ++a) {
+    const int64_t stride = (int64_t)(Ns[a] / 512 - kCarryElems) * 1024;
+    for (int64_t c = 0; c < nz->n_chunks; ++c) {
+      const int64_t c0 = nz->chunk_offsets[c], c1 = nz->chunk_offsets[c + 1];
+      int64_t seg_n = 0;
+      for (int64_t o = c0; o < c1; o += stride) {
+        if (seg_n == 0) csegs[a].push_back(CarrySeg{(int64_t)ctiles[a].size(), 0, 0});
+        ctiles[a].push_back(FftTile{o, o + stride < c1 ? o + stride : c1, c0, c1, nz->chunk_filter[c], 0});
+        csegs[a].back().count += 1;
+        seg_n = seg_n + 1 == kSegTiles ? 0 : seg_n + 1;
+      }
+    }
+    nz->n_csegs[a] = (int64_t)csegs[a].size();
+  }
   FftTile* d_tiles[2];
   for (int a = 0; a < 2; ++a) d_tiles[a] = cv.take<FftTile>(tiles[a].size());
+  FftTile* d_ctiles[2];
+  CarrySeg* d_csegs[2];
+  for (int a = 0; a < 2; ++a) {
+    d_ctiles[a] = cv.take<FftTile>(ctiles[a].size());
+    d_csegs[a] = cv.take<CarrySeg>(csegs[a].size());
+  }
   void* d_ab[2];
   void* d_tw[2];
   d_ab[0] = cv.take<cpx<double>>((size_t)nf * kFftN64);
@@ -121,6 +145,14 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
       MM_HIP(hipMemcpyAsync(d_tiles[a], tiles[a].data(), tiles[a].size() * sizeof(FftTile), hipMemcpyHostToDevice,
                             s));
     nz->tiles[a] = d_tiles[a];
+    if (!ctiles[a].empty()) {
+      MM_HIP(hipMemcpyAsync(d_ctiles[a], ctiles[a].data(), ctiles[a].size() * sizeof(FftTile),
+                            hipMemcpyHostToDevice, s));
+      MM_HIP(hipMemcpyAsync(d_csegs[a], csegs[a].data(), csegs[a].size() * sizeof(CarrySeg),
+                            hipMemcpyHostToDevice, s));
+    }
+    nz->ctiles[a] = d_ctiles[a];
+    nz->csegs[a] = d_csegs[a];
   }
   MM_HIP(hipMemcpyAsync(d_coeff, coeff_host, (size_t)nf * lam * sizeof(double), hipMemcpyHostToDevice, s));
   MM_HIP(hipMemcpyAsync(d_cos, cos_t.data(), cos_t.size() * sizeof(double), hipMemcpyHostToDevice, s));

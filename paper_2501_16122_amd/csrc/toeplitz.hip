@@ -94,9 +94,10 @@ __device__ __forceinline__ void passes(cpx<C>* buf, cpx<C>* v, const cpx<C>* __r
 template <class C, int N, int T, int R>
 __device__ __forceinline__ void spectral_load(const cpx<C>* buf, const cpx<C>* __restrict__ abf, cpx<C>* v) {
   constexpr int BPT = N / T / R;
+  const int tid = fft_tid();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int j = threadIdx.x + b * T;
+    const int j = tid + b * T;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int k = j + m * (N / R);
@@ -126,7 +127,7 @@ __device__ __forceinline__ void middle_r2(cpx<double>* buf, const cpx<double>* _
                                           const cpx<double>* __restrict__ tw) {
   constexpr int H = N / 2, Q = H / 2, PPT = Q / T;
   static_assert(PPT * T == Q, "quadruples must tile the threads");
-  const int tid = threadIdx.x;
+  const int tid = fft_tid();
   cpx<double> o[PPT][4];
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
@@ -228,6 +229,79 @@ struct Angle {
     }
   }
 };
+
+// P^T of one tile's outputs: q[k] += z * (1, cos 2psi, sin 2psi) over the
+// valid window positions [vlo, vhi), through LDS bins over the compact-index
+// window [kmin, kmax].  The window is binned in passes of at most kBinSlots
+// pixels (one pass for compact scans); a pass reads the indices (unless kept
+// in registers: kKeepK) and weights of its own samples only, so wide windows
+// (sparse or large grids) cost extra L2 reads instead of one global atomic
+// per sample.  v holds the outputs in the layout of the first forward pass.
+template <class S, class C, int kW, bool kKeepK>
+__device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, const int32_t* kk,
+                                             const int32_t* __restrict__ sk, const S* __restrict__ ps0,
+                                             const cpx<S>* __restrict__ w0, int32_t vlo, int32_t vhi, int32_t kmin,
+                                             int32_t kmax, double* __restrict__ q) {
+  using P = Plan<C>;
+  using F = Fft<C>;
+  using A = Angle<C, S, kW>;
+  constexpr int N = P::N, T = P::T, E = N / T, GS = P::kScatterBatch;
+  constexpr int kTBinSlots = Lds<C>::kBinSlots;
+  const int tid = threadIdx.x;
+  for (int32_t wlo = kmin; wlo <= kmax; wlo += kTBinSlots) {
+    const int nb = kmax - wlo + 1 < kTBinSlots ? kmax - wlo + 1 : kTBinSlots;
+    // opaque copies of the index view and thread id: keep the per-sample
+    // offsets and loads inside the pass instead of 2E of them hoisted and
+    // held live across all passes
+    const int32_t* skp = sk;
+    int tidp = tid;
+    asm volatile("" : "+s"(skp), "+v"(tidp));
+    for (int i = tid; i < nb; i += T) {
+      bins[i] = 0.0;
+      bins[kTBinSlots + i] = 0.0;
+      bins[2 * kTBinSlots + i] = 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += GS) {
+      __builtin_amdgcn_sched_barrier(0);  // keep one batch of loads in flight at a time
+      int32_t ks[2 * GS];
+      typename A::type ps[2 * GS];
+#pragma unroll
+      for (int i = 0; i < 2 * GS; ++i) {
+        const int pos = 2 * (tidp + T * (e0 + i / 2)) + (i & 1);
+        const bool valid = pos >= vlo && pos < vhi;
+        int32_t k;
+        if constexpr (kKeepK) k = valid ? kk[2 * e0 + i] : -1;
+        else k = valid ? skp[pos] : -1;
+        const int32_t rel = k - wlo;
+        ks[i] = (k >= 0 && rel < nb && rel >= 0) ? rel : -1;
+        ps[i] = ks[i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
+      }
+#pragma unroll
+      for (int i = 0; i < 2 * GS; ++i) {
+        const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
+        const C z = (i & 1) ? o.y : o.x;
+        C c, s;
+        A::eval(ps[i], &c, &s);
+        if (ks[i] >= 0) {
+          atomicAdd(&bins[ks[i]], double(z));
+          atomicAdd(&bins[kTBinSlots + ks[i]], double(z * c));
+          atomicAdd(&bins[2 * kTBinSlots + ks[i]], double(z * s));
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nb; i += T) {
+      const double v0 = bins[i], v1 = bins[kTBinSlots + i], v2 = bins[2 * kTBinSlots + i];
+      double* qk = q + 3 * (int64_t)(wlo + i);
+      if (v0 != 0.0) atomicAdd(qk + 0, v0);
+      if (v1 != 0.0) atomicAdd(qk + 1, v1);
+      if (v2 != 0.0) atomicAdd(qk + 2, v2);
+    }
+    __syncthreads();  // the next pass (or tile) reuses the bins
+  }
+}
 
 // kIn: 0 = timeline input tod_in; 1 = gather P x.
 // kOut: 0 = timeline output tod_out; 1 = scatter q += P^T z.
@@ -411,62 +485,167 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
     kmax = s_red[T / 64 + w] > kmax ? s_red[T / 64 + w] : kmax;
   }
   if (kmax < kmin) return;
-  double* bins = reinterpret_cast<double*>(buf);
-  // The window [kmin, kmax] is binned in passes of at most kTBinSlots pixels
-  // (one pass for compact scans); a pass reads the indices and weights of
-  // its own samples only, so wide windows (sparse or large grids) cost extra
-  // L2 reads instead of one global atomic per sample.
-  for (int32_t wlo = kmin; wlo <= kmax; wlo += kTBinSlots) {
-    const int nb = kmax - wlo + 1 < kTBinSlots ? kmax - wlo + 1 : kTBinSlots;
-    // opaque copy of the index view: keeps its loads inside the pass
-    // instead of 2E indices hoisted and held live across all passes
-    const int32_t* skp = sk;
-    int tidp = tid;
-    asm volatile("" : "+s"(skp), "+v"(tidp));
-    for (int i = tid; i < nb; i += T) {
-      bins[i] = 0.0;
-      bins[kTBinSlots + i] = 0.0;
-      bins[2 * kTBinSlots + i] = 0.0;
-    }
-    __syncthreads();
+  scatter_bins<S, C, kW, kKeepK>(v, reinterpret_cast<double*>(buf), kk, sk, ps0, w0, vlo, vhi, kmin, kmax, q);
+}
+
+// One halo-carrying tile (gather P x, scatter P^T; tiles kStride = (E -
+// kCarryElems) * 2T samples apart, see CarrySeg).  When `have`, the P x of
+// window elements [0, kCarryElems) is this thread's carry from the previous
+// tile of the segment: those window positions are the previous window's
+// last kCarryElems elements, in the same thread.  On return carry holds this
+// window's last kCarryElems elements, and (cmin, cmax) the compact-index
+// range of their samples that are valid outputs of the next tile.  The map
+// is read through L2 (no staging); indices are reloaded for the scatter.
+template <class S, class C, int kW>
+__device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t lambda,
+                                                    const cpx<C>* __restrict__ abf, const cpx<C>* __restrict__ tw,
+                                                    const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
+                                                    const cpx<S>* __restrict__ wts, const double* __restrict__ x,
+                                                    double* __restrict__ q, cpx<C>* carry, bool have, int32_t& cmin,
+                                                    int32_t& cmax) {
+  using P = Plan<C>;
+  using F = Fft<C>;
+  using A = Angle<C, S, kW>;
+  constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch;
+  constexpr int M = E - kCarryElems;  // element shift between consecutive tiles
+  constexpr int kStride = M * 2 * T;
+  static_assert(E == F::RIn && E == F::ROut, "element e must sit in register slot e");
+  static_assert(kCarryElems % G == 0 && M >= kCarryElems, "carried elements must fill whole gather batches");
+  __shared__ cpx<C> buf[lds_elems<N>()];
+  __shared__ int32_t s_red[4 * (P::T / 64)];
+
+  const int64_t in0 = tl.out_start - (lambda - 1);
+  const int32_t vlo = lambda - 1;
+  const int32_t vhi = vlo + (int32_t)(tl.out_end - tl.out_start);
+  const int32_t ilo = (int32_t)(tl.chunk_start > in0 ? tl.chunk_start - in0 : 0);
+  const int32_t ihi = (int32_t)(tl.chunk_end - in0 < L ? tl.chunk_end - in0 : L);
+  const int32_t* __restrict__ sk = sample_k + in0;
+  const S* __restrict__ ps0 = kW == 0 ? psi + in0 : nullptr;
+  const cpx<S>* __restrict__ w0 = kW == 1 ? wts + in0 : nullptr;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));  // per-tile offsets: not hoisted out of the segment loop
+
+  cpx<C> v[E];
+  int32_t kk[2 * E];
 #pragma unroll
-    for (int e0 = 0; e0 < E; e0 += GS) {
-      __builtin_amdgcn_sched_barrier(0);  // keep one batch of loads in flight at a time
-      int32_t ks[2 * GS];
-      typename A::type ps[2 * GS];
+  for (int i = 0; i < 2 * E; ++i) {
+    const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
+    const bool fresh = !(have && i / 2 < kCarryElems);
+    kk[i] = (fresh && pos >= ilo && pos < ihi) ? sk[pos] : -1;
+  }
+  int32_t kmin = INT32_MAX, kmax = -1, nmin = INT32_MAX, nmax = -1;
 #pragma unroll
-      for (int i = 0; i < 2 * GS; ++i) {
-        const int pos = 2 * (tidp + T * (e0 + i / 2)) + (i & 1);
-        const bool valid = pos >= vlo && pos < vhi;
-        int32_t k;
-        if constexpr (kKeepK) k = valid ? kk[2 * e0 + i] : -1;
-        else k = valid ? skp[pos] : -1;
-        const int32_t rel = k - wlo;
-        ks[i] = (k >= 0 && rel < nb && rel >= 0) ? rel : -1;
-        ps[i] = ks[i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
+  for (int i = 0; i < 2 * E; ++i) {
+    const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
+    if (kk[i] >= 0) {
+      if (pos >= vlo && pos < vhi) {
+        kmin = kk[i] < kmin ? kk[i] : kmin;
+        kmax = kk[i] > kmax ? kk[i] : kmax;
       }
+      if (pos >= vlo + kStride) {
+        nmin = kk[i] < nmin ? kk[i] : nmin;
+        nmax = kk[i] > nmax ? kk[i] : nmax;
+      }
+    }
+  }
+  kmin = wave_min(kmin);
+  kmax = wave_max(kmax);
+  nmin = wave_min(nmin);
+  nmax = wave_max(nmax);
+  constexpr int W = T / 64;
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6] = kmin;
+    s_red[W + (tid >> 6)] = kmax;
+    s_red[2 * W + (tid >> 6)] = nmin;
+    s_red[3 * W + (tid >> 6)] = nmax;
+  }
+  // P x of the fresh elements, in batches of pointing weights
 #pragma unroll
-      for (int i = 0; i < 2 * GS; ++i) {
-        const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
-        const C z = (i & 1) ? o.y : o.x;
+  for (int e0 = 0; e0 < E; e0 += G) {
+    if (have && e0 < kCarryElems) {
+#pragma unroll
+      for (int e = e0; e < e0 + G; ++e) v[e] = carry[e];
+      continue;
+    }
+    __builtin_amdgcn_sched_barrier(0);  // one batch of loads in flight at a time
+    typename A::type ps[2 * G];
+#pragma unroll
+    for (int i = 0; i < 2 * G; ++i) {
+      const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
+      ps[i] = kk[2 * e0 + i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * G; ++i) {
+      const int32_t k = kk[2 * e0 + i];
+      C val = C(0);
+      if (k >= 0) {
         C c, s;
         A::eval(ps[i], &c, &s);
-        if (ks[i] >= 0) {
-          atomicAdd(&bins[ks[i]], double(z));
-          atomicAdd(&bins[kTBinSlots + ks[i]], double(z * c));
-          atomicAdd(&bins[2 * kTBinSlots + ks[i]], double(z * s));
-        }
+        const double* xk = x + 3 * (int64_t)k;
+        val = C(xk[0]) + c * C(xk[1]) + s * C(xk[2]);
       }
+      if (i & 1) v[e0 + i / 2].y = val;
+      else v[e0 + i / 2].x = val;
     }
-    __syncthreads();
-    for (int i = tid; i < nb; i += T) {
-      const double v0 = bins[i], v1 = bins[kTBinSlots + i], v2 = bins[2 * kTBinSlots + i];
-      double* qk = q + 3 * (int64_t)(wlo + i);
-      if (v0 != 0.0) atomicAdd(qk + 0, v0);
-      if (v1 != 0.0) atomicAdd(qk + 1, v1);
-      if (v2 != 0.0) atomicAdd(qk + 2, v2);
-    }
-    __syncthreads();  // the next pass clears the bins
+  }
+#pragma unroll
+  for (int c = 0; c < kCarryElems; ++c) carry[c] = v[M + c];
+  __syncthreads();
+  kmin = s_red[0];
+  kmax = s_red[W];
+  nmin = s_red[2 * W];
+  nmax = s_red[3 * W];
+#pragma unroll
+  for (int w = 1; w < W; ++w) {
+    kmin = s_red[w] < kmin ? s_red[w] : kmin;
+    kmax = s_red[W + w] > kmax ? s_red[W + w] : kmax;
+    nmin = s_red[2 * W + w] < nmin ? s_red[2 * W + w] : nmin;
+    nmax = s_red[3 * W + w] > nmax ? s_red[3 * W + w] : nmax;
+  }
+  if (have) {  // valid outputs among the carried positions
+    kmin = cmin < kmin ? cmin : kmin;
+    kmax = cmax > kmax ? cmax : kmax;
+  }
+  cmin = nmin;
+  cmax = nmax;
+
+  F::template forward<N, T>(buf, v, tw);
+  F::template inverse<N, T>(buf, abf, v, tw);
+  __syncthreads();  // every thread is done reading buf
+  scatter_bins<S, C, kW, false>(v, reinterpret_cast<double*>(buf), nullptr, sk, ps0, w0, vlo, vhi, kmin, kmax, q);
+}
+
+// Segments of halo-carrying tiles, one segment (of one right-hand side) per
+// workgroup, mapped to workgroups like k_toeplitz maps tiles.
+template <class S, class C, int kW>
+__global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_carry(
+    const FftTile* __restrict__ tiles, const CarrySeg* __restrict__ segs, int64_t n_segs, int32_t lambda,
+    const cpx<C>* __restrict__ ab, const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k,
+    const S* __restrict__ psi, const cpx<S>* __restrict__ wts, const double* __restrict__ x, double* __restrict__ q,
+    RhsBatch rb, int32_t variant) {
+  int64_t seg;
+  int rhs;
+  if (variant & kOpLinearOrder) {
+    seg = blockIdx.x / rb.nrhs;
+    rhs = (int)(blockIdx.x % rb.nrhs);
+  } else {
+    const int64_t per_xcd = (n_segs + 7) / 8;
+    const int64_t local = blockIdx.x / 8;
+    seg = (int64_t)(blockIdx.x % 8) * per_xcd + local / rb.nrhs;
+    rhs = (int)(local % rb.nrhs);
+  }
+  if (seg >= n_segs) return;
+  if (rb.done != nullptr && rb.done[(int64_t)rhs * rb.done_stride]) return;
+  x += rhs * rb.vstride;
+  q += rhs * rb.vstride;
+  const CarrySeg sg = segs[seg];
+  cpx<C> carry[kCarryElems];
+  int32_t cmin = INT32_MAX, cmax = -1;
+  for (int t = 0; t < sg.count; ++t) {
+    const FftTile tl = tiles[sg.first + t];
+    toeplitz_tile_carry<S, C, kW>(tl, lambda, ab + (int64_t)tl.filter * Plan<C>::N, tw, sample_k, psi, wts, x, q,
+                                  carry, t > 0, cmin, cmax);
+    __syncthreads();  // the next tile reuses the LDS
   }
 }
 
@@ -541,6 +720,19 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
              double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
+  // the halo-carrying form streams stored weights (with psi it spills)
+  if constexpr (kIn == 1 && kOut == 1 && kW == 1) {
+    if (variant & kOpCarry) {
+      if (nz->n_csegs[a] == 0) return MM_OK;
+      const int64_t g = 8 * ((nz->n_csegs[a] + 7) / 8) * rb.nrhs;
+      hipLaunchKernelGGL((k_toeplitz_carry<S, C, kW>), dim3(g), dim3(Plan<C>::T), 0, s, nz->ctiles[a],
+                         nz->csegs[a], nz->n_csegs[a], nz->lambda, (const cpx<C>*)nz->ab[a],
+                         (const cpx<C>*)nz->tw[a], pt->sample_k, (const S*)pt->psi,
+                         (const cpx<S>*)pt->weights, x, q, rb, variant);
+      MM_HIP(hipGetLastError());
+      return MM_OK;
+    }
+  }
   const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8) * rb.nrhs;
   hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
                      nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
