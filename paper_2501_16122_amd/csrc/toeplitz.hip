@@ -237,11 +237,17 @@ struct Angle {
 // in registers: kKeepK) and weights of its own samples only, so wide windows
 // (sparse or large grids) cost extra L2 reads instead of one global atomic
 // per sample.  v holds the outputs in the layout of the first forward pass.
-template <class S, class C, int kW, bool kKeepK>
+// Elements [kKeepW0, kKeepW1) of each thread (FP64 plan) hold most valid
+// outputs at lambda = 4096; their pointing weights can stay in registers from
+// the gather (wk) instead of being read again.
+constexpr int kKeepW0 = 5, kKeepW1 = 11;
+
+template <class S, class C, int kW, bool kKeepK, bool kKeepW = false>
 __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, const int32_t* kk,
                                              const int32_t* __restrict__ sk, const S* __restrict__ ps0,
                                              const cpx<S>* __restrict__ w0, int32_t vlo, int32_t vhi, int32_t kmin,
-                                             int32_t kmax, double* __restrict__ q) {
+                                             int32_t kmax, double* __restrict__ q,
+                                             const typename Angle<C, S, kW>::type* wk = nullptr) {
   using P = Plan<C>;
   using F = Fft<C>;
   using A = Angle<C, S, kW>;
@@ -276,7 +282,11 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
         else k = valid ? skp[pos] : -1;
         const int32_t rel = k - wlo;
         ks[i] = (k >= 0 && rel < nb && rel >= 0) ? rel : -1;
-        ps[i] = ks[i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
+        const int e = e0 + i / 2;
+        if (kKeepW && e >= kKeepW0 && e < kKeepW1)
+          ps[i] = ks[i] >= 0 ? wk[2 * (e - kKeepW0) + (i & 1)] : A::zero();
+        else
+          ps[i] = ks[i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
       }
 #pragma unroll
       for (int i = 0; i < 2 * GS; ++i) {
@@ -342,7 +352,9 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
   // With 16 elements per thread the compact indices stay in registers from
   // the gather to the scatter (no reload); with 32 they would not fit.
   constexpr bool kKeepK = kIn == 1 && kOut == 1 && E <= 16;
+  constexpr bool kKeepW = kKeepK && kW == 1 && E == 16;
   int32_t kk[2 * E];
+  typename A::type wk[kKeepW ? 2 * (kKeepW1 - kKeepW0) : 1];
   if constexpr (kIn == 1) {
     // (1) compact index of every window sample of this thread, one batch
 #pragma unroll
@@ -406,6 +418,10 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
       for (int i = 0; i < 2 * G; ++i) {
         const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
         ps[i] = kk[2 * e0 + i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
+        if constexpr (kKeepW) {
+          const int e = e0 + i / 2;
+          if (e >= kKeepW0 && e < kKeepW1) wk[2 * (e - kKeepW0) + (i & 1)] = ps[i];
+        }
       }
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
@@ -485,7 +501,8 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
     kmax = s_red[T / 64 + w] > kmax ? s_red[T / 64 + w] : kmax;
   }
   if (kmax < kmin) return;
-  scatter_bins<S, C, kW, kKeepK>(v, reinterpret_cast<double*>(buf), kk, sk, ps0, w0, vlo, vhi, kmin, kmax, q);
+  scatter_bins<S, C, kW, kKeepK, kKeepW>(v, reinterpret_cast<double*>(buf), kk, sk, ps0, w0, vlo, vhi, kmin, kmax, q,
+                                         wk);
 }
 
 // One halo-carrying tile (gather P x, scatter P^T; tiles kStride = (E -
