@@ -205,9 +205,48 @@ def apply_ninv_toeplitz(noise: ToeplitzNoise, y: np.ndarray) -> np.ndarray:
     return z
 
 
+@dataclasses.dataclass
+class CirculantNoise(ToeplitzNoise):
+    """Circulant N^-1 on each stationary chunk (Sec. IV): the chunk is taken
+    as periodic, and its first row holds the band filter c_0 .. c_{lam-1} and
+    its mirror image, so the product is a circular convolution, diagonal in
+    the Fourier basis of the chunk.  Chunks must be longer than 2 (lam - 1)."""
+
+
+def circulant_noise(coeff, chunk_offsets, chunk_filter=None) -> CirculantNoise:
+    t = toeplitz_noise(coeff, chunk_offsets, chunk_filter)
+    lens = np.diff(t.chunk_offsets)
+    if np.any((lens > 0) & (lens <= 2 * (t.lam - 1))):
+        raise ValueError("a circulant chunk must be longer than 2 (lam - 1)")
+    return CirculantNoise(t.coeff, t.chunk_offsets, t.chunk_filter)
+
+
+def apply_ninv_circulant(noise: CirculantNoise, y: np.ndarray) -> np.ndarray:
+    """z = h (*) y per chunk, the circular convolution with the chunk's first
+    row h (h_tau = h_{n - tau} = c_tau for tau < lam, 0 elsewhere), by the
+    FFT of the chunk."""
+    y = np.asarray(y, dtype=np.float64)
+    z = np.zeros_like(y)
+    offs = noise.chunk_offsets
+    for ci in range(offs.size - 1):
+        a, b = int(offs[ci]), int(offs[ci + 1])
+        n = b - a
+        if n <= 0:
+            continue
+        c = noise.coeff[noise.chunk_filter[ci]]
+        h = np.zeros(n)
+        h[:c.size] = c
+        if c.size > 1:
+            h[n - c.size + 1:] = c[:0:-1]
+        z[a:b] = np.fft.irfft(np.fft.rfft(y[a:b]) * np.fft.rfft(h), n)
+    return z
+
+
 def apply_ninv(pt: Pointing, noise, y):
     if noise is None:
         return apply_ninv_white(pt, y)
+    if isinstance(noise, CirculantNoise):
+        return apply_ninv_circulant(noise, y)
     return apply_ninv_toeplitz(noise, y)
 
 

@@ -502,3 +502,81 @@ def test_planted_transposed_inverse_block(monkeypatch):
     monkeypatch.setattr(om, "apply_M", bad)
     assert not _run_pin(test_apply_M_is_inverse_block)
     monkeypatch.setattr(om, "apply_M", real)
+
+
+# ---- circulant N^-1 per chunk (Sec. IV) ------------------------------------
+
+def _dense_circulant(c, n):
+    """Row i, column j: c_d with d the distance between i and j around a
+    circle of n samples, when d < len(c); built entry by entry."""
+    lam = len(c)
+    m = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            d = abs(i - j)
+            d = min(d, n - d)
+            if d < lam:
+                m[i, j] = c[d]
+    return m
+
+
+def test_circulant_matches_dense_and_toeplitz_interior():
+    rng = np.random.default_rng(31)
+    c = rng.normal(size=7)
+    offs = np.array([0, 40, 40, 97])  # an empty chunk and a ragged one
+    y = rng.normal(size=97)
+    z = oracle.apply_ninv_circulant(oracle.circulant_noise(c, offs), y)
+    for a, b in [(0, 40), (40, 97)]:
+        assert np.allclose(z[a:b], _dense_circulant(c, b - a) @ y[a:b], rtol=1e-12, atol=1e-12)
+    # away from the chunk edges the wrap does not reach: Toeplitz outputs
+    zt = oracle.apply_ninv_toeplitz(oracle.toeplitz_noise(c, offs), y)
+    for a, b in [(0, 40), (40, 97)]:
+        assert np.allclose(z[a + 6:b - 6], zt[a + 6:b - 6], rtol=1e-12, atol=1e-12)
+        assert not np.allclose(z[a:a + 6], zt[a:a + 6])
+
+
+def test_circulant_invariants():
+    rng = np.random.default_rng(32)
+    c = rng.normal(size=16)
+    n = 128
+    nz = oracle.circulant_noise(c, [0, n])
+    y = rng.normal(size=n)
+    # shift invariance around the chunk
+    assert np.allclose(oracle.apply_ninv_circulant(nz, np.roll(y, 5)),
+                       np.roll(oracle.apply_ninv_circulant(nz, y), 5), rtol=1e-12, atol=1e-12)
+    # the constant vector is an eigenvector with eigenvalue c_0 + 2 sum c_tau
+    one = np.ones(n)
+    assert np.allclose(oracle.apply_ninv_circulant(nz, one), (c[0] + 2 * c[1:].sum()) * one, rtol=1e-12)
+    # chunks too short for the band are refused
+    with pytest.raises(ValueError):
+        oracle.circulant_noise(c, [0, 30])
+
+
+def test_tapered_circulant_is_spd():
+    w = synth.Workload("spd_c", 911, 8, 8, 1, 1 << 14, noise="oneoverf", chunk=1 << 14, lam=256)
+    c = synth.toeplitz_coeff(w)
+    nz = oracle.circulant_noise(c, [0, 4096])
+    # symmetric: eigenvalues are the real spectrum of the first row
+    h = oracle.apply_ninv_circulant(nz, np.eye(1, 4096, 0).ravel())
+    ev = np.fft.rfft(h).real
+    assert ev.min() > 0
+
+
+def test_planted_circulant_mirror_off_by_one(monkeypatch):
+    orig = oracle.apply_ninv_circulant
+
+    def wrong(noise, y):
+        c = noise.coeff[0]
+        n = y.size
+        h = np.zeros(n)
+        h[:c.size] = c
+        h[n - c.size + 1:] = c[:-1][::-1]  # mirror shifted by one lag: h[n - tau] = c[tau - 1]
+        return np.fft.irfft(np.fft.rfft(y) * np.fft.rfft(h), n)
+
+    monkeypatch.setattr(oracle, "apply_ninv_circulant", wrong)
+    rng = np.random.default_rng(33)
+    c = rng.normal(size=5)
+    y = rng.normal(size=30)
+    z = oracle.apply_ninv_circulant(oracle.circulant_noise(c, [0, 30]), y)
+    assert not np.allclose(z, _dense_circulant(c, 30) @ y, rtol=1e-6)
+    assert np.allclose(orig(oracle.circulant_noise(c, [0, 30]), y), _dense_circulant(c, 30) @ y, rtol=1e-12)
