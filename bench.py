@@ -359,6 +359,7 @@ def main():
     ap.add_argument("--multi-rhs", type=int, default=8, help="realisations in the multi-RHS measurement (0 = skip)")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--batch", type=int, default=16, help="uneven solves in the batched measurement (0 = skip)")
+    ap.add_argument("--circulant", type=int, default=1, help="1 = also solve with circulant N^-1 (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: single-GPU only (asked for --gpus {args.gpus}); sharding the timeline across "
@@ -402,13 +403,14 @@ def main():
     d_host = t_d.cpu().numpy() if args.cpu_det > 0 else None
     log(f"inputs resident on the device; {pt0.n_kept} kept pixels")
 
-    def step(psi_t, d_t, mixed):
+    def step(psi_t, d_t, mixed, noise=None, keep_map=False):
         pt = b.Pointing(t_pix, psi_t, offs, wdet, w.n_pix, w.min_hits, w.cond_max)
         if w.toeplitz:
             pt.attach_weights()  # precomputed (cos 2psi, sin 2psi), part of the build
-        s = b.Solver(pt, nz, tol=1e-10, mixed=mixed, timing=1, check_every=8, autotune=1)
+        s = b.Solver(pt, noise if noise is not None else nz, tol=1e-10, mixed=mixed, timing=1, check_every=8,
+                     autotune=1)
         out = s.solve(d_t)
-        return out["info"]
+        return (out["info"], out["map"]) if keep_map else out["info"]
 
     for i in range(args.warmup):
         info = step(t_psi, t_d, 0)
@@ -469,6 +471,39 @@ def main():
         "final_true_rel_resid": max(i["true_rel_resid"] for i in infos),
         "roofline": roof,
     }
+
+    if args.circulant and w.toeplitz:
+        # the same workload with circulant N^-1 (the band filter on periodic
+        # chunks): speed, and accuracy of both maps against the input sky
+        nzc = b.Noise.circulant(coeff, chunks, dev)
+        step(t_psi, t_d, 0, nzc)
+        torch.cuda.synchronize()
+        c_times, c_infos = [], []
+        for i in range(2):
+            ts = time.perf_counter()
+            info_c, map_c = step(t_psi, t_d, 0, nzc, keep_map=True)
+            c_times.append(time.perf_counter() - ts)
+            c_infos.append(info_c)
+        _, map_t = step(t_psi, t_d, 0, None, keep_map=True)
+        kept_np = kept.cpu().numpy()
+        truth = m[kept_np]
+
+        def err(mp):
+            e = mp.cpu().numpy().reshape(-1, 3)[kept_np] - truth
+            return [round(float(np.linalg.norm(e[:, i]) / np.linalg.norm(truth[:, i])), 6) for i in range(3)]
+
+        dm = (map_c - map_t).cpu().numpy().reshape(-1, 3)[kept_np]
+        mt = map_t.cpu().numpy().reshape(-1, 3)[kept_np]
+        result["circulant"] = {
+            "time_to_map_ms": round(1e3 * float(np.median(c_times)), 3), "pcg_iters": c_infos[-1]["iters"],
+            "operator_ms_avg": round(c_infos[-1]["op_ms"] / max(c_infos[-1]["op_launches"], 1), 4),
+            "map_error_vs_input_sky_iqu": {"circulant": err(map_c), "band_toeplitz": err(map_t)},
+            "circulant_vs_band_toeplitz_map_iqu": [
+                round(float(np.linalg.norm(dm[:, i]) / np.linalg.norm(mt[:, i])), 6) for i in range(3)],
+            "note": "same filter (4096 lags, tapered) on each 2^20-sample chunk taken as periodic; FP64, 1e-10; "
+                    "map errors are relative L2 per Stokes of (GLS map - input sky) over kept pixels"}
+        nzc.close()
+        log(f"circulant: {result['circulant']['time_to_map_ms']} ms per map")
 
     if args.fp32_steps > 0:
         psi32 = t_psi.float()

@@ -141,6 +141,17 @@ int mm_noise_toeplitz(const double* coeff_host, int32_t lambda, int32_t n_filt,
                       const int64_t* chunk_offsets_host, const int32_t* chunk_filter_host,
                       int64_t n_chunks, void* workspace, size_t ws_bytes, void* stream,
                       mm_noise_t* out);
+/* Circulant N^-1 per stationary chunk (the structured noise model of
+ * Sec. IV, diagonal in the chunk's Fourier basis): each chunk is taken as
+ * periodic and its first row holds coeff[f][0 .. lambda-1] and their mirror
+ * image, i.e. z_i = sum_j coeff[f][d(i,j)] y_j over the chunk with d the
+ * distance around it (d < lambda).  Arguments, tables and workspace (sized by
+ * mm_noise_toeplitz_workspace_size) as for mm_noise_toeplitz; every
+ * non-empty chunk must be longer than 2 (lambda - 1), else MM_EINVAL. */
+int mm_noise_circulant(const double* coeff_host, int32_t lambda, int32_t n_filt,
+                       const int64_t* chunk_offsets_host, const int32_t* chunk_filter_host,
+                       int64_t n_chunks, void* workspace, size_t ws_bytes, void* stream,
+                       mm_noise_t* out);
 int mm_noise_destroy(mm_noise_t nz);
 
 /* ------------------------------------------------------------------------
@@ -158,6 +169,12 @@ int mm_apply_Ninv(mm_noise_t nz, mm_pointing_t pt, const void* tod_in, void* tod
 /* q = P^T N^-1 P x in one fused pass: the timeline-length intermediate stays
  * on chip (registers for white noise, LDS for band-Toeplitz). */
 int mm_apply_A(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, void* stream);
+/* mm_apply_A with an explicit band-Toeplitz operator variant (the bits of
+ * mm_solve_opts.op_variant, 0 <= variant < 8; ignored for white noise).
+ * Every variant computes the same sums up to the order of floating-point
+ * atomics; this call lets a caller check or time one. */
+int mm_apply_A_variant(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, int32_t variant,
+                       void* stream);
 /* b = P^T N^-1 tod (the right-hand side of eq. (6)), fused likewise. */
 int mm_rhs(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* b, int32_t arith, void* stream);
 /* Q = A X for n_rhs vectors at once (X, Q: f64[n_rhs][3 * n_kept]); the

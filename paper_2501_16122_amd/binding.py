@@ -59,11 +59,13 @@ SIGNATURES = {
     "mm_noise_white": (_c.c_int, [_pf64, _i32, _vp, _sz, _vp, _c.POINTER(_vp)]),
     "mm_noise_toeplitz_workspace_size": (_c.c_int, [_i32, _i32, _pi64, _i64, _psz]),
     "mm_noise_toeplitz": (_c.c_int, [_pf64, _i32, _i32, _pi64, _pi32, _i64, _vp, _sz, _vp, _c.POINTER(_vp)]),
+    "mm_noise_circulant": (_c.c_int, [_pf64, _i32, _i32, _pi64, _pi32, _i64, _vp, _sz, _vp, _c.POINTER(_vp)]),
     "mm_noise_destroy": (_c.c_int, [_vp]),
     "mm_apply_P": (_c.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "mm_apply_PT": (_c.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "mm_apply_Ninv": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
     "mm_apply_A": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "mm_apply_A_variant": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _vp]),
     "mm_rhs": (_c.c_int, [_vp, _vp, _vp, _vp, _i32, _vp]),
     "mm_apply_A_multi": (_c.c_int, [_vp, _vp, _i32, _vp, _vp, _i32, _vp]),
     "mm_apply_M": (_c.c_int, [_vp, _vp, _vp, _vp]),
@@ -246,7 +248,9 @@ class Noise:
         return cls(h, ws, "white")
 
     @classmethod
-    def toeplitz(cls, coeff, chunk_offsets, device, chunk_filter=None, stream=None):
+    def toeplitz(cls, coeff, chunk_offsets, device, chunk_filter=None, stream=None, circulant=False):
+        """Band-Toeplitz N^-1 per chunk (circulant=True: the same band filter
+        on each chunk taken as periodic)."""
         torch = _torch()
         lib = load()
         c = np.ascontiguousarray(np.atleast_2d(coeff), dtype=np.float64)
@@ -260,10 +264,15 @@ class Noise:
                                                     _c.byref(sz)))
         ws = torch.empty(sz.value, dtype=torch.uint8, device=device)
         h = _vp()
-        _check(lib.mm_noise_toeplitz(c.ctypes.data_as(_pf64), c.shape[1], c.shape[0], offs.ctypes.data_as(_pi64),
-                                     None if filt is None else filt.ctypes.data_as(_pi32), n_chunks, _ptr(ws),
-                                     sz.value, _stream(stream), _c.byref(h)))
-        return cls(h, ws, "toeplitz")
+        make = lib.mm_noise_circulant if circulant else lib.mm_noise_toeplitz
+        _check(make(c.ctypes.data_as(_pf64), c.shape[1], c.shape[0], offs.ctypes.data_as(_pi64),
+                    None if filt is None else filt.ctypes.data_as(_pi32), n_chunks, _ptr(ws), sz.value,
+                    _stream(stream), _c.byref(h)))
+        return cls(h, ws, "circulant" if circulant else "toeplitz")
+
+    @classmethod
+    def circulant(cls, coeff, chunk_offsets, device, chunk_filter=None, stream=None):
+        return cls.toeplitz(coeff, chunk_offsets, device, chunk_filter, stream, circulant=True)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -316,13 +325,19 @@ def apply_Ninv(nz: Noise, pt: Pointing, tod_in, tod_out=None, arith="f64", strea
     return tod_out
 
 
-def apply_A(pt: Pointing, nz: Noise, x, q=None, arith="f64", stream=None):
+def apply_A(pt: Pointing, nz: Noise, x, q=None, arith="f64", stream=None, variant=None):
+    """q = P^T N^-1 P x; ``variant`` selects a band-Toeplitz operator variant
+    (the bits of the solve option op_variant), None = the default."""
     torch = _torch()
     _vec(pt, x, "x")
     if q is None:
         q = torch.empty(3 * pt.n_kept, dtype=torch.float64, device=pt.device)
     _vec(pt, q, "q")
-    _check(load().mm_apply_A(pt.handle, nz.handle, _ptr(x), _ptr(q), _arith(arith), _stream(stream)))
+    if variant is None:
+        _check(load().mm_apply_A(pt.handle, nz.handle, _ptr(x), _ptr(q), _arith(arith), _stream(stream)))
+    else:
+        _check(load().mm_apply_A_variant(pt.handle, nz.handle, _ptr(x), _ptr(q), _arith(arith), int(variant),
+                                         _stream(stream)))
     return q
 
 

@@ -106,6 +106,50 @@ int check_noise_vs_pointing(const mm_noise_s* nz, const mm_pointing_s* pt) {
   return MM_OK;
 }
 
+int check_chunks(const int64_t* offs, int64_t n_chunks) {
+  if (!offs || n_chunks < 0) return fail(MM_EINVAL, "bad chunk offsets");
+  if (offs[0] < 0) return fail(MM_EINVAL, "chunk offsets must be >= 0");
+  for (int64_t c = 0; c < n_chunks; ++c)
+    if (offs[c + 1] < offs[c]) return fail(MM_EINVAL, "chunk offsets must be non-decreasing");
+  return MM_OK;
+}
+
+int make_banded_noise(int kind, const double* coeff_host, int32_t lambda, int32_t n_filt,
+                      const int64_t* chunk_offsets_host, const int32_t* chunk_filter_host, int64_t n_chunks,
+                      void* workspace, size_t ws_bytes, void* stream, mm_noise_t* out) {
+  if (!out) return fail(MM_EINVAL, "null output handle pointer");
+  *out = nullptr;
+  if (!coeff_host || !workspace || lambda < 1 || lambda > kMaxLambda || n_filt < 1)
+    return fail(MM_EINVAL, "bad Toeplitz arguments (1 <= lambda <= 4096)");
+  if (int rc = check_chunks(chunk_offsets_host, n_chunks)) return rc;
+  for (int64_t i = 0; i < (int64_t)n_filt * lambda; ++i)
+    if (!std::isfinite(coeff_host[i])) return fail(MM_EINVAL, "non-finite Toeplitz coefficient");
+  auto* nz = new (std::nothrow) mm_noise_s();
+  if (!nz) return fail(MM_EINVAL, "out of host memory");
+  nz->kind = kind;
+  nz->lambda = lambda;
+  nz->n_filt = n_filt;
+  nz->n_chunks = n_chunks;
+  nz->chunk_offsets.assign(chunk_offsets_host, chunk_offsets_host + n_chunks + 1);
+  nz->chunk_filter.resize(n_chunks);
+  for (int64_t c = 0; c < n_chunks; ++c) {
+    const int32_t f = chunk_filter_host ? chunk_filter_host[c] : 0;
+    if (f < 0 || f >= n_filt) {
+      delete nz;
+      return fail(MM_EINVAL, "chunk_filter out of range");
+    }
+    nz->chunk_filter[c] = f;
+  }
+  (void)hipGetDevice(&nz->device);
+  int rc = prepare_toeplitz_tables(nz, coeff_host, workspace, ws_bytes, as_stream(stream), nullptr);
+  if (rc) {
+    delete nz;
+    return rc;
+  }
+  *out = nz;
+  return MM_OK;
+}
+
 }  // namespace mm
 
 using namespace mm;
@@ -272,13 +316,6 @@ int mm_noise_white(const double* det_weight_host, int32_t n_det, void* workspace
   return MM_OK;
 }
 
-static int check_chunks(const int64_t* offs, int64_t n_chunks) {
-  if (!offs || n_chunks < 0) return fail(MM_EINVAL, "bad chunk offsets");
-  if (offs[0] < 0) return fail(MM_EINVAL, "chunk offsets must be >= 0");
-  for (int64_t c = 0; c < n_chunks; ++c)
-    if (offs[c + 1] < offs[c]) return fail(MM_EINVAL, "chunk offsets must be non-decreasing");
-  return MM_OK;
-}
 
 int mm_noise_toeplitz_workspace_size(int32_t lambda, int32_t n_filt, const int64_t* chunk_offsets_host,
                                      int64_t n_chunks, size_t* bytes) {
@@ -294,41 +331,29 @@ int mm_noise_toeplitz_workspace_size(int32_t lambda, int32_t n_filt, const int64
   return prepare_toeplitz_tables(&tmp, nullptr, nullptr, 0, nullptr, bytes);
 }
 
+
 int mm_noise_toeplitz(const double* coeff_host, int32_t lambda, int32_t n_filt, const int64_t* chunk_offsets_host,
                       const int32_t* chunk_filter_host, int64_t n_chunks, void* workspace, size_t ws_bytes,
                       void* stream, mm_noise_t* out) {
+  return make_banded_noise(1, coeff_host, lambda, n_filt, chunk_offsets_host, chunk_filter_host, n_chunks, workspace,
+                           ws_bytes, stream, out);
+}
+
+int mm_noise_circulant(const double* coeff_host, int32_t lambda, int32_t n_filt, const int64_t* chunk_offsets_host,
+                       const int32_t* chunk_filter_host, int64_t n_chunks, void* workspace, size_t ws_bytes,
+                       void* stream, mm_noise_t* out) {
   if (!out) return fail(MM_EINVAL, "null output handle pointer");
   *out = nullptr;
-  if (!coeff_host || !workspace || lambda < 1 || lambda > kMaxLambda || n_filt < 1)
-    return fail(MM_EINVAL, "bad Toeplitz arguments (1 <= lambda <= 4096)");
-  if (int rc = check_chunks(chunk_offsets_host, n_chunks)) return rc;
-  for (int64_t i = 0; i < (int64_t)n_filt * lambda; ++i)
-    if (!std::isfinite(coeff_host[i])) return fail(MM_EINVAL, "non-finite Toeplitz coefficient");
-  auto* nz = new (std::nothrow) mm_noise_s();
-  if (!nz) return fail(MM_EINVAL, "out of host memory");
-  nz->kind = 1;
-  nz->lambda = lambda;
-  nz->n_filt = n_filt;
-  nz->n_chunks = n_chunks;
-  nz->chunk_offsets.assign(chunk_offsets_host, chunk_offsets_host + n_chunks + 1);
-  nz->chunk_filter.resize(n_chunks);
-  for (int64_t c = 0; c < n_chunks; ++c) {
-    const int32_t f = chunk_filter_host ? chunk_filter_host[c] : 0;
-    if (f < 0 || f >= n_filt) {
-      delete nz;
-      return fail(MM_EINVAL, "chunk_filter out of range");
+  if (chunk_offsets_host && lambda >= 1)
+    for (int64_t c = 0; c < n_chunks; ++c) {
+      const int64_t n = chunk_offsets_host[c + 1] - chunk_offsets_host[c];
+      if (n > 0 && n <= 2 * (int64_t)(lambda - 1))
+        return fail(MM_EINVAL, "a circulant chunk must be longer than 2 (lambda - 1)");
     }
-    nz->chunk_filter[c] = f;
-  }
-  (void)hipGetDevice(&nz->device);
-  int rc = prepare_toeplitz_tables(nz, coeff_host, workspace, ws_bytes, as_stream(stream), nullptr);
-  if (rc) {
-    delete nz;
-    return rc;
-  }
-  *out = nz;
-  return MM_OK;
+  return make_banded_noise(2, coeff_host, lambda, n_filt, chunk_offsets_host, chunk_filter_host, n_chunks, workspace,
+                           ws_bytes, stream, out);
 }
+
 
 int mm_noise_destroy(mm_noise_t nz) {
   delete nz;
@@ -373,6 +398,18 @@ int mm_apply_A(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int3
   hipStream_t s = as_stream(stream);
   if (int rc = launch_fill(q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
   return apply_A_impl(pt, nz, x, q, arith, RhsBatch{}, s);
+}
+
+int mm_apply_A_variant(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, int32_t variant,
+                       void* stream) {
+  if (variant < 0 || variant >= kOpVariants) return fail(MM_EINVAL, "operator variant out of range");
+  if (int rc = check_pointing(pt)) return rc;
+  if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
+  if (!valid_dtype(arith)) return fail(MM_EINVAL, "bad arith");
+  if (pt->n_kept && (!x || !q)) return fail(MM_EINVAL, "null vector");
+  hipStream_t s = as_stream(stream);
+  if (int rc = launch_fill(q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
+  return apply_A_impl(pt, nz, x, q, arith, RhsBatch{}, s, variant);
 }
 
 int mm_apply_A_multi(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const double* x, double* q, int32_t arith,

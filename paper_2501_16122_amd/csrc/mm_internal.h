@@ -52,7 +52,7 @@ struct FftTile {
   int64_t chunk_start;
   int64_t chunk_end;
   int32_t filter;
-  int32_t pad_;
+  int32_t wrap;  // 1: circulant chunk (window positions past its edges wrap around it)
 };
 static_assert(sizeof(FftTile) == 40, "FftTile layout");
 
@@ -126,7 +126,7 @@ struct mm_pointing_s {
 };
 
 struct mm_noise_s {
-  int kind = 0;  // 0 = white, 1 = band-Toeplitz
+  int kind = 0;  // 0 = white, 1 = band-Toeplitz, 2 = circulant (band filter, periodic chunks)
   int device = 0;
   // white
   int32_t n_det = 0;

@@ -77,6 +77,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   const int nf = nz->n_filt;
   Carver cv(ws, ws_bytes);
   const int Ns[2] = {kFftN64, kFftN32};
+  const int32_t wrap = nz->kind == 2 ? 1 : 0;
   std::vector<FftTile> tiles[2];
   for (int a = 0; a < 2; ++a) {
     const int64_t L = 2 * (int64_t)Ns[a];
@@ -84,7 +85,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     for (int64_t c = 0; c < nz->n_chunks; ++c) {
       const int64_t c0 = nz->chunk_offsets[c], c1 = nz->chunk_offsets[c + 1];
       for (int64_t o = c0; o < c1; o += V)
-        tiles[a].push_back(FftTile{o, o + V < c1 ? o + V : c1, c0, c1, nz->chunk_filter[c], 0});
+        tiles[a].push_back(FftTile{o, o + V < c1 ? o + V : c1, c0, c1, nz->chunk_filter[c], wrap});
     }
     nz->n_tiles[a] = (int64_t)tiles[a].size();
   }
@@ -99,7 +100,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
       int64_t seg_n = 0;
       for (int64_t o = c0; o < c1; o += stride) {
         if (seg_n == 0) csegs[a].push_back(CarrySeg{(int64_t)ctiles[a].size(), 0, 0});
-        ctiles[a].push_back(FftTile{o, o + stride < c1 ? o + stride : c1, c0, c1, nz->chunk_filter[c], 0});
+        ctiles[a].push_back(FftTile{o, o + stride < c1 ? o + stride : c1, c0, c1, nz->chunk_filter[c], wrap});
         csegs[a].back().count += 1;
         seg_n = seg_n + 1 == kSegTiles ? 0 : seg_n + 1;
       }

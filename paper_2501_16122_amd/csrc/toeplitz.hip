@@ -237,6 +237,23 @@ struct Angle {
 // in registers: kKeepK) and weights of its own samples only, so wide windows
 // (sparse or large grids) cost extra L2 reads instead of one global atomic
 // per sample.  v holds the outputs in the layout of the first forward pass.
+// Window position -> the (window-relative, possibly negative) position of
+// the sample it holds: itself inside the chunk [ilo, ihi); for a circulant
+// chunk (wrap) a position up to lam1 = lambda - 1 before or after the chunk
+// holds the sample one chunk length away.  Returns false for none (zero):
+// positions further out never reach a valid output.
+__device__ __forceinline__ bool src_pos(int pos, int ilo, int ihi, bool wrap, int clen, int lam1, int& sp) {
+  sp = pos;
+  if (pos >= ilo && pos < ihi) return true;
+  if (!wrap) return false;
+  if (pos < ilo) {
+    sp = pos + clen;
+    return true;
+  }
+  sp = pos - clen;
+  return pos < ihi + lam1;
+}
+
 // Elements [kKeepW0, kKeepW1) of each thread (FP64 plan) hold most valid
 // outputs at lambda = 4096; their pointing weights can stay in registers from
 // the gather (wk) instead of being read again.
@@ -337,7 +354,9 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
   // window positions inside the chunk: [ilo, ihi)
   const int32_t ilo = (int32_t)(tl.chunk_start > in0 ? tl.chunk_start - in0 : 0);
   const int32_t ihi = (int32_t)(tl.chunk_end - in0 < L ? tl.chunk_end - in0 : L);
-  // tile-based views indexed by window position (only [ilo, ihi) is read)
+  const bool wrap = tl.wrap != 0;
+  const int32_t clen = (int32_t)(tl.chunk_end - tl.chunk_start);
+  // tile-based views indexed by window position (only the chunk is read)
   const int32_t* __restrict__ sk = sample_k != nullptr ? sample_k + in0 : nullptr;
   const S* __restrict__ ps0 = (kW == 0 && psi != nullptr) ? psi + in0 : nullptr;
   const cpx<S>* __restrict__ w0 = (kW == 1 && wts != nullptr) ? wts + in0 : nullptr;
@@ -360,7 +379,8 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
 #pragma unroll
     for (int i = 0; i < 2 * E; ++i) {
       const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
-      kk[i] = (pos >= ilo && pos < ihi) ? sk[pos] : -1;
+      int sp;
+      kk[i] = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp) ? sk[sp] : -1;
     }
     int32_t amin = INT32_MAX, amax = -1;  // window of every kept sample (map staging)
 #pragma unroll
@@ -417,7 +437,9 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
         const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
-        ps[i] = kk[2 * e0 + i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
+        int sp;
+        src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+        ps[i] = kk[2 * e0 + i] >= 0 ? A::load(ps0, w0, sp) : A::zero();
         if constexpr (kKeepW) {
           const int e = e0 + i / 2;
           if (e >= kKeepW0 && e < kKeepW1) wk[2 * (e - kKeepW0) + (i & 1)] = ps[i];
@@ -448,9 +470,10 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
         const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
-        const bool in = pos >= ilo && pos < ihi;
-        if (kOut == 1) kt[i] = (in && pos >= vlo && pos < vhi) ? sk[pos] : -1;
-        tv[i] = in ? tin[pos] : S(0);
+        int sp;
+        const bool in = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+        if (kOut == 1) kt[i] = (pos >= ilo && pos < ihi && pos >= vlo && pos < vhi) ? sk[pos] : -1;
+        tv[i] = in ? tin[sp] : S(0);
       }
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
@@ -536,6 +559,8 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
   const int32_t vhi = vlo + (int32_t)(tl.out_end - tl.out_start);
   const int32_t ilo = (int32_t)(tl.chunk_start > in0 ? tl.chunk_start - in0 : 0);
   const int32_t ihi = (int32_t)(tl.chunk_end - in0 < L ? tl.chunk_end - in0 : L);
+  const bool wrap = tl.wrap != 0;
+  const int32_t clen = (int32_t)(tl.chunk_end - tl.chunk_start);
   const int32_t* __restrict__ sk = sample_k + in0;
   const S* __restrict__ ps0 = kW == 0 ? psi + in0 : nullptr;
   const cpx<S>* __restrict__ w0 = kW == 1 ? wts + in0 : nullptr;
@@ -548,7 +573,8 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
   for (int i = 0; i < 2 * E; ++i) {
     const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
     const bool fresh = !(have && i / 2 < kCarryElems);
-    kk[i] = (fresh && pos >= ilo && pos < ihi) ? sk[pos] : -1;
+    int sp;
+    kk[i] = (src_pos(pos, ilo, ihi, wrap, clen, vlo, sp) && fresh) ? sk[sp] : -1;
   }
   int32_t kmin = INT32_MAX, kmax = -1, nmin = INT32_MAX, nmax = -1;
 #pragma unroll
@@ -589,7 +615,9 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
 #pragma unroll
     for (int i = 0; i < 2 * G; ++i) {
       const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
-      ps[i] = kk[2 * e0 + i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
+      int sp;
+      src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+      ps[i] = kk[2 * e0 + i] >= 0 ? A::load(ps0, w0, sp) : A::zero();
     }
 #pragma unroll
     for (int i = 0; i < 2 * G; ++i) {

@@ -1,0 +1,86 @@
+"""Parity at the full size of the GLS workload (512^2 grid, 64 detectors x
+2^22 samples, band-Toeplitz N^-1 with 4096 lags on chunks of 2^20): the
+build bit-exact against the oracle over all 2^28 samples, and the fused
+operator, in the variants the bench runs, on sampled pixels.  A pixel's row
+of A = P^T N^-1 P x only involves the chunks its samples fall in, so the
+oracle evaluates A on those chunks alone (chunks do not couple)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle.mapmaking as oracle
+from paper_2501_16122_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def _b():
+    from paper_2501_16122_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def full():
+    b = _b()
+    w = synth.C2_GLS
+    pix, psi = synth.pointing(w)
+    offs, wdet = synth.det_offsets(w), synth.det_weight(w)
+    opt = oracle.build_pointing(pix, psi, offs, wdet, w.n_pix)
+    pt = b.Pointing(torch.from_numpy(pix).to(DEV), torch.from_numpy(psi).to(DEV), offs, wdet, w.n_pix)
+    pt.attach_weights()
+    coeff, chunks = synth.toeplitz_coeff(w), synth.chunk_offsets(w)
+    nz = b.Noise.toeplitz(coeff, chunks, DEV)
+    yield w, pix, psi, opt, pt, nz, coeff, chunks
+    pt.close()
+    nz.close()
+
+
+def test_full_size_build_bit_exact(full):
+    w, pix, psi, opt, pt, nz, coeff, chunks = full
+    out = pt.export()
+    assert pt.n_kept == opt.n_kept
+    assert np.array_equal(out["hits"].cpu().numpy(), opt.hits.astype(np.int32))
+    assert np.array_equal(out["mask"].cpu().numpy().astype(bool), opt.mask)
+    assert np.array_equal(out["compact"].cpu().numpy(), opt.compact.astype(np.int32))
+    assert np.array_equal(out["kept"].cpu().numpy(), opt.kept.astype(np.int32))
+    minv = out["minv"].cpu().numpy()
+    assert np.linalg.norm(minv - opt.minv.reshape(minv.shape)) <= 1e-12 * np.linalg.norm(opt.minv)
+    assert oracle.mask_margin(opt) > 1e-9
+
+
+def _oracle_rows(opt, coeff, chunks, x, sel):
+    """A x at the compact indices `sel`, from the chunks their samples fall in."""
+    hit = np.isin(opt.sample_k, sel)
+    cidx = np.unique(np.searchsorted(chunks, np.flatnonzero(hit), side="right") - 1)
+    idx = np.concatenate([np.arange(chunks[c], chunks[c + 1]) for c in cidx])
+    lens = np.array([chunks[c + 1] - chunks[c] for c in cidx])
+    sub = dataclasses.replace(opt, pix=opt.pix[idx], cos2=opt.cos2[idx], sin2=opt.sin2[idx],
+                              weight=opt.weight[idx], sample_k=opt.sample_k[idx])
+    noise = oracle.toeplitz_noise(coeff, np.concatenate([[0], np.cumsum(lens)]))
+    q = oracle.apply_A(sub, noise, x).reshape(-1, 3)
+    return q[sel], len(cidx)
+
+
+@pytest.mark.parametrize("variant", [0, 2, 5])
+def test_full_size_operator_sampled_pixels(full, variant):
+    b = _b()
+    w, pix, psi, opt, pt, nz, coeff, chunks = full
+    rng = np.random.default_rng(2025 + variant)
+    x = rng.normal(size=3 * opt.n_kept)
+    q = b.apply_A(pt, nz, torch.from_numpy(x).to(DEV), variant=variant).cpu().numpy().reshape(-1, 3)
+    # a few kept pixels of one grid row: their samples share the chunks
+    row = (137 + 97 * variant) % w.height
+    cand = opt.compact[row * w.width:(row + 1) * w.width]
+    sel = rng.choice(cand[cand >= 0], size=6, replace=False)
+    ref, n_chunks = _oracle_rows(opt, coeff, chunks, x, sel)
+    assert n_chunks >= 64  # every detector crosses the row
+    err = np.abs(q[sel] - ref).max() / np.abs(ref).max()
+    assert err < 1e-12, err
+    # the same rows in FP32 timeline arithmetic: FP32 rounding only
+    q32 = b.apply_A(pt, nz, torch.from_numpy(x).to(DEV), arith="f32", variant=variant).cpu().numpy().reshape(-1, 3)
+    err32 = np.abs(q32[sel] - ref).max() / np.abs(ref).max()
+    assert err32 < 1e-5, err32
