@@ -8,6 +8,11 @@ and written so that each step can be read against the paper:
 * eq. (2)/(8): a sample sees one pixel through the row [1, cos 2psi, sin 2psi]
   (the paper's text once says cos/sin of theta; its equations use 2 theta,
   which is the reading taken here);
+* Sec. III-B sizes the reduced pixel-domain array at two or three values per
+  sky pixel: besides the I, Q, U map, a polarisation-only map (Q, U; the row
+  keeps the two angle columns) and, with one value per pixel, an
+  intensity-only map (I; the row is the 1 alone) use the same operators with
+  fewer columns;
 * eq. (3): d = P s + n;
 * eq. (5)/(6): the GLS map solves A x = b with A = P^T N^-1 P, b = P^T N^-1 d;
 * eq. (7): the block-Jacobi preconditioner M = (P^T diag(N)^-1 P)^-1, whose
@@ -49,6 +54,22 @@ def pointing_weights(psi: np.ndarray):
     return np.cos(two_psi), np.sin(two_psi)
 
 
+NCOMP = {"IQU": 3, "QU": 2, "I": 1}
+
+
+def pointing_rows(stokes: str, c: np.ndarray, s: np.ndarray):
+    """The columns of P a sample sees for each map form, as per-sample
+    arrays: IQU (1, cos 2psi, sin 2psi) as in eq. (8); QU the two angle
+    columns alone; I the constant column alone."""
+    if stokes == "IQU":
+        return (np.ones_like(c), c, s)
+    if stokes == "QU":
+        return (c, s)
+    if stokes == "I":
+        return (np.ones_like(c),)
+    raise ValueError(f"unknown map form {stokes!r}")
+
+
 def sample_weights(det_offsets: np.ndarray, det_weight: np.ndarray) -> np.ndarray:
     """Per-sample diagonal of N^-1 for white noise: 1/sigma_d^2 of its detector."""
     det_offsets = np.asarray(det_offsets, dtype=np.int64)
@@ -66,13 +87,21 @@ class Pointing:
     weight: np.ndarray       # f64[N_t], diag(N)^-1 per sample
     n_pix: int
     hits: np.ndarray         # int64[n_pix]
-    blocks: np.ndarray       # f64[n_pix, 3, 3]: P^T diag(N)^-1 P restricted to pixel p
+    blocks: np.ndarray       # f64[n_pix, nc, nc]: P^T diag(N)^-1 P restricted to pixel p
     cond: np.ndarray         # f64[n_pix]: 2-norm condition number (inf if singular)
     mask: np.ndarray         # bool[n_pix]: True = removed from the unknowns
     kept: np.ndarray         # int64[n_kept], ascending pixel indices
     compact: np.ndarray      # int64[n_pix]: position in ``kept`` or -1
-    minv: np.ndarray         # f64[n_kept, 3, 3]: inverse blocks (eq. (7))
+    minv: np.ndarray         # f64[n_kept, nc, nc]: inverse blocks (eq. (7))
     sample_k: np.ndarray     # int64[N_t]: compact index of each sample (-1 = masked)
+    stokes: str = "IQU"      # map form: "IQU", "QU" or "I" (nc = 3, 2, 1 values per pixel)
+
+    @property
+    def ncomp(self) -> int:
+        return NCOMP[self.stokes]
+
+    def rows(self):
+        return pointing_rows(self.stokes, self.cos2, self.sin2)
 
     @property
     def n_kept(self) -> int:
@@ -83,10 +112,20 @@ class Pointing:
         return int(self.pix.size)
 
 
-def build_pointing(pix, psi, det_offsets, det_weight, n_pix, min_hits=3, cond_max=1e3) -> Pointing:
-    """Hits, the 3x3 blocks of P^T diag(N)^-1 P, their conditioning, the mask
-    and the inverse blocks of the preconditioner (eq. (7))."""
+def build_pointing(pix, psi, det_offsets, det_weight, n_pix, min_hits=None, cond_max=1e3,
+                   stokes="IQU") -> Pointing:
+    """Hits, the nc x nc blocks of P^T diag(N)^-1 P, their conditioning, the
+    mask and the inverse blocks of the preconditioner (eq. (7)).  min_hits
+    defaults to nc, the fewest samples that can make a block invertible.
+    psi may be None for the intensity-only form, whose rows do not use it."""
+    nc = NCOMP[stokes]
+    if min_hits is None:
+        min_hits = nc
     pix = np.asarray(pix)
+    if psi is None:
+        if stokes != "I":
+            raise ValueError("the angle is needed unless the map is intensity-only")
+        psi = np.zeros(pix.size)
     if pix.size and (pix.min() < 0 or pix.max() >= n_pix):
         raise ValueError("pixel index out of range")
     c, s = pointing_weights(psi)
@@ -94,16 +133,16 @@ def build_pointing(pix, psi, det_offsets, det_weight, n_pix, min_hits=3, cond_ma
     if w.size != pix.size:
         raise ValueError("detector offsets do not cover the timeline")
     hits = np.bincount(pix, minlength=n_pix).astype(np.int64)
-    # The block of pixel p is sum over its samples of w a a^T, a = (1, c, s).
-    a = (np.ones_like(c), c, s)
-    blocks = np.zeros((n_pix, 3, 3))
-    for i in range(3):
-        for j in range(3):
+    # The block of pixel p is sum over its samples of w a a^T, a the row of P.
+    a = pointing_rows(stokes, c, s)
+    blocks = np.zeros((n_pix, nc, nc))
+    for i in range(nc):
+        for j in range(nc):
             blocks[:, i, j] = np.bincount(pix, weights=w * a[i] * a[j], minlength=n_pix)
     cond = np.full(n_pix, np.inf)
     seen = hits > 0
     ev = np.linalg.eigvalsh(blocks[seen])
-    lo, hi = ev[:, 0], ev[:, 2]
+    lo, hi = ev[:, 0], ev[:, -1]
     with np.errstate(divide="ignore", invalid="ignore"):
         cond_seen = np.where(lo > 0, hi / lo, np.inf)
     cond[seen] = cond_seen
@@ -111,17 +150,17 @@ def build_pointing(pix, psi, det_offsets, det_weight, n_pix, min_hits=3, cond_ma
     kept = np.flatnonzero(~mask)
     compact = np.full(n_pix, -1, dtype=np.int64)
     compact[kept] = np.arange(kept.size)
-    minv = np.linalg.inv(blocks[kept]) if kept.size else np.zeros((0, 3, 3))
+    minv = np.linalg.inv(blocks[kept]) if kept.size else np.zeros((0, nc, nc))
     return Pointing(pix=pix, cos2=c, sin2=s, weight=w, n_pix=n_pix, hits=hits,
                     blocks=blocks, cond=cond, mask=mask, kept=kept, compact=compact,
-                    minv=minv, sample_k=compact[pix])
+                    minv=minv, sample_k=compact[pix], stokes=stokes)
 
 
-def mask_margin(pt: Pointing, cond_max=1e3) -> float:
+def mask_margin(pt: Pointing, cond_max=1e3, min_hits=None) -> float:
     """Smallest distance, in decades, between a pixel's condition number and
     the masking threshold (over pixels with enough hits and finite cond).
     A tiny margin means the keep/mask decision hangs on rounding."""
-    sel = (pt.hits >= 3) & np.isfinite(pt.cond)
+    sel = (pt.hits >= (pt.ncomp if min_hits is None else min_hits)) & np.isfinite(pt.cond)
     if not np.any(sel):
         return np.inf
     return float(np.min(np.abs(np.log10(pt.cond[sel] / cond_max))))
@@ -133,25 +172,28 @@ def mask_margin(pt: Pointing, cond_max=1e3) -> float:
 
 def apply_P(pt: Pointing, x: np.ndarray) -> np.ndarray:
     """y_t = I_k + Q_k cos 2psi_t + U_k sin 2psi_t with k the compact index
-    of the sample's pixel; 0 for samples of masked pixels."""
-    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    of the sample's pixel (the columns the map form keeps); 0 for samples of
+    masked pixels."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, pt.ncomp)
     k = pt.sample_k
     ok = k >= 0
     kk = np.where(ok, k, 0)
-    y = x[kk, 0] + x[kk, 1] * pt.cos2 + x[kk, 2] * pt.sin2
+    y = np.zeros(k.size)
+    for j, a in enumerate(pt.rows()):
+        y = y + x[kk, j] * a
     return np.where(ok, y, 0.0)
 
 
 def apply_PT(pt: Pointing, y: np.ndarray) -> np.ndarray:
-    """(P^T y)_k = sum over kept samples of pixel k of y_t (1, cos, sin)."""
+    """(P^T y)_k = sum over kept samples of pixel k of y_t times the row
+    (1, cos, sin), or the columns the map form keeps."""
     y = np.asarray(y, dtype=np.float64)
     ok = pt.sample_k >= 0
     k = pt.sample_k[ok]
     yo = y[ok]
-    q = np.zeros((pt.n_kept, 3))
-    q[:, 0] = np.bincount(k, weights=yo, minlength=pt.n_kept)
-    q[:, 1] = np.bincount(k, weights=yo * pt.cos2[ok], minlength=pt.n_kept)
-    q[:, 2] = np.bincount(k, weights=yo * pt.sin2[ok], minlength=pt.n_kept)
+    q = np.zeros((pt.n_kept, pt.ncomp))
+    for j, a in enumerate(pt.rows()):
+        q[:, j] = np.bincount(k, weights=yo * a[ok], minlength=pt.n_kept)
     return q.reshape(-1)
 
 
@@ -262,7 +304,7 @@ def rhs(pt: Pointing, noise, d):
 
 def apply_M(pt: Pointing, r: np.ndarray) -> np.ndarray:
     """z = M r with M the block-diagonal inverse of eq. (7)."""
-    r = np.asarray(r, dtype=np.float64).reshape(-1, 3)
+    r = np.asarray(r, dtype=np.float64).reshape(-1, pt.ncomp)
     return np.einsum("kij,kj->ki", pt.minv, r).reshape(-1)
 
 
@@ -331,9 +373,9 @@ def pcg(apply_a, apply_m, b, tol=1e-10, max_iter=2000, fixed_iters=None, x0=None
 
 
 def expand(pt: Pointing, x: np.ndarray) -> np.ndarray:
-    """Compact IQU unknowns -> full-grid f64[n_pix, 3], 0 at masked pixels."""
-    out = np.zeros((pt.n_pix, 3))
-    out[pt.kept] = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    """Compact unknowns -> full-grid f64[n_pix, nc], 0 at masked pixels."""
+    out = np.zeros((pt.n_pix, pt.ncomp))
+    out[pt.kept] = np.asarray(x, dtype=np.float64).reshape(-1, pt.ncomp)
     return out
 
 
@@ -349,15 +391,16 @@ def binned_map(pt: Pointing, d) -> np.ndarray:
     """White-noise GLS map: per kept pixel, B_p^-1 (sum w a d).  With diagonal
     N^-1 the matrix A is block-diagonal (eq. (7)), so this is the exact
     solution of eq. (5)."""
-    b = rhs(pt, None, d).reshape(-1, 3)
+    b = rhs(pt, None, d).reshape(-1, pt.ncomp)
     x = np.linalg.solve(pt.blocks[pt.kept], b[..., None])[..., 0]
     return x.reshape(-1)
 
 
-def rel_l2_per_stokes(m, m_ref, kept=None):
-    """||m - m_ref|| / ||m_ref|| separately for I, Q and U (over kept pixels)."""
-    m = np.asarray(m, dtype=np.float64).reshape(-1, 3)
-    m_ref = np.asarray(m_ref, dtype=np.float64).reshape(-1, 3)
+def rel_l2_per_stokes(m, m_ref, kept=None, ncomp=3):
+    """||m - m_ref|| / ||m_ref|| separately for each Stokes parameter of the
+    map (I, Q, U; or those of the map form's ncomp) over kept pixels."""
+    m = np.asarray(m, dtype=np.float64).reshape(-1, ncomp)
+    m_ref = np.asarray(m_ref, dtype=np.float64).reshape(-1, ncomp)
     if kept is not None:
         m, m_ref = m[kept], m_ref[kept]
     num = np.linalg.norm(m - m_ref, axis=0)
