@@ -35,6 +35,12 @@
  *   [det_offsets[d], det_offsets[d+1])); pixel indices are int32 in
  *   [0, n_pix); maps over the kept pixels are interleaved I, Q, U
  *   (f64[3 * n_kept], eq. (8)); full-grid maps are f64[3 * n_pix].
+ * - Map forms: a pointing handle solves for nc values per pixel, nc being
+ *   its MM_STOKES_* form: I, Q, U (nc = 3, the default), Q, U only (nc = 2:
+ *   the row of P keeps cos 2psi, sin 2psi) or I only (nc = 1: the row is the
+ *   constant 1 and psi is not read).  Sec. III-B sizes the pixel-domain
+ *   array at two or three values per pixel.  Every "3" in the vector and map
+ *   sizes below is the handle's nc.
  * - Precision: `dtype` is the storage type of psi and of every timeline
  *   (MM_F64 or MM_F32).  `arith` selects the arithmetic of an operator's
  *   timeline-domain work (MM_F64 or MM_F32); pixel-domain vectors, bin sums
@@ -61,13 +67,16 @@ enum {
 
 enum { MM_F64 = 0, MM_F32 = 1 };
 
+/* Map forms (the value is the number of unknowns per pixel, nc). */
+enum { MM_STOKES_I = 1, MM_STOKES_QU = 2, MM_STOKES_IQU = 3 };
+
 typedef struct mm_pointing_s* mm_pointing_t;
 typedef struct mm_noise_s* mm_noise_t;
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* mm_last_error(void);
 
-/* ABI revision of this header (bumped on incompatible change): 2. */
+/* ABI revision of this header (bumped on incompatible change): 3. */
 int mm_abi_version(void);
 
 /* ------------------------------------------------------------------------
@@ -98,6 +107,23 @@ int mm_pointing_build(const int32_t* pix, const void* psi, int32_t dtype, int64_
                       int32_t n_pix, int32_t min_hits, double cond_max,
                       void* workspace, size_t ws_bytes, void* stream, mm_pointing_t* out);
 
+/* mm_pointing_build for a chosen map form (Sec. III-B: two or three values
+ * per pixel; the intensity-only form has one).  stokes is MM_STOKES_IQU (as
+ * mm_pointing_build), MM_STOKES_QU or MM_STOKES_I.  The blocks of eq. (7)
+ * are nc x nc: for QU the sums of w (cos^2, cos sin, sin^2), for I the sum
+ * of w; a QU block's condition number is its 2-norm one, an I block's is 1
+ * (+inf when its sum is 0).  min_hits applies as given (nc is the natural
+ * choice).  psi may be NULL for MM_STOKES_I, which never reads it; the same
+ * workspace size as mm_pointing_build suffices.  Errors as mm_pointing_build,
+ * plus MM_EINVAL for another stokes value. */
+int mm_pointing_build_stokes(const int32_t* pix, const void* psi, int32_t dtype, int64_t n_samples,
+                             const int64_t* det_offsets_host, int32_t n_det, const double* det_weight_host,
+                             int32_t n_pix, int32_t stokes, int32_t min_hits, double cond_max,
+                             void* workspace, size_t ws_bytes, void* stream, mm_pointing_t* out);
+
+/* The handle's map form (MM_STOKES_*, i.e. nc) in *stokes (host). */
+int mm_pointing_stokes(mm_pointing_t pt, int32_t* stokes);
+
 /* Sizes of a built handle (host outputs; any pointer may be NULL). */
 int mm_pointing_info(mm_pointing_t pt, int32_t* n_kept, int64_t* n_samples, int32_t* n_pix,
                      int32_t* n_det, int32_t* dtype);
@@ -105,7 +131,7 @@ int mm_pointing_info(mm_pointing_t pt, int32_t* n_kept, int64_t* n_samples, int3
 /* Copy the integer products of the build (any pointer may be NULL):
  *   hits int32[n_pix], mask uint8[n_pix] (1 = masked),
  *   compact int32[n_pix] (-1 = masked), kept int32[n_kept],
- *   minv f64[9 * n_kept] (row-major 3x3 inverse blocks, eq. (7)). */
+ *   minv f64[nc * nc * n_kept] (row-major nc x nc inverse blocks, eq. (7)). */
 int mm_pointing_export(mm_pointing_t pt, int32_t* hits, uint8_t* mask, int32_t* compact,
                        int32_t* kept, double* minv, void* stream);
 
@@ -115,7 +141,8 @@ int mm_pointing_export(mm_pointing_t pt, int32_t* hits, uint8_t* mask, int32_t* 
  *   weights   dtype[2 * n_samples] device, interleaved (cos, sin) per sample,
  *             same dtype as psi; borrowed until detached or destroyed
  * Stored weights serve arithmetic no finer than their dtype (FP32 weights are
- * not used by FP64 arithmetic).  weights = NULL detaches.  Stream-ordered. */
+ * not used by FP64 arithmetic).  weights = NULL detaches.  Stream-ordered.
+ * The intensity-only form has no weights (MM_EINVAL). */
 int mm_pointing_attach_weights(mm_pointing_t pt, void* weights, void* stream);
 
 /* Free the host-side handle; the caller frees its own arrays and workspace. */
@@ -155,7 +182,7 @@ int mm_noise_circulant(const double* coeff_host, int32_t lambda, int32_t n_filt,
 int mm_noise_destroy(mm_noise_t nz);
 
 /* ------------------------------------------------------------------------
- * Operators (eq. (3), (6), (7)).  x, q, r, z are f64[3 * n_kept]; timelines
+ * Operators (eq. (3), (6), (7)).  x, q, r, z are f64[nc * n_kept]; timelines
  * are dtype[n_samples] of the pointing's dtype.  Outputs are overwritten.
  * ------------------------------------------------------------------------ */
 
@@ -177,14 +204,14 @@ int mm_apply_A_variant(mm_pointing_t pt, mm_noise_t nz, const double* x, double*
                        void* stream);
 /* b = P^T N^-1 tod (the right-hand side of eq. (6)), fused likewise. */
 int mm_rhs(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* b, int32_t arith, void* stream);
-/* Q = A X for n_rhs vectors at once (X, Q: f64[n_rhs][3 * n_kept]); the
+/* Q = A X for n_rhs vectors at once (X, Q: f64[n_rhs][nc * n_kept]); the
  * right-hand sides of one tile run side by side, so the pointing is streamed
  * from memory once for all of them. */
 int mm_apply_A_multi(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const double* x, double* q, int32_t arith,
                      void* stream);
-/* z = M r with the 3x3 inverse blocks of eq. (7). */
+/* z = M r with the nc x nc inverse blocks of eq. (7). */
 int mm_apply_M(mm_pointing_t pt, const double* r, double* z, void* stream);
-/* map_full f64[3 * n_pix] = x at kept pixels, 0 at masked ones. */
+/* map_full f64[nc * n_pix] = x at kept pixels, 0 at masked ones. */
 int mm_expand_map(mm_pointing_t pt, const double* x, double* map_full, void* stream);
 
 /* ------------------------------------------------------------------------
@@ -232,8 +259,8 @@ int mm_solve_opts_default(mm_solve_opts* opts);
 int mm_solve_workspace_size(mm_pointing_t pt, mm_noise_t nz, const mm_solve_opts* opts, size_t* bytes);
 
 /* Solve for the map from the timeline `tod` (dtype of the pointing).
- *   map_out   f64[3 * n_pix] device, full grid (0 at masked pixels), may be NULL
- *   x_out     f64[3 * n_kept] device, compact solution, may be NULL
+ *   map_out   f64[nc * n_pix] device, full grid (0 at masked pixels), may be NULL
+ *   x_out     f64[nc * n_kept] device, compact solution, may be NULL
  *   history_host  f64[history_len] host, ||r_k||/||b|| for k = 0.. (may be NULL)
  * Returns MM_OK, MM_NOTCONVERGED or an error (MM_EBREAKDOWN keeps the last
  * good iterate in the outputs). */
@@ -269,8 +296,8 @@ int mm_solver_step(mm_solver_t sv, int32_t k);
  * info (n_rhs entries, may be NULL) reports the last landed state. */
 int mm_solver_poll(mm_solver_t sv, int32_t* done, int32_t* in_flight, mm_solve_info* info);
 
-/* Blocking: true FP64 residual, then the full-grid maps (f64[n_rhs][3 * n_pix],
- * may be NULL) and compact solutions (f64[n_rhs][3 * n_kept], may be NULL).
+/* Blocking: true FP64 residual, then the full-grid maps (f64[n_rhs][nc * n_pix],
+ * may be NULL) and compact solutions (f64[n_rhs][nc * n_kept], may be NULL).
  * history_host receives right-hand side 0's residual history (inner, or the
  * outer FP64 one for mixed solves).  Returns like mm_solve. */
 int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_info* info, double* history_host,
@@ -286,9 +313,9 @@ int mm_solver_destroy(mm_solver_t sv);
  * launch per PCG vector step over all their vectors; for mixed-precision
  * members a pending outer refinement step runs first.  Members may differ in
  * size, pointing, noise model and tolerances; they must share one device,
- * the stream they were created on, the timeline dtype and the precision mode
- * (mixed or not), and hold at most 16 right-hand sides in all (MM_EINVAL
- * otherwise).  Asynchronous: every member records its state copy as after
+ * the stream they were created on, the timeline dtype, the precision mode
+ * (mixed or not) and the map form, and hold at most 16 right-hand sides in
+ * all (MM_EINVAL otherwise).  Asynchronous: every member records its state copy as after
  * mm_solver_step and is polled and finished on its own.  Batched steps are
  * not timed (opts.timing). */
 int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k);

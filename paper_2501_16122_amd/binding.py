@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(PKG, "libmapmaker.so")
 MM_OK, MM_NOTCONVERGED = 0, 1
 MM_EINVAL, MM_ENOSPC, MM_EHIP, MM_EBREAKDOWN = -1, -2, -3, -4
 MM_F64, MM_F32 = 0, 1
+MM_STOKES_I, MM_STOKES_QU, MM_STOKES_IQU = 1, 2, 3
 
 _c = ctypes
 _vp = _c.c_void_p
@@ -51,6 +52,9 @@ SIGNATURES = {
     "mm_pointing_workspace_size": (_c.c_int, [_i64, _i32, _i32, _psz]),
     "mm_pointing_build": (_c.c_int, [_vp, _vp, _i32, _i64, _pi64, _i32, _pf64, _i32, _i32, _f64, _vp, _sz, _vp,
                                      _c.POINTER(_vp)]),
+    "mm_pointing_build_stokes": (_c.c_int, [_vp, _vp, _i32, _i64, _pi64, _i32, _pf64, _i32, _i32, _i32, _f64, _vp,
+                                            _sz, _vp, _c.POINTER(_vp)]),
+    "mm_pointing_stokes": (_c.c_int, [_vp, _pi32]),
     "mm_pointing_info": (_c.c_int, [_vp, _pi32, _pi64, _pi32, _pi32, _pi32]),
     "mm_pointing_export": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mm_pointing_attach_weights": (_c.c_int, [_vp, _vp, _vp]),
@@ -158,21 +162,43 @@ def _arith(a) -> int:
     raise ValueError(f"bad arith {a!r}")
 
 
+STOKES = {"IQU": MM_STOKES_IQU, "QU": MM_STOKES_QU, "I": MM_STOKES_I}
+
+
 class Pointing:
-    """Handle over the precomputed pointing (hits, masks, 3x3 inverse blocks).
+    """Handle over the precomputed pointing (hits, masks, nc x nc inverse
+    blocks) for one map form: ``stokes`` "IQU" (3 values per pixel), "QU" (2)
+    or "I" (1; ``psi`` may then be None, with ``tod_dtype`` giving the
+    timeline dtype).  ``min_hits`` defaults to nc.
 
     Borrows ``pix`` and ``psi`` (device tensors) for its lifetime and owns a
     device workspace tensor."""
 
-    def __init__(self, pix, psi, det_offsets, det_weight, n_pix, min_hits=3, cond_max=1e3, stream=None):
+    def __init__(self, pix, psi, det_offsets, det_weight, n_pix, min_hits=None, cond_max=1e3, stream=None,
+                 stokes="IQU", tod_dtype=None):
         torch = _torch()
         lib = load()
+        if stokes not in STOKES:
+            raise ValueError(f"stokes must be one of {sorted(STOKES)}")
+        self.stokes, self.ncomp = stokes, STOKES[stokes]
+        if min_hits is None:
+            min_hits = self.ncomp
         _dev_check(pix, torch.int32, name="pix")
-        _dev_check(psi, name="psi")
-        self.dtype = _dtype_code(psi)
         n = pix.numel()
-        if psi.numel() != n:
-            raise ValueError("pix and psi differ in length")
+        if psi is None:
+            if stokes != "I":
+                raise ValueError("psi is needed unless stokes='I'")
+            if tod_dtype is None:
+                raise ValueError("give tod_dtype when psi is None")
+            self.tod_dtype = tod_dtype
+        else:
+            _dev_check(psi, name="psi")
+            if psi.numel() != n:
+                raise ValueError("pix and psi differ in length")
+            self.tod_dtype = psi.dtype
+        self.dtype = MM_F64 if self.tod_dtype == torch.float64 else MM_F32
+        if self.tod_dtype not in (torch.float64, torch.float32):
+            raise TypeError(f"unsupported dtype {self.tod_dtype}")
         offs = np.ascontiguousarray(det_offsets, dtype=np.int64)
         w = np.ascontiguousarray(det_weight, dtype=np.float64)
         n_det = offs.size - 1
@@ -180,9 +206,10 @@ class Pointing:
         _check(lib.mm_pointing_workspace_size(n, n_det, int(n_pix), _c.byref(sz)))
         self.workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=pix.device)
         h = _vp()
-        _check(lib.mm_pointing_build(_ptr(pix), _ptr(psi), self.dtype, n, offs.ctypes.data_as(_pi64), n_det,
-                                     w.ctypes.data_as(_pf64), int(n_pix), int(min_hits), float(cond_max),
-                                     _ptr(self.workspace), sz.value, _stream(stream), _c.byref(h)))
+        _check(lib.mm_pointing_build_stokes(_ptr(pix), _ptr(psi), self.dtype, n, offs.ctypes.data_as(_pi64), n_det,
+                                            w.ctypes.data_as(_pf64), int(n_pix), self.ncomp, int(min_hits),
+                                            float(cond_max), _ptr(self.workspace), sz.value, _stream(stream),
+                                            _c.byref(h)))
         self.handle = h
         self._keep = (pix, psi)
         self.n_samples, self.n_pix, self.n_det = n, int(n_pix), n_det
@@ -190,7 +217,7 @@ class Pointing:
         _check(lib.mm_pointing_info(h, _c.byref(nk), None, None, None, None))
         self.n_kept = nk.value
         self.device = pix.device
-        self.tod_dtype = psi.dtype
+        self.weights = None
 
     def export(self, stream=None):
         torch = _torch()
@@ -199,16 +226,21 @@ class Pointing:
         mask = torch.empty(self.n_pix, dtype=torch.uint8, device=dev)
         compact = torch.empty(self.n_pix, dtype=torch.int32, device=dev)
         kept = torch.empty(max(1, self.n_kept), dtype=torch.int32, device=dev)
-        minv = torch.empty(max(1, 9 * self.n_kept), dtype=torch.float64, device=dev)
+        nc = self.ncomp
+        minv = torch.empty(max(1, nc * nc * self.n_kept), dtype=torch.float64, device=dev)
         _check(load().mm_pointing_export(self.handle, _ptr(hits), _ptr(mask), _ptr(compact), _ptr(kept), _ptr(minv),
                                          _stream(stream)))
         return {"hits": hits, "mask": mask, "compact": compact, "kept": kept[:self.n_kept],
-                "minv": minv[:9 * self.n_kept].view(-1, 3, 3)}
+                "minv": minv[:nc * nc * self.n_kept].view(-1, nc, nc)}
 
     def attach_weights(self, stream=None):
         """Precompute (cos 2psi, sin 2psi) per sample into a device tensor the
-        handle keeps; the band-Toeplitz operators then stream it."""
+        handle keeps; the band-Toeplitz operators then stream it.  The
+        intensity-only form reads no angle: nothing to attach (None)."""
         torch = _torch()
+        if self.ncomp == 1:
+            self.weights = None
+            return None
         self.weights = torch.empty(2 * max(1, self.n_samples), dtype=self.tod_dtype, device=self.device)
         _check(load().mm_pointing_attach_weights(self.handle, _ptr(self.weights), _stream(stream)))
         return self.weights
@@ -288,7 +320,7 @@ class Noise:
 
 def _vec(pt: Pointing, x, name):
     torch = _torch()
-    _dev_check(x, torch.float64, 3 * pt.n_kept, name)
+    _dev_check(x, torch.float64, pt.ncomp * pt.n_kept, name)
 
 
 def _tod(pt: Pointing, t, name):
@@ -309,7 +341,7 @@ def apply_PT(pt: Pointing, tod, q=None, arith="f64", stream=None):
     torch = _torch()
     _tod(pt, tod, "tod")
     if q is None:
-        q = torch.empty(3 * pt.n_kept, dtype=torch.float64, device=pt.device)
+        q = torch.empty(pt.ncomp * pt.n_kept, dtype=torch.float64, device=pt.device)
     _vec(pt, q, "q")
     _check(load().mm_apply_PT(pt.handle, _ptr(tod), _ptr(q), _arith(arith), _stream(stream)))
     return q
@@ -331,7 +363,7 @@ def apply_A(pt: Pointing, nz: Noise, x, q=None, arith="f64", stream=None, varian
     torch = _torch()
     _vec(pt, x, "x")
     if q is None:
-        q = torch.empty(3 * pt.n_kept, dtype=torch.float64, device=pt.device)
+        q = torch.empty(pt.ncomp * pt.n_kept, dtype=torch.float64, device=pt.device)
     _vec(pt, q, "q")
     if variant is None:
         _check(load().mm_apply_A(pt.handle, nz.handle, _ptr(x), _ptr(q), _arith(arith), _stream(stream)))
@@ -345,20 +377,20 @@ def rhs(pt: Pointing, nz: Noise, tod, b=None, arith="f64", stream=None):
     torch = _torch()
     _tod(pt, tod, "tod")
     if b is None:
-        b = torch.empty(3 * pt.n_kept, dtype=torch.float64, device=pt.device)
+        b = torch.empty(pt.ncomp * pt.n_kept, dtype=torch.float64, device=pt.device)
     _vec(pt, b, "b")
     _check(load().mm_rhs(pt.handle, nz.handle, _ptr(tod), _ptr(b), _arith(arith), _stream(stream)))
     return b
 
 
 def apply_A_multi(pt: Pointing, nz: Noise, x, q=None, arith="f64", stream=None):
-    """Q = A X for X of shape (n_rhs, 3 n_kept) in one launch."""
+    """Q = A X for X of shape (n_rhs, nc n_kept) in one launch."""
     torch = _torch()
     n_rhs = x.shape[0]
-    _dev_check(x, torch.float64, n_rhs * 3 * pt.n_kept, "x")
+    _dev_check(x, torch.float64, n_rhs * pt.ncomp * pt.n_kept, "x")
     if q is None:
         q = torch.empty_like(x)
-    _dev_check(q, torch.float64, n_rhs * 3 * pt.n_kept, "q")
+    _dev_check(q, torch.float64, n_rhs * pt.ncomp * pt.n_kept, "q")
     _check(load().mm_apply_A_multi(pt.handle, nz.handle, n_rhs, _ptr(x), _ptr(q), _arith(arith), _stream(stream)))
     return q
 
@@ -377,8 +409,8 @@ def expand_map(pt: Pointing, x, out=None, stream=None):
     torch = _torch()
     _vec(pt, x, "x")
     if out is None:
-        out = torch.empty(3 * pt.n_pix, dtype=torch.float64, device=pt.device)
-    _dev_check(out, torch.float64, 3 * pt.n_pix, "map")
+        out = torch.empty(pt.ncomp * pt.n_pix, dtype=torch.float64, device=pt.device)
+    _dev_check(out, torch.float64, pt.ncomp * pt.n_pix, "map")
     _check(load().mm_expand_map(pt.handle, _ptr(x), _ptr(out), _stream(stream)))
     return out
 
@@ -410,9 +442,9 @@ class Solver:
         pt = self.pt
         _tod(pt, tod, "tod")
         if map_out is None:
-            map_out = torch.empty(3 * pt.n_pix, dtype=torch.float64, device=pt.device)
+            map_out = torch.empty(pt.ncomp * pt.n_pix, dtype=torch.float64, device=pt.device)
         if x_out is None:
-            x_out = torch.empty(max(1, 3 * pt.n_kept), dtype=torch.float64, device=pt.device)
+            x_out = torch.empty(max(1, pt.ncomp * pt.n_kept), dtype=torch.float64, device=pt.device)
         info = SolveInfo()
         hist = np.zeros(self.hist_len) if history else None
         rc = load().mm_solve(pt.handle, self.nz.handle, _ptr(tod), _ptr(map_out), _ptr(x_out),
@@ -421,7 +453,7 @@ class Solver:
                              0 if hist is None else hist.size, _ptr(self.workspace), self.workspace.numel(),
                              _stream(stream))
         _check(rc, allow=(MM_OK, MM_NOTCONVERGED))
-        out = {"map": map_out, "x": x_out[:3 * pt.n_kept], "info": info.as_dict(), "status": rc}
+        out = {"map": map_out, "x": x_out[:pt.ncomp * pt.n_kept], "info": info.as_dict(), "status": rc}
         if hist is not None:
             n = (info.iters + 1) if not self.opts.mixed else info.outer_iters + 1
             out["history"] = hist[:n]
@@ -477,15 +509,15 @@ class AsyncSolver:
     def finish(self, history=False):
         torch = _torch()
         pt = self.pt
-        maps = torch.empty((self.n_rhs, 3 * pt.n_pix), dtype=torch.float64, device=pt.device)
-        xs = torch.empty((self.n_rhs, max(1, 3 * pt.n_kept)), dtype=torch.float64, device=pt.device)
+        maps = torch.empty((self.n_rhs, pt.ncomp * pt.n_pix), dtype=torch.float64, device=pt.device)
+        xs = torch.empty((self.n_rhs, max(1, pt.ncomp * pt.n_kept)), dtype=torch.float64, device=pt.device)
         infos = (SolveInfo * self.n_rhs)()
         hl = max(self.opts.max_iter, self.opts.fixed_iter, self.opts.max_outer) + 1
         hist = np.zeros(hl) if history else None
         rc = load().mm_solver_finish(self.handle, _ptr(maps), _ptr(xs), infos,
                                      None if hist is None else hist.ctypes.data_as(_pf64), 0 if hist is None else hl)
         _check(rc, allow=(MM_OK, MM_NOTCONVERGED))
-        out = {"maps": maps, "x": xs[:, :3 * pt.n_kept], "info": [i.as_dict() for i in infos], "status": rc}
+        out = {"maps": maps, "x": xs[:, :pt.ncomp * pt.n_kept], "info": [i.as_dict() for i in infos], "status": rc}
         if hist is not None:
             i0 = out["info"][0]
             out["history"] = hist[: (i0["outer_iters"] + 1 if self.opts.mixed else i0["iters"] + 1)]

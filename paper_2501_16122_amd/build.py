@@ -21,7 +21,7 @@ ARCH = os.environ.get("MM_OFFLOAD_ARCH", "gfx950")
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 CFLAGS = [
-    "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
+    "-O3", "-fPIC", "-std=c++20", f"--offload-arch={ARCH}",
     # FP64 atomics compile to hardware global/LDS atomic adds
     "-munsafe-fp-atomics",
     # no packed-FP32 instructions anywhere in the library

@@ -77,7 +77,7 @@ int apply_A_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x,
 }
 
 int rhs_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const void* tod, double* b, int arith, hipStream_t s) {
-  int rc = launch_fill(b, 3 * (int64_t)pt->n_kept, 0.0, s);
+  int rc = launch_fill(b, (int64_t)pt->ncomp * pt->n_kept, 0.0, s);
   if (rc) return rc;
   if (nz->kind == 0) return launch_rhs_white(pt, nz->det_w, tod, b, arith, s);
   return launch_fused_toeplitz(pt, nz, nullptr, tod, b, arith, RhsBatch{}, s);
@@ -158,7 +158,7 @@ extern "C" {
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
 
-int mm_abi_version(void) { return 2; }
+int mm_abi_version(void) { return 3; }
 
 int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, size_t* bytes) {
   if (!bytes || n_samples < 0 || n_det <= 0 || n_pix <= 0) return fail(MM_EINVAL, "bad pointing sizes");
@@ -174,11 +174,22 @@ int mm_pointing_build(const int32_t* pix, const void* psi, int32_t dtype, int64_
                       const int64_t* det_offsets_host, int32_t n_det, const double* det_weight_host, int32_t n_pix,
                       int32_t min_hits, double cond_max, void* workspace, size_t ws_bytes, void* stream,
                       mm_pointing_t* out) {
+  return mm_pointing_build_stokes(pix, psi, dtype, n_samples, det_offsets_host, n_det, det_weight_host, n_pix,
+                                  MM_STOKES_IQU, min_hits, cond_max, workspace, ws_bytes, stream, out);
+}
+
+int mm_pointing_build_stokes(const int32_t* pix, const void* psi, int32_t dtype, int64_t n_samples,
+                             const int64_t* det_offsets_host, int32_t n_det, const double* det_weight_host,
+                             int32_t n_pix, int32_t stokes, int32_t min_hits, double cond_max, void* workspace,
+                             size_t ws_bytes, void* stream, mm_pointing_t* out) {
   if (!out) return fail(MM_EINVAL, "null output handle pointer");
   *out = nullptr;
   if (!valid_dtype(dtype)) return fail(MM_EINVAL, "dtype must be MM_F64 or MM_F32");
+  if (stokes != MM_STOKES_IQU && stokes != MM_STOKES_QU && stokes != MM_STOKES_I)
+    return fail(MM_EINVAL, "stokes must be MM_STOKES_IQU, MM_STOKES_QU or MM_STOKES_I");
   if (n_samples < 0 || n_det <= 0 || n_pix <= 0) return fail(MM_EINVAL, "bad sizes");
-  if (n_samples > 0 && (!pix || !psi)) return fail(MM_EINVAL, "null pix or psi");
+  if (n_samples > 0 && !pix) return fail(MM_EINVAL, "null pix");
+  if (n_samples > 0 && !psi && stokes != MM_STOKES_I) return fail(MM_EINVAL, "null psi (needed unless stokes = I)");
   if (!det_offsets_host || !det_weight_host || !workspace) return fail(MM_EINVAL, "null argument");
   if (det_offsets_host[0] != 0 || det_offsets_host[n_det] != n_samples)
     return fail(MM_EINVAL, "det_offsets must start at 0 and end at n_samples");
@@ -195,11 +206,12 @@ int mm_pointing_build(const int32_t* pix, const void* psi, int32_t dtype, int64_
   auto* pt = new (std::nothrow) mm_pointing_s();
   if (!pt) return fail(MM_EINVAL, "out of host memory");
   pt->dtype = dtype;
+  pt->ncomp = stokes;
   pt->n_samples = n_samples;
   pt->n_det = n_det;
   pt->n_pix = n_pix;
   pt->pix = pix;
-  pt->psi = psi;
+  pt->psi = stokes == MM_STOKES_I ? nullptr : psi;  // the intensity-only row never uses the angle
   pt->det_offsets.assign(det_offsets_host, det_offsets_host + n_det + 1);
   pt->det_weight.assign(det_weight_host, det_weight_host + n_det);
   (void)hipGetDevice(&pt->device);
@@ -262,6 +274,13 @@ int mm_pointing_info(mm_pointing_t pt, int32_t* n_kept, int64_t* n_samples, int3
   return MM_OK;
 }
 
+int mm_pointing_stokes(mm_pointing_t pt, int32_t* stokes) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (!stokes) return fail(MM_EINVAL, "null output");
+  *stokes = pt->ncomp;
+  return MM_OK;
+}
+
 int mm_pointing_export(mm_pointing_t pt, int32_t* hits, uint8_t* mask, int32_t* compact, int32_t* kept, double* minv,
                        void* stream) {
   if (int rc = check_pointing(pt)) return rc;
@@ -274,6 +293,7 @@ int mm_pointing_attach_weights(mm_pointing_t pt, void* weights, void* stream) {
     pt->weights = nullptr;
     return MM_OK;
   }
+  if (pt->ncomp == 1) return fail(MM_EINVAL, "the intensity-only form has no pointing weights");
   if (int rc = launch_compute_weights(pt, weights, as_stream(stream))) return rc;
   pt->weights = weights;
   return MM_OK;
@@ -372,7 +392,7 @@ int mm_apply_PT(mm_pointing_t pt, const void* tod, double* q, int32_t arith, voi
   if (!valid_dtype(arith)) return fail(MM_EINVAL, "bad arith");
   if ((pt->n_kept && !q) || (pt->n_samples && !tod)) return fail(MM_EINVAL, "null vector");
   hipStream_t s = as_stream(stream);
-  if (int rc = launch_fill(q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
+  if (int rc = launch_fill(q, (int64_t)pt->ncomp * pt->n_kept, 0.0, s)) return rc;
   return launch_apply_PT(pt, tod, q, arith, s);
 }
 
@@ -396,7 +416,7 @@ int mm_apply_A(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int3
   if (!valid_dtype(arith)) return fail(MM_EINVAL, "bad arith");
   if (pt->n_kept && (!x || !q)) return fail(MM_EINVAL, "null vector");
   hipStream_t s = as_stream(stream);
-  if (int rc = launch_fill(q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
+  if (int rc = launch_fill(q, (int64_t)pt->ncomp * pt->n_kept, 0.0, s)) return rc;
   return apply_A_impl(pt, nz, x, q, arith, RhsBatch{}, s);
 }
 
@@ -408,7 +428,7 @@ int mm_apply_A_variant(mm_pointing_t pt, mm_noise_t nz, const double* x, double*
   if (!valid_dtype(arith)) return fail(MM_EINVAL, "bad arith");
   if (pt->n_kept && (!x || !q)) return fail(MM_EINVAL, "null vector");
   hipStream_t s = as_stream(stream);
-  if (int rc = launch_fill(q, 3 * (int64_t)pt->n_kept, 0.0, s)) return rc;
+  if (int rc = launch_fill(q, (int64_t)pt->ncomp * pt->n_kept, 0.0, s)) return rc;
   return apply_A_impl(pt, nz, x, q, arith, RhsBatch{}, s, variant);
 }
 
@@ -419,7 +439,7 @@ int mm_apply_A_multi(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const doubl
   if (!valid_dtype(arith) || n_rhs < 1) return fail(MM_EINVAL, "bad arith or n_rhs");
   if (pt->n_kept && (!x || !q)) return fail(MM_EINVAL, "null vector");
   hipStream_t s = as_stream(stream);
-  const int64_t n3 = 3 * (int64_t)pt->n_kept;
+  const int64_t n3 = (int64_t)pt->ncomp * pt->n_kept;
   if (int rc = launch_fill(q, n3 * n_rhs, 0.0, s)) return rc;
   RhsBatch rb;
   rb.nrhs = n_rhs;

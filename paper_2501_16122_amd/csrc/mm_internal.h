@@ -99,6 +99,7 @@ struct Carver {
 
 struct mm_pointing_s {
   int32_t dtype = MM_F64;
+  int32_t ncomp = 3;  // values per pixel: 3 = I, Q, U; 2 = Q, U; 1 = I
   int64_t n_samples = 0;
   int32_t n_det = 0;
   int32_t n_pix = 0;
@@ -115,8 +116,8 @@ struct mm_pointing_s {
   uint8_t* mask = nullptr;       // [n_pix]
   int32_t* compact = nullptr;    // [n_pix]
   int32_t* kept = nullptr;       // [n_pix] (first n_kept used)
-  double* blocks = nullptr;      // [6 * n_pix] upper triangles of P^T diag(N)^-1 P
-  double* minv = nullptr;        // [6 * n_pix] upper triangles of the inverses (compact order)
+  double* blocks = nullptr;      // [nb * n_pix] upper triangles of P^T diag(N)^-1 P, nb = ncomp (ncomp + 1) / 2
+  double* minv = nullptr;        // [nb * n_pix] upper triangles of the inverses (compact order)
   int32_t* sample_k = nullptr;   // [n_samples] compact index per sample, -1 = masked
   double* det_w = nullptr;       // [n_det]
   mm::PtTile* tiles = nullptr;   // [n_tiles]
@@ -149,12 +150,24 @@ struct mm_noise_s {
   // operator variants picked by the autotuner, per problem shape
   struct Tuned {
     int64_t n_samples;
-    int32_t n_kept, dtype, arith, nrhs, variant, pad_;
+    int32_t n_kept, dtype, arith, nrhs, variant, ncomp;
   };
   mutable std::vector<Tuned> tuned;
 };
 
 namespace mm {
+
+// Calls f.template operator()<NC>() with the map form's number of values
+// per pixel as a compile-time constant.
+template <class F>
+int by_ncomp(int nc, F&& f) {
+  switch (nc) {
+    case 3: return f.template operator()<3>();
+    case 2: return f.template operator()<2>();
+    case 1: return f.template operator()<1>();
+    default: return fail(MM_EINVAL, "map form must have 1, 2 or 3 values per pixel");
+  }
+}
 
 // ---------------------------------------------------------------------------
 // kernel launchers (each defined in the .hip file that holds its kernel)
@@ -250,6 +263,8 @@ struct PcgArgs {
   int64_t vstride;
   int32_t n_kept;
   int32_t hist_len;
+  int32_t ncomp;     // values per kept pixel (vectors hold ncomp * n_kept)
+  int32_t max_iter;  // inner iteration cap of a re-initialised inner solve (batched refinement)
 };
 
 // Outer FP64 refinement state per right-hand side.
@@ -276,7 +291,7 @@ struct OuterArgs {
   double* hist;      // [nrhs][hist_len]
   int64_t vstride;
   int32_t hist_len;
-  int32_t pad_;
+  int32_t max_outer;  // refinement step cap (batched refinement)
 };
 
 // ---------------------------------------------------------------------------
@@ -310,9 +325,9 @@ struct OpBatch {
 static_assert(sizeof(OpBatch) <= 2048, "operator batch must stay a small kernel argument");
 
 // q += P^T N^-1 P x for every slot, one persistent launch per noise kind.
-// dtype / arith / weights must be common to all slots of the launch.
-int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, hipStream_t s);
-int launch_white_batch(const OpBatch& b, int dtype, int arith, hipStream_t s);
+// dtype / arith / weights / map form must be common to all slots of the launch.
+int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, int ncomp, hipStream_t s);
+int launch_white_batch(const OpBatch& b, int dtype, int arith, int ncomp, hipStream_t s);
 
 int launch_pcg_init(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, double tol, int32_t max_iter,
                     int32_t fixed_iter, const OuterState* gate, hipStream_t s);
@@ -326,13 +341,11 @@ int launch_outer_end(const OuterArgs& o, const PcgArgs& a, int nrhs, double tol,
 // One slot of a batched PCG launch: single right-hand-side views (slice 0)
 // of a solver's inner and outer state, and its preconditioner blocks.
 struct PcgSlot {
-  PcgArgs A;
-  OuterArgs O;
+  PcgArgs A;          // A.max_iter: inner iteration cap
+  OuterArgs O;        // O.max_outer: refinement step cap
   const double* minv;
   double tol;         // outer tolerance (mixed)
   double inner_tol;   // inner tolerance of a re-initialised inner solve
-  int32_t max_iter;   // inner iteration cap
-  int32_t max_outer;  // refinement step cap
 };
 struct PcgBatch {
   int32_t n = 0;

@@ -71,11 +71,20 @@ __device__ bool grid_sum2(double& a, double& b, double* partials, uint32_t* coun
   return true;
 }
 
-__device__ __forceinline__ void apply_m3(const double* __restrict__ m, double r0, double r1, double r2,
-                                         double& z0, double& z1, double& z2) {
-  z0 = m[0] * r0 + m[1] * r1 + m[2] * r2;
-  z1 = m[1] * r0 + m[3] * r1 + m[4] * r2;
-  z2 = m[2] * r0 + m[4] * r1 + m[5] * r2;
+// z = B^-1 r for one pixel: the symmetric NC x NC inverse block of eq. (7)
+// stored as its upper triangle, row-major.
+template <int NC>
+__device__ __forceinline__ void apply_m(const double* __restrict__ m, const double* r, double* z) {
+  if constexpr (NC == 3) {
+    z[0] = m[0] * r[0] + m[1] * r[1] + m[2] * r[2];
+    z[1] = m[1] * r[0] + m[3] * r[1] + m[4] * r[2];
+    z[2] = m[2] * r[0] + m[4] * r[1] + m[5] * r[2];
+  } else if constexpr (NC == 2) {
+    z[0] = m[0] * r[0] + m[1] * r[1];
+    z[1] = m[1] * r[0] + m[2] * r[1];
+  } else {
+    z[0] = m[0] * r[0];
+  }
 }
 
 // One right-hand side: its vectors, state, partials and history.
@@ -87,13 +96,15 @@ struct Slice {
   double* hist;
   int32_t n_kept;
   int32_t hist_len;
+  int32_t ncomp;  // values per kept pixel
+  int64_t n;      // ncomp * n_kept values per vector
 };
 
 __device__ __forceinline__ Slice slice(const PcgArgs& a, int y) {
   const int64_t o = (int64_t)y * a.vstride;
   return Slice{a.x + o, a.r + o, a.z + o, a.p + o, a.q + o, a.b + o,
                a.partials + (int64_t)y * 2 * kPcgBlocks, a.st + y, a.hist + (int64_t)y * a.hist_len,
-               a.n_kept, a.hist_len};
+               a.n_kept, a.hist_len, a.ncomp, (int64_t)a.ncomp * a.n_kept};
 }
 
 // The outer refinement vectors and state of one right-hand side.
@@ -116,24 +127,41 @@ __device__ __forceinline__ OSlice oslice(const OuterArgs& o, int y) {
 
 // x = 0, r = b, z = M r, p = z, q = 0, rho = r.z, ||b||.  Skipped while the
 // gate (outer state) is done or has no step pending.
+template <int NC>
+__device__ __forceinline__ void pcg_init_sums(const Slice& S, const double* __restrict__ minv, double& bb,
+                                              double& rz) {
+  constexpr int NB = NC * (NC + 1) / 2;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
+    double bv[NC], zv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) bv[c] = S.b[NC * k + c];
+    apply_m<NC>(minv + NB * k, bv, zv);
+    double sb = 0.0, sz = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t i = NC * k + c;
+      S.x[i] = 0.0;
+      S.r[i] = bv[c];
+      S.z[i] = zv[c];
+      S.p[i] = zv[c];
+      S.q[i] = 0.0;
+      sb += bv[c] * bv[c];
+      sz += bv[c] * zv[c];
+    }
+    bb += sb;
+    rz += sz;
+  }
+}
+
 __device__ __forceinline__ void pcg_init_body(const Slice& S, const double* __restrict__ minv, double tol,
                                               int32_t max_iter, int32_t fixed_iter, const OuterState* gate) {
   if (gate != nullptr && (gate->done || gate->skip)) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   double bb = 0.0, rz = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
-    const double b0 = S.b[3 * k], b1 = S.b[3 * k + 1], b2 = S.b[3 * k + 2];
-    double z0, z1, z2;
-    apply_m3(minv + 6 * k, b0, b1, b2, z0, z1, z2);
-    S.x[3 * k] = 0.0; S.x[3 * k + 1] = 0.0; S.x[3 * k + 2] = 0.0;
-    S.r[3 * k] = b0; S.r[3 * k + 1] = b1; S.r[3 * k + 2] = b2;
-    S.z[3 * k] = z0; S.z[3 * k + 1] = z1; S.z[3 * k + 2] = z2;
-    S.p[3 * k] = z0; S.p[3 * k + 1] = z1; S.p[3 * k + 2] = z2;
-    S.q[3 * k] = 0.0; S.q[3 * k + 1] = 0.0; S.q[3 * k + 2] = 0.0;
-    bb += b0 * b0 + b1 * b1 + b2 * b2;
-    rz += b0 * z0 + b1 * z1 + b2 * z2;
-  }
+  if (S.ncomp == 3) pcg_init_sums<3>(S, minv, bb, rz);
+  else if (S.ncomp == 2) pcg_init_sums<2>(S, minv, bb, rz);
+  else pcg_init_sums<1>(S, minv, bb, rz);
   if (!grid_sum2(bb, rz, S.partials, &S.st->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
     PcgState* st = S.st;
@@ -162,7 +190,7 @@ __device__ __forceinline__ void pcg_alpha_body(const Slice& S) {
   __shared__ double sh[16];
   __shared__ bool s_last;
   double pq = 0.0, unused = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)S.n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
        i += (int64_t)gridDim.x * blockDim.x)
     pq += S.p[i] * S.q[i];
   if (!grid_sum2(pq, unused, S.partials, &S.st->counter, sh, &s_last)) return;
@@ -177,26 +205,41 @@ __device__ __forceinline__ void pcg_alpha_body(const Slice& S) {
 }
 
 // x += alpha p, r -= alpha q, z = M r, ||r||, r.z, the stopping test, beta
+template <int NC>
+__device__ __forceinline__ void pcg_update_sums(const Slice& S, const double* __restrict__ minv, double alpha,
+                                                double& rr, double& rz) {
+  constexpr int NB = NC * (NC + 1) / 2;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
+    double rv[NC], zv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t i = NC * k + c;
+      S.x[i] += alpha * S.p[i];
+      rv[c] = S.r[i] - alpha * S.q[i];
+      S.r[i] = rv[c];
+    }
+    apply_m<NC>(minv + NB * k, rv, zv);
+    double sr = 0.0, sz = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      S.z[NC * k + c] = zv[c];
+      sr += rv[c] * rv[c];
+      sz += rv[c] * zv[c];
+    }
+    rr += sr;
+    rz += sz;
+  }
+}
+
 __device__ __forceinline__ void pcg_update_body(const Slice& S, const double* __restrict__ minv) {
   if (S.st->done) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   const double alpha = S.st->alpha;
   double rr = 0.0, rz = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
-    double rv[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      S.x[3 * k + c] += alpha * S.p[3 * k + c];
-      rv[c] = S.r[3 * k + c] - alpha * S.q[3 * k + c];
-      S.r[3 * k + c] = rv[c];
-    }
-    double z0, z1, z2;
-    apply_m3(minv + 6 * k, rv[0], rv[1], rv[2], z0, z1, z2);
-    S.z[3 * k] = z0; S.z[3 * k + 1] = z1; S.z[3 * k + 2] = z2;
-    rr += rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
-    rz += rv[0] * z0 + rv[1] * z1 + rv[2] * z2;
-  }
+  if (S.ncomp == 3) pcg_update_sums<3>(S, minv, alpha, rr, rz);
+  else if (S.ncomp == 2) pcg_update_sums<2>(S, minv, alpha, rr, rz);
+  else pcg_update_sums<1>(S, minv, alpha, rr, rz);
   if (!grid_sum2(rr, rz, S.partials, &S.st->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
     PcgState* st = S.st;
@@ -228,7 +271,7 @@ __device__ __forceinline__ void pcg_update_body(const Slice& S, const double* __
 __device__ __forceinline__ void pcg_direction_body(const Slice& S) {
   if (S.st->done) return;
   const double beta = S.st->beta;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)S.n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
        i += (int64_t)gridDim.x * blockDim.x) {
     S.p[i] = S.z[i] + beta * S.p[i];
     S.q[i] = 0.0;
@@ -241,7 +284,7 @@ __device__ __forceinline__ void pcg_direction_body(const Slice& S) {
 __device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S) {
   __shared__ double sh[16];
   __shared__ bool s_last;
-  const int64_t n3 = 3 * (int64_t)S.n_kept;
+  const int64_t n3 = S.n;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     S.st->done = 1;
     S.st->iter = 0;
@@ -279,7 +322,7 @@ __device__ __forceinline__ void outer_add_body(const OSlice& O, const Slice& S) 
     if (blockIdx.x == 0 && threadIdx.x == 0) os->skip = 1;
     return;
   }
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)S.n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
        i += (int64_t)gridDim.x * blockDim.x) {
     O.xt[i] += S.x[i];
     S.q[i] = 0.0;
@@ -298,7 +341,7 @@ __device__ __forceinline__ void outer_end_body(const OSlice& O, const Slice& S, 
   __shared__ double sh[16];
   __shared__ bool s_last;
   double rr = 0.0, unused = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)S.n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double v = O.b64[i] - S.q[i];
     O.rt[i] = v;
@@ -371,12 +414,12 @@ __global__ __launch_bounds__(kPcgThreads) void k_outer_add_b(PcgBatch b) {
 
 __global__ __launch_bounds__(kPcgThreads) void k_outer_end_b(PcgBatch b) {
   const PcgSlot& p = b.s[blockIdx.y];
-  outer_end_body(oslice(p.O, 0), slice(p.A, 0), p.tol, p.max_outer);
+  outer_end_body(oslice(p.O, 0), slice(p.A, 0), p.tol, p.O.max_outer);
 }
 
 __global__ __launch_bounds__(kPcgThreads) void k_pcg_reinit_b(PcgBatch b) {
   const PcgSlot& p = b.s[blockIdx.y];
-  pcg_init_body(slice(p.A, 0), p.minv, p.inner_tol, p.max_iter, 0, p.O.os);
+  pcg_init_body(slice(p.A, 0), p.minv, p.inner_tol, p.A.max_iter, 0, p.O.os);
 }
 
 // scratch0 = ||a - b||^2, scratch1 = ||a||^2 per slice
@@ -387,7 +430,7 @@ __global__ __launch_bounds__(kPcgThreads) void k_diff_norm(PcgArgs A, const doub
   Slice S = slice(A, blockIdx.y);
   const int64_t off = (int64_t)blockIdx.y * A.vstride;
   double dd = 0.0, aa = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * (int64_t)A.n_kept;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double d = a[off + i] - b[off + i];
     dd += d * d;

@@ -1,13 +1,17 @@
-// Pointing build: hits, the 3x3 blocks of P^T diag(N)^-1 P (eq. (7)), their
+// Pointing build: hits, the NC x NC blocks of P^T diag(N)^-1 P (eq. (7); NC
+// = 3, 2 or 1 values per pixel for the IQU, QU and I map forms), their
 // 2-norm conditioning, the mask, the ascending compaction of kept pixels and
 // the inverse blocks of the preconditioner; then the per-sample compact index
-// and each tile's compact-index window used by the hot kernels.
+// and each tile's compact-index window used by the hot kernels.  Blocks and
+// inverses are stored as upper triangles, row-major, NC (NC + 1) / 2 doubles
+// per pixel.
 #include <climits>
 
 #pragma clang fp contract(off)
 
 #include "mm_internal.h"
 #include "sincos2.h"
+#include "stokes.h"
 
 namespace mm {
 namespace {
@@ -38,11 +42,13 @@ __device__ T block_reduce(T v, T* sh, bool is_min) {
   return r;
 }
 
-// K1: per tile, bin hits and w * (1, c, s, cc, cs, ss) of every sample into
-// LDS slots over the tile's pixel range, then add the slots to the global
-// sums with one atomic per touched pixel; samples beyond the LDS window go
-// straight to global atomics.  An out-of-range pixel sets flags[0].
-template <class S>
+// K1: per tile, bin hits and the upper triangle of w a a^T (a the row of P:
+// (1, c, s), (c, s) or (1)) of every sample into LDS slots over the tile's
+// pixel range, then add the slots to the global sums with one atomic per
+// touched pixel; samples beyond the LDS window go straight to global atomics.
+// An out-of-range pixel sets flags[0] (an unusable angle flags[0] bit 1; the
+// intensity form reads no angle).
+template <class S, int NC>
 __global__ __launch_bounds__(kBuildThreads) void k_pointing_hist(const PtTile* __restrict__ tiles,
                                                                  const int32_t* __restrict__ pix,
                                                                  const S* __restrict__ psi,
@@ -50,8 +56,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_pointing_hist(const PtTile* _
                                                                  int32_t* __restrict__ hits,
                                                                  double* __restrict__ blocks,
                                                                  int32_t* __restrict__ flags) {
+  constexpr int NB = Stokes<NC>::kBlock;
   __shared__ int32_t s_hits[kBuildBins];
-  __shared__ double s_acc[6 * kBuildBins];
+  __shared__ double s_acc[NB * kBuildBins];
   __shared__ int32_t s_red[16];
   const PtTile tl = tiles[blockIdx.x];
   int32_t lo = INT_MAX, hi = INT_MIN;
@@ -69,7 +76,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_pointing_hist(const PtTile* _
   for (int i = threadIdx.x; i < kBuildBins; i += blockDim.x) {
     s_hits[i] = 0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) s_acc[j * kBuildBins + i] = 0.0;
+    for (int j = 0; j < NB; ++j) s_acc[j * kBuildBins + i] = 0.0;
   }
   __syncthreads();
   const double w = det_w[tl.det];
@@ -77,22 +84,36 @@ __global__ __launch_bounds__(kBuildThreads) void k_pointing_hist(const PtTile* _
     const int64_t t = tl.start + i;
     const int32_t p = pix[t];
     if (p < 0 || p >= n_pix) continue;
-    if (!(fabs(2.0 * double(psi[t])) < sc::kReduceMax)) {  // also NaN / inf
-      atomicOr(&flags[0], 2);
-      continue;
+    double a[3] = {1.0, 0.0, 0.0};  // the row of P
+    if constexpr (Stokes<NC>::kAngle) {
+      if (!(fabs(2.0 * double(psi[t])) < sc::kReduceMax)) {  // also NaN / inf
+        atomicOr(&flags[0], 2);
+        continue;
+      }
+      double c, s;
+      sincos2<double>(psi[t], &c, &s);
+      if constexpr (NC == 3) {
+        a[1] = c;
+        a[2] = s;
+      } else {
+        a[0] = c;
+        a[1] = s;
+      }
     }
-    double c, s;
-    sincos2<double>(psi[t], &c, &s);
-    const double v[6] = {w, w * c, w * s, w * c * c, w * c * s, w * s * s};
+    double v[NB];
+#pragma unroll
+    for (int i = 0, j = 0; i < NC; ++i)
+#pragma unroll
+      for (int k = i; k < NC; ++k) v[j++] = w * a[i] * a[k];
     const int32_t rel = p - base;
     if (rel < kBuildBins) {
       atomicAdd(&s_hits[rel], 1);
 #pragma unroll
-      for (int j = 0; j < 6; ++j) atomicAdd(&s_acc[j * kBuildBins + rel], v[j]);
+      for (int j = 0; j < NB; ++j) atomicAdd(&s_acc[j * kBuildBins + rel], v[j]);
     } else {
       atomicAdd(&hits[p], 1);
 #pragma unroll
-      for (int j = 0; j < 6; ++j) atomicAdd(&blocks[6 * (int64_t)p + j], v[j]);
+      for (int j = 0; j < NB; ++j) atomicAdd(&blocks[NB * (int64_t)p + j], v[j]);
     }
   }
   __syncthreads();
@@ -102,7 +123,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_pointing_hist(const PtTile* _
     const int64_t p = base + i;
     atomicAdd(&hits[p], h);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) atomicAdd(&blocks[6 * p + j], s_acc[j * kBuildBins + i]);
+    for (int j = 0; j < NB; ++j) atomicAdd(&blocks[NB * p + j], s_acc[j * kBuildBins + i]);
   }
 }
 
@@ -147,10 +168,34 @@ __device__ void sym3_eigvals(const double b[6], double ev[3]) {
   ev[0] = a00; ev[1] = a11; ev[2] = a22;
 }
 
+// 2-norm condition number of a block (upper triangle b): lambda_max /
+// lambda_min, +inf when lambda_min <= 0 (NaN propagates and masks).
+template <int NC>
+__device__ __forceinline__ double block_cond(const double* b) {
+  if constexpr (NC == 3) {
+    double ev[3];
+    sym3_eigvals(b, ev);
+    const double lo = fmin(ev[0], fmin(ev[1], ev[2]));
+    const double hi = fmax(ev[0], fmax(ev[1], ev[2]));
+    return lo > 0.0 ? hi / lo : INFINITY;
+  } else if constexpr (NC == 2) {
+    // [[a, c], [c, d]]: eigenvalues m -/+ r with m the mean of the diagonal
+    // and r = hypot((a - d) / 2, c); the smaller one as det / the larger
+    const double a = b[0], c = b[1], d = b[2];
+    const double m = 0.5 * (a + d), r = hypot(0.5 * (a - d), c);
+    const double hi = m + r;
+    const double lo = hi > 0.0 ? (a * d - c * c) / hi : -1.0;
+    return lo > 0.0 ? hi / lo : INFINITY;
+  } else {
+    return b[0] > 0.0 ? 1.0 : INFINITY;
+  }
+}
+
 // K2a: per pixel, the keep decision (hits >= min_hits and cond <= cond_max)
 // and the per-block count of kept pixels.
 constexpr int kScanBlock = 1024;  // pixels per scan block (4 per thread)
 
+template <int NC>
 __global__ __launch_bounds__(256) void k_pixel_keep(const int32_t* __restrict__ hits,
                                                     const double* __restrict__ blocks, int32_t n_pix,
                                                     int32_t min_hits, double cond_max,
@@ -162,14 +207,11 @@ __global__ __launch_bounds__(256) void k_pixel_keep(const int32_t* __restrict__ 
     if (p >= n_pix) continue;
     bool keep = false;
     if (hits[p] >= min_hits) {
-      double b[6], ev[3];
+      constexpr int NB = Stokes<NC>::kBlock;
+      double b[NB];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) b[i] = blocks[6 * p + i];
-      sym3_eigvals(b, ev);
-      double lo = fmin(ev[0], fmin(ev[1], ev[2]));
-      double hi = fmax(ev[0], fmax(ev[1], ev[2]));
-      const double cond = lo > 0.0 ? hi / lo : INFINITY;
-      keep = cond <= cond_max;  // NaN -> masked
+      for (int i = 0; i < NB; ++i) b[i] = blocks[NB * p + i];
+      keep = block_cond<NC>(b) <= cond_max;  // NaN -> masked
     }
     mask[p] = keep ? 0 : 1;
     cnt += keep ? 1 : 0;
@@ -205,8 +247,36 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int32_t* __restrict__ coun
   if (threadIdx.x == 0) *total = carry;
 }
 
+// Closed-form inverse (adjugate / determinant) of a kept block, both as
+// upper triangles.
+template <int NC>
+__device__ __forceinline__ void block_inverse(const double* m, double* o) {
+  if constexpr (NC == 3) {
+    const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5];
+    // [[a b c] [b d e] [c e f]]
+    const double A = d * f - e * e, B = c * e - b * f, C = b * e - c * d;
+    const double det = a * A + b * B + c * C;
+    const double inv = 1.0 / det;
+    o[0] = A * inv;
+    o[1] = B * inv;
+    o[2] = C * inv;
+    o[3] = (a * f - c * c) * inv;
+    o[4] = (b * c - a * e) * inv;
+    o[5] = (a * d - b * b) * inv;
+  } else if constexpr (NC == 2) {
+    const double a = m[0], b = m[1], d = m[2];  // [[a b] [b d]]
+    const double inv = 1.0 / (a * d - b * b);
+    o[0] = d * inv;
+    o[1] = -b * inv;
+    o[2] = a * inv;
+  } else {
+    o[0] = 1.0 / m[0];
+  }
+}
+
 // K2c: compact index of every pixel (ascending), the kept list and the
-// closed-form inverse (adjugate / determinant) of each kept block.
+// inverse of each kept block.
+template <int NC>
 __global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ mask,
                                                  const int32_t* __restrict__ block_offsets,
                                                  const double* __restrict__ blocks, int32_t n_pix,
@@ -241,18 +311,13 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ mas
     const int32_t k = boff + sh[i] - 1;
     compact[p] = k;
     kept[k] = (int32_t)p;
-    const double a = blocks[6 * p + 0], b = blocks[6 * p + 1], c = blocks[6 * p + 2];
-    const double d = blocks[6 * p + 3], e = blocks[6 * p + 4], f = blocks[6 * p + 5];
-    // [[a b c] [b d e] [c e f]]
-    const double A = d * f - e * e, B = c * e - b * f, C = b * e - c * d;
-    const double det = a * A + b * B + c * C;
-    const double inv = 1.0 / det;
-    minv[6 * (int64_t)k + 0] = A * inv;
-    minv[6 * (int64_t)k + 1] = B * inv;
-    minv[6 * (int64_t)k + 2] = C * inv;
-    minv[6 * (int64_t)k + 3] = (a * f - c * c) * inv;
-    minv[6 * (int64_t)k + 4] = (b * c - a * e) * inv;
-    minv[6 * (int64_t)k + 5] = (a * d - b * b) * inv;
+    constexpr int NB = Stokes<NC>::kBlock;
+    double m[NB], o[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) m[j] = blocks[NB * p + j];
+    block_inverse<NC>(m, o);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) minv[NB * (int64_t)k + j] = o[j];
   }
 }
 
@@ -282,38 +347,46 @@ __global__ __launch_bounds__(256) void k_sample_index(PtTile* __restrict__ tiles
   }
 }
 
-__global__ void k_export_minv(const double* __restrict__ minv6, int32_t n_kept, double* __restrict__ out9) {
+// Inverse blocks as full row-major NC x NC matrices.
+template <int NC>
+__global__ void k_export_minv(const double* __restrict__ minv_ut, int32_t n_kept, double* __restrict__ out) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_kept) return;
-  const double* m = minv6 + 6 * k;
-  double* o = out9 + 9 * k;
-  o[0] = m[0]; o[1] = m[1]; o[2] = m[2];
-  o[3] = m[1]; o[4] = m[3]; o[5] = m[4];
-  o[6] = m[2]; o[7] = m[4]; o[8] = m[5];
+  constexpr int NB = Stokes<NC>::kBlock;
+  const double* m = minv_ut + NB * k;
+  double* o = out + NC * NC * k;
+#pragma unroll
+  for (int i = 0, j = 0; i < NC; ++i)
+#pragma unroll
+    for (int c = i; c < NC; ++c, ++j) {
+      o[NC * i + c] = m[j];
+      o[NC * c + i] = m[j];
+    }
 }
 
-}  // namespace
-
-int launch_pointing_build(mm_pointing_s* pt, int32_t min_hits, double cond_max, hipStream_t s) {
+template <int NC>
+int build_nc(mm_pointing_s* pt, int32_t min_hits, double cond_max, hipStream_t s) {
   const int64_t nb_scan = (pt->n_pix + kScanBlock - 1) / kScanBlock;
   MM_HIP(hipMemsetAsync(pt->hits, 0, sizeof(int32_t) * pt->n_pix, s));
-  MM_HIP(hipMemsetAsync(pt->blocks, 0, sizeof(double) * 6 * (size_t)pt->n_pix, s));
+  MM_HIP(hipMemsetAsync(pt->blocks, 0, sizeof(double) * Stokes<NC>::kBlock * (size_t)pt->n_pix, s));
   MM_HIP(hipMemsetAsync(pt->flags, 0, sizeof(int32_t) * 4, s));
   if (pt->n_tiles > 0) {
     if (pt->dtype == MM_F64)
-      hipLaunchKernelGGL(k_pointing_hist<double>, dim3(pt->n_tiles), dim3(kBuildThreads), 0, s, pt->tiles, pt->pix,
-                         static_cast<const double*>(pt->psi), pt->det_w, pt->n_pix, pt->hits, pt->blocks, pt->flags);
+      hipLaunchKernelGGL((k_pointing_hist<double, NC>), dim3(pt->n_tiles), dim3(kBuildThreads), 0, s, pt->tiles,
+                         pt->pix, static_cast<const double*>(pt->psi), pt->det_w, pt->n_pix, pt->hits, pt->blocks,
+                         pt->flags);
     else
-      hipLaunchKernelGGL(k_pointing_hist<float>, dim3(pt->n_tiles), dim3(kBuildThreads), 0, s, pt->tiles, pt->pix,
-                         static_cast<const float*>(pt->psi), pt->det_w, pt->n_pix, pt->hits, pt->blocks, pt->flags);
+      hipLaunchKernelGGL((k_pointing_hist<float, NC>), dim3(pt->n_tiles), dim3(kBuildThreads), 0, s, pt->tiles,
+                         pt->pix, static_cast<const float*>(pt->psi), pt->det_w, pt->n_pix, pt->hits, pt->blocks,
+                         pt->flags);
     MM_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_pixel_keep, dim3(nb_scan), dim3(256), 0, s, pt->hits, pt->blocks, pt->n_pix, min_hits, cond_max,
-                     pt->mask, pt->scan_tmp);
+  hipLaunchKernelGGL(k_pixel_keep<NC>, dim3(nb_scan), dim3(256), 0, s, pt->hits, pt->blocks, pt->n_pix, min_hits,
+                     cond_max, pt->mask, pt->scan_tmp);
   MM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, pt->scan_tmp, (int32_t)nb_scan, &pt->flags[1]);
   MM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_compact, dim3(nb_scan), dim3(256), 0, s, pt->mask, pt->scan_tmp, pt->blocks, pt->n_pix,
+  hipLaunchKernelGGL(k_compact<NC>, dim3(nb_scan), dim3(256), 0, s, pt->mask, pt->scan_tmp, pt->blocks, pt->n_pix,
                      pt->compact, pt->kept, pt->minv);
   MM_HIP(hipGetLastError());
   if (pt->n_tiles > 0) {
@@ -324,6 +397,17 @@ int launch_pointing_build(mm_pointing_s* pt, int32_t min_hits, double cond_max, 
   return MM_OK;
 }
 
+}  // namespace
+
+int launch_pointing_build(mm_pointing_s* pt, int32_t min_hits, double cond_max, hipStream_t s) {
+  switch (pt->ncomp) {
+    case 3: return build_nc<3>(pt, min_hits, cond_max, s);
+    case 2: return build_nc<2>(pt, min_hits, cond_max, s);
+    case 1: return build_nc<1>(pt, min_hits, cond_max, s);
+    default: return fail(MM_EINVAL, "map form must have 1, 2 or 3 values per pixel");
+  }
+}
+
 int launch_export(const mm_pointing_s* pt, int32_t* hits, uint8_t* mask, int32_t* compact, int32_t* kept,
                   double* minv, hipStream_t s) {
   if (hits) MM_HIP(hipMemcpyAsync(hits, pt->hits, sizeof(int32_t) * pt->n_pix, hipMemcpyDeviceToDevice, s));
@@ -332,7 +416,10 @@ int launch_export(const mm_pointing_s* pt, int32_t* hits, uint8_t* mask, int32_t
   if (kept && pt->n_kept)
     MM_HIP(hipMemcpyAsync(kept, pt->kept, sizeof(int32_t) * pt->n_kept, hipMemcpyDeviceToDevice, s));
   if (minv && pt->n_kept) {
-    hipLaunchKernelGGL(k_export_minv, dim3((pt->n_kept + 255) / 256), dim3(256), 0, s, pt->minv, pt->n_kept, minv);
+    const dim3 g((pt->n_kept + 255) / 256), b(256);
+    if (pt->ncomp == 3) hipLaunchKernelGGL(k_export_minv<3>, g, b, 0, s, pt->minv, pt->n_kept, minv);
+    else if (pt->ncomp == 2) hipLaunchKernelGGL(k_export_minv<2>, g, b, 0, s, pt->minv, pt->n_kept, minv);
+    else hipLaunchKernelGGL(k_export_minv<1>, g, b, 0, s, pt->minv, pt->n_kept, minv);
     MM_HIP(hipGetLastError());
   }
   return MM_OK;

@@ -39,8 +39,8 @@ struct Layout {
 int32_t inner_hist_len(const mm_solve_opts& o) { return std::max<int32_t>(1, (o.fixed_iter > 0 ? o.fixed_iter : o.max_iter) + 1); }
 int32_t outer_hist_len(const mm_solve_opts& o) { return std::max<int32_t>(1, o.max_outer + 1); }
 
-size_t carve(Carver& cv, int32_t n_kept, int32_t nrhs, const mm_solve_opts& o, Layout* L) {
-  const size_t n3 = 3 * (size_t)n_kept, nv = n3 * nrhs;
+size_t carve(Carver& cv, int32_t n_kept, int32_t ncomp, int32_t nrhs, const mm_solve_opts& o, Layout* L) {
+  const size_t n3 = (size_t)ncomp * n_kept, nv = n3 * nrhs;
   PcgArgs& A = L->A;
   A.x = cv.take<double>(nv);
   A.r = cv.take<double>(nv);
@@ -54,6 +54,8 @@ size_t carve(Carver& cv, int32_t n_kept, int32_t nrhs, const mm_solve_opts& o, L
   A.hist = cv.take<double>((size_t)A.hist_len * nrhs);
   A.vstride = (int64_t)n3;
   A.n_kept = n_kept;
+  A.ncomp = ncomp;
+  A.max_iter = o.max_iter;
   A.b = L->b;
   OuterArgs& O = L->O;
   O.xt = cv.take<double>(nv);
@@ -65,7 +67,7 @@ size_t carve(Carver& cv, int32_t n_kept, int32_t nrhs, const mm_solve_opts& o, L
   O.hist_len = outer_hist_len(o);
   O.hist = cv.take<double>((size_t)O.hist_len * nrhs);
   O.vstride = (int64_t)n3;
-  O.pad_ = 0;
+  O.max_outer = o.max_outer;
   return cv.used;
 }
 
@@ -169,7 +171,7 @@ struct mm_solver_s {
     const int arith = mixed ? MM_F32 : MM_F64;
     for (const auto& t : nz->tuned)
       if (t.n_samples == pt->n_samples && t.n_kept == pt->n_kept && t.dtype == pt->dtype && t.arith == arith &&
-          t.nrhs == nrhs) {
+          t.nrhs == nrhs && t.ncomp == pt->ncomp) {
         variant = t.variant;
         return MM_OK;
       }
@@ -208,7 +210,7 @@ struct mm_solver_s {
     if (rc) return rc;
     if ((rc = launch_fill(L.A.q, n3 * nrhs, 0.0, s))) return rc;
     variant = best_v;
-    nz->tuned.push_back(mm_noise_s::Tuned{pt->n_samples, pt->n_kept, pt->dtype, arith, nrhs, best_v, 0});
+    nz->tuned.push_back(mm_noise_s::Tuned{pt->n_samples, pt->n_kept, pt->dtype, arith, nrhs, best_v, pt->ncomp});
     return MM_OK;
   }
 
@@ -308,7 +310,7 @@ int mm_solver_workspace_size(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, con
   if (opts) o = *opts;
   Carver cv(nullptr, 0);
   Layout L;
-  *bytes = carve(cv, pt->n_kept, n_rhs, o, &L);
+  *bytes = carve(cv, pt->n_kept, pt->ncomp, n_rhs, o, &L);
   return MM_OK;
 }
 
@@ -337,13 +339,13 @@ int mm_solver_create(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const void*
   sv->o = o;
   sv->s = reinterpret_cast<hipStream_t>(stream);
   sv->nrhs = n_rhs;
-  sv->n3 = 3 * (int64_t)pt->n_kept;
+  sv->n3 = (int64_t)pt->ncomp * pt->n_kept;
   sv->mixed = o.mixed != 0;
   sv->timing = o.timing != 0;
   sv->st.assign(n_rhs, PcgState{});
   sv->os.assign(n_rhs, OuterState{});
   Carver cv(workspace, ws_bytes);
-  carve(cv, pt->n_kept, n_rhs, o, &sv->L);
+  carve(cv, pt->n_kept, pt->ncomp, n_rhs, o, &sv->L);
   auto bail = [&](int rc) {
     delete sv;
     return rc;
@@ -377,7 +379,7 @@ int mm_solver_create(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const void*
       return bail(rc);
   }
   sv->variant = o.op_variant;
-  if (o.autotune && nz->kind == 1)
+  if (o.autotune && nz->kind != 0)
     if (int rc = sv->tune()) return bail(rc);
   *out = sv;
   return MM_OK;
@@ -422,7 +424,8 @@ int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_i
   }
   for (int r = 0; r < sv->nrhs; ++r) {
     if (maps_out)
-      if (int rc = launch_expand(pt, xf + r * sv->n3, maps_out + r * 3 * (int64_t)pt->n_pix, s)) return rc;
+      if (int rc = launch_expand(pt, xf + r * sv->n3, maps_out + r * (int64_t)pt->ncomp * pt->n_pix, s))
+        return rc;
   }
   if (x_out) MM_HIP(hipMemcpyAsync(x_out, xf, sizeof(double) * sv->n3 * sv->nrhs, hipMemcpyDeviceToDevice, s));
   MM_HIP(hipStreamSynchronize(s));
@@ -466,8 +469,8 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
     for (int32_t j = 0; j < i; ++j)
       if (solvers[j] == sv) return fail(MM_EINVAL, "solver listed twice in batch");
     if (sv->s != s0->s) return fail(MM_EINVAL, "batch members must share one stream");
-    if (sv->mixed != s0->mixed || sv->pt->dtype != s0->pt->dtype)
-      return fail(MM_EINVAL, "batch members must share the timeline dtype and precision mode");
+    if (sv->mixed != s0->mixed || sv->pt->dtype != s0->pt->dtype || sv->pt->ncomp != s0->pt->ncomp)
+      return fail(MM_EINVAL, "batch members must share the timeline dtype, precision mode and map form");
     if (sv->pt->device != s0->pt->device) return fail(MM_EINVAL, "batch members must share one device");
     slots += sv->nrhs;
   }
@@ -475,12 +478,13 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
   hipStream_t s = s0->s;
   const bool mixed = s0->mixed;
   const int dtype = s0->pt->dtype;
+  const int ncomp = s0->pt->ncomp;
   const int arith = mixed ? MM_F32 : MM_F64;
   // stored weights only where every band-Toeplitz slot has usable ones
   auto weights_ok = [&](int ar) {
     for (int32_t i = 0; i < n; ++i) {
       const mm_pointing_s* pt = solvers[i]->pt;
-      if (solvers[i]->nz->kind == 1 && !(pt->weights != nullptr && (ar == MM_F32 || pt->dtype == MM_F64)))
+      if (solvers[i]->nz->kind != 0 && !(pt->weights != nullptr && (ar == MM_F32 || pt->dtype == MM_F64)))
         return false;
     }
     return true;
@@ -503,7 +507,7 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
     o.done = done;
     o.variant = sv->variant;
     int64_t items;
-    if (nz->kind == 1) {
+    if (nz->kind != 0) {
       o.tiles = nz->tiles[plan];
       o.ab = nz->ab[plan];
       o.tw = nz->tw[plan];
@@ -539,25 +543,25 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
       p.minv = sv->pt->minv;
       p.tol = sv->o.tol;
       p.inner_tol = sv->o.inner_tol;
-      p.max_iter = sv->o.max_iter;
-      p.max_outer = sv->o.max_outer;
+      p.A.max_iter = sv->o.max_iter;
+      p.O.max_outer = sv->o.max_outer;
       const int plan_in = arith == MM_F64 ? 0 : 1;
-      add_op(sv->nz->kind == 1 ? t_in : w_in_b, sv, plan_in, p.A.p, p.A.q, &p.A.st->done);
-      add_op(sv->nz->kind == 1 ? t_out : w_out_b, sv, 0, p.O.xt, p.A.q, &p.O.os->skip);
+      add_op(sv->nz->kind != 0 ? t_in : w_in_b, sv, plan_in, p.A.p, p.A.q, &p.A.st->done);
+      add_op(sv->nz->kind != 0 ? t_out : w_out_b, sv, 0, p.O.xt, p.A.q, &p.O.os->skip);
     }
   }
   if (mixed && pending) {
     // one outer step for every slot whose inner solve has ended (the
     // device-side flags decide; the others are marked skip and stay put)
     if (int rc = launch_outer_add_batch(pb, s)) return rc;
-    if (int rc = launch_toeplitz_batch(t_out, dtype, MM_F64, w_out, s)) return rc;
-    if (int rc = launch_white_batch(w_out_b, dtype, MM_F64, s)) return rc;
+    if (int rc = launch_toeplitz_batch(t_out, dtype, MM_F64, w_out, ncomp, s)) return rc;
+    if (int rc = launch_white_batch(w_out_b, dtype, MM_F64, ncomp, s)) return rc;
     if (int rc = launch_outer_end_batch(pb, s)) return rc;
     for (int32_t i = 0; i < n; ++i) solvers[i]->outer_pending = false;
   }
   for (int32_t i = 0; i < k; ++i) {
-    if (int rc = launch_toeplitz_batch(t_in, dtype, arith, w_in, s)) return rc;
-    if (int rc = launch_white_batch(w_in_b, dtype, arith, s)) return rc;
+    if (int rc = launch_toeplitz_batch(t_in, dtype, arith, w_in, ncomp, s)) return rc;
+    if (int rc = launch_white_batch(w_in_b, dtype, arith, ncomp, s)) return rc;
     if (int rc = launch_pcg_iteration_tail_batch(pb, s)) return rc;
   }
   for (int32_t i = 0; i < n; ++i) {
@@ -578,7 +582,7 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (pt->n_kept == 0) {
     if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
-    if (map_out) MM_HIP(hipMemsetAsync(map_out, 0, sizeof(double) * 3 * (size_t)pt->n_pix, s));
+    if (map_out) MM_HIP(hipMemsetAsync(map_out, 0, sizeof(double) * pt->ncomp * (size_t)pt->n_pix, s));
     MM_HIP(hipStreamSynchronize(s));
     if (info) {
       *info = mm_solve_info{};

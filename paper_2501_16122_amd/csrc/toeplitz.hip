@@ -25,6 +25,7 @@
 #include "fft_lds.h"
 #include "mm_internal.h"
 #include "sincos2.h"
+#include "stokes.h"
 
 namespace mm {
 namespace {
@@ -50,11 +51,15 @@ struct Plan<float> {
   static constexpr int kScatterBatch = 4;
 };
 
-template <class C>
+// LDS reuse outside the FFT: P^T bins (NC doubles per pixel) and the staged
+// map window (NC values per pixel, padded to 4 doubles for IQU so that the
+// (I, Q) pair stays 16-byte aligned).
+template <class C, int NC>
 struct Lds {
   static constexpr int kBytes = lds_elems<Plan<C>::N>() * (int)sizeof(cpx<C>);
-  static constexpr int kBinSlots = (kBytes / 24) & ~63;  // P^T bins reuse the FFT buffer
-  static constexpr int kXPixels = kBytes / 32;           // staged map pixels (4-double stride)
+  static constexpr int kBinSlots = (kBytes / (8 * NC)) & ~63;
+  static constexpr int kXStride = NC == 3 ? 4 : NC;
+  static constexpr int kXPixels = kBytes / (8 * kXStride);
 };
 
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
@@ -259,7 +264,7 @@ __device__ __forceinline__ bool src_pos(int pos, int ilo, int ihi, bool wrap, in
 // the gather (wk) instead of being read again.
 constexpr int kKeepW0 = 5, kKeepW1 = 11;
 
-template <class S, class C, int kW, bool kKeepK, bool kKeepW = false>
+template <class S, class C, int kW, int NC, bool kKeepK, bool kKeepW = false>
 __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, const int32_t* kk,
                                              const int32_t* __restrict__ sk, const S* __restrict__ ps0,
                                              const cpx<S>* __restrict__ w0, int32_t vlo, int32_t vhi, int32_t kmin,
@@ -269,7 +274,8 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
   using F = Fft<C>;
   using A = Angle<C, S, kW>;
   constexpr int N = P::N, T = P::T, E = N / T, GS = P::kScatterBatch;
-  constexpr int kTBinSlots = Lds<C>::kBinSlots;
+  constexpr int kTBinSlots = Lds<C, NC>::kBinSlots;
+  constexpr bool kAng = Stokes<NC>::kAngle;
   const int tid = threadIdx.x;
   for (int32_t wlo = kmin; wlo <= kmax; wlo += kTBinSlots) {
     const int nb = kmax - wlo + 1 < kTBinSlots ? kmax - wlo + 1 : kTBinSlots;
@@ -279,11 +285,9 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
     const int32_t* skp = sk;
     int tidp = tid;
     asm volatile("" : "+s"(skp), "+v"(tidp));
-    for (int i = tid; i < nb; i += T) {
-      bins[i] = 0.0;
-      bins[kTBinSlots + i] = 0.0;
-      bins[2 * kTBinSlots + i] = 0.0;
-    }
+    for (int i = tid; i < nb; i += T)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) bins[c * kTBinSlots + i] = 0.0;
     __syncthreads();
 #pragma unroll
     for (int e0 = 0; e0 < E; e0 += GS) {
@@ -300,7 +304,9 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
         const int32_t rel = k - wlo;
         ks[i] = (k >= 0 && rel < nb && rel >= 0) ? rel : -1;
         const int e = e0 + i / 2;
-        if (kKeepW && e >= kKeepW0 && e < kKeepW1)
+        if (!kAng)
+          ps[i] = A::zero();
+        else if (kKeepW && e >= kKeepW0 && e < kKeepW1)
           ps[i] = ks[i] >= 0 ? wk[2 * (e - kKeepW0) + (i & 1)] : A::zero();
         else
           ps[i] = ks[i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
@@ -309,22 +315,24 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
       for (int i = 0; i < 2 * GS; ++i) {
         const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
         const C z = (i & 1) ? o.y : o.x;
-        C c, s;
-        A::eval(ps[i], &c, &s);
+        C c = C(0), s = C(0);
+        if constexpr (kAng) A::eval(ps[i], &c, &s);
         if (ks[i] >= 0) {
-          atomicAdd(&bins[ks[i]], double(z));
-          atomicAdd(&bins[kTBinSlots + ks[i]], double(z * c));
-          atomicAdd(&bins[2 * kTBinSlots + ks[i]], double(z * s));
+          double t[NC];
+          Stokes<NC>::terms(z, c, s, t);
+#pragma unroll
+          for (int j = 0; j < NC; ++j) atomicAdd(&bins[j * kTBinSlots + ks[i]], t[j]);
         }
       }
     }
     __syncthreads();
     for (int i = tid; i < nb; i += T) {
-      const double v0 = bins[i], v1 = bins[kTBinSlots + i], v2 = bins[2 * kTBinSlots + i];
-      double* qk = q + 3 * (int64_t)(wlo + i);
-      if (v0 != 0.0) atomicAdd(qk + 0, v0);
-      if (v1 != 0.0) atomicAdd(qk + 1, v1);
-      if (v2 != 0.0) atomicAdd(qk + 2, v2);
+      double* qk = q + NC * (int64_t)(wlo + i);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const double b = bins[j * kTBinSlots + i];
+        if (b != 0.0) atomicAdd(qk + j, b);
+      }
     }
     __syncthreads();  // the next pass (or tile) reuses the bins
   }
@@ -333,7 +341,8 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
 // kIn: 0 = timeline input tod_in; 1 = gather P x.
 // kOut: 0 = timeline output tod_out; 1 = scatter q += P^T z.
 // kW: 1 = stream the precomputed (cos 2psi, sin 2psi) pairs instead of psi.
-template <class S, class C, int kIn, int kOut, int kW>
+// NC: values per pixel of the map form (the intensity form reads no angle).
+template <class S, class C, int kIn, int kOut, int kW, int NC>
 __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda, const cpx<C>* __restrict__ abf,
                                               const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k,
                                               const S* __restrict__ psi, const cpx<S>* __restrict__ wts,
@@ -342,8 +351,9 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
   using P = Plan<C>;
   using F = Fft<C>;
   using A = Angle<C, S, kW>;
-  constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch, GS = P::kScatterBatch;
-  constexpr int kTBinSlots = Lds<C>::kBinSlots, kXPixels = Lds<C>::kXPixels;
+  constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch;
+  constexpr int kXPixels = Lds<C, NC>::kXPixels, kXStride = Lds<C, NC>::kXStride;
+  constexpr bool kAng = Stokes<NC>::kAngle;
   static_assert(E % G == 0, "gather batches must tile the elements");
   __shared__ cpx<C> buf[lds_elems<N>()];
   __shared__ int32_t s_red[4 * (P::T / 64)];
@@ -358,8 +368,8 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
   const int32_t clen = (int32_t)(tl.chunk_end - tl.chunk_start);
   // tile-based views indexed by window position (only the chunk is read)
   const int32_t* __restrict__ sk = sample_k != nullptr ? sample_k + in0 : nullptr;
-  const S* __restrict__ ps0 = (kW == 0 && psi != nullptr) ? psi + in0 : nullptr;
-  const cpx<S>* __restrict__ w0 = (kW == 1 && wts != nullptr) ? wts + in0 : nullptr;
+  const S* __restrict__ ps0 = (kAng && kW == 0 && psi != nullptr) ? psi + in0 : nullptr;
+  const cpx<S>* __restrict__ w0 = (kAng && kW == 1 && wts != nullptr) ? wts + in0 : nullptr;
   const S* __restrict__ tin = tod_in != nullptr ? tod_in + in0 : nullptr;
   S* __restrict__ tout = tod_out != nullptr ? tod_out + in0 : nullptr;
   const int tid = threadIdx.x;
@@ -420,12 +430,12 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
     const int xspan = amax - amin + 1;
     const bool staged = amax >= amin && xspan <= kXPixels && (variant & kOpNoStaging) == 0;
     if (staged) {
-      // pixel p of the window at xs[4p .. 4p+2]: 32-byte stride keeps the
-      // (I, Q) pair 16-byte aligned for one LDS read
-      const double* xw = x + 3 * (int64_t)amin;
-      for (int i = tid; i < 3 * xspan; i += T) {
-        const int p = i / 3;
-        xs[4 * p + (i - 3 * p)] = xw[i];
+      // pixel p of the window at xs[kXStride p ..]: for IQU the 32-byte
+      // stride keeps the (I, Q) pair 16-byte aligned for one LDS read
+      const double* xw = x + NC * (int64_t)amin;
+      for (int i = tid; i < NC * xspan; i += T) {
+        const int p = i / NC;
+        xs[kXStride * p + (i - NC * p)] = xw[i];
       }
     }
     __syncthreads();
@@ -439,7 +449,7 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
         const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
         int sp;
         src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
-        ps[i] = kk[2 * e0 + i] >= 0 ? A::load(ps0, w0, sp) : A::zero();
+        ps[i] = (kAng && kk[2 * e0 + i] >= 0) ? A::load(ps0, w0, sp) : A::zero();
         if constexpr (kKeepW) {
           const int e = e0 + i / 2;
           if (e >= kKeepW0 && e < kKeepW1) wk[2 * (e - kKeepW0) + (i & 1)] = ps[i];
@@ -450,10 +460,10 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
         const int32_t k = kk[2 * e0 + i];
         C val = C(0);
         if (k >= 0) {
-          C c, s;
-          A::eval(ps[i], &c, &s);
-          const double* xk = staged ? xs + 4 * (k - amin) : x + 3 * (int64_t)k;
-          val = C(xk[0]) + c * C(xk[1]) + s * C(xk[2]);
+          C c = C(0), s = C(0);
+          if constexpr (kAng) A::eval(ps[i], &c, &s);
+          const double* xk = staged ? xs + kXStride * (k - amin) : x + NC * (int64_t)k;
+          val = Stokes<NC>::project(xk, c, s);
         }
         cpx<C>& slot = v[slot_of<N, T, F::RIn>(e0 + i / 2)];
         if (i & 1) slot.y = val;
@@ -524,8 +534,8 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
     kmax = s_red[T / 64 + w] > kmax ? s_red[T / 64 + w] : kmax;
   }
   if (kmax < kmin) return;
-  scatter_bins<S, C, kW, kKeepK, kKeepW>(v, reinterpret_cast<double*>(buf), kk, sk, ps0, w0, vlo, vhi, kmin, kmax, q,
-                                         wk);
+  scatter_bins<S, C, kW, NC, kKeepK, kKeepW>(v, reinterpret_cast<double*>(buf), kk, sk, ps0, w0, vlo, vhi, kmin,
+                                             kmax, q, wk);
 }
 
 // One halo-carrying tile (gather P x, scatter P^T; tiles kStride = (E -
@@ -536,7 +546,7 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
 // window's last kCarryElems elements, and (cmin, cmax) the compact-index
 // range of their samples that are valid outputs of the next tile.  The map
 // is read through L2 (no staging); indices are reloaded for the scatter.
-template <class S, class C, int kW>
+template <class S, class C, int kW, int NC>
 __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t lambda,
                                                     const cpx<C>* __restrict__ abf, const cpx<C>* __restrict__ tw,
                                                     const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
@@ -549,6 +559,7 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
   constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch;
   constexpr int M = E - kCarryElems;  // element shift between consecutive tiles
   constexpr int kStride = M * 2 * T;
+  constexpr bool kAng = Stokes<NC>::kAngle;
   static_assert(E == F::RIn && E == F::ROut, "element e must sit in register slot e");
   static_assert(kCarryElems % G == 0 && M >= kCarryElems, "carried elements must fill whole gather batches");
   __shared__ cpx<C> buf[lds_elems<N>()];
@@ -562,8 +573,8 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
   const bool wrap = tl.wrap != 0;
   const int32_t clen = (int32_t)(tl.chunk_end - tl.chunk_start);
   const int32_t* __restrict__ sk = sample_k + in0;
-  const S* __restrict__ ps0 = kW == 0 ? psi + in0 : nullptr;
-  const cpx<S>* __restrict__ w0 = kW == 1 ? wts + in0 : nullptr;
+  const S* __restrict__ ps0 = (kAng && kW == 0) ? psi + in0 : nullptr;
+  const cpx<S>* __restrict__ w0 = (kAng && kW == 1) ? wts + in0 : nullptr;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));  // per-tile offsets: not hoisted out of the segment loop
 
@@ -617,17 +628,16 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
       const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
       int sp;
       src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
-      ps[i] = kk[2 * e0 + i] >= 0 ? A::load(ps0, w0, sp) : A::zero();
+      ps[i] = (kAng && kk[2 * e0 + i] >= 0) ? A::load(ps0, w0, sp) : A::zero();
     }
 #pragma unroll
     for (int i = 0; i < 2 * G; ++i) {
       const int32_t k = kk[2 * e0 + i];
       C val = C(0);
       if (k >= 0) {
-        C c, s;
-        A::eval(ps[i], &c, &s);
-        const double* xk = x + 3 * (int64_t)k;
-        val = C(xk[0]) + c * C(xk[1]) + s * C(xk[2]);
+        C c = C(0), s = C(0);
+        if constexpr (kAng) A::eval(ps[i], &c, &s);
+        val = Stokes<NC>::project(x + NC * (int64_t)k, c, s);
       }
       if (i & 1) v[e0 + i / 2].y = val;
       else v[e0 + i / 2].x = val;
@@ -657,12 +667,13 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
   F::template forward<N, T>(buf, v, tw);
   F::template inverse<N, T>(buf, abf, v, tw);
   __syncthreads();  // every thread is done reading buf
-  scatter_bins<S, C, kW, false>(v, reinterpret_cast<double*>(buf), nullptr, sk, ps0, w0, vlo, vhi, kmin, kmax, q);
+  scatter_bins<S, C, kW, NC, false>(v, reinterpret_cast<double*>(buf), nullptr, sk, ps0, w0, vlo, vhi, kmin, kmax,
+                                    q);
 }
 
 // Segments of halo-carrying tiles, one segment (of one right-hand side) per
 // workgroup, mapped to workgroups like k_toeplitz maps tiles.
-template <class S, class C, int kW>
+template <class S, class C, int kW, int NC>
 __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_carry(
     const FftTile* __restrict__ tiles, const CarrySeg* __restrict__ segs, int64_t n_segs, int32_t lambda,
     const cpx<C>* __restrict__ ab, const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k,
@@ -688,8 +699,8 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_ca
   int32_t cmin = INT32_MAX, cmax = -1;
   for (int t = 0; t < sg.count; ++t) {
     const FftTile tl = tiles[sg.first + t];
-    toeplitz_tile_carry<S, C, kW>(tl, lambda, ab + (int64_t)tl.filter * Plan<C>::N, tw, sample_k, psi, wts, x, q,
-                                  carry, t > 0, cmin, cmax);
+    toeplitz_tile_carry<S, C, kW, NC>(tl, lambda, ab + (int64_t)tl.filter * Plan<C>::N, tw, sample_k, psi, wts, x,
+                                      q, carry, t > 0, cmin, cmax);
     __syncthreads();  // the next tile reuses the LDS
   }
 }
@@ -699,7 +710,7 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_ca
 // of tiles; neighbouring tiles (which share their overlap-save halos) then
 // run close together on one L2, and the right-hand sides of one tile are
 // adjacent, so its pointing is read from HBM once.
-template <class S, class C, int kIn, int kOut, int kW>
+template <class S, class C, int kIn, int kOut, int kW, int NC>
 __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(
     const FftTile* __restrict__ tiles, int64_t n_tiles, int32_t lambda, const cpx<C>* __restrict__ ab,
     const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
@@ -721,8 +732,8 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(
   if (x != nullptr) x += rhs * rb.vstride;
   q += rhs * rb.vstride;
   const FftTile tl = tiles[tile];
-  toeplitz_tile<S, C, kIn, kOut, kW>(tl, lambda, ab + (int64_t)tl.filter * Plan<C>::N, tw, sample_k, psi, wts, x,
-                                     tod_in, tod_out, q, variant);
+  toeplitz_tile<S, C, kIn, kOut, kW, NC>(tl, lambda, ab + (int64_t)tl.filter * Plan<C>::N, tw, sample_k, psi, wts, x,
+                                         tod_in, tod_out, q, variant);
 }
 
 // One launch over the tiles of several slots (right-hand sides of different
@@ -731,7 +742,7 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(
 // equal share of every solve (tiles of different solves differ in cost) and
 // still walks neighbouring tiles of one solve together.  A slot whose done
 // flag is set is skipped.
-template <class S, class C, int kW>
+template <class S, class C, int kW, int NC>
 __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_batch(OpBatch b) {
   const int x = blockIdx.x % 8;
   int64_t j = blockIdx.x / 8;  // position in XCD x's list
@@ -755,22 +766,24 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_ba
   const OpSlot& o = b.s[sl];
   if (o.done != nullptr && *o.done != 0) return;
   const FftTile tl = static_cast<const FftTile*>(o.tiles)[idx];
-  toeplitz_tile<S, C, 1, 1, kW>(tl, o.lambda, static_cast<const cpx<C>*>(o.ab) + (int64_t)tl.filter * Plan<C>::N,
-                                static_cast<const cpx<C>*>(o.tw), o.sample_k, static_cast<const S*>(o.psi),
-                                static_cast<const cpx<S>*>(o.wts), o.x, nullptr, nullptr, o.q, o.variant);
+  toeplitz_tile<S, C, 1, 1, kW, NC>(tl, o.lambda,
+                                    static_cast<const cpx<C>*>(o.ab) + (int64_t)tl.filter * Plan<C>::N,
+                                    static_cast<const cpx<C>*>(o.tw), o.sample_k, static_cast<const S*>(o.psi),
+                                    static_cast<const cpx<S>*>(o.wts), o.x, nullptr, nullptr, o.q, o.variant);
 }
 
-template <class S, class C, int kIn, int kOut, int kW>
+template <class S, class C, int kIn, int kOut, int kW, int NC>
 int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod_in, void* tod_out,
              double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
-  // the halo-carrying form streams stored weights (with psi it spills)
-  if constexpr (kIn == 1 && kOut == 1 && kW == 1) {
+  // the halo-carrying form streams stored weights (with psi it spills), or
+  // no angle at all (intensity only)
+  if constexpr (kIn == 1 && kOut == 1 && (kW == 1 || NC == 1)) {
     if (variant & kOpCarry) {
       if (nz->n_csegs[a] == 0) return MM_OK;
       const int64_t g = 8 * ((nz->n_csegs[a] + 7) / 8) * rb.nrhs;
-      hipLaunchKernelGGL((k_toeplitz_carry<S, C, kW>), dim3(g), dim3(Plan<C>::T), 0, s, nz->ctiles[a],
+      hipLaunchKernelGGL((k_toeplitz_carry<S, C, kW, NC>), dim3(g), dim3(Plan<C>::T), 0, s, nz->ctiles[a],
                          nz->csegs[a], nz->n_csegs[a], nz->lambda, (const cpx<C>*)nz->ab[a],
                          (const cpx<C>*)nz->tw[a], pt->sample_k, (const S*)pt->psi,
                          (const cpx<S>*)pt->weights, x, q, rb, variant);
@@ -779,7 +792,7 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
     }
   }
   const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8) * rb.nrhs;
-  hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
+  hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW, NC>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
                      nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
                      pt ? pt->sample_k : nullptr, pt ? (const S*)pt->psi : nullptr,
                      pt ? (const cpx<S>*)pt->weights : nullptr, x, (const S*)tod_in, (S*)tod_out, q, rb, variant);
@@ -787,55 +800,77 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
   return MM_OK;
 }
 
-// Stored weights serve an arithmetic no finer than their storage.
+// Stored weights serve an arithmetic no finer than their storage; the
+// intensity-only form needs none.
 inline bool use_weights(const mm_pointing_s* pt, int arith) {
-  return pt != nullptr && pt->weights != nullptr && (arith == MM_F32 || pt->dtype == MM_F64);
+  return pt != nullptr && pt->ncomp != 1 && pt->weights != nullptr && (arith == MM_F32 || pt->dtype == MM_F64);
 }
 
+template <int kIn, int kOut, int NC>
+int dispatch_nc(const mm_pointing_s* pt, const mm_noise_s* nz, int dtype, int arith, const double* x,
+                const void* tod_in, void* tod_out, double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
+  const bool w = kOut == 1 && use_weights(pt, arith);
+  constexpr int kW1 = NC == 1 ? 0 : 1;  // no weights without an angle
+  if (dtype == MM_F64) {
+    if (arith == MM_F64)
+      return w ? launch_t<double, double, kIn, kOut, kW1, NC>(pt, nz, x, tod_in, tod_out, q, rb, s, variant)
+               : launch_t<double, double, kIn, kOut, 0, NC>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
+    return w ? launch_t<double, float, kIn, kOut, kW1, NC>(pt, nz, x, tod_in, tod_out, q, rb, s, variant)
+             : launch_t<double, float, kIn, kOut, 0, NC>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
+  }
+  if (arith == MM_F64)
+    return launch_t<float, double, kIn, kOut, 0, NC>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
+  return w ? launch_t<float, float, kIn, kOut, kW1, NC>(pt, nz, x, tod_in, tod_out, q, rb, s, variant)
+           : launch_t<float, float, kIn, kOut, 0, NC>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
+}
+
+// The map form matters only where the pointing is applied (kIn or kOut).
 template <int kIn, int kOut>
 int dispatch(const mm_pointing_s* pt, const mm_noise_s* nz, int dtype, int arith, const double* x,
              const void* tod_in, void* tod_out, double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
-  const bool w = kOut == 1 && use_weights(pt, arith);
-  if (dtype == MM_F64) {
-    if (arith == MM_F64)
-      return w ? launch_t<double, double, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s, variant)
-               : launch_t<double, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
-    return w ? launch_t<double, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s, variant)
-             : launch_t<double, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
+  if constexpr (kIn == 0 && kOut == 0) {
+    return dispatch_nc<0, 0, 3>(pt, nz, dtype, arith, x, tod_in, tod_out, q, rb, s, variant);
+  } else {
+    return by_ncomp(pt->ncomp, [&]<int NC>() -> int {
+      return dispatch_nc<kIn, kOut, NC>(pt, nz, dtype, arith, x, tod_in, tod_out, q, rb, s, variant);
+    });
   }
-  if (arith == MM_F64) return launch_t<float, double, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
-  return w ? launch_t<float, float, kIn, kOut, 1>(pt, nz, x, tod_in, tod_out, q, rb, s, variant)
-           : launch_t<float, float, kIn, kOut, 0>(pt, nz, x, tod_in, tod_out, q, rb, s, variant);
+}
+
+template <int NC>
+int launch_batch_nc(const OpBatch& b, dim3 grid, int dtype, int arith, bool weights, hipStream_t s) {
+  const int T = arith == MM_F64 ? Plan<double>::T : Plan<float>::T;
+  constexpr int kW1 = NC == 1 ? 0 : 1;  // no weights without an angle
+  if (dtype == MM_F64) {
+    if (arith == MM_F64) {
+      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<double, double, kW1, NC>), grid, dim3(T), 0, s, b);
+      else hipLaunchKernelGGL((k_toeplitz_batch<double, double, 0, NC>), grid, dim3(T), 0, s, b);
+    } else {
+      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<double, float, kW1, NC>), grid, dim3(T), 0, s, b);
+      else hipLaunchKernelGGL((k_toeplitz_batch<double, float, 0, NC>), grid, dim3(T), 0, s, b);
+    }
+  } else {
+    if (arith == MM_F64) {
+      hipLaunchKernelGGL((k_toeplitz_batch<float, double, 0, NC>), grid, dim3(T), 0, s, b);
+    } else {
+      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<float, float, kW1, NC>), grid, dim3(T), 0, s, b);
+      else hipLaunchKernelGGL((k_toeplitz_batch<float, float, 0, NC>), grid, dim3(T), 0, s, b);
+    }
+  }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
 }
 
 }  // namespace
 
-int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, hipStream_t s) {
+int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, int ncomp, hipStream_t s) {
   if (b.n == 0) return MM_OK;
   // XCD x's list holds up to ceil(n_s / 8) tiles of every slot s
   int64_t per_xcd = 0;
   for (int k = 0; k < b.n; ++k) per_xcd += (b.off[k + 1] - b.off[k] + 7) / 8;
   if (per_xcd == 0) return MM_OK;
   const dim3 grid((unsigned)(8 * per_xcd));
-  const int T = arith == MM_F64 ? Plan<double>::T : Plan<float>::T;
-  if (dtype == MM_F64) {
-    if (arith == MM_F64) {
-      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<double, double, 1>), grid, dim3(T), 0, s, b);
-      else hipLaunchKernelGGL((k_toeplitz_batch<double, double, 0>), grid, dim3(T), 0, s, b);
-    } else {
-      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<double, float, 1>), grid, dim3(T), 0, s, b);
-      else hipLaunchKernelGGL((k_toeplitz_batch<double, float, 0>), grid, dim3(T), 0, s, b);
-    }
-  } else {
-    if (arith == MM_F64) {
-      hipLaunchKernelGGL((k_toeplitz_batch<float, double, 0>), grid, dim3(T), 0, s, b);
-    } else {
-      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<float, float, 1>), grid, dim3(T), 0, s, b);
-      else hipLaunchKernelGGL((k_toeplitz_batch<float, float, 0>), grid, dim3(T), 0, s, b);
-    }
-  }
-  MM_HIP(hipGetLastError());
-  return MM_OK;
+  return by_ncomp(ncomp, [&]<int NC>() -> int { return launch_batch_nc<NC>(b, grid, dtype, arith, weights, s); });
 }
 
 int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,

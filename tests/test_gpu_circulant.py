@@ -103,3 +103,24 @@ def test_circulant_rejects_short_chunks():
     coeff = synth.toeplitz_coeff(W.replace(lam=64))
     with pytest.raises(b.MapMakerError):
         b.Noise.circulant(coeff, np.array([0, 100, 226]), DEV)  # 126 <= 2 * 63
+
+
+def test_circulant_in_batched_steps(prob):
+    # a circulant member shares the band-Toeplitz batch launches (its tiles
+    # carry the wrap flag) and matches the same solve alone
+    b = _b()
+    opt, noise, d, pt, nz = prob
+    td = torch.from_numpy(d).to(DEV)
+    opts = dict(tol=1e-11, check_every=4)
+    alone = b.Solver(pt, nz, **opts).solve(td)["x"].cpu().numpy()
+    s1 = b.AsyncSolver(pt, nz, td, **opts)
+    s2 = b.AsyncSolver(pt, b.Noise.white(synth.det_weight(W), DEV), td, **opts)
+    for _ in range(200):
+        b.batch_step([s1, s2], 4)
+        torch.cuda.synchronize()
+        if s1.poll()[0] and s2.poll()[0]:
+            break
+    r1 = s1.finish()
+    assert r1["info"][0]["converged"] == 1
+    assert np.all(oracle.rel_l2_per_stokes(r1["x"][0].cpu().numpy(), alone) < 1e-10)
+    assert s2.finish()["info"][0]["converged"] == 1
