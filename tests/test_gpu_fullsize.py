@@ -84,3 +84,53 @@ def test_full_size_operator_sampled_pixels(full, variant):
     q32 = b.apply_A(pt, nz, torch.from_numpy(x).to(DEV), arith="f32", variant=variant).cpu().numpy().reshape(-1, 3)
     err32 = np.abs(q32[sel] - ref).max() / np.abs(ref).max()
     assert err32 < 1e-5, err32
+
+
+@pytest.fixture(scope="module", params=["QU", "I"])
+def full_form(request):
+    b = _b()
+    w = synth.C2_GLS
+    pix, psi = synth.pointing(w)
+    offs, wdet = synth.det_offsets(w), synth.det_weight(w)
+    form = request.param
+    opt = oracle.build_pointing(pix, psi, offs, wdet, w.n_pix, stokes=form)
+    t_psi = None if form == "I" else torch.from_numpy(psi).to(DEV)
+    pt = b.Pointing(torch.from_numpy(pix).to(DEV), t_psi, offs, wdet, w.n_pix, stokes=form,
+                    tod_dtype=torch.float64)
+    pt.attach_weights()
+    coeff, chunks = synth.toeplitz_coeff(w), synth.chunk_offsets(w)
+    nz = b.Noise.toeplitz(coeff, chunks, DEV)
+    yield w, opt, pt, nz, coeff, chunks
+    pt.close()
+    nz.close()
+
+
+def test_full_size_forms_build_and_sampled_pixels(full_form):
+    # the polarisation-only and intensity-only forms at the full size: build
+    # bit-exact, and A on sampled pixels in the variant the bench picks (5)
+    # and the plain one (0)
+    b = _b()
+    w, opt, pt, nz, coeff, chunks = full_form
+    out = pt.export()
+    assert pt.n_kept == opt.n_kept
+    assert np.array_equal(out["mask"].cpu().numpy().astype(bool), opt.mask)
+    assert np.array_equal(out["kept"].cpu().numpy(), opt.kept.astype(np.int32))
+    assert oracle.mask_margin(opt) > 1e-9
+    nc = opt.ncomp
+    rng = np.random.default_rng(77 + nc)
+    x = rng.normal(size=nc * opt.n_kept)
+    row = (211 + 31 * nc) % w.height
+    cand = opt.compact[row * w.width:(row + 1) * w.width]
+    sel = rng.choice(cand[cand >= 0], size=5, replace=False)
+    hit = np.isin(opt.sample_k, sel)
+    cidx = np.unique(np.searchsorted(chunks, np.flatnonzero(hit), side="right") - 1)
+    idx = np.concatenate([np.arange(chunks[c], chunks[c + 1]) for c in cidx])
+    lens = np.array([chunks[c + 1] - chunks[c] for c in cidx])
+    sub = dataclasses.replace(opt, pix=opt.pix[idx], cos2=opt.cos2[idx], sin2=opt.sin2[idx],
+                              weight=opt.weight[idx], sample_k=opt.sample_k[idx])
+    ref = oracle.apply_A(sub, oracle.toeplitz_noise(coeff, np.concatenate([[0], np.cumsum(lens)])), x)
+    ref = ref.reshape(-1, nc)[sel]
+    for v in (0, 5):
+        q = b.apply_A(pt, nz, torch.from_numpy(x).to(DEV), variant=v).cpu().numpy().reshape(-1, nc)
+        err = np.abs(q[sel] - ref).max() / np.abs(ref).max()
+        assert err < 1e-12, (v, err)
