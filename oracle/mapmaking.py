@@ -284,9 +284,60 @@ def apply_ninv_circulant(noise: CirculantNoise, y: np.ndarray) -> np.ndarray:
     return z
 
 
+@dataclasses.dataclass
+class TemplateNoise:
+    """A general weight W of eq. (4) built from filtering templates (Sec.
+    IV): the white weights w (1/sigma_d^2 per detector) with polynomial
+    baselines marginalised on each interval,
+        W = N_w^-1 - N_w^-1 T (T^T N_w^-1 T)^-1 T^T N_w^-1,
+    where T holds, for every interval, the polynomials of degree < order in
+    the sample position (columns zero outside the interval).  Intervals do
+    not cross detector starts, so w is constant on each and W acts there as
+    w (I - T (T^T T)^-1 T^T); samples outside every interval get w alone."""
+
+    interval_offsets: np.ndarray  # int64[n_intervals + 1]
+    order: int                    # polynomial degrees 0 .. order-1 (0 = no templates)
+
+
+def template_noise(interval_offsets, order) -> TemplateNoise:
+    offs = np.asarray(interval_offsets, dtype=np.int64)
+    if np.any(np.diff(offs) < 0) or order < 0:
+        raise ValueError("bad template intervals or order")
+    return TemplateNoise(offs, int(order))
+
+
+def template_matrix(n: int, order: int) -> np.ndarray:
+    """T of one interval of n samples: Legendre polynomials of degree
+    < min(order, n) at n equispaced positions spanning [-1, 1] (any basis of
+    the same polynomials gives the same W)."""
+    k = min(order, n)
+    u = np.linspace(-1.0, 1.0, n) if n > 1 else np.zeros(1)
+    return np.polynomial.legendre.legvander(u, k - 1) if k > 0 else np.zeros((n, 0))
+
+
+def apply_w_templates(pt: Pointing, noise: TemplateNoise, y: np.ndarray) -> np.ndarray:
+    """z = W y with W of TemplateNoise: per interval w (y - T (T^T T)^-1 T^T y)."""
+    y = np.asarray(y, dtype=np.float64)
+    z = pt.weight * y
+    offs = noise.interval_offsets
+    for ii in range(offs.size - 1):
+        a, b = int(offs[ii]), int(offs[ii + 1])
+        if b <= a or noise.order == 0:
+            continue
+        if np.any(pt.weight[a:b] != pt.weight[a]):
+            raise ValueError("a template interval must lie within one detector")
+        T = template_matrix(b - a, noise.order)
+        ya = y[a:b]
+        coef = np.linalg.solve(T.T @ T, T.T @ ya)
+        z[a:b] = pt.weight[a:b] * (ya - T @ coef)
+    return z
+
+
 def apply_ninv(pt: Pointing, noise, y):
     if noise is None:
         return apply_ninv_white(pt, y)
+    if isinstance(noise, TemplateNoise):
+        return apply_w_templates(pt, noise, y)
     if isinstance(noise, CirculantNoise):
         return apply_ninv_circulant(noise, y)
     return apply_ninv_toeplitz(noise, y)
