@@ -179,6 +179,29 @@ int mm_noise_circulant(const double* coeff_host, int32_t lambda, int32_t n_filt,
                        const int64_t* chunk_offsets_host, const int32_t* chunk_filter_host,
                        int64_t n_chunks, void* workspace, size_t ws_bytes, void* stream,
                        mm_noise_t* out);
+/* Template-filtered white weights: a general W of eq. (4) built from the
+ * filtering templates of Sec. IV.  On interval i, samples
+ * [interval_offsets[i], interval_offsets[i+1]) of one detector d, the
+ * polynomial baselines of degree < K_i (K_i = interval_order_host[i], or
+ * `order` for every interval when that pointer is NULL; 0 <= K_i <= 8) are
+ * marginalised:
+ *     W y = w_d (y - T (T^T T)^-1 T^T y)   on the interval,
+ * T the polynomials of degree < min(K_i, length) in the sample position
+ * (any basis: W does not depend on it), w_d = det_weight_host[d].  So
+ * A = P^T W P and b = P^T W d give the map with every interval's baselines
+ * projected out; K_i = 0 is plain white weighting.  The intervals must
+ * partition the timeline: interval_offsets[0] = 0, non-decreasing, the last
+ * equal to the pointing's n_samples, none crossing a detector start (checked
+ * at apply time, MM_EINVAL).  A map component constant over whole intervals
+ * (the I monopole with K_i >= 1) is then unconstrained; PCG started from 0
+ * stays orthogonal to it.  The handle works with every operator and solve
+ * entry point except mm_batch_step; the operator variants do not apply.
+ * Workspace: mm_noise_templates_workspace_size; copies its tables there and
+ * synchronises `stream` once. */
+int mm_noise_templates_workspace_size(int32_t n_det, int64_t n_intervals, size_t* bytes);
+int mm_noise_templates(const double* det_weight_host, int32_t n_det, const int64_t* interval_offsets_host,
+                       const int32_t* interval_order_host, int32_t order, int64_t n_intervals,
+                       void* workspace, size_t ws_bytes, void* stream, mm_noise_t* out);
 int mm_noise_destroy(mm_noise_t nz);
 
 /* ------------------------------------------------------------------------

@@ -296,14 +296,16 @@ class TemplateNoise:
     w (I - T (T^T T)^-1 T^T); samples outside every interval get w alone."""
 
     interval_offsets: np.ndarray  # int64[n_intervals + 1]
-    order: int                    # polynomial degrees 0 .. order-1 (0 = no templates)
+    orders: np.ndarray            # int[n_intervals]: degrees 0 .. order-1 per interval (0 = none)
 
 
 def template_noise(interval_offsets, order) -> TemplateNoise:
+    """order: one value for every interval, or one per interval."""
     offs = np.asarray(interval_offsets, dtype=np.int64)
-    if np.any(np.diff(offs) < 0) or order < 0:
+    orders = np.broadcast_to(np.asarray(order, dtype=np.int64), (max(offs.size - 1, 0),)).copy()
+    if np.any(np.diff(offs) < 0) or np.any(orders < 0):
         raise ValueError("bad template intervals or order")
-    return TemplateNoise(offs, int(order))
+    return TemplateNoise(offs, orders)
 
 
 def template_matrix(n: int, order: int) -> np.ndarray:
@@ -322,11 +324,12 @@ def apply_w_templates(pt: Pointing, noise: TemplateNoise, y: np.ndarray) -> np.n
     offs = noise.interval_offsets
     for ii in range(offs.size - 1):
         a, b = int(offs[ii]), int(offs[ii + 1])
-        if b <= a or noise.order == 0:
+        order = int(noise.orders[ii])
+        if b <= a or order == 0:
             continue
         if np.any(pt.weight[a:b] != pt.weight[a]):
             raise ValueError("a template interval must lie within one detector")
-        T = template_matrix(b - a, noise.order)
+        T = template_matrix(b - a, order)
         ya = y[a:b]
         coef = np.linalg.solve(T.T @ T, T.T @ ya)
         z[a:b] = pt.weight[a:b] * (ya - T @ coef)

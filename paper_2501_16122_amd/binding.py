@@ -64,6 +64,8 @@ SIGNATURES = {
     "mm_noise_toeplitz_workspace_size": (_c.c_int, [_i32, _i32, _pi64, _i64, _psz]),
     "mm_noise_toeplitz": (_c.c_int, [_pf64, _i32, _i32, _pi64, _pi32, _i64, _vp, _sz, _vp, _c.POINTER(_vp)]),
     "mm_noise_circulant": (_c.c_int, [_pf64, _i32, _i32, _pi64, _pi32, _i64, _vp, _sz, _vp, _c.POINTER(_vp)]),
+    "mm_noise_templates_workspace_size": (_c.c_int, [_i32, _i64, _psz]),
+    "mm_noise_templates": (_c.c_int, [_pf64, _i32, _pi64, _pi32, _i32, _i64, _vp, _sz, _vp, _c.POINTER(_vp)]),
     "mm_noise_destroy": (_c.c_int, [_vp]),
     "mm_apply_P": (_c.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "mm_apply_PT": (_c.c_int, [_vp, _vp, _vp, _i32, _vp]),
@@ -262,7 +264,8 @@ class Pointing:
 
 
 class Noise:
-    """N^-1: white (per-detector weights) or band-Toeplitz per chunk."""
+    """N^-1 (or a general weight W): white, band-Toeplitz or circulant per chunk, or
+    white with polynomial templates marginalised per interval."""
 
     def __init__(self, handle, workspace, kind):
         self.handle, self.workspace, self.kind = handle, workspace, kind
@@ -305,6 +308,26 @@ class Noise:
     @classmethod
     def circulant(cls, coeff, chunk_offsets, device, chunk_filter=None, stream=None):
         return cls.toeplitz(coeff, chunk_offsets, device, chunk_filter, stream, circulant=True)
+
+    @classmethod
+    def templates(cls, det_weight, interval_offsets, order, device, orders=None, stream=None):
+        """White weights with polynomial baselines of degree < order (or
+        orders[i] per interval) marginalised on each interval; the intervals
+        partition the timeline."""
+        torch = _torch()
+        lib = load()
+        w = np.ascontiguousarray(det_weight, dtype=np.float64)
+        offs = np.ascontiguousarray(interval_offsets, dtype=np.int64)
+        n = offs.size - 1
+        o = None if orders is None else np.ascontiguousarray(orders, dtype=np.int32)
+        sz = _c.c_size_t()
+        _check(lib.mm_noise_templates_workspace_size(w.size, n, _c.byref(sz)))
+        ws = torch.empty(max(1, sz.value), dtype=torch.uint8, device=device)
+        h = _vp()
+        _check(lib.mm_noise_templates(w.ctypes.data_as(_pf64), w.size, offs.ctypes.data_as(_pi64),
+                                      None if o is None else o.ctypes.data_as(_pi32), int(order), n, _ptr(ws),
+                                      sz.value, _stream(stream), _c.byref(h)))
+        return cls(h, ws, "templates")
 
     def close(self):
         if getattr(self, "handle", None):

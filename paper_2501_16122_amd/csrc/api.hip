@@ -73,6 +73,7 @@ size_t carve_pointing(Carver& cv, int64_t n_samples, int32_t n_det, int32_t n_pi
 int apply_A_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, double* q, int arith,
                  const RhsBatch& rb, hipStream_t s, int32_t variant) {
   if (nz->kind == 0) return launch_fused_white(pt, nz->det_w, x, q, arith, rb, s);
+  if (nz->kind == 3) return launch_fused_templates(pt, nz, x, nullptr, q, arith, rb, s);
   return launch_fused_toeplitz(pt, nz, x, nullptr, q, arith, rb, s, variant);
 }
 
@@ -80,6 +81,7 @@ int rhs_impl(const mm_pointing_s* pt, const mm_noise_s* nz, const void* tod, dou
   int rc = launch_fill(b, (int64_t)pt->ncomp * pt->n_kept, 0.0, s);
   if (rc) return rc;
   if (nz->kind == 0) return launch_rhs_white(pt, nz->det_w, tod, b, arith, s);
+  if (nz->kind == 3) return launch_fused_templates(pt, nz, nullptr, tod, b, arith, RhsBatch{}, s);
   return launch_fused_toeplitz(pt, nz, nullptr, tod, b, arith, RhsBatch{}, s);
 }
 
@@ -93,6 +95,11 @@ int check_noise_vs_pointing(const mm_noise_s* nz, const mm_pointing_s* pt) {
   if (nz->kind == 0) {
     if (nz->n_det != pt->n_det) return fail(MM_EINVAL, "white noise has a different detector count");
     return MM_OK;
+  }
+  if (nz->kind == 3) {
+    if (nz->n_det != pt->n_det) return fail(MM_EINVAL, "template weights have a different detector count");
+    if (nz->chunk_offsets.back() != pt->n_samples)
+      return fail(MM_EINVAL, "template intervals must end at the last sample of the timeline");
   }
   if (nz->chunk_offsets.back() > pt->n_samples) return fail(MM_EINVAL, "noise chunks extend past the timeline");
   // no chunk may straddle a detector start
@@ -310,6 +317,59 @@ int mm_noise_white_workspace_size(int32_t n_det, size_t* bytes) {
   return MM_OK;
 }
 
+int mm_noise_templates_workspace_size(int32_t n_det, int64_t n_intervals, size_t* bytes) {
+  if (!bytes || n_det <= 0 || n_intervals < 0) return fail(MM_EINVAL, "bad template sizes");
+  Carver cv(nullptr, 0);
+  cv.take<double>(n_det);
+  cv.take<TplInterval>(n_intervals);
+  *bytes = cv.used;
+  return MM_OK;
+}
+
+int mm_noise_templates(const double* det_weight_host, int32_t n_det, const int64_t* interval_offsets_host,
+                       const int32_t* interval_order_host, int32_t order, int64_t n_intervals, void* workspace,
+                       size_t ws_bytes, void* stream, mm_noise_t* out) {
+  if (!out) return fail(MM_EINVAL, "null output handle pointer");
+  *out = nullptr;
+  if (!det_weight_host || n_det <= 0 || !workspace || !interval_offsets_host || n_intervals < 0)
+    return fail(MM_EINVAL, "bad template arguments");
+  for (int32_t d = 0; d < n_det; ++d)
+    if (!(det_weight_host[d] >= 0.0) || !std::isfinite(det_weight_host[d]))
+      return fail(MM_EINVAL, "detector weights must be finite and >= 0");
+  if (interval_offsets_host[0] != 0) return fail(MM_EINVAL, "template intervals must start at sample 0");
+  if (int rc = check_chunks(interval_offsets_host, n_intervals)) return rc;
+  std::vector<TplInterval> iv(n_intervals);
+  for (int64_t i = 0; i < n_intervals; ++i) {
+    const int32_t o = interval_order_host ? interval_order_host[i] : order;
+    if (o < 0 || o > kMaxTplOrder) return fail(MM_EINVAL, "template order must be in [0, 8]");
+    iv[i] = TplInterval{interval_offsets_host[i], interval_offsets_host[i + 1], o, 0};
+  }
+  size_t need = 0;
+  mm_noise_templates_workspace_size(n_det, n_intervals, &need);
+  if (ws_bytes < need) return fail(MM_ENOSPC, "noise workspace too small");
+  auto* nz = new (std::nothrow) mm_noise_s();
+  if (!nz) return fail(MM_EINVAL, "out of host memory");
+  nz->kind = 3;
+  nz->n_det = n_det;
+  nz->n_chunks = n_intervals;
+  nz->chunk_offsets.assign(interval_offsets_host, interval_offsets_host + n_intervals + 1);
+  Carver cv(workspace, ws_bytes);
+  nz->det_w = cv.take<double>(n_det);
+  nz->tpl = cv.take<TplInterval>(n_intervals);
+  (void)hipGetDevice(&nz->device);
+  hipStream_t s = as_stream(stream);
+  hipError_t e = hipMemcpyAsync(nz->det_w, det_weight_host, sizeof(double) * n_det, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && n_intervals > 0)
+    e = hipMemcpyAsync(nz->tpl, iv.data(), sizeof(TplInterval) * n_intervals, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete nz;
+    return hip_fail(e, "upload template tables");
+  }
+  *out = nz;
+  return MM_OK;
+}
+
 int mm_noise_white(const double* det_weight_host, int32_t n_det, void* workspace, size_t ws_bytes, void* stream,
                    mm_noise_t* out) {
   if (!out) return fail(MM_EINVAL, "null output handle pointer");
@@ -404,6 +464,7 @@ int mm_apply_Ninv(mm_noise_t nz, mm_pointing_t pt, const void* tod_in, void* tod
   if (tod_in == tod_out && pt->n_samples) return fail(MM_EINVAL, "tod_out must not alias tod_in");
   hipStream_t s = as_stream(stream);
   if (nz->kind == 0) return launch_ninv_white(pt, nz->det_w, tod_in, tod_out, arith, s);
+  if (nz->kind == 3) return launch_ninv_templates(pt, nz, tod_in, tod_out, arith, s);
   // samples outside every chunk are zero
   const size_t esz = pt->dtype == MM_F64 ? 8 : 4;
   MM_HIP(hipMemsetAsync(tod_out, 0, esz * (size_t)pt->n_samples, s));

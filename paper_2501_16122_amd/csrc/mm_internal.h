@@ -70,6 +70,17 @@ struct CarrySeg {
   int32_t pad_;
 };
 
+// An interval of the template-filtered weight: samples [start, end) of one
+// detector, with polynomial baselines of degree < order projected out.
+constexpr int kMaxTplOrder = 8;
+struct TplInterval {
+  int64_t start;
+  int64_t end;
+  int32_t order;
+  int32_t pad_;
+};
+static_assert(sizeof(TplInterval) == 24, "TplInterval layout");
+
 // Real-signal length L and complex FFT length N = L/2 per arithmetic.
 // FP64: L = 2^14 (8192 complex doubles = 128 KiB of LDS);
 // FP32: L = 2^15 (16384 complex floats = 128 KiB of LDS).
@@ -127,11 +138,16 @@ struct mm_pointing_s {
 };
 
 struct mm_noise_s {
-  int kind = 0;  // 0 = white, 1 = band-Toeplitz, 2 = circulant (band filter, periodic chunks)
+  // 0 = white, 1 = band-Toeplitz, 2 = circulant (band filter, periodic chunks),
+  // 3 = white with polynomial templates marginalised per interval
+  int kind = 0;
   int device = 0;
-  // white
+  // white (and the weights of the template-filtered form)
   int32_t n_det = 0;
   double* det_w = nullptr;
+  // template-filtered: its intervals (partitioning the timeline; their
+  // offsets are also kept in chunk_offsets for the detector checks)
+  mm::TplInterval* tpl = nullptr;
   // band-Toeplitz
   int32_t lambda = 0;
   int32_t n_filt = 0;
@@ -214,6 +230,11 @@ int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const vo
 constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpCarry = 4, kOpVariants = 8;
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
                           double* q, int arith, const RhsBatch& rb, hipStream_t s, int32_t variant = 0);
+// template-filtered white weights (noise kind 3)
+int launch_fused_templates(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
+                           double* q, int arith, const RhsBatch& rb, hipStream_t s);
+int launch_ninv_templates(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
+                          hipStream_t s);
 int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, size_t ws_bytes,
                             hipStream_t s, size_t* bytes_needed);
 

@@ -379,7 +379,7 @@ int mm_solver_create(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const void*
       return bail(rc);
   }
   sv->variant = o.op_variant;
-  if (o.autotune && nz->kind != 0)
+  if (o.autotune && (nz->kind == 1 || nz->kind == 2))
     if (int rc = sv->tune()) return bail(rc);
   *out = sv;
   return MM_OK;
@@ -472,6 +472,7 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
     if (sv->mixed != s0->mixed || sv->pt->dtype != s0->pt->dtype || sv->pt->ncomp != s0->pt->ncomp)
       return fail(MM_EINVAL, "batch members must share the timeline dtype, precision mode and map form");
     if (sv->pt->device != s0->pt->device) return fail(MM_EINVAL, "batch members must share one device");
+    if (sv->nz->kind == 3) return fail(MM_EINVAL, "template-filtered weights are not batched");
     slots += sv->nrhs;
   }
   if (slots > kMaxBatch) return fail(MM_EINVAL, "more than 16 right-hand sides in one batch");

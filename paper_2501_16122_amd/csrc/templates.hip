@@ -1,0 +1,288 @@
+// Template-filtered white weights: a general W of eq. (4) built from the
+// filtering templates of Sec. IV.  On each interval of one detector the
+// white weight w = 1/sigma_d^2 is applied after the polynomial baselines of
+// degree < K are projected out:
+//     W y = w (y - Pi y),   Pi = T (T^T T)^-1 T^T,
+// with T the polynomials of degree < K in the sample position.  Pi does not
+// depend on the basis; here it is the discrete orthogonal (Gram) polynomial
+// basis of the interval's n equispaced positions, for which T^T T is
+// diagonal with closed-form entries, so Pi y = sum_j (<p_j, y> / h_j) p_j.
+//
+// One workgroup per interval and right-hand side, in two passes over the
+// interval's samples: (1) the K projections <p_j, y> (FP64 sums, reduced in
+// the workgroup), (2) the filtered, weighted z = w (y - Pi y), either
+// written as a timeline or scattered by P^T through LDS bins per sub-tile of
+// 4096 samples (as the white fused operator does).  With y = P x the gather
+// is recomputed in the second pass instead of storing the timeline.
+#include <climits>
+
+#include "mm_internal.h"
+#include "sincos2.h"
+#include "stokes.h"
+
+namespace mm {
+namespace {
+
+constexpr int kTplThreads = 256;
+constexpr int kTplSub = 4096;                     // samples per binning sub-tile
+constexpr int kTplJ = kTplSub / kTplThreads;      // samples per thread per sub-tile
+constexpr int kTplBins = 2048;                    // LDS bins per pass (NC doubles each)
+
+// Gram polynomials on the positions i = 0 .. n-1 of an interval, scaled to
+// O(1): with v = (2 i - n + 1) / n,
+//   p_0 = 1,  p_1 = v,  p_{k+1} = ((2k+1) v p_k - k (1 - k^2/n^2) p_{k-1}) / (k+1),
+// orthogonal over the n positions with sum_i p_k(i)^2 = n prod_{j<=k} (1 - j^2/n^2) / (2k+1).
+struct Gram {
+  double beta[kMaxTplOrder];  // k (1 - k^2/n^2) / (k+1)
+  double inv_n;
+  int order;                  // effective order min(K, n)
+
+  __device__ void init(int64_t n, int k_req) {
+    order = (int64_t)k_req < n ? k_req : (int)n;
+    inv_n = 1.0 / (double)n;
+#pragma unroll
+    for (int k = 0; k < kMaxTplOrder; ++k) {
+      const double kk = (double)k * inv_n;
+      beta[k] = (double)k * (1.0 - kk * kk) / (double)(k + 1);
+    }
+  }
+  __device__ double norm(int64_t n, int k) const {
+    double h = (double)n;
+    for (int j = 1; j <= k; ++j) {
+      const double r = (double)j * inv_n;
+      h *= 1.0 - r * r;
+    }
+    return h / (double)(2 * k + 1);
+  }
+  // p_0 .. p_{order-1} at position i (entries past the order are unused)
+  __device__ __forceinline__ void eval(int64_t i, double* p) const {
+    const double v = (double)(2 * i + 1) * inv_n - 1.0;
+    p[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k < kMaxTplOrder; ++k) {
+      if (k == 1) p[1] = v;
+      else p[k] = ((double)(2 * k - 1) / (double)k) * v * p[k - 1] - beta[k - 1] * p[k - 2];
+    }
+  }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_minmax(T v, bool is_min) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const T o = __shfl_down(v, off, 64);
+    v = is_min ? (o < v ? o : v) : (o > v ? o : v);
+  }
+  return v;
+}
+
+// kIn: 1 = y = P x, 0 = y = tod_in.  kOut: 1 = q += P^T z, 0 = tod_out = z.
+template <class S, class C, int NC, int kIn, int kOut>
+__global__ __launch_bounds__(kTplThreads) void k_templates(
+    const TplInterval* __restrict__ iv, const PtTile* __restrict__ tiles, int64_t n_tiles,
+    const double* __restrict__ det_w, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
+    const double* __restrict__ x, const S* __restrict__ tin, S* __restrict__ tout, double* __restrict__ q,
+    RhsBatch rb) {
+  constexpr int W = kTplThreads / 64;
+  __shared__ double s_sum[kMaxTplOrder * W];
+  __shared__ int32_t s_k[2 * W];
+  __shared__ double s_w;
+  __shared__ double bins[kOut == 1 ? NC * kTplBins : 1];
+  if (rb.done != nullptr && rb.done[(int64_t)blockIdx.y * rb.done_stride]) return;
+  if (x != nullptr) x += blockIdx.y * rb.vstride;
+  if (q != nullptr) q += blockIdx.y * rb.vstride;
+  const TplInterval I = iv[blockIdx.x];
+  const int64_t a = I.start, n = I.end - I.start;
+  if (n <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // the detector weight: the pointing tile holding the interval's first sample
+  if (tid == 0) {
+    int64_t lo = 0, hi = n_tiles - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) / 2;
+      if (tiles[mid].start <= a) lo = mid;
+      else hi = mid - 1;
+    }
+    s_w = det_w[tiles[lo].det];
+  }
+  Gram g;
+  g.init(n, I.order);
+  const int K = g.order;
+
+  // y at sample t (0 for samples of masked pixels when y = P x)
+  auto y_at = [&](int64_t t, int32_t& k, C& c, C& s) -> C {
+    if constexpr (kIn == 1) {
+      k = sample_k[t];
+      if (k < 0) return C(0);
+      if constexpr (Stokes<NC>::kAngle) sincos2<C>(psi[t], &c, &s);
+      return Stokes<NC>::project(x + NC * (int64_t)k, c, s);
+    } else {
+      if constexpr (kOut == 1) {
+        k = sample_k[t];
+        if (k >= 0 && Stokes<NC>::kAngle) sincos2<C>(psi[t], &c, &s);
+      }
+      return C(tin[t]);
+    }
+  };
+
+  // (1) projections onto the template polynomials
+  double coef[kMaxTplOrder];
+#pragma unroll
+  for (int j = 0; j < kMaxTplOrder; ++j) coef[j] = 0.0;
+  if (K > 0) {
+    for (int64_t i = tid; i < n; i += kTplThreads) {
+      int32_t k = -1;
+      C c = C(0), s = C(0);
+      const double y = double(y_at(a + i, k, c, s));
+      double p[kMaxTplOrder];
+      g.eval(i, p);
+#pragma unroll
+      for (int j = 0; j < kMaxTplOrder; ++j)
+        if (j < K) coef[j] += p[j] * y;
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxTplOrder; ++j) {
+      if (j < K) {
+        const double v = wave_sum(coef[j]);
+        if (lane == 0) s_sum[j * W + wid] = v;
+      }
+    }
+  }
+  __syncthreads();
+  const double w = s_w;
+#pragma unroll
+  for (int j = 0; j < kMaxTplOrder; ++j) {
+    coef[j] = 0.0;
+    if (j < K) {
+      double v = 0.0;
+      for (int u = 0; u < W; ++u) v += s_sum[j * W + u];
+      coef[j] = v / g.norm(n, j);
+    }
+  }
+
+  // (2) z = w (y - Pi y), written out or scattered by P^T per sub-tile
+  for (int64_t s0 = 0; s0 < n; s0 += kTplSub) {
+    int32_t kv[kTplJ];
+    double v[kTplJ][NC];
+    int32_t kmin = INT_MAX, kmax = -1;
+#pragma unroll
+    for (int jj = 0; jj < kTplJ; ++jj) {
+      const int64_t i = s0 + tid + (int64_t)kTplThreads * jj;
+      kv[jj] = -1;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[jj][c] = 0.0;
+      if (i < n) {
+        int32_t k = -1;
+        C c = C(0), s = C(0);
+        const C y = y_at(a + i, k, c, s);
+        double base = 0.0;
+        if (K > 0) {
+          double p[kMaxTplOrder];
+          g.eval(i, p);
+#pragma unroll
+          for (int j = 0; j < kMaxTplOrder; ++j)
+            if (j < K) base += coef[j] * p[j];
+        }
+        const C z = C(w * (double(y) - base));
+        if constexpr (kOut == 0) {
+          tout[a + i] = S(z);
+        } else if (k >= 0) {
+          kv[jj] = k;
+          Stokes<NC>::terms(z, c, s, v[jj]);
+          kmin = k < kmin ? k : kmin;
+          kmax = k > kmax ? k : kmax;
+        }
+      }
+    }
+    if constexpr (kOut == 1) {
+      kmin = wave_minmax<int32_t>(kmin, true);
+      kmax = wave_minmax<int32_t>(kmax, false);
+      __syncthreads();  // s_k and the bins are free
+      if (lane == 0) {
+        s_k[wid] = kmin;
+        s_k[W + wid] = kmax;
+      }
+      __syncthreads();
+      kmin = s_k[0];
+      kmax = s_k[W];
+      for (int u = 1; u < W; ++u) {
+        kmin = s_k[u] < kmin ? s_k[u] : kmin;
+        kmax = s_k[W + u] > kmax ? s_k[W + u] : kmax;
+      }
+      for (int32_t lo = kmin; lo <= kmax; lo += kTplBins) {
+        const int nb = kmax - lo + 1 < kTplBins ? kmax - lo + 1 : kTplBins;
+        for (int i = tid; i < nb; i += kTplThreads)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) bins[c * kTplBins + i] = 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < kTplJ; ++jj) {
+          const int rel = kv[jj] - lo;
+          if (kv[jj] >= 0 && rel >= 0 && rel < nb)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) atomicAdd(&bins[c * kTplBins + rel], v[jj][c]);
+        }
+        __syncthreads();
+        for (int i = tid; i < nb; i += kTplThreads) {
+          double* qk = q + NC * (int64_t)(lo + i);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const double b = bins[c * kTplBins + i];
+            if (b != 0.0) atomicAdd(qk + c, b);
+          }
+        }
+        __syncthreads();  // the next pass clears the bins
+      }
+    }
+  }
+}
+
+template <int NC, int kIn, int kOut>
+int launch_nc(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tin, void* tout,
+              double* q, int arith, const RhsBatch& rb, hipStream_t s) {
+  if (nz->n_chunks == 0 || pt->n_tiles == 0) return MM_OK;
+  const dim3 g((unsigned)nz->n_chunks, rb.nrhs), b(kTplThreads);
+  const TplInterval* iv = nz->tpl;
+  if (pt->dtype == MM_F64) {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_templates<double, double, NC, kIn, kOut>), g, b, 0, s, iv, pt->tiles, pt->n_tiles,
+                         nz->det_w, pt->sample_k, (const double*)pt->psi, x, (const double*)tin, (double*)tout, q,
+                         rb);
+    else
+      hipLaunchKernelGGL((k_templates<double, float, NC, kIn, kOut>), g, b, 0, s, iv, pt->tiles, pt->n_tiles,
+                         nz->det_w, pt->sample_k, (const double*)pt->psi, x, (const double*)tin, (double*)tout, q,
+                         rb);
+  } else {
+    if (arith == MM_F64)
+      hipLaunchKernelGGL((k_templates<float, double, NC, kIn, kOut>), g, b, 0, s, iv, pt->tiles, pt->n_tiles,
+                         nz->det_w, pt->sample_k, (const float*)pt->psi, x, (const float*)tin, (float*)tout, q,
+                         rb);
+    else
+      hipLaunchKernelGGL((k_templates<float, float, NC, kIn, kOut>), g, b, 0, s, iv, pt->tiles, pt->n_tiles,
+                         nz->det_w, pt->sample_k, (const float*)pt->psi, x, (const float*)tin, (float*)tout, q,
+                         rb);
+  }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+}  // namespace
+
+int launch_fused_templates(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
+                           double* q, int arith, const RhsBatch& rb, hipStream_t s) {
+  return by_ncomp(pt->ncomp, [&]<int NC>() -> int {
+    if (x != nullptr) return launch_nc<NC, 1, 1>(pt, nz, x, nullptr, nullptr, q, arith, rb, s);
+    return launch_nc<NC, 0, 1>(pt, nz, nullptr, tod, nullptr, q, arith, rb, s);
+  });
+}
+
+int launch_ninv_templates(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
+                          hipStream_t s) {
+  return launch_nc<3, 0, 0>(pt, nz, nullptr, in, out, nullptr, arith, RhsBatch{}, s);
+}
+
+}  // namespace mm

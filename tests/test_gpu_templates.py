@@ -1,0 +1,149 @@
+"""Template-filtered white weights (a general W of eq. (4): polynomial
+baselines marginalised per interval) on the GPU against the oracle: the
+weight alone, the fused A and b in every map form and arithmetic, the solve
+at a fixed iteration count, exact removal of baselines from noiseless data,
+and the argument checks."""
+import numpy as np
+import pytest
+
+import oracle.mapmaking as oracle
+from paper_2501_16122_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+# 3 detectors of 3*2^16 + 777 samples on a 128^2 grid
+W = synth.Workload("tpl_128x128_3x197385", 951, 128, 128, 3, 3 * (1 << 16) + 777, t_psi=1500.0, noise="white")
+
+
+def _b():
+    from paper_2501_16122_amd import binding
+    return binding
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+def intervals(w, length=5003):
+    """Ragged intervals inside each detector, plus a 1-sample interval and
+    one short one, partitioning the timeline; orders vary per interval."""
+    offs = [0]
+    for d in range(w.n_det):
+        a, b = d * w.n_samp, (d + 1) * w.n_samp
+        cuts = list(range(a + length, b, length))
+        cuts = [a + 1, a + 7] + cuts if d == 1 else cuts
+        offs += cuts + [b]
+    offs = np.array(offs, dtype=np.int64)
+    orders = (np.arange(offs.size - 1) % 5).astype(np.int32)  # 0 .. 4
+    orders[3] = 8
+    return offs, orders
+
+
+class Setup:
+    def __init__(self, stokes, precision="f64"):
+        b = _b()
+        w = W.replace(precision=precision)
+        pix, psi = synth.pointing(w)
+        self.psi = synth.storage(w, psi)
+        self.offs, self.wdet = synth.det_offsets(w), synth.det_weight(w) * np.array([1.0, 0.5, 2.0])
+        self.opt = oracle.build_pointing(pix, self.psi, self.offs, self.wdet, w.n_pix, stokes=stokes)
+        self.nc = self.opt.ncomp
+        self.ivals, self.orders = intervals(w)
+        self.noise = oracle.template_noise(self.ivals, self.orders)
+        self.t_pix = torch.from_numpy(pix).to(DEV)
+        self.t_psi = torch.from_numpy(self.psi).to(DEV)
+        self.pt = b.Pointing(self.t_pix, self.t_psi, self.offs, self.wdet, w.n_pix, stokes=stokes)
+        self.nz = b.Noise.templates(self.wdet, self.ivals, 0, DEV, orders=self.orders)
+        m = np.random.default_rng(3).normal(size=self.nc * self.opt.n_kept)
+        self.d = synth.storage(w, oracle.apply_P(self.opt, m) + synth.noise(w))
+        self.t_d = torch.from_numpy(self.d).to(DEV)
+
+
+@pytest.fixture(scope="module", params=["IQU", "QU", "I"])
+def setup(request):
+    return Setup(request.param)
+
+
+def test_weight_matches_oracle(setup):
+    b = _b()
+    y = np.random.default_rng(1).normal(size=setup.opt.n_samples) + 3.0
+    z = b.apply_Ninv(setup.nz, setup.pt, torch.from_numpy(y).to(DEV)).cpu().numpy()
+    ref = oracle.apply_w_templates(setup.opt, setup.noise, y)
+    assert rel(z, ref) < 1e-12
+    z32 = b.apply_Ninv(setup.nz, setup.pt, torch.from_numpy(y).to(DEV), arith="f32").cpu().numpy()
+    assert rel(z32, ref) < 1e-5
+
+
+def test_fused_operator_and_rhs(setup):
+    b = _b()
+    o = setup.opt
+    x = np.random.default_rng(2).normal(size=setup.nc * o.n_kept)
+    tx = torch.from_numpy(x).to(DEV)
+    ref = oracle.apply_A(o, setup.noise, x)
+    assert rel(b.apply_A(setup.pt, setup.nz, tx).cpu(), ref) < 1e-12
+    assert rel(b.apply_A(setup.pt, setup.nz, tx, arith="f32").cpu(), ref) < 1e-5
+    Q = b.apply_A_multi(setup.pt, setup.nz, torch.stack([tx, -tx]).contiguous()).cpu().numpy()
+    assert rel(Q[0], ref) < 1e-12 and rel(Q[1], -ref) < 1e-12
+    assert rel(b.rhs(setup.pt, setup.nz, setup.t_d).cpu(), oracle.rhs(o, setup.noise, setup.d)) < 1e-12
+
+
+def test_solve_fixed_iterations(setup):
+    b = _b()
+    k = 20
+    out = b.Solver(setup.pt, setup.nz, fixed_iter=k, tol=0.0).solve(setup.t_d)
+    _, info, x_ref = oracle.solve(setup.opt, setup.noise, setup.d, fixed_iters=k)
+    err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref, ncomp=setup.nc)
+    assert np.all(err < 1e-10), err
+
+
+def test_baselines_removed_from_noiseless_data():
+    # d = P m + polynomial baselines of degree < 3 on every interval: the
+    # polarisation map is recovered whatever the baselines
+    b = _b()
+    s = Setup("QU")
+    o = s.opt
+    nz = b.Noise.templates(s.wdet, s.ivals, 3, DEV)
+    m = np.random.default_rng(5).normal(size=2 * o.n_kept)
+    d = oracle.apply_P(o, m)
+    rng = np.random.default_rng(6)
+    for a, c in zip(s.ivals[:-1], s.ivals[1:]):
+        u = np.linspace(-1, 1, c - a) if c - a > 1 else np.zeros(1)
+        d[a:c] += np.polynomial.polynomial.polyval(u, rng.normal(size=3) * 30.0)
+    out = b.Solver(s.pt, nz, tol=1e-12).solve(torch.from_numpy(d).to(DEV))
+    assert out["info"]["converged"] == 1
+    assert np.all(oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), m, ncomp=2) < 1e-8)
+    white = b.Solver(s.pt, b.Noise.white(s.wdet, DEV), tol=1e-12).solve(torch.from_numpy(d).to(DEV))
+    assert np.all(oracle.rel_l2_per_stokes(white["x"].cpu().numpy(), m, ncomp=2) > 1e-2)
+
+
+def test_mixed_precision_solve():
+    b = _b()
+    s = Setup("QU", precision="f32")
+    out = b.Solver(s.pt, s.nz, tol=1e-10, mixed=1).solve(s.t_d)
+    assert out["info"]["converged"] == 1 and out["info"]["true_rel_resid"] <= 1e-10
+    _, _, x_ref = oracle.solve(s.opt, s.noise, s.d, tol=1e-13)
+    assert np.all(oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref, ncomp=2) < 1e-7)
+
+
+def test_argument_checks(setup):
+    b = _b()
+    n = setup.opt.n_samples
+    x = torch.zeros(setup.nc * setup.opt.n_kept, dtype=torch.float64, device=DEV)
+    short = b.Noise.templates(setup.wdet, np.array([0, n - 5]), 2, DEV)       # does not reach the end
+    with pytest.raises(b.MapMakerError):
+        b.apply_A(setup.pt, short, x)
+    across = b.Noise.templates(setup.wdet, np.array([0, W.n_samp + 10, n]), 2, DEV)  # crosses a detector
+    with pytest.raises(b.MapMakerError):
+        b.apply_A(setup.pt, across, x)
+    with pytest.raises(b.MapMakerError):
+        b.Noise.templates(setup.wdet, np.array([0, n]), 9, DEV)
+    with pytest.raises(b.MapMakerError):
+        b.Noise.templates(setup.wdet, np.array([3, n]), 1, DEV)
+    s1 = b.AsyncSolver(setup.pt, setup.nz, setup.t_d)
+    with pytest.raises(b.MapMakerError):
+        b.batch_step([s1], 2)
