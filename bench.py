@@ -33,6 +33,7 @@ FP64_PEAK_TFLOPS = 78.6
 # source files of the dominant kernel (the fused band-Toeplitz A); a stored
 # counter summary is used only while these are unchanged
 KERNEL_SOURCES = ["paper_2501_16122_amd/csrc/toeplitz.hip", "paper_2501_16122_amd/csrc/fft_lds.h",
+                  "paper_2501_16122_amd/csrc/stokes.h",
                   "paper_2501_16122_amd/csrc/sincos2.h"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_toeplitz_fused_f64_gls512.counters.json")
 
@@ -348,6 +349,82 @@ def serving_section(torch, b, synth, dev, n_req=24, rate=20.0):
                     "is that solver serving the same arrivals first-come first-served"}
 
 
+def templates_section(torch, b, w, dev, t_pix, t_psi, t_d, t_m, noise, offs, wdet, nz, kept, m, step):
+    """The headline data solved with white weights and polynomial baselines
+    (degree < 3 on every 2^16-sample interval) marginalised instead of the
+    band-Toeplitz N^-1, in the I, Q, U form and in the Q, U form (whose data
+    hold only the Q, U sky): speed and map error against the input sky."""
+    ivals = np.arange(0, w.n_samples + 1, 1 << 16)
+    nzt = b.Noise.templates(wdet, ivals, 3, dev)
+    kept_np = kept.cpu().numpy()
+    out = {}
+
+    def err(x, truth, demean_i):
+        e = x - truth
+        if demean_i:
+            e[:, 0] -= e[:, 0].mean()  # with offsets marginalised the I monopole is unconstrained
+        return [round(float(np.linalg.norm(e[:, i]) / np.linalg.norm(truth[:, i])), 6) for i in range(truth.shape[1])]
+
+    # I, Q, U: the headline timeline (about 700 iterations: the filter leaves
+    # large-scale I modes poorly constrained; one timed solve, no warm-up)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    info_t, map_t = step(t_psi, t_d, 0, nzt, keep_map=True)
+    t_iqu = time.perf_counter() - ts
+    _, map_g = step(t_psi, t_d, 0, None, keep_map=True)
+    truth = m[kept_np]
+    op = info_t["op_ms"] / max(info_t["op_launches"], 1)
+    out["IQU"] = {
+        "time_to_map_ms": round(1e3 * t_iqu, 3), "pcg_iters": info_t["iters"],
+        "final_true_rel_resid": info_t["true_rel_resid"], "operator_ms_avg": round(op, 4),
+        "map_error_vs_input_sky": {
+            "templates": err(map_t.cpu().numpy().reshape(-1, 3)[kept_np], truth, True),
+            "band_toeplitz": err(map_g.cpu().numpy().reshape(-1, 3)[kept_np], truth, True)}}
+
+    # Q, U: data from the Q, U sky and the same noise
+    t_noise = torch.from_numpy(noise).to(dev)
+    pt0 = b.Pointing(t_pix, t_psi, offs, wdet, w.n_pix, stokes="QU")
+    kq = pt0.export()["kept"].long()
+    m_qu = t_m[kq][:, 1:].reshape(-1).contiguous()
+    d_qu = b.apply_P(pt0, m_qu)
+    d_qu += t_noise
+    del t_noise
+    pt0.close()
+
+    def qu(noise_h):
+        pt = b.Pointing(t_pix, t_psi, offs, wdet, w.n_pix, stokes="QU")
+        pt.attach_weights()
+        r = b.Solver(pt, noise_h, tol=1e-10, timing=1, check_every=8, autotune=1).solve(d_qu)
+        pt.close()
+        return r
+
+    qu(nzt)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(2):
+        ts = time.perf_counter()
+        r = qu(nzt)
+        times.append(time.perf_counter() - ts)
+    rg = qu(nz)
+    truth_qu = m_qu.view(-1, 2).cpu().numpy()
+    op = r["info"]["op_ms"] / max(r["info"]["op_launches"], 1)
+    out["QU"] = {
+        "time_to_map_ms": round(1e3 * float(np.median(times)), 3), "pcg_iters": r["info"]["iters"],
+        "final_true_rel_resid": r["info"]["true_rel_resid"], "operator_ms_avg": round(op, 4),
+        "map_error_vs_input_sky": {
+            "templates": err(r["x"].view(-1, 2).cpu().numpy(), truth_qu, False),
+            "band_toeplitz": err(rg["x"].view(-1, 2).cpu().numpy(), truth_qu, False)}}
+    del d_qu
+    nzt.close()
+    torch.cuda.empty_cache()
+    out["intervals"], out["interval_samples"], out["order"] = int(ivals.size - 1), 1 << 16, 3
+    out["note"] = ("1/f data; W = white weights with polynomial baselines (degree < 3) marginalised on each "
+                   "2^16-sample interval instead of the band-Toeplitz N^-1; FP64 to 1e-10 with stored pointing "
+                   "weights, pointing build included; map errors relative L2 per Stokes over kept pixels (I mean "
+                   "removed); the operator reads the index and the (cos, sin) pair in each of its two passes")
+    return out
+
+
 def stokes_section(torch, b, w, dev, t_pix, t_psi, t_m, noise, offs, wdet, nz, iqu_times):
     """The polarisation-only (Q, U) and intensity-only (I) map forms on the
     same scan and band-Toeplitz N^-1: each solves data made from its own
@@ -414,6 +491,8 @@ def main():
     ap.add_argument("--batch", type=int, default=16, help="uneven solves in the batched measurement (0 = skip)")
     ap.add_argument("--circulant", type=int, default=1, help="1 = also solve with circulant N^-1 (0 = skip)")
     ap.add_argument("--stokes", type=int, default=1, help="1 = also solve the QU-only and I-only forms (0 = skip)")
+    ap.add_argument("--templates", type=int, default=1,
+                    help="1 = also solve with polynomial baselines marginalised instead of N^-1 (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: single-GPU only (asked for --gpus {args.gpus}); sharding the timeline across "
@@ -558,6 +637,12 @@ def main():
                     "map errors are relative L2 per Stokes of (GLS map - input sky) over kept pixels"}
         nzc.close()
         log(f"circulant: {result['circulant']['time_to_map_ms']} ms per map")
+
+    if args.templates and w.toeplitz:
+        result["templates"] = templates_section(torch, b, w, dev, t_pix, t_psi, t_d, t_m, noise, offs, wdet, nz,
+                                                kept, m, step)
+        log("templates: " + ", ".join(f"{k} {v['time_to_map_ms']} ms" for k, v in result["templates"].items()
+                                      if isinstance(v, dict)))
 
     if args.stokes and w.toeplitz:
         result["stokes_forms"] = stokes_section(torch, b, w, dev, t_pix, t_psi, t_m, noise, offs, wdet, nz, times)

@@ -11,11 +11,12 @@
 // One workgroup per interval and right-hand side, in two passes over the
 // interval's samples: (1) the K projections <p_j, y> (FP64 sums, reduced in
 // the workgroup), (2) the filtered, weighted z = w (y - Pi y), either
-// written as a timeline or scattered by P^T through LDS bins per sub-tile of
-// 4096 samples (as the white fused operator does).  With y = P x the gather
+// written as a timeline or scattered by P^T through LDS bins per batch of
+// 2048 samples (as the white fused operator does).  With y = P x the gather
 // is recomputed in the second pass instead of storing the timeline.
 #include <climits>
 
+#include "fft_lds.h"
 #include "mm_internal.h"
 #include "sincos2.h"
 #include "stokes.h"
@@ -24,8 +25,8 @@ namespace mm {
 namespace {
 
 constexpr int kTplThreads = 256;
-constexpr int kTplSub = 4096;                     // samples per binning sub-tile
-constexpr int kTplJ = kTplSub / kTplThreads;      // samples per thread per sub-tile
+constexpr int kTplJ = 8;                          // samples per thread per batch
+constexpr int kTplSub = kTplJ * kTplThreads;      // samples per batch (and binning sub-tile)
 constexpr int kTplBins = 2048;                    // LDS bins per pass (NC doubles each)
 
 // Gram polynomials on the positions i = 0 .. n-1 of an interval, scaled to
@@ -60,7 +61,8 @@ struct Gram {
     p[0] = 1.0;
 #pragma unroll
     for (int k = 1; k < kMaxTplOrder; ++k) {
-      if (k == 1) p[1] = v;
+      if (k >= order) p[k] = 0.0;  // uniform over the workgroup
+      else if (k == 1) p[1] = v;
       else p[k] = ((double)(2 * k - 1) / (double)k) * v * p[k - 1] - beta[k - 1] * p[k - 2];
     }
   }
@@ -81,12 +83,13 @@ __device__ __forceinline__ T wave_minmax(T v, bool is_min) {
 }
 
 // kIn: 1 = y = P x, 0 = y = tod_in.  kOut: 1 = q += P^T z, 0 = tod_out = z.
-template <class S, class C, int NC, int kIn, int kOut>
+// kW: 1 = stream the stored (cos 2psi, sin 2psi) pairs instead of psi.
+template <class S, class C, int NC, int kIn, int kOut, int kW>
 __global__ __launch_bounds__(kTplThreads) void k_templates(
     const TplInterval* __restrict__ iv, const PtTile* __restrict__ tiles, int64_t n_tiles,
     const double* __restrict__ det_w, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
-    const double* __restrict__ x, const S* __restrict__ tin, S* __restrict__ tout, double* __restrict__ q,
-    RhsBatch rb) {
+    const cpx<S>* __restrict__ wts, const double* __restrict__ x, const S* __restrict__ tin, S* __restrict__ tout,
+    double* __restrict__ q, RhsBatch rb) {
   constexpr int W = kTplThreads / 64;
   __shared__ double s_sum[kMaxTplOrder * W];
   __shared__ int32_t s_k[2 * W];
@@ -113,19 +116,40 @@ __global__ __launch_bounds__(kTplThreads) void k_templates(
   g.init(n, I.order);
   const int K = g.order;
 
-  // y at sample t (0 for samples of masked pixels when y = P x)
-  auto y_at = [&](int64_t t, int32_t& k, C& c, C& s) -> C {
-    if constexpr (kIn == 1) {
-      k = sample_k[t];
-      if (k < 0) return C(0);
-      if constexpr (Stokes<NC>::kAngle) sincos2<C>(psi[t], &c, &s);
-      return Stokes<NC>::project(x + NC * (int64_t)k, c, s);
-    } else {
-      if constexpr (kOut == 1) {
-        k = sample_k[t];
-        if (k >= 0 && Stokes<NC>::kAngle) sincos2<C>(psi[t], &c, &s);
+  // One batch: kTplJ samples per thread at interval positions i0 + tid +
+  // kTplThreads j.  All index and angle loads are issued before the map
+  // gathers and the arithmetic, so each thread keeps a batch of loads in
+  // flight.  y = P x (0 for samples of masked pixels) or the input timeline;
+  // k = the compact index (-1 = masked or past the end), (c, s) the angle
+  // terms where the row needs them.
+  constexpr bool kAng = Stokes<NC>::kAngle && (kIn == 1 || kOut == 1);
+  auto load_batch = [&](int64_t i0, int32_t* kb, C* yb, C* cb, C* sb) {
+    S ang[kTplJ];
+    cpx<S> cs[kTplJ];
+    S tv[kTplJ];
+#pragma unroll
+    for (int j = 0; j < kTplJ; ++j) {
+      const int64_t i = i0 + tid + (int64_t)kTplThreads * j;
+      const bool ok = i < n;
+      kb[j] = -1;
+      if constexpr (kIn == 1 || kOut == 1) kb[j] = ok ? sample_k[a + i] : -1;
+      if constexpr (kAng && kW == 1) cs[j] = kb[j] >= 0 ? wts[a + i] : cpx<S>{S(0), S(0)};
+      if constexpr (kAng && kW == 0) ang[j] = kb[j] >= 0 ? psi[a + i] : S(0);
+      if constexpr (kIn == 0) tv[j] = ok ? tin[a + i] : S(0);
+    }
+#pragma unroll
+    for (int j = 0; j < kTplJ; ++j) {
+      C c = C(0), sn = C(0);
+      if constexpr (kAng && kW == 1) {
+        c = C(cs[j].x);
+        sn = C(cs[j].y);
       }
-      return C(tin[t]);
+      if constexpr (kAng && kW == 0)
+        if (kb[j] >= 0) sincos2<C>(ang[j], &c, &sn);
+      cb[j] = c;
+      sb[j] = sn;
+      if constexpr (kIn == 1) yb[j] = kb[j] >= 0 ? Stokes<NC>::project(x + NC * (int64_t)kb[j], c, sn) : C(0);
+      else yb[j] = C(tv[j]);
     }
   };
 
@@ -134,15 +158,22 @@ __global__ __launch_bounds__(kTplThreads) void k_templates(
 #pragma unroll
   for (int j = 0; j < kMaxTplOrder; ++j) coef[j] = 0.0;
   if (K > 0) {
-    for (int64_t i = tid; i < n; i += kTplThreads) {
-      int32_t k = -1;
-      C c = C(0), s = C(0);
-      const double y = double(y_at(a + i, k, c, s));
-      double p[kMaxTplOrder];
-      g.eval(i, p);
+    for (int64_t i0 = 0; i0 < n; i0 += kTplSub) {
+      int32_t kb[kTplJ];
+      C yb[kTplJ], cb[kTplJ], sb[kTplJ];
+      load_batch(i0, kb, yb, cb, sb);
 #pragma unroll
-      for (int j = 0; j < kMaxTplOrder; ++j)
-        if (j < K) coef[j] += p[j] * y;
+      for (int j = 0; j < kTplJ; ++j) {
+        const int64_t i = i0 + tid + (int64_t)kTplThreads * j;
+        if (i < n) {
+          double p[kMaxTplOrder];
+          g.eval(i, p);
+          const double y = double(yb[j]);
+#pragma unroll
+          for (int o = 0; o < kMaxTplOrder; ++o)
+            if (o < K) coef[o] += p[o] * y;
+        }
+      }
     }
 #pragma unroll
     for (int j = 0; j < kMaxTplOrder; ++j) {
@@ -164,37 +195,34 @@ __global__ __launch_bounds__(kTplThreads) void k_templates(
     }
   }
 
-  // (2) z = w (y - Pi y), written out or scattered by P^T per sub-tile
+  // (2) z = w (y - Pi y), written out or scattered by P^T per batch
   for (int64_t s0 = 0; s0 < n; s0 += kTplSub) {
     int32_t kv[kTplJ];
+    C yb[kTplJ], cb[kTplJ], sb[kTplJ];
+    load_batch(s0, kv, yb, cb, sb);
     double v[kTplJ][NC];
     int32_t kmin = INT_MAX, kmax = -1;
 #pragma unroll
     for (int jj = 0; jj < kTplJ; ++jj) {
       const int64_t i = s0 + tid + (int64_t)kTplThreads * jj;
-      kv[jj] = -1;
 #pragma unroll
       for (int c = 0; c < NC; ++c) v[jj][c] = 0.0;
       if (i < n) {
-        int32_t k = -1;
-        C c = C(0), s = C(0);
-        const C y = y_at(a + i, k, c, s);
         double base = 0.0;
         if (K > 0) {
           double p[kMaxTplOrder];
           g.eval(i, p);
 #pragma unroll
-          for (int j = 0; j < kMaxTplOrder; ++j)
-            if (j < K) base += coef[j] * p[j];
+          for (int o = 0; o < kMaxTplOrder; ++o)
+            if (o < K) base += coef[o] * p[o];
         }
-        const C z = C(w * (double(y) - base));
+        const C z = C(w * (double(yb[jj]) - base));
         if constexpr (kOut == 0) {
           tout[a + i] = S(z);
-        } else if (k >= 0) {
-          kv[jj] = k;
-          Stokes<NC>::terms(z, c, s, v[jj]);
-          kmin = k < kmin ? k : kmin;
-          kmax = k > kmax ? k : kmax;
+        } else if (kv[jj] >= 0) {
+          Stokes<NC>::terms(z, cb[jj], sb[jj], v[jj]);
+          kmin = kv[jj] < kmin ? kv[jj] : kmin;
+          kmax = kv[jj] > kmax ? kv[jj] : kmax;
         }
       }
     }
@@ -241,33 +269,35 @@ __global__ __launch_bounds__(kTplThreads) void k_templates(
   }
 }
 
+template <class S, class C, int NC, int kIn, int kOut, int kW>
+int launch_one(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tin, void* tout,
+               double* q, const RhsBatch& rb, hipStream_t s) {
+  const dim3 g((unsigned)nz->n_chunks, rb.nrhs), b(kTplThreads);
+  hipLaunchKernelGGL((k_templates<S, C, NC, kIn, kOut, kW>), g, b, 0, s, nz->tpl, pt->tiles, pt->n_tiles, nz->det_w,
+                     pt->sample_k, (const S*)pt->psi, (const cpx<S>*)pt->weights, x, (const S*)tin, (S*)tout, q,
+                     rb);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+// Stored weights serve an arithmetic no finer than their storage; the
+// intensity-only form and the timeline-out form use none.
 template <int NC, int kIn, int kOut>
 int launch_nc(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tin, void* tout,
               double* q, int arith, const RhsBatch& rb, hipStream_t s) {
   if (nz->n_chunks == 0 || pt->n_tiles == 0) return MM_OK;
-  const dim3 g((unsigned)nz->n_chunks, rb.nrhs), b(kTplThreads);
-  const TplInterval* iv = nz->tpl;
+  constexpr int kW1 = (NC == 1 || kOut == 0) ? 0 : 1;
+  const bool w = kW1 == 1 && pt->weights != nullptr && (arith == MM_F32 || pt->dtype == MM_F64);
   if (pt->dtype == MM_F64) {
     if (arith == MM_F64)
-      hipLaunchKernelGGL((k_templates<double, double, NC, kIn, kOut>), g, b, 0, s, iv, pt->tiles, pt->n_tiles,
-                         nz->det_w, pt->sample_k, (const double*)pt->psi, x, (const double*)tin, (double*)tout, q,
-                         rb);
-    else
-      hipLaunchKernelGGL((k_templates<double, float, NC, kIn, kOut>), g, b, 0, s, iv, pt->tiles, pt->n_tiles,
-                         nz->det_w, pt->sample_k, (const double*)pt->psi, x, (const double*)tin, (double*)tout, q,
-                         rb);
-  } else {
-    if (arith == MM_F64)
-      hipLaunchKernelGGL((k_templates<float, double, NC, kIn, kOut>), g, b, 0, s, iv, pt->tiles, pt->n_tiles,
-                         nz->det_w, pt->sample_k, (const float*)pt->psi, x, (const float*)tin, (float*)tout, q,
-                         rb);
-    else
-      hipLaunchKernelGGL((k_templates<float, float, NC, kIn, kOut>), g, b, 0, s, iv, pt->tiles, pt->n_tiles,
-                         nz->det_w, pt->sample_k, (const float*)pt->psi, x, (const float*)tin, (float*)tout, q,
-                         rb);
+      return w ? launch_one<double, double, NC, kIn, kOut, kW1>(pt, nz, x, tin, tout, q, rb, s)
+               : launch_one<double, double, NC, kIn, kOut, 0>(pt, nz, x, tin, tout, q, rb, s);
+    return w ? launch_one<double, float, NC, kIn, kOut, kW1>(pt, nz, x, tin, tout, q, rb, s)
+             : launch_one<double, float, NC, kIn, kOut, 0>(pt, nz, x, tin, tout, q, rb, s);
   }
-  MM_HIP(hipGetLastError());
-  return MM_OK;
+  if (arith == MM_F64) return launch_one<float, double, NC, kIn, kOut, 0>(pt, nz, x, tin, tout, q, rb, s);
+  return w ? launch_one<float, float, NC, kIn, kOut, kW1>(pt, nz, x, tin, tout, q, rb, s)
+           : launch_one<float, float, NC, kIn, kOut, 0>(pt, nz, x, tin, tout, q, rb, s);
 }
 
 }  // namespace

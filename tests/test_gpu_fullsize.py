@@ -134,3 +134,29 @@ def test_full_size_forms_build_and_sampled_pixels(full_form):
         q = b.apply_A(pt, nz, torch.from_numpy(x).to(DEV), variant=v).cpu().numpy().reshape(-1, nc)
         err = np.abs(q[sel] - ref).max() / np.abs(ref).max()
         assert err < 1e-12, (v, err)
+
+
+def test_full_size_templates_sampled_pixels(full):
+    # template-filtered weights (degree < 3 on every 2^16-sample interval) at
+    # the full size, as the bench runs them: A on sampled pixels, from the
+    # intervals their samples fall in (intervals do not couple)
+    b = _b()
+    w, pix, psi, opt, pt, nz, coeff, chunks = full
+    ivals = np.arange(0, w.n_samples + 1, 1 << 16)
+    nzt = b.Noise.templates(synth.det_weight(w), ivals, 3, DEV)
+    rng = np.random.default_rng(4242)
+    x = rng.normal(size=3 * opt.n_kept)
+    q = b.apply_A(pt, nzt, torch.from_numpy(x).to(DEV)).cpu().numpy().reshape(-1, 3)
+    row = 301 % w.height
+    cand = opt.compact[row * w.width:(row + 1) * w.width]
+    sel = rng.choice(cand[cand >= 0], size=6, replace=False)
+    hit = np.isin(opt.sample_k, sel)
+    iidx = np.unique(np.searchsorted(ivals, np.flatnonzero(hit), side="right") - 1)
+    idx = np.concatenate([np.arange(ivals[i], ivals[i + 1]) for i in iidx])
+    lens = np.array([ivals[i + 1] - ivals[i] for i in iidx])
+    sub = dataclasses.replace(opt, pix=opt.pix[idx], cos2=opt.cos2[idx], sin2=opt.sin2[idx],
+                              weight=opt.weight[idx], sample_k=opt.sample_k[idx])
+    ref = oracle.apply_A(sub, oracle.template_noise(np.concatenate([[0], np.cumsum(lens)]), 3), x).reshape(-1, 3)
+    err = np.abs(q[sel] - ref[sel]).max() / np.abs(ref[sel]).max()
+    assert err < 1e-12, err
+    nzt.close()

@@ -90,6 +90,14 @@ def test_fused_operator_and_rhs(setup):
     Q = b.apply_A_multi(setup.pt, setup.nz, torch.stack([tx, -tx]).contiguous()).cpu().numpy()
     assert rel(Q[0], ref) < 1e-12 and rel(Q[1], -ref) < 1e-12
     assert rel(b.rhs(setup.pt, setup.nz, setup.t_d).cpu(), oracle.rhs(o, setup.noise, setup.d)) < 1e-12
+    # the same with stored pointing weights streamed instead of psi
+    setup.pt.attach_weights()
+    try:
+        assert rel(b.apply_A(setup.pt, setup.nz, tx).cpu(), ref) < 1e-12
+        assert rel(b.apply_A(setup.pt, setup.nz, tx, arith="f32").cpu(), ref) < 1e-5
+        assert rel(b.rhs(setup.pt, setup.nz, setup.t_d).cpu(), oracle.rhs(o, setup.noise, setup.d)) < 1e-12
+    finally:
+        setup.pt.detach_weights()
 
 
 def test_solve_fixed_iterations(setup):
