@@ -247,16 +247,12 @@ struct Angle {
 // chunk (wrap) a position up to lam1 = lambda - 1 before or after the chunk
 // holds the sample one chunk length away.  Returns false for none (zero):
 // positions further out never reach a valid output.
+// Branch-free (selects only), so that the loads it guards can be issued
+// unconditionally from a safe position and all of a batch stay in flight.
 __device__ __forceinline__ bool src_pos(int pos, int ilo, int ihi, bool wrap, int clen, int lam1, int& sp) {
-  sp = pos;
-  if (pos >= ilo && pos < ihi) return true;
-  if (!wrap) return false;
-  if (pos < ilo) {
-    sp = pos + clen;
-    return true;
-  }
-  sp = pos - clen;
-  return pos < ihi + lam1;
+  const bool in = pos >= ilo && pos < ihi;
+  sp = in ? pos : (pos < ilo ? pos + clen : pos - clen);
+  return in || (wrap && pos < ihi + lam1);
 }
 
 // Elements [kKeepW0, kKeepW1) of each thread (FP64 plan) hold most valid
@@ -298,18 +294,22 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
       for (int i = 0; i < 2 * GS; ++i) {
         const int pos = 2 * (tidp + T * (e0 + i / 2)) + (i & 1);
         const bool valid = pos >= vlo && pos < vhi;
+        const int posa = valid ? pos : vlo;  // a valid output: its loads are always in bounds
         int32_t k;
         if constexpr (kKeepK) k = valid ? kk[2 * e0 + i] : -1;
-        else k = valid ? skp[pos] : -1;
+        else {
+          const int32_t kr = skp[posa];
+          k = valid ? kr : -1;
+        }
         const int32_t rel = k - wlo;
         ks[i] = (k >= 0 && rel < nb && rel >= 0) ? rel : -1;
         const int e = e0 + i / 2;
         if (!kAng)
           ps[i] = A::zero();
         else if (kKeepW && e >= kKeepW0 && e < kKeepW1)
-          ps[i] = ks[i] >= 0 ? wk[2 * (e - kKeepW0) + (i & 1)] : A::zero();
+          ps[i] = wk[2 * (e - kKeepW0) + (i & 1)];
         else
-          ps[i] = ks[i] >= 0 ? A::load(ps0, w0, pos) : A::zero();
+          ps[i] = A::load(ps0, w0, posa);
       }
 #pragma unroll
       for (int i = 0; i < 2 * GS; ++i) {
@@ -390,7 +390,9 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
     for (int i = 0; i < 2 * E; ++i) {
       const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
       int sp;
-      kk[i] = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp) ? sk[sp] : -1;
+      const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+      const int32_t kr = sk[ok ? sp : ilo];  // ilo: inside the chunk, always in bounds
+      kk[i] = ok ? kr : -1;
     }
     int32_t amin = INT32_MAX, amax = -1;  // window of every kept sample (map staging)
 #pragma unroll
@@ -448,8 +450,8 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
       for (int i = 0; i < 2 * G; ++i) {
         const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
         int sp;
-        src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
-        ps[i] = (kAng && kk[2 * e0 + i] >= 0) ? A::load(ps0, w0, sp) : A::zero();
+        const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+        ps[i] = kAng ? A::load(ps0, w0, ok ? sp : ilo) : A::zero();
         if constexpr (kKeepW) {
           const int e = e0 + i / 2;
           if (e >= kKeepW0 && e < kKeepW1) wk[2 * (e - kKeepW0) + (i & 1)] = ps[i];
@@ -458,13 +460,13 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
         const int32_t k = kk[2 * e0 + i];
-        C val = C(0);
-        if (k >= 0) {
-          C c = C(0), s = C(0);
-          if constexpr (kAng) A::eval(ps[i], &c, &s);
-          const double* xk = staged ? xs + kXStride * (k - amin) : x + NC * (int64_t)k;
-          val = Stokes<NC>::project(xk, c, s);
-        }
+        // a masked sample reads some kept pixel (the window's first, else
+        // pixel 0: the operator runs only with kept pixels) and is zeroed
+        const int32_t ka = k >= 0 ? k : (amax >= amin ? amin : 0);
+        C c = C(0), s = C(0);
+        if constexpr (kAng) A::eval(ps[i], &c, &s);
+        const double* xk = staged ? xs + kXStride * (ka - amin) : x + NC * (int64_t)ka;
+        const C val = k >= 0 ? Stokes<NC>::project(xk, c, s) : C(0);
         cpx<C>& slot = v[slot_of<N, T, F::RIn>(e0 + i / 2)];
         if (i & 1) slot.y = val;
         else slot.x = val;
@@ -482,8 +484,13 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
         const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
         int sp;
         const bool in = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
-        if (kOut == 1) kt[i] = (pos >= ilo && pos < ihi && pos >= vlo && pos < vhi) ? sk[pos] : -1;
-        tv[i] = in ? tin[sp] : S(0);
+        if (kOut == 1) {
+          const bool v = pos >= ilo && pos < ihi && pos >= vlo && pos < vhi;
+          const int32_t kr = sk[v ? pos : ilo];
+          kt[i] = v ? kr : -1;
+        }
+        const S t = tin[in ? sp : ilo];
+        tv[i] = in ? t : S(0);
       }
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
@@ -583,9 +590,14 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
 #pragma unroll
   for (int i = 0; i < 2 * E; ++i) {
     const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
-    const bool fresh = !(have && i / 2 < kCarryElems);
     int sp;
-    kk[i] = (src_pos(pos, ilo, ihi, wrap, clen, vlo, sp) && fresh) ? sk[sp] : -1;
+    const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+    if (i / 2 < kCarryElems && have) {  // carried: uniform over the workgroup
+      kk[i] = -1;
+    } else {
+      const int32_t kr = sk[ok ? sp : ilo];
+      kk[i] = ok ? kr : -1;
+    }
   }
   int32_t kmin = INT32_MAX, kmax = -1, nmin = INT32_MAX, nmax = -1;
 #pragma unroll
@@ -627,18 +639,15 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
     for (int i = 0; i < 2 * G; ++i) {
       const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
       int sp;
-      src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
-      ps[i] = (kAng && kk[2 * e0 + i] >= 0) ? A::load(ps0, w0, sp) : A::zero();
+      const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+      ps[i] = kAng ? A::load(ps0, w0, ok ? sp : ilo) : A::zero();
     }
 #pragma unroll
     for (int i = 0; i < 2 * G; ++i) {
       const int32_t k = kk[2 * e0 + i];
-      C val = C(0);
-      if (k >= 0) {
-        C c = C(0), s = C(0);
-        if constexpr (kAng) A::eval(ps[i], &c, &s);
-        val = Stokes<NC>::project(x + NC * (int64_t)k, c, s);
-      }
+      C c = C(0), s = C(0);
+      if constexpr (kAng) A::eval(ps[i], &c, &s);
+      const C val = k >= 0 ? Stokes<NC>::project(x + NC * (int64_t)(k >= 0 ? k : 0), c, s) : C(0);
       if (i & 1) v[e0 + i / 2].y = val;
       else v[e0 + i / 2].x = val;
     }
@@ -880,6 +889,7 @@ int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const vo
 
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
                           double* q, int arith, const RhsBatch& rb, hipStream_t s, int32_t variant) {
+  if (pt->n_kept == 0) return MM_OK;  // nothing to gather or scatter (the kernels assume a kept pixel)
   if (x != nullptr) return dispatch<1, 1>(pt, nz, pt->dtype, arith, x, nullptr, nullptr, q, rb, s, variant);
   return dispatch<0, 1>(pt, nz, pt->dtype, arith, nullptr, tod, nullptr, q, rb, s, variant);
 }
