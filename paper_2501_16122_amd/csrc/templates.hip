@@ -127,15 +127,21 @@ __global__ __launch_bounds__(kTplThreads) void k_templates(
     S ang[kTplJ];
     cpx<S> cs[kTplJ];
     S tv[kTplJ];
+    // loads past the end of the interval read its last sample instead (in
+    // bounds, unconditional, then discarded)
 #pragma unroll
     for (int j = 0; j < kTplJ; ++j) {
       const int64_t i = i0 + tid + (int64_t)kTplThreads * j;
       const bool ok = i < n;
+      const int64_t t = a + (ok ? i : n - 1);
       kb[j] = -1;
-      if constexpr (kIn == 1 || kOut == 1) kb[j] = ok ? sample_k[a + i] : -1;
-      if constexpr (kAng && kW == 1) cs[j] = kb[j] >= 0 ? wts[a + i] : cpx<S>{S(0), S(0)};
-      if constexpr (kAng && kW == 0) ang[j] = kb[j] >= 0 ? psi[a + i] : S(0);
-      if constexpr (kIn == 0) tv[j] = ok ? tin[a + i] : S(0);
+      if constexpr (kIn == 1 || kOut == 1) {
+        const int32_t kr = sample_k[t];
+        kb[j] = ok ? kr : -1;
+      }
+      if constexpr (kAng && kW == 1) cs[j] = wts[t];
+      if constexpr (kAng && kW == 0) ang[j] = psi[t];
+      if constexpr (kIn == 0) tv[j] = tin[t];
     }
 #pragma unroll
     for (int j = 0; j < kTplJ; ++j) {
@@ -148,8 +154,13 @@ __global__ __launch_bounds__(kTplThreads) void k_templates(
         if (kb[j] >= 0) sincos2<C>(ang[j], &c, &sn);
       cb[j] = c;
       sb[j] = sn;
-      if constexpr (kIn == 1) yb[j] = kb[j] >= 0 ? Stokes<NC>::project(x + NC * (int64_t)kb[j], c, sn) : C(0);
-      else yb[j] = C(tv[j]);
+      if constexpr (kIn == 1) {
+        // masked samples read pixel 0 (the operator runs only with kept pixels) and are zeroed
+        const C yv = Stokes<NC>::project(x + NC * (int64_t)(kb[j] >= 0 ? kb[j] : 0), c, sn);
+        yb[j] = kb[j] >= 0 ? yv : C(0);
+      } else {
+        yb[j] = (i0 + tid + (int64_t)kTplThreads * j) < n ? C(tv[j]) : C(0);
+      }
     }
   };
 
@@ -304,6 +315,7 @@ int launch_nc(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, co
 
 int launch_fused_templates(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
                            double* q, int arith, const RhsBatch& rb, hipStream_t s) {
+  if (pt->n_kept == 0) return MM_OK;  // nothing to gather or scatter (the kernel assumes a kept pixel)
   return by_ncomp(pt->ncomp, [&]<int NC>() -> int {
     if (x != nullptr) return launch_nc<NC, 1, 1>(pt, nz, x, nullptr, nullptr, q, arith, rb, s);
     return launch_nc<NC, 0, 1>(pt, nz, nullptr, tod, nullptr, q, arith, rb, s);
