@@ -127,23 +127,29 @@ __device__ __forceinline__ void fused_white_tile(const PtTile& tl, const int32_t
   const C w = C(det_w[tl.det]);
   int32_t kv[J];
   double v[J][NC];
+  // index and angle loads first, all unconditional from in-bounds positions
+  // (past the tile's end: its first sample), so that they stay in flight
+  // together; masked samples gather the tile's first kept pixel and are dropped
+  S ang[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int i = threadIdx.x + kOpThreads * j;
-    kv[j] = -1;
+    const int64_t t = tl.start + (i < tl.len ? i : 0);
+    const int32_t k = sample_k[t];
+    kv[j] = i < tl.len ? k : -1;
+    if constexpr (Stokes<NC>::kAngle) ang[j] = psi[t];
+  }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) v[j][c] = 0.0;
-    if (i < tl.len) {
-      const int64_t t = tl.start + i;
-      const int32_t k = sample_k[t];
-      if (k >= 0) {
-        C c, s;
-        angle<NC>(psi, t, &c, &s);
-        const C z = w * Stokes<NC>::project(x + NC * (int64_t)k, c, s);
-        kv[j] = k - tl.kmin;
-        Stokes<NC>::terms(z, c, s, v[j]);
-      }
-    }
+  for (int j = 0; j < J; ++j) {
+    const int32_t k = kv[j];
+    C c = C(0), s = C(0);
+    if constexpr (Stokes<NC>::kAngle) sincos2<C>(ang[j], &c, &s);
+    const C z = w * Stokes<NC>::project(x + NC * (int64_t)(k >= 0 ? k : tl.kmin), c, s);
+    double o[NC];
+    Stokes<NC>::terms(z, c, s, o);
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) v[j][cc] = k >= 0 ? o[cc] : 0.0;
+    kv[j] = k >= 0 ? k - tl.kmin : -1;
   }
   const int span = tl.kmax - tl.kmin + 1;
   for (int lo = 0; lo < span; lo += kBinSlots) {
