@@ -78,6 +78,23 @@ def stored_traffic():
     return c.get("hbm_bytes_per_launch")
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    """HBM bandwidth a plain device copy reaches (read + write bytes per
+    second), the measured counterpart of the nominal peak."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    return round(gbs, 1)
+
+
 def cpu_baseline(w, pix, psi, d, n_det_sample):
     """The FP64 oracle on the first n_det_sample detectors of the same
     workload, single process: build + per-iteration time of A = P^T N^-1 P."""
@@ -574,7 +591,8 @@ def main():
             if w.toeplitz else "k_fused_white<double,double>",
             "kernel_ms_avg": round(kernel_ms, 4), "launches": op_n,
             "op_variant": infos[-1]["op_variant"],
-            "algorithmic_bytes_per_launch": alg_bytes}
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "measured_copy_gbs": copy_bandwidth(torch, dev)}
     if w.toeplitz:
         flops = fft_flops_per_launch(w)
         tf = flops / (kernel_ms * 1e-3) / 1e12
