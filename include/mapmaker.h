@@ -326,6 +326,23 @@ int mm_solver_poll(mm_solver_t sv, int32_t* done, int32_t* in_flight, mm_solve_i
 int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_info* info, double* history_host,
                      int32_t history_len);
 
+/* Checkpoint and resume (the solver state of the a9/a10 rows: preempting a
+ * resumable solve to free its workspace, or resuming it elsewhere).
+ * mm_solver_snapshot_size: bytes of a snapshot (a small header plus the
+ * solver's share of its workspace).  mm_solver_snapshot (blocking: waits
+ * for the solver's stream) copies the state after the last enqueued step
+ * into dst, host or device memory, `bytes` >= the size (else MM_ENOSPC).
+ * mm_solver_restore (blocking) overwrites the state of `sv` with a
+ * snapshot; sv must have been created for the same problem: the same
+ * pointing sizes, map form, dtype, number of right-hand sides and options
+ * (MM_EINVAL otherwise).  The restored solve continues with mm_solver_step
+ * and ends with mm_solver_finish as if it had never stopped, up to the
+ * rounding order of floating-point atomics.  Timing statistics are not
+ * part of a snapshot. */
+int mm_solver_snapshot_size(mm_solver_t sv, size_t* bytes);
+int mm_solver_snapshot(mm_solver_t sv, void* dst, size_t bytes);
+int mm_solver_restore(mm_solver_t sv, const void* src, size_t bytes);
+
 /* Free the host side (pinned state copy, events); the caller frees the workspace. */
 int mm_solver_destroy(mm_solver_t sv);
 

@@ -85,6 +85,9 @@ SIGNATURES = {
     "mm_solver_step": (_c.c_int, [_vp, _i32]),
     "mm_solver_poll": (_c.c_int, [_vp, _pi32, _pi32, _c.POINTER(SolveInfo)]),
     "mm_solver_finish": (_c.c_int, [_vp, _vp, _vp, _c.POINTER(SolveInfo), _pf64, _i32]),
+    "mm_solver_snapshot_size": (_c.c_int, [_vp, _psz]),
+    "mm_solver_snapshot": (_c.c_int, [_vp, _vp, _sz]),
+    "mm_solver_restore": (_c.c_int, [_vp, _vp, _sz]),
     "mm_solver_destroy": (_c.c_int, [_vp]),
     "mm_batch_step": (_c.c_int, [_c.POINTER(_vp), _i32, _i32]),
 }
@@ -545,6 +548,21 @@ class AsyncSolver:
             i0 = out["info"][0]
             out["history"] = hist[: (i0["outer_iters"] + 1 if self.opts.mixed else i0["iters"] + 1)]
         return out
+
+    def snapshot(self, device=None):
+        """The solve's state after the last step, as a uint8 tensor (host
+        memory unless a device is given); blocks until the stream is idle."""
+        torch = _torch()
+        sz = _c.c_size_t()
+        _check(load().mm_solver_snapshot_size(self.handle, _c.byref(sz)))
+        buf = torch.empty(sz.value, dtype=torch.uint8, device=device if device is not None else "cpu")
+        _check(load().mm_solver_snapshot(self.handle, _ptr(buf), sz.value))
+        return buf
+
+    def restore(self, buf):
+        """Continue from a snapshot of a solve of the same problem."""
+        _check(load().mm_solver_restore(self.handle, _ptr(buf), buf.numel()))
+        self.done = False
 
     def close(self):
         if getattr(self, "handle", None):

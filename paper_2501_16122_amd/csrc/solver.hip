@@ -93,6 +93,8 @@ struct mm_solver_s {
   int32_t variant = 0;         // band-Toeplitz operator variant
   bool outer_pending = false;  // the last poll saw a finished inner solve
   bool step_pending = false;   // a state copy is in flight
+  void* ws = nullptr;          // the caller's workspace and the bytes the solver uses of it
+  size_t ws_used = 0;
   hipEvent_t ev = nullptr;
   PcgState* h_st = nullptr;    // pinned mirrors
   OuterState* h_os = nullptr;
@@ -346,6 +348,8 @@ int mm_solver_create(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const void*
   sv->os.assign(n_rhs, OuterState{});
   Carver cv(workspace, ws_bytes);
   carve(cv, pt->n_kept, pt->ncomp, n_rhs, o, &sv->L);
+  sv->ws = workspace;
+  sv->ws_used = cv.used;
   auto bail = [&](int rc) {
     delete sv;
     return rc;
@@ -450,6 +454,86 @@ int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_i
   }
   if (breakdown) return fail(MM_EBREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite value)");
   if (!converged && !(sv->o.fixed_iter > 0 && !sv->mixed)) return MM_NOTCONVERGED;
+  return MM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Snapshot layout: this header, then the solver's workspace bytes.  The
+// workspace holds no pointers (only vectors and scalar state), so a
+// snapshot restores into any solver created for the same problem.
+struct SnapHeader {
+  uint64_t magic;
+  int32_t version, nrhs, mixed, variant, outer_pending, ncomp, dtype, pad_;
+  int64_t n3, n_kept, n_samples, ws_used;
+};
+constexpr uint64_t kSnapMagic = 0x4d4d534e41503031ull;  // "MMSNAP01"
+
+SnapHeader snap_header(const mm_solver_s* sv) {
+  SnapHeader h{};
+  h.magic = kSnapMagic;
+  h.version = 1;
+  h.nrhs = sv->nrhs;
+  h.mixed = sv->mixed ? 1 : 0;
+  h.variant = sv->variant;
+  h.outer_pending = sv->outer_pending ? 1 : 0;
+  h.ncomp = sv->pt->ncomp;
+  h.dtype = sv->pt->dtype;
+  h.n3 = sv->n3;
+  h.n_kept = sv->pt->n_kept;
+  h.n_samples = sv->pt->n_samples;
+  h.ws_used = (int64_t)sv->ws_used;
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mm_solver_snapshot_size(mm_solver_t sv, size_t* bytes) {
+  if (!sv || !bytes) return fail(MM_EINVAL, "bad snapshot size query");
+  *bytes = sizeof(SnapHeader) + sv->ws_used;
+  return MM_OK;
+}
+
+int mm_solver_snapshot(mm_solver_t sv, void* dst, size_t bytes) {
+  if (!sv || !dst) return fail(MM_EINVAL, "bad snapshot arguments");
+  if (bytes < sizeof(SnapHeader) + sv->ws_used) return fail(MM_ENOSPC, "snapshot buffer too small");
+  MM_HIP(hipStreamSynchronize(sv->s));  // no step in flight
+  int32_t done = 0;
+  if (int rc = sv->poll(&done)) return rc;  // land the last state copy (outer_pending)
+  const SnapHeader h = snap_header(sv);
+  char* d = static_cast<char*>(dst);
+  MM_HIP(hipMemcpy(d, &h, sizeof(h), hipMemcpyDefault));
+  MM_HIP(hipMemcpy(d + sizeof(h), sv->ws, sv->ws_used, hipMemcpyDefault));
+  return MM_OK;
+}
+
+int mm_solver_restore(mm_solver_t sv, const void* src, size_t bytes) {
+  if (!sv || !src || bytes < sizeof(SnapHeader)) return fail(MM_EINVAL, "bad restore arguments");
+  SnapHeader h{};
+  MM_HIP(hipStreamSynchronize(sv->s));
+  MM_HIP(hipMemcpy(&h, src, sizeof(h), hipMemcpyDefault));
+  const SnapHeader mine = snap_header(sv);
+  if (h.magic != kSnapMagic || h.version != 1) return fail(MM_EINVAL, "not a solver snapshot");
+  if (h.nrhs != mine.nrhs || h.mixed != mine.mixed || h.ncomp != mine.ncomp || h.dtype != mine.dtype ||
+      h.n3 != mine.n3 || h.n_kept != mine.n_kept || h.n_samples != mine.n_samples || h.ws_used != mine.ws_used)
+    return fail(MM_EINVAL, "snapshot of a different problem (sizes, right-hand sides, form, dtype or options)");
+  if (bytes < sizeof(SnapHeader) + (size_t)h.ws_used) return fail(MM_EINVAL, "truncated snapshot");
+  MM_HIP(hipMemcpy(sv->ws, static_cast<const char*>(src) + sizeof(h), sv->ws_used, hipMemcpyDefault));
+  sv->variant = h.variant;
+  sv->outer_pending = h.outer_pending != 0;
+  sv->tev_used = 0;
+  // refresh the host mirrors from the restored device state
+  if (int rc = sv->record_state()) return rc;
+  MM_HIP(hipStreamSynchronize(sv->s));
+  const bool pending = sv->outer_pending;
+  int32_t done = 0;
+  if (int rc = sv->poll(&done)) return rc;
+  sv->outer_pending = sv->outer_pending || pending;
+  sv->work_seen = sv->work_total();
   return MM_OK;
 }
 

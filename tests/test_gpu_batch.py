@@ -149,3 +149,54 @@ def test_batch_rejects_bad_groups():
     torch.cuda.synchronize()
     for s in (s64, s32, s_other, many):
         s.close()
+
+
+def _run(s, max_steps=400):
+    for _ in range(max_steps):
+        s.step()
+        s.stream.synchronize()
+        if s.poll()[0]:
+            break
+    out = s.finish()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_snapshot_and_restore_resume_the_solve(mixed):
+    # stop a solve midway, snapshot it (to host and to device memory), resume
+    # it in fresh solvers of the same problem: the same map as uninterrupted
+    b = _b()
+    w = synth.Workload("snap_128x128_3x70000", 971, 128, 128, 3, 70000, t_psi=900.0, noise="oneoverf",
+                       chunk=30000, lam=256, precision="f32" if mixed else "f64")
+    pix, psi = synth.pointing(w)
+    psi = synth.storage(w, psi)
+    offs, wdet = synth.det_offsets(w), synth.det_weight(w)
+    pt = b.Pointing(torch.from_numpy(pix).to(DEV), torch.from_numpy(psi).to(DEV), offs, wdet, w.n_pix)
+    pt.attach_weights()
+    nz = b.Noise.toeplitz(synth.toeplitz_coeff(w), synth.chunk_offsets(w), DEV)
+    opt = oracle.build_pointing(pix, psi, offs, wdet, w.n_pix)
+    d = synth.storage(w, oracle.apply_P(opt, synth.sky(w)[opt.kept].reshape(-1)) + synth.noise(w))
+    td = torch.from_numpy(d).to(DEV)
+    opts = dict(tol=1e-10, check_every=4, mixed=mixed)
+    ref = _run(b.AsyncSolver(pt, nz, td, **opts))
+    a = b.AsyncSolver(pt, nz, td, **opts)
+    for _ in range(3):
+        a.step()
+    snap_h = a.snapshot()
+    snap_d = a.snapshot(device=DEV)
+    assert snap_h.device.type == "cpu" and snap_d.is_cuda
+    a.close()
+    for snap in (snap_h, snap_d):
+        s = b.AsyncSolver(pt, nz, td, **opts)
+        s.restore(snap)
+        out = _run(s)
+        assert out["info"][0]["converged"] == 1
+        assert out["info"][0]["iters"] == ref["info"][0]["iters"]
+        err = oracle.rel_l2_per_stokes(out["x"][0].cpu().numpy(), ref["x"][0].cpu().numpy())
+        assert np.all(err < 1e-9), err
+    # a snapshot does not restore into a different problem
+    other = b.AsyncSolver(pt, nz, torch.stack([td, td]).contiguous(), **opts)
+    with pytest.raises(b.MapMakerError):
+        other.restore(snap_h)
+    other.close()
