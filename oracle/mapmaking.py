@@ -385,9 +385,9 @@ def pcg(apply_a, apply_m, b, tol=1e-10, max_iter=2000, fixed_iters=None, x0=None
     """
     b = np.asarray(b, dtype=np.float64)
     bnorm = float(np.linalg.norm(b))
+    if bnorm == 0.0:  # A x = 0 with A SPD: x = 0, whatever the start
+        return np.zeros_like(b), PCGInfo(0, True, False, 0.0, 0.0, [0.0])
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
-    if bnorm == 0.0:
-        return x, PCGInfo(0, True, False, 0.0, 0.0, [0.0])
     r = b - apply_a(x) if x0 is not None else b.copy()
     z = apply_m(r)
     p = z.copy()

@@ -392,6 +392,27 @@ def test_pcg_finite_termination():
     assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-8)
 
 
+def test_pcg_start_vector():
+    # from x0 the residual starts at b - A x0: at the solution the solve stops
+    # at once; from another start the iterates are scipy's CG from that start
+    rng = np.random.default_rng(13)
+    n = 12
+    Q = rng.normal(size=(n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.normal(size=n)
+    xs = np.linalg.solve(A, b)
+    x, info = oracle.pcg(lambda v: A @ v, lambda v: v, b, tol=1e-10, x0=xs)
+    assert info.iters == 0 and info.converged and np.array_equal(x, xs)
+    x0 = rng.normal(size=n)
+    for k in (1, 3, 6):
+        x, info = oracle.pcg(lambda v: A @ v, lambda v: v, b, fixed_iters=k, x0=x0)
+        xc, _ = scipy.sparse.linalg.cg(A, b, x0=x0, rtol=0.0, atol=0.0, maxiter=k)
+        assert np.allclose(x, xc, rtol=1e-11, atol=1e-13)
+        assert info.history[0] == pytest.approx(np.linalg.norm(b - A @ x0) / np.linalg.norm(b), rel=1e-14)
+    x, info = oracle.pcg(lambda v: A @ v, lambda v: v, np.zeros(n), x0=x0)
+    assert info.iters == 0 and np.all(x == 0)
+
+
 def test_binned_config1_mask_margin():
     # the keep/mask decision of the smallest headline configuration does not
     # hang on rounding (margin in decades to cond = 1e3)
