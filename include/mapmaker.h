@@ -76,7 +76,7 @@ typedef struct mm_noise_s* mm_noise_t;
 /* Message of the last failing call on this thread ("" if none). */
 const char* mm_last_error(void);
 
-/* ABI revision of this header (bumped on incompatible change): 3. */
+/* ABI revision of this header (bumped on incompatible change): 4. */
 int mm_abi_version(void);
 
 /* ------------------------------------------------------------------------
@@ -259,6 +259,9 @@ typedef struct {
                            runs that carry the overlapping half-window from tile to tile
                            (needs stored pointing weights; never stages)                    */
   int32_t reserved_;
+  const double* x0;     /* start vector (device, f64[n_rhs][nc * n_kept]) or NULL for x0 = 0;
+                           the residual starts at b - A x0 (FP64), the mixed form refines from
+                           x0; the solve's outputs do not alias it                           */
 } mm_solve_opts;
 
 typedef struct {

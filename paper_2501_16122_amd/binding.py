@@ -33,7 +33,7 @@ _psz = _c.POINTER(_c.c_size_t)
 class SolveOpts(_c.Structure):
     _fields_ = [("tol", _f64), ("max_iter", _i32), ("fixed_iter", _i32), ("check_every", _i32),
                 ("mixed", _i32), ("max_outer", _i32), ("inner_tol", _f64), ("timing", _i32),
-                ("autotune", _i32), ("op_variant", _i32), ("reserved_", _i32)]
+                ("autotune", _i32), ("op_variant", _i32), ("reserved_", _i32), ("x0", _vp)]
 
 
 class SolveInfo(_c.Structure):
@@ -463,10 +463,14 @@ class Solver:
         self.workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=pt.device)
         self.hist_len = max(self.opts.max_iter, self.opts.fixed_iter, self.opts.max_outer) + 1
 
-    def solve(self, tod, map_out=None, x_out=None, stream=None, history=False):
+    def solve(self, tod, map_out=None, x_out=None, stream=None, history=False, x0=None):
+        """x0: optional start vector (f64[nc * n_kept] device tensor)."""
         torch = _torch()
         pt = self.pt
         _tod(pt, tod, "tod")
+        if x0 is not None:
+            _vec(pt, x0, "x0")
+        self.opts.x0 = None if x0 is None else x0.data_ptr()
         if map_out is None:
             map_out = torch.empty(pt.ncomp * pt.n_pix, dtype=torch.float64, device=pt.device)
         if x_out is None:
@@ -499,13 +503,17 @@ class AsyncSolver:
     timeline) sharing ``pt`` and ``nz``; advanced by ``step`` on its own
     stream, polled without blocking, finished by ``finish``."""
 
-    def __init__(self, pt: Pointing, nz: Noise, tod, stream=None, **opts):
+    def __init__(self, pt: Pointing, nz: Noise, tod, stream=None, x0=None, **opts):
         torch = _torch()
         lib = load()
         self.pt, self.nz = pt, nz
         self.n_rhs = 1 if tod.dim() == 1 else tod.shape[0]
         _dev_check(tod, pt.tod_dtype, self.n_rhs * pt.n_samples, "tod")
         self.opts = solve_opts(**opts)
+        if x0 is not None:  # start vector(s), read on the solver's stream at creation
+            _dev_check(x0, torch.float64, self.n_rhs * pt.ncomp * pt.n_kept, "x0")
+            self.opts.x0 = x0.data_ptr()
+        self._x0 = x0
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         sz = _c.c_size_t()
         _check(lib.mm_solver_workspace_size(pt.handle, nz.handle, self.n_rhs, _c.byref(self.opts), _c.byref(sz)))

@@ -165,7 +165,7 @@ extern "C" {
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
 
-int mm_abi_version(void) { return 3; }
+int mm_abi_version(void) { return 4; }
 
 int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, size_t* bytes) {
   if (!bytes || n_samples < 0 || n_det <= 0 || n_pix <= 0) return fail(MM_EINVAL, "bad pointing sizes");

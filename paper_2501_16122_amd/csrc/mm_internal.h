@@ -350,12 +350,15 @@ static_assert(sizeof(OpBatch) <= 2048, "operator batch must stay a small kernel 
 int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, int ncomp, hipStream_t s);
 int launch_white_batch(const OpBatch& b, int dtype, int arith, int ncomp, hipStream_t s);
 
+// from_x0: start from the x already in place, with A x0 in q and
+// ||b - A x0||^2, ||b||^2 in each state's scratch0/scratch1 (launch_diff_norm)
 int launch_pcg_init(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, double tol, int32_t max_iter,
-                    int32_t fixed_iter, const OuterState* gate, hipStream_t s);
+                    int32_t fixed_iter, const OuterState* gate, hipStream_t s, bool from_x0 = false);
 int launch_pcg_iteration_tail(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, hipStream_t s);
 // per right-hand side: st->scratch0 = ||x - y||^2, st->scratch1 = ||x||^2
 int launch_diff_norm(const PcgArgs& a, int nrhs, const double* x, const double* y, hipStream_t s);
-int launch_outer_init(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s);
+// from_x0: start from the xt already in place, with A64 xt in the inner q
+int launch_outer_init(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s, bool from_x0 = false);
 int launch_outer_add(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s);
 int launch_outer_end(const OuterArgs& o, const PcgArgs& a, int nrhs, double tol, int32_t max_outer, hipStream_t s);
 

@@ -126,47 +126,57 @@ __device__ __forceinline__ OSlice oslice(const OuterArgs& o, int y) {
 // ---- bodies (one right-hand side each) ------------------------------------
 
 // x = 0, r = b, z = M r, p = z, q = 0, rho = r.z, ||b||.  Skipped while the
-// gate (outer state) is done or has no step pending.
+// gate (outer state) is done or has no step pending.  From a start vector
+// (from_x0): x already holds x0 and q holds A x0, so r = b - A x0 (x is
+// reset to 0 when b = 0, whose solution is 0).
 template <int NC>
-__device__ __forceinline__ void pcg_init_sums(const Slice& S, const double* __restrict__ minv, double& bb,
-                                              double& rz) {
+__device__ __forceinline__ void pcg_init_sums(const Slice& S, const double* __restrict__ minv, bool from_x0,
+                                              bool zero_b, double& bb, double& rz) {
   constexpr int NB = NC * (NC + 1) / 2;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
-    double bv[NC], zv[NC];
+    double bv[NC], rv[NC], zv[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) bv[c] = S.b[NC * k + c];
-    apply_m<NC>(minv + NB * k, bv, zv);
+    for (int c = 0; c < NC; ++c) {
+      bv[c] = S.b[NC * k + c];
+      rv[c] = from_x0 ? bv[c] - S.q[NC * k + c] : bv[c];
+    }
+    apply_m<NC>(minv + NB * k, rv, zv);
     double sb = 0.0, sz = 0.0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int64_t i = NC * k + c;
-      S.x[i] = 0.0;
-      S.r[i] = bv[c];
+      if (!from_x0 || zero_b) S.x[i] = 0.0;
+      S.r[i] = rv[c];
       S.z[i] = zv[c];
       S.p[i] = zv[c];
       S.q[i] = 0.0;
       sb += bv[c] * bv[c];
-      sz += bv[c] * zv[c];
+      sz += rv[c] * zv[c];
     }
     bb += sb;
     rz += sz;
   }
 }
 
+// from_x0: st->scratch0 = ||b - A x0||^2 and st->scratch1 = ||b||^2 were
+// computed beforehand (launch_diff_norm).
 __device__ __forceinline__ void pcg_init_body(const Slice& S, const double* __restrict__ minv, double tol,
-                                              int32_t max_iter, int32_t fixed_iter, const OuterState* gate) {
+                                              int32_t max_iter, int32_t fixed_iter, const OuterState* gate,
+                                              bool from_x0 = false) {
   if (gate != nullptr && (gate->done || gate->skip)) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   double bb = 0.0, rz = 0.0;
-  if (S.ncomp == 3) pcg_init_sums<3>(S, minv, bb, rz);
-  else if (S.ncomp == 2) pcg_init_sums<2>(S, minv, bb, rz);
-  else pcg_init_sums<1>(S, minv, bb, rz);
+  const double r0 = from_x0 ? S.st->scratch0 : 0.0, b0 = from_x0 ? S.st->scratch1 : 0.0;
+  const bool zero_b = from_x0 && !(b0 > 0.0);
+  if (S.ncomp == 3) pcg_init_sums<3>(S, minv, from_x0, zero_b, bb, rz);
+  else if (S.ncomp == 2) pcg_init_sums<2>(S, minv, from_x0, zero_b, bb, rz);
+  else pcg_init_sums<1>(S, minv, from_x0, zero_b, bb, rz);
   if (!grid_sum2(bb, rz, S.partials, &S.st->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
     PcgState* st = S.st;
     const double bnorm = sqrt(bb);
-    const double rel = bnorm > 0.0 ? 1.0 : 0.0;
+    const double rel = bnorm > 0.0 ? (from_x0 ? sqrt(r0) / bnorm : 1.0) : 0.0;
     st->rho = rz;
     st->alpha = 0.0;
     st->beta = 0.0;
@@ -280,8 +290,11 @@ __device__ __forceinline__ void pcg_direction_body(const Slice& S) {
 
 // ---- outer FP64 refinement ------------------------------------------------
 // init: xt = 0, rt = b64, ||b64||; the inner state starts "done" so that
-// nothing runs until the first inner solve is initialised.
-__device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S) {
+// nothing runs until the first inner solve is initialised.  From a start
+// vector (from_x0): xt already holds x0, q holds A64 x0 and the inner
+// scratch1 ||b64||^2, so rt = b64 - A64 x0; ||rt||^2 (sum 2) gives the
+// starting residual.
+__device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S, bool from_x0 = false) {
   __shared__ double sh[16];
   __shared__ bool s_last;
   const int64_t n3 = S.n;
@@ -290,18 +303,22 @@ __device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S)
     S.st->iter = 0;
     S.st->breakdown = 0;
   }
-  double bb = 0.0, unused = 0.0;
+  // with b64 = 0 (||b64||^2 in the inner scratch1, see launch_diff_norm) the solution is 0
+  const bool zero_b = from_x0 && !(S.st->scratch1 > 0.0);
+  double bb = 0.0, rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += (int64_t)gridDim.x * blockDim.x) {
     const double v = O.b64[i];
-    O.xt[i] = 0.0;
-    O.rt[i] = v;
+    const double r = from_x0 && !zero_b ? v - S.q[i] : v;
+    if (!from_x0 || zero_b) O.xt[i] = 0.0;
+    O.rt[i] = r;
     bb += v * v;
+    rr += r * r;
   }
-  if (!grid_sum2(bb, unused, O.partials, &O.os->counter, sh, &s_last)) return;
+  if (!grid_sum2(bb, rr, O.partials, &O.os->counter, sh, &s_last)) return;
   if (threadIdx.x == 0) {
     OuterState* os = O.os;
     os->bnorm = sqrt(bb);
-    os->rel = os->bnorm > 0.0 ? 1.0 : 0.0;
+    os->rel = os->bnorm > 0.0 ? (from_x0 ? sqrt(rr) / os->bnorm : 1.0) : 0.0;
     os->iters = 0;
     os->inner_total = 0;
     os->converged = os->bnorm == 0.0 ? 1 : 0;
@@ -369,8 +386,9 @@ __device__ __forceinline__ void outer_end_body(const OSlice& O, const Slice& S, 
 
 __global__ __launch_bounds__(kPcgThreads) void k_pcg_init(PcgArgs a, const double* __restrict__ minv, double tol,
                                                           int32_t max_iter, int32_t fixed_iter,
-                                                          const OuterState* gate) {
-  pcg_init_body(slice(a, blockIdx.y), minv, tol, max_iter, fixed_iter, gate ? gate + blockIdx.y : nullptr);
+                                                          const OuterState* gate, int32_t from_x0) {
+  pcg_init_body(slice(a, blockIdx.y), minv, tol, max_iter, fixed_iter, gate ? gate + blockIdx.y : nullptr,
+                from_x0 != 0);
 }
 
 __global__ __launch_bounds__(kPcgThreads) void k_pcg_alpha(PcgArgs a) { pcg_alpha_body(slice(a, blockIdx.y)); }
@@ -383,8 +401,8 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_direction(PcgArgs a) {
   pcg_direction_body(slice(a, blockIdx.y));
 }
 
-__global__ __launch_bounds__(kPcgThreads) void k_outer_init(OuterArgs o, PcgArgs a) {
-  outer_init_body(oslice(o, blockIdx.y), slice(a, blockIdx.y));
+__global__ __launch_bounds__(kPcgThreads) void k_outer_init(OuterArgs o, PcgArgs a, int32_t from_x0) {
+  outer_init_body(oslice(o, blockIdx.y), slice(a, blockIdx.y), from_x0 != 0);
 }
 
 __global__ __launch_bounds__(kPcgThreads) void k_outer_add(OuterArgs o, PcgArgs a) {
@@ -446,9 +464,9 @@ __global__ __launch_bounds__(kPcgThreads) void k_diff_norm(PcgArgs A, const doub
 }  // namespace
 
 int launch_pcg_init(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, double tol, int32_t max_iter,
-                    int32_t fixed_iter, const OuterState* gate, hipStream_t s) {
+                    int32_t fixed_iter, const OuterState* gate, hipStream_t s, bool from_x0) {
   hipLaunchKernelGGL(k_pcg_init, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a, pt->minv, tol, max_iter,
-                     fixed_iter, gate);
+                     fixed_iter, gate, (int32_t)from_x0);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
@@ -467,8 +485,8 @@ int launch_diff_norm(const PcgArgs& a, int nrhs, const double* x, const double* 
   return MM_OK;
 }
 
-int launch_outer_init(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_init, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, o, a);
+int launch_outer_init(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s, bool from_x0) {
+  hipLaunchKernelGGL(k_outer_init, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, o, a, (int32_t)from_x0);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }

@@ -300,6 +300,7 @@ int mm_solve_opts_default(mm_solve_opts* o) {
   o->autotune = 0;
   o->op_variant = 0;
   o->reserved_ = 0;
+  o->x0 = nullptr;
   return MM_OK;
 }
 
@@ -373,13 +374,26 @@ int mm_solver_create(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const void*
     const char* t = static_cast<const char*>(tod) + (size_t)r * esz * (size_t)pt->n_samples;
     if (int rc = rhs_impl(pt, nz, t, rhs_dst + r * sv->n3, MM_F64, sv->s)) return bail(rc);
   }
+  const bool from_x0 = o.x0 != nullptr;
+  if (from_x0) {
+    // start vector: x (FP64 solve) or xt (outer FP64 refinement) = x0, and
+    // q = A64 x0 in FP64 arithmetic; then ||b - A x0||^2, ||b||^2
+    double* xs = sv->mixed ? sv->L.O.xt : sv->L.A.x;
+    MM_HIP(hipMemcpyAsync(xs, o.x0, sizeof(double) * sv->n3 * n_rhs, hipMemcpyDeviceToDevice, sv->s));
+    if (int rc = launch_fill(sv->L.A.q, sv->n3 * n_rhs, 0.0, sv->s)) return bail(rc);
+    RhsBatch rb;
+    rb.nrhs = n_rhs;
+    rb.vstride = sv->n3;
+    if (int rc = apply_A_impl(pt, nz, xs, sv->L.A.q, MM_F64, rb, sv->s, o.op_variant)) return bail(rc);
+    if (int rc = launch_diff_norm(sv->L.A, n_rhs, rhs_dst, sv->L.A.q, sv->s)) return bail(rc);
+  }
   if (sv->mixed) {
     sv->L.A.b = sv->L.O.rt;  // inner solves run on the outer residual
-    if (int rc = launch_outer_init(sv->L.O, sv->L.A, n_rhs, sv->s)) return bail(rc);
+    if (int rc = launch_outer_init(sv->L.O, sv->L.A, n_rhs, sv->s, from_x0)) return bail(rc);
     if (int rc = launch_pcg_init(pt, sv->L.A, n_rhs, o.inner_tol, o.max_iter, 0, sv->L.O.os, sv->s))
       return bail(rc);
   } else {
-    if (int rc = launch_pcg_init(pt, sv->L.A, n_rhs, o.tol, o.max_iter, o.fixed_iter, nullptr, sv->s))
+    if (int rc = launch_pcg_init(pt, sv->L.A, n_rhs, o.tol, o.max_iter, o.fixed_iter, nullptr, sv->s, from_x0))
       return bail(rc);
   }
   sv->variant = o.op_variant;

@@ -39,7 +39,7 @@ def test_binding_covers_every_declared_symbol():
 @pytest.mark.skipif(not os.path.exists(binding.LIB_PATH), reason="library not built")
 def test_host_only_calls():
     lib = binding.load()
-    assert lib.mm_abi_version() == 3
+    assert lib.mm_abi_version() == 4
     sz = ctypes.c_size_t()
     assert lib.mm_pointing_workspace_size(1 << 20, 4, 4096, ctypes.byref(sz)) == 0
     assert sz.value > 4 * (1 << 20)

@@ -264,3 +264,44 @@ def test_carry_variant_mixed_precision():
     _, _, x_ref = oracle.solve(opt, noise, ds[0].astype(np.float64), tol=1e-13)
     err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref)
     assert np.all(err < 1e-9), err
+
+
+@pytest.mark.parametrize("white", [False, True])
+def test_start_vector_matches_oracle(white):
+    # PCG from a start vector x0: the same iterates as the oracle's from x0;
+    # started at the solution the solve stops at once; the mixed form refines
+    # from x0; several right-hand sides each start from their own x0
+    b = _b()
+    w = SMALL_T.replace(noise="white", chunk=0, lam=0) if white else SMALL_T
+    pt, nz, opt, noise, ds = _device_problem(w, n_rhs=2)
+    td = torch.from_numpy(ds[0]).to(DEV)
+    rng = np.random.default_rng(31)
+    x0 = rng.normal(size=3 * opt.n_kept)
+    tx0 = torch.from_numpy(x0).to(DEV)
+    k = 1 if white else 12  # white: M = A^-1, one iteration reaches the solution
+    out = b.Solver(pt, nz, fixed_iter=k, tol=0.0).solve(td, x0=tx0)
+    bb = oracle.rhs(opt, noise, ds[0])
+    x_ref, info = oracle.pcg(lambda v: oracle.apply_A(opt, noise, v), lambda v: oracle.apply_M(opt, v), bb,
+                             fixed_iters=k, x0=x0)
+    assert np.all(oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref) < 1e-10)
+    conv = b.Solver(pt, nz, tol=1e-11).solve(td)
+    again = b.Solver(pt, nz, tol=1e-10).solve(td, x0=conv["x"].clone())
+    assert again["info"]["iters"] == 0 and again["info"]["converged"] == 1
+    assert torch.equal(again["x"], conv["x"])
+    mixed = b.Solver(pt, nz, tol=1e-10, mixed=1).solve(td, x0=tx0)
+    assert mixed["info"]["converged"] == 1 and mixed["info"]["true_rel_resid"] <= 1e-10
+    assert np.all(oracle.rel_l2_per_stokes(mixed["x"].cpu().numpy(), conv["x"].cpu().numpy()) < 1e-7)
+    # two right-hand sides, two start vectors
+    X0 = torch.stack([tx0, torch.zeros_like(tx0)]).contiguous()
+    two = torch.stack([torch.from_numpy(ds[0]), torch.from_numpy(ds[1])]).to(DEV).contiguous()
+    s = b.AsyncSolver(pt, nz, two, x0=X0, fixed_iter=k, tol=0.0)
+    for _ in range(10):
+        s.step()
+        s.stream.synchronize()
+        if s.poll()[0]:
+            break
+    res = s.finish()
+    assert np.all(oracle.rel_l2_per_stokes(res["x"][0].cpu().numpy(), x_ref) < 1e-10)
+    x_ref1, _ = oracle.pcg(lambda v: oracle.apply_A(opt, noise, v), lambda v: oracle.apply_M(opt, v),
+                           oracle.rhs(opt, noise, ds[1]), fixed_iters=k)
+    assert np.all(oracle.rel_l2_per_stokes(res["x"][1].cpu().numpy(), x_ref1) < 1e-10)
