@@ -235,9 +235,10 @@ struct Angle {
   }
 };
 
-// P^T of one tile's outputs: q[k] += z * (1, cos 2psi, sin 2psi) over the
-// valid window positions [vlo, vhi), through LDS bins over the compact-index
-// window [kmin, kmax].  The window is binned in passes of at most kBinSlots
+// P^T of one tile's outputs: q[k] += z * (the row of P: (1, cos 2psi,
+// sin 2psi), or the columns the map form keeps) over the valid window
+// positions [vlo, vhi), through LDS bins over the compact-index window
+// [kmin, kmax].  The window is binned in passes of at most kBinSlots
 // pixels (one pass for compact scans); a pass reads the indices (unless kept
 // in registers: kKeepK) and weights of its own samples only, so wide windows
 // (sparse or large grids) cost extra L2 reads instead of one global atomic
