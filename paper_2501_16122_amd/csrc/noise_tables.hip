@@ -9,6 +9,7 @@
 // is summed on the device, one frequency per thread, from a cosine table
 // indexed by k tau mod L.  The weights follow from H as described in
 // toeplitz.hip.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -90,19 +91,37 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     nz->n_tiles[a] = (int64_t)tiles[a].size();
   }
   // halo-carrying tiles (stride (E - kCarryElems) * 1024 window positions,
-  // E = N / 512 elements per thread) and their segments
+  // E = N / 512 elements per thread) and their segments.  Longer segments
+  // gather fewer halos; the segment length is the longest (up to
+  // kSegTiles) that still gives every CU two segments, and each chunk's
+  // tiles are split into segments of equal length (within one tile).
+  int n_cu = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, nz->device) == hipSuccess && prop.multiProcessorCount > 0)
+      n_cu = prop.multiProcessorCount;
+  }
   std::vector<FftTile> ctiles[2];
   std::vector<CarrySeg> csegs[2];
   for (int a = 0; a < 2; ++a) {
     const int64_t stride = (int64_t)(Ns[a] / 512 - kCarryElems) * 1024;
+    int64_t n_ct = 0;
+    for (int64_t c = 0; c < nz->n_chunks; ++c)
+      n_ct += (nz->chunk_offsets[c + 1] - nz->chunk_offsets[c] + stride - 1) / stride;
+    const int64_t seg_len = std::max<int64_t>(1, std::min<int64_t>(kSegTiles, n_ct / (2 * (int64_t)n_cu)));
     for (int64_t c = 0; c < nz->n_chunks; ++c) {
       const int64_t c0 = nz->chunk_offsets[c], c1 = nz->chunk_offsets[c + 1];
-      int64_t seg_n = 0;
-      for (int64_t o = c0; o < c1; o += stride) {
-        if (seg_n == 0) csegs[a].push_back(CarrySeg{(int64_t)ctiles[a].size(), 0, 0});
-        ctiles[a].push_back(FftTile{o, o + stride < c1 ? o + stride : c1, c0, c1, nz->chunk_filter[c], wrap});
-        csegs[a].back().count += 1;
-        seg_n = seg_n + 1 == kSegTiles ? 0 : seg_n + 1;
+      const int64_t nt = (c1 - c0 + stride - 1) / stride;
+      if (nt == 0) continue;
+      const int64_t ns = (nt + seg_len - 1) / seg_len;  // segments of this chunk
+      int64_t t = 0;
+      for (int64_t sgi = 0; sgi < ns; ++sgi) {
+        const int64_t cnt = nt / ns + (sgi < nt % ns ? 1 : 0);
+        csegs[a].push_back(CarrySeg{(int64_t)ctiles[a].size(), (int32_t)cnt, 0});
+        for (int64_t u = 0; u < cnt; ++u, ++t) {
+          const int64_t o = c0 + t * stride;
+          ctiles[a].push_back(FftTile{o, o + stride < c1 ? o + stride : c1, c0, c1, nz->chunk_filter[c], wrap});
+        }
       }
     }
     nz->n_csegs[a] = (int64_t)csegs[a].size();

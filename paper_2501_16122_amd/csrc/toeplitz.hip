@@ -42,7 +42,7 @@ template <>
 struct Plan<double> {
   static constexpr int N = kFftN64, T = 512, kMinBlocks = 1;
   static constexpr int kGatherBatch = 8;   // entries (sample pairs) per load batch
-  static constexpr int kScatterBatch = 4;
+  static constexpr int kScatterBatch = 8;
 };
 template <>
 struct Plan<float> {
