@@ -63,7 +63,7 @@ static_assert(sizeof(FftTile) == 40, "FftTile layout");
 // a run of up to kSegTiles such tiles of one chunk, handled by one workgroup
 // in order.
 constexpr int kCarryElems = 8;
-constexpr int kSegTiles = 32;  // longest segment
+constexpr int kSegTiles = 64;  // longest segment
 struct CarrySeg {
   int64_t first;  // index of its first tile in the halo-carrying tile list
   int32_t count;

@@ -93,8 +93,8 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   // halo-carrying tiles (stride (E - kCarryElems) * 1024 window positions,
   // E = N / 512 elements per thread) and their segments.  Longer segments
   // gather fewer halos; the segment length is the longest (up to
-  // kSegTiles) that still gives every CU two segments, and each chunk's
-  // tiles are split into segments of equal length (within one tile).
+  // kSegTiles) that still gives every CU a segment, and each chunk's tiles
+  // are split into segments of equal length (within one tile).
   int n_cu = 256;
   {
     hipDeviceProp_t prop;
@@ -108,7 +108,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     int64_t n_ct = 0;
     for (int64_t c = 0; c < nz->n_chunks; ++c)
       n_ct += (nz->chunk_offsets[c + 1] - nz->chunk_offsets[c] + stride - 1) / stride;
-    const int64_t seg_len = std::max<int64_t>(1, std::min<int64_t>(kSegTiles, n_ct / (2 * (int64_t)n_cu)));
+    const int64_t seg_len = std::max<int64_t>(1, std::min<int64_t>(kSegTiles, n_ct / (int64_t)n_cu));
     for (int64_t c = 0; c < nz->n_chunks; ++c) {
       const int64_t c0 = nz->chunk_offsets[c], c1 = nz->chunk_offsets[c + 1];
       const int64_t nt = (c1 - c0 + stride - 1) / stride;
