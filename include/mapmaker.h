@@ -12,8 +12,8 @@
  * found by preconditioned conjugate gradient on A x = b with
  * A = P^T N^-1 P and b = P^T N^-1 d (eq. (6)) and the block-Jacobi
  * preconditioner M = (P^T diag(N)^-1 P)^-1 made of per-pixel 3x3 inverses
- * (nc x nc for the map forms with fewer values per pixel, see below)
- * (eq. (7)).  The operators are lazy (Sec. III-A): building a handle
+ * (eq. (7); nc x nc for the map forms with fewer values per pixel, see
+ * below).  The operators are lazy (Sec. III-A): building a handle
  * precomputes the pointing elements and preconditioner once, and each apply
  * call only streams the timeline.
  *
