@@ -80,40 +80,55 @@ __global__ __launch_bounds__(kBuildThreads) void k_pointing_hist(const PtTile* _
   }
   __syncthreads();
   const double w = det_w[tl.det];
-  for (int i = threadIdx.x; i < tl.len; i += blockDim.x) {
-    const int64_t t = tl.start + i;
-    const int32_t p = pix[t];
-    if (p < 0 || p >= n_pix) continue;
-    double a[3] = {1.0, 0.0, 0.0};  // the row of P
-    if constexpr (Stokes<NC>::kAngle) {
-      if (!(fabs(2.0 * double(psi[t])) < sc::kReduceMax)) {  // also NaN / inf
-        atomicOr(&flags[0], 2);
-        continue;
-      }
-      double c, s;
-      sincos2<double>(psi[t], &c, &s);
-      if constexpr (NC == 3) {
-        a[1] = c;
-        a[2] = s;
-      } else {
-        a[0] = c;
-        a[1] = s;
-      }
+  // batches of kB samples per thread: the pixel and angle loads of a batch
+  // are issued together, unconditionally (past the tile's end from its first
+  // sample, then skipped)
+  constexpr int kB = 8;
+  for (int i0 = 0; i0 < tl.len; i0 += kB * kBuildThreads) {
+    int32_t pb[kB];
+    S ab[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int i = i0 + threadIdx.x + kBuildThreads * u;
+      const int64_t t = tl.start + (i < tl.len ? i : 0);
+      pb[u] = i < tl.len ? pix[t] : -1;
+      if constexpr (Stokes<NC>::kAngle) ab[u] = psi[t];
     }
-    double v[NB];
 #pragma unroll
-    for (int i = 0, j = 0; i < NC; ++i)
+    for (int u = 0; u < kB; ++u) {
+      const int32_t p = pb[u];
+      if (p < 0 || p >= n_pix) continue;
+      double a[3] = {1.0, 0.0, 0.0};  // the row of P
+      if constexpr (Stokes<NC>::kAngle) {
+        if (!(fabs(2.0 * double(ab[u])) < sc::kReduceMax)) {  // also NaN / inf
+          atomicOr(&flags[0], 2);
+          continue;
+        }
+        double c, s;
+        sincos2<double>(ab[u], &c, &s);
+        if constexpr (NC == 3) {
+          a[1] = c;
+          a[2] = s;
+        } else {
+          a[0] = c;
+          a[1] = s;
+        }
+      }
+      double v[NB];
 #pragma unroll
-      for (int k = i; k < NC; ++k) v[j++] = w * a[i] * a[k];
-    const int32_t rel = p - base;
-    if (rel < kBuildBins) {
-      atomicAdd(&s_hits[rel], 1);
+      for (int i = 0, j = 0; i < NC; ++i)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) atomicAdd(&s_acc[j * kBuildBins + rel], v[j]);
-    } else {
-      atomicAdd(&hits[p], 1);
+        for (int k = i; k < NC; ++k) v[j++] = w * a[i] * a[k];
+      const int32_t rel = p - base;
+      if (rel < kBuildBins) {
+        atomicAdd(&s_hits[rel], 1);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) atomicAdd(&blocks[NB * (int64_t)p + j], v[j]);
+        for (int j = 0; j < NB; ++j) atomicAdd(&s_acc[j * kBuildBins + rel], v[j]);
+      } else {
+        atomicAdd(&hits[p], 1);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) atomicAdd(&blocks[NB * (int64_t)p + j], v[j]);
+      }
     }
   }
   __syncthreads();
