@@ -57,12 +57,12 @@ struct FftTile {
 static_assert(sizeof(FftTile) == 40, "FftTile layout");
 
 // Halo-carrying tiles: consecutive tiles of one chunk start kCarryStride[a]
-// samples apart, a multiple of the 1024 window positions one element of
-// every thread covers, so the gathered P x of a window's last kCarryElems
-// elements is the next window's first, in the same registers.  A segment is
+// samples apart, a multiple of the window positions one register element of
+// every thread covers, so the gathered P x of a window's last elements is
+// the next window's first, in the same registers.  A segment is
 // a run of up to kSegTiles such tiles of one chunk, handled by one workgroup
 // in order.
-constexpr int kCarryElems = 8;
+constexpr int64_t kCarryStride[2] = {8192, 24576};  // samples between carrying tiles (FP64, FP32 plan)
 constexpr int kSegTiles = 64;  // longest segment
 struct CarrySeg {
   int64_t first;  // index of its first tile in the halo-carrying tile list

@@ -90,8 +90,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     }
     nz->n_tiles[a] = (int64_t)tiles[a].size();
   }
-  // halo-carrying tiles (stride (E - kCarryElems) * 1024 window positions,
-  // E = N / 512 elements per thread) and their segments.  Longer segments
+  // halo-carrying tiles (kCarryStride samples apart) and their segments.  Longer segments
   // gather fewer halos; the segment length is the longest (up to
   // kSegTiles) that still gives every CU a segment, and each chunk's tiles
   // are split into segments of equal length (within one tile).
@@ -104,7 +103,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   std::vector<FftTile> ctiles[2];
   std::vector<CarrySeg> csegs[2];
   for (int a = 0; a < 2; ++a) {
-    const int64_t stride = (int64_t)(Ns[a] / 512 - kCarryElems) * 1024;
+    const int64_t stride = kCarryStride[a];
     int64_t n_ct = 0;
     for (int64_t c = 0; c < nz->n_chunks; ++c)
       n_ct += (nz->chunk_offsets[c + 1] - nz->chunk_offsets[c] + stride - 1) / stride;

@@ -38,18 +38,30 @@ namespace {
 //   8192-point FP32 plan with two workgroups per CU measured slower).
 template <class C>
 struct Plan;
+// kCarryElems: register elements a halo-carrying tile takes over from the
+// previous one (its stride is (E - kCarryElems) * 2T samples, kCarryStride);
+// [kKeepW0, kKeepW1): elements whose pointing weights stay in registers from
+// the gather to the scatter on plain tiles (they hold most valid outputs at
+// lambda = 4096; empty: none).
 template <>
 struct Plan<double> {
   static constexpr int N = kFftN64, T = 512, kMinBlocks = 1;
   static constexpr int kGatherBatch = 8;   // entries (sample pairs) per load batch
   static constexpr int kScatterBatch = 8;
+  static constexpr int kCarryElems = 8, kKeepW0 = 5, kKeepW1 = 11;
 };
 template <>
 struct Plan<float> {
   static constexpr int N = kFftN32, T = 512, kMinBlocks = 1;
   static constexpr int kGatherBatch = 8;
   static constexpr int kScatterBatch = 4;
+  static constexpr int kCarryElems = 8, kKeepW0 = 0, kKeepW1 = 0;
 };
+static_assert((Plan<double>::N / Plan<double>::T - Plan<double>::kCarryElems) * 2 * Plan<double>::T ==
+                  kCarryStride[0],
+              "FP64 halo-carrying stride");
+static_assert((Plan<float>::N / Plan<float>::T - Plan<float>::kCarryElems) * 2 * Plan<float>::T == kCarryStride[1],
+              "FP32 halo-carrying stride");
 
 // LDS reuse outside the FFT: P^T bins (NC doubles per pixel) and the staged
 // map window (NC values per pixel, padded to 4 doubles for IQU so that the
@@ -256,10 +268,6 @@ __device__ __forceinline__ bool src_pos(int pos, int ilo, int ihi, bool wrap, in
   return in || (wrap && pos < ihi + lam1);
 }
 
-// Elements [kKeepW0, kKeepW1) of each thread (FP64 plan) hold most valid
-// outputs at lambda = 4096; their pointing weights can stay in registers from
-// the gather (wk) instead of being read again.
-constexpr int kKeepW0 = 5, kKeepW1 = 11;
 
 template <class S, class C, int kW, int NC, bool kKeepK, bool kKeepW = false>
 __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, const int32_t* kk,
@@ -307,8 +315,8 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
         const int e = e0 + i / 2;
         if (!kAng)
           ps[i] = A::zero();
-        else if (kKeepW && e >= kKeepW0 && e < kKeepW1)
-          ps[i] = wk[2 * (e - kKeepW0) + (i & 1)];
+        else if (kKeepW && e >= P::kKeepW0 && e < P::kKeepW1)
+          ps[i] = wk[2 * (e - P::kKeepW0) + (i & 1)];
         else
           ps[i] = A::load(ps0, w0, posa);
       }
@@ -382,9 +390,9 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
   // With 16 elements per thread the compact indices stay in registers from
   // the gather to the scatter (no reload); with 32 they would not fit.
   constexpr bool kKeepK = kIn == 1 && kOut == 1 && E <= 16;
-  constexpr bool kKeepW = kKeepK && kW == 1 && E == 16;
+  constexpr bool kKeepW = kKeepK && kW == 1 && P::kKeepW1 > P::kKeepW0;
   int32_t kk[2 * E];
-  typename A::type wk[kKeepW ? 2 * (kKeepW1 - kKeepW0) : 1];
+  typename A::type wk[kKeepW ? 2 * (P::kKeepW1 - P::kKeepW0) : 1];
   if constexpr (kIn == 1) {
     // (1) compact index of every window sample of this thread, one batch
 #pragma unroll
@@ -455,7 +463,7 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
         ps[i] = kAng ? A::load(ps0, w0, ok ? sp : ilo) : A::zero();
         if constexpr (kKeepW) {
           const int e = e0 + i / 2;
-          if (e >= kKeepW0 && e < kKeepW1) wk[2 * (e - kKeepW0) + (i & 1)] = ps[i];
+          if (e >= P::kKeepW0 && e < P::kKeepW1) wk[2 * (e - P::kKeepW0) + (i & 1)] = ps[i];
         }
       }
 #pragma unroll
@@ -565,6 +573,7 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
   using F = Fft<C>;
   using A = Angle<C, S, kW>;
   constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch;
+  constexpr int kCarryElems = P::kCarryElems;
   constexpr int M = E - kCarryElems;  // element shift between consecutive tiles
   constexpr int kStride = M * 2 * T;
   constexpr bool kAng = Stokes<NC>::kAngle;
@@ -705,7 +714,7 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_ca
   x += rhs * rb.vstride;
   q += rhs * rb.vstride;
   const CarrySeg sg = segs[seg];
-  cpx<C> carry[kCarryElems];
+  cpx<C> carry[Plan<C>::kCarryElems];
   int32_t cmin = INT32_MAX, cmax = -1;
   for (int t = 0; t < sg.count; ++t) {
     const FftTile tl = tiles[sg.first + t];
