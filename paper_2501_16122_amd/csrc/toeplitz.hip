@@ -43,12 +43,18 @@ struct Plan;
 // [kKeepW0, kKeepW1): elements whose pointing weights stay in registers from
 // the gather to the scatter on plain tiles (they hold most valid outputs at
 // lambda = 4096; empty: none).
+// kPairMerge: the scatter adds the two samples of a register element into
+// one set of bin atomics when they fall in the same pixel (consecutive
+// samples usually do).  kLateReduce: a halo-carrying tile reduces its
+// compact-index range after the gather, so the index and weight loads are
+// in flight together.  Both measured faster in FP64 only.
 template <>
 struct Plan<double> {
   static constexpr int N = kFftN64, T = 512, kMinBlocks = 1;
   static constexpr int kGatherBatch = 8;   // entries (sample pairs) per load batch
   static constexpr int kScatterBatch = 8;
   static constexpr int kCarryElems = 8, kKeepW0 = 5, kKeepW1 = 11;
+  static constexpr bool kPairMerge = true, kLateReduce = true;
 };
 template <>
 struct Plan<float> {
@@ -56,6 +62,7 @@ struct Plan<float> {
   static constexpr int kGatherBatch = 8;
   static constexpr int kScatterBatch = 4;
   static constexpr int kCarryElems = 8, kKeepW0 = 0, kKeepW1 = 0;
+  static constexpr bool kPairMerge = false, kLateReduce = false;
 };
 static_assert((Plan<double>::N / Plan<double>::T - Plan<double>::kCarryElems) * 2 * Plan<double>::T ==
                   kCarryStride[0],
@@ -320,17 +327,45 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
         else
           ps[i] = A::load(ps0, w0, posa);
       }
+      if constexpr (P::kPairMerge) {
 #pragma unroll
-      for (int i = 0; i < 2 * GS; ++i) {
-        const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
-        const C z = (i & 1) ? o.y : o.x;
-        C c = C(0), s = C(0);
-        if constexpr (kAng) A::eval(ps[i], &c, &s);
-        if (ks[i] >= 0) {
-          double t[NC];
-          Stokes<NC>::terms(z, c, s, t);
+        for (int i = 0; i < 2 * GS; i += 2) {
+          const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
+          C c0 = C(0), s0 = C(0), c1 = C(0), s1 = C(0);
+          if constexpr (kAng) {
+            A::eval(ps[i], &c0, &s0);
+            A::eval(ps[i + 1], &c1, &s1);
+          }
+          double t0[NC], t1[NC];
+          Stokes<NC>::terms(o.x, c0, s0, t0);
+          Stokes<NC>::terms(o.y, c1, s1, t1);
+          // the pair's second sample joins the first's atomics when both bin
+          // into the same slot
+          const bool same = ks[i] >= 0 && ks[i] == ks[i + 1];
 #pragma unroll
-          for (int j = 0; j < NC; ++j) atomicAdd(&bins[j * kTBinSlots + ks[i]], t[j]);
+          for (int j = 0; j < NC; ++j) t0[j] += same ? t1[j] : 0.0;
+          if (ks[i] >= 0) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) atomicAdd(&bins[j * kTBinSlots + ks[i]], t0[j]);
+          }
+          if (ks[i + 1] >= 0 && !same) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) atomicAdd(&bins[j * kTBinSlots + ks[i + 1]], t1[j]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 2 * GS; ++i) {
+          const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
+          const C z = (i & 1) ? o.y : o.x;
+          C c = C(0), s = C(0);
+          if constexpr (kAng) A::eval(ps[i], &c, &s);
+          if (ks[i] >= 0) {
+            double t[NC];
+            Stokes<NC>::terms(z, c, s, t);
+#pragma unroll
+            for (int j = 0; j < NC; ++j) atomicAdd(&bins[j * kTBinSlots + ks[i]], t[j]);
+          }
         }
       }
     }
@@ -610,30 +645,34 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
     }
   }
   int32_t kmin = INT32_MAX, kmax = -1, nmin = INT32_MAX, nmax = -1;
+  constexpr int W = T / 64;
+  // the compact-index ranges of the valid outputs (this tile) and of the
+  // samples that become the next tile's carried valid outputs
+  if constexpr (!P::kLateReduce) {
 #pragma unroll
-  for (int i = 0; i < 2 * E; ++i) {
-    const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
-    if (kk[i] >= 0) {
-      if (pos >= vlo && pos < vhi) {
-        kmin = kk[i] < kmin ? kk[i] : kmin;
-        kmax = kk[i] > kmax ? kk[i] : kmax;
-      }
-      if (pos >= vlo + kStride) {
-        nmin = kk[i] < nmin ? kk[i] : nmin;
-        nmax = kk[i] > nmax ? kk[i] : nmax;
+    for (int i = 0; i < 2 * E; ++i) {
+      const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
+      if (kk[i] >= 0) {
+        if (pos >= vlo && pos < vhi) {
+          kmin = kk[i] < kmin ? kk[i] : kmin;
+          kmax = kk[i] > kmax ? kk[i] : kmax;
+        }
+        if (pos >= vlo + kStride) {
+          nmin = kk[i] < nmin ? kk[i] : nmin;
+          nmax = kk[i] > nmax ? kk[i] : nmax;
+        }
       }
     }
-  }
-  kmin = wave_min(kmin);
-  kmax = wave_max(kmax);
-  nmin = wave_min(nmin);
-  nmax = wave_max(nmax);
-  constexpr int W = T / 64;
-  if ((tid & 63) == 0) {
-    s_red[tid >> 6] = kmin;
-    s_red[W + (tid >> 6)] = kmax;
-    s_red[2 * W + (tid >> 6)] = nmin;
-    s_red[3 * W + (tid >> 6)] = nmax;
+    kmin = wave_min(kmin);
+    kmax = wave_max(kmax);
+    nmin = wave_min(nmin);
+    nmax = wave_max(nmax);
+    if ((tid & 63) == 0) {
+      s_red[tid >> 6] = kmin;
+      s_red[W + (tid >> 6)] = kmax;
+      s_red[2 * W + (tid >> 6)] = nmin;
+      s_red[3 * W + (tid >> 6)] = nmax;
+    }
   }
   // P x of the fresh elements, in batches of pointing weights
 #pragma unroll
@@ -660,6 +699,32 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
       const C val = k >= 0 ? Stokes<NC>::project(x + NC * (int64_t)(k >= 0 ? k : 0), c, s) : C(0);
       if (i & 1) v[e0 + i / 2].y = val;
       else v[e0 + i / 2].x = val;
+    }
+  }
+  if constexpr (P::kLateReduce) {  // the same, after the gather
+#pragma unroll
+    for (int i = 0; i < 2 * E; ++i) {
+      const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
+      if (kk[i] >= 0) {
+        if (pos >= vlo && pos < vhi) {
+          kmin = kk[i] < kmin ? kk[i] : kmin;
+          kmax = kk[i] > kmax ? kk[i] : kmax;
+        }
+        if (pos >= vlo + kStride) {
+          nmin = kk[i] < nmin ? kk[i] : nmin;
+          nmax = kk[i] > nmax ? kk[i] : nmax;
+        }
+      }
+    }
+    kmin = wave_min(kmin);
+    kmax = wave_max(kmax);
+    nmin = wave_min(nmin);
+    nmax = wave_max(nmax);
+    if ((tid & 63) == 0) {
+      s_red[tid >> 6] = kmin;
+      s_red[W + (tid >> 6)] = kmax;
+      s_red[2 * W + (tid >> 6)] = nmin;
+      s_red[3 * W + (tid >> 6)] = nmax;
     }
   }
 #pragma unroll
