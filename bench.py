@@ -113,12 +113,13 @@ def _cpu_baseline(w, pix, psi, d, n_det_sample):
     t_build = time.perf_counter() - t0
     nz = oracle.toeplitz_noise(synth.toeplitz_coeff(ws), synth.chunk_offsets(ws))
     b = oracle.rhs(opt, nz, d[:ns])
-    reps = 3
-    x = b.copy()
+    # at least 3 applications, then more until about 10 s of CPU work
+    reps, x = 0, b.copy()
     t0 = time.perf_counter()
-    for _ in range(reps):
+    while reps < 3 or (time.perf_counter() - t0 < 10.0 and reps < 60):
         q = oracle.apply_A(opt, nz, x)
         x = oracle.apply_M(opt, q)
+        reps += 1
     t_iter = (time.perf_counter() - t0) / reps
     return {"value": ns / t_iter, "unit": "TOD samples/s per PCG iteration", "cores": 1, "kind": "oracle",
             "sample": f"first {n_det_sample} of {w.n_det} detectors ({ns} samples) of the same workload; "
@@ -502,7 +503,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gls", choices=["gls", "shard", "binned"])
     ap.add_argument("--fp32-steps", type=int, default=3, help="timed FP32-refined steps (0 = skip)")
-    ap.add_argument("--cpu-det", type=int, default=2, help="detectors in the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-det", type=int, default=4, help="detectors in the oracle sample (0 = skip)")
     ap.add_argument("--multi-rhs", type=int, default=8, help="realisations in the multi-RHS measurement (0 = skip)")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--batch", type=int, default=16, help="uneven solves in the batched measurement (0 = skip)")
