@@ -259,7 +259,13 @@ typedef struct {
                            global memory instead of staged in LDS, bit 2 = shorter tiles in
                            runs that carry the overlapping half-window from tile to tile
                            (needs stored pointing weights; never stages)                    */
-  int32_t reserved_;
+  int32_t graph;        /* 1: the first mm_solver_step of a given length k records its k
+                           iterations (operator and PCG launches) into a HIP graph and
+                           every later step of that length replays it with one graph
+                           launch on the solver's stream (recorded on a private stream,
+                           so the caller's may be the null stream); another k records
+                           anew.  Same kernels and arguments as the eager launches.
+                           Ignored when timing = 1 and by mm_batch_step.  Default 0       */
   const double* x0;     /* start vector (device, f64[n_rhs][nc * n_kept]) or NULL for x0 = 0;
                            the residual starts at b - A x0 (FP64), the mixed form refines from
                            x0; the solve's outputs do not alias it                           */

@@ -33,7 +33,7 @@ _psz = _c.POINTER(_c.c_size_t)
 class SolveOpts(_c.Structure):
     _fields_ = [("tol", _f64), ("max_iter", _i32), ("fixed_iter", _i32), ("check_every", _i32),
                 ("mixed", _i32), ("max_outer", _i32), ("inner_tol", _f64), ("timing", _i32),
-                ("autotune", _i32), ("op_variant", _i32), ("reserved_", _i32), ("x0", _vp)]
+                ("autotune", _i32), ("op_variant", _i32), ("graph", _i32), ("x0", _vp)]
 
 
 class SolveInfo(_c.Structure):

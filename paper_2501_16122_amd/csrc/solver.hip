@@ -76,6 +76,7 @@ int check_opts(const mm_solve_opts& o) {
     return fail(MM_EINVAL, "bad solve options");
   if (o.mixed && o.fixed_iter > 0) return fail(MM_EINVAL, "fixed_iter is not available with mixed precision");
   if (o.op_variant < 0 || o.op_variant >= kOpVariants) return fail(MM_EINVAL, "op_variant out of range");
+  if (o.graph != 0 && o.graph != 1) return fail(MM_EINVAL, "graph must be 0 or 1");
   return MM_OK;
 }
 
@@ -108,8 +109,14 @@ struct mm_solver_s {
   std::vector<double> iter_ms;
   double op_ms = 0.0;
   int32_t op_launches = 0;
+  // recorded iteration chunk (opts.graph): graph_k iterations, replayed on s
+  hipStream_t cs = nullptr;  // private stream the chunk is recorded on
+  hipGraphExec_t gexec = nullptr;
+  int32_t graph_k = -1;
 
   ~mm_solver_s() {
+    drop_graph();
+    if (cs) (void)hipStreamDestroy(cs);
     if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t e : tev) (void)hipEventDestroy(e);
     if (h_st) (void)hipHostFree(h_st);
@@ -149,6 +156,13 @@ struct mm_solver_s {
     rb.done = &L.A.st[0].done;
     rb.done_stride = kPcgDoneStride;
     const int arith = mixed ? MM_F32 : MM_F64;
+    if (o.graph && !timing) {
+      if (graph_k != k)
+        if (int rc = record_chunk(k, rb, arith)) return rc;
+      MM_HIP(hipGraphLaunch(gexec, s));
+      tev_used = 0;
+      return record_state();
+    }
     if (timing && (int32_t)tev.size() < 2 * k + 1) {
       for (hipEvent_t e : tev) (void)hipEventDestroy(e);
       tev.assign(2 * (size_t)k + 1, nullptr);
@@ -163,6 +177,40 @@ struct mm_solver_s {
     if (timing) MM_HIP(hipEventRecord(tev[2 * k], s));
     tev_used = timing ? k : 0;
     return record_state();
+  }
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    graph_k = -1;
+  }
+
+  // Record k iterations (the eager loop of step, launched on the private
+  // stream cs under capture, so nothing runs) and instantiate the graph.
+  // The launches clear memory with fill kernels, never with memset nodes.
+  int record_chunk(int32_t k, const RhsBatch& rb, int arith) {
+    drop_graph();
+    if (!cs) MM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    MM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = MM_OK;
+    for (int32_t i = 0; i < k && rc == MM_OK; ++i) {
+      rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, cs, variant);
+      if (rc == MM_OK) rc = launch_pcg_iteration_tail(pt, L.A, nrhs, cs);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);  // always ends the capture
+    if (rc != MM_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != MM_OK ? rc : hip_fail(e, "iteration graph capture");
+    }
+    const hipError_t ei = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      gexec = nullptr;
+      return hip_fail(ei, "iteration graph instantiate");
+    }
+    graph_k = k;
+    return MM_OK;
   }
 
   // Autotuner: time each variant of the fused band-Toeplitz operator on
@@ -299,7 +347,7 @@ int mm_solve_opts_default(mm_solve_opts* o) {
   o->timing = 0;
   o->autotune = 0;
   o->op_variant = 0;
-  o->reserved_ = 0;
+  o->graph = 0;
   o->x0 = nullptr;
   return MM_OK;
 }

@@ -1,0 +1,174 @@
+"""Recorded iteration chunks (solve option graph = 1): every replay of the
+recorded k iterations advances the solve as the eager launches do.  Checked
+step by step against an eager solver, with unrelated eager work and
+synchronisations between the replays; at fixed iteration counts against the
+oracle; for white, band-Toeplitz and template weights, FP64 and mixed
+precision, several right-hand sides, changes of chunk length, a solver on
+the null stream, and snapshot/restore."""
+import numpy as np
+import pytest
+
+import oracle.mapmaking as oracle
+from paper_2501_16122_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+W = synth.Workload("graph_64x64_2x60000", 971, 64, 64, 2, 60000, t_psi=900.0, noise="oneoverf", chunk=20000,
+                   lam=256)
+
+
+def _b():
+    from paper_2501_16122_amd import binding
+    return binding
+
+
+class Problem:
+    def __init__(self, kind, n_rhs=1, stokes="IQU"):
+        b = _b()
+        w = W
+        pix, psi = synth.pointing(w)
+        psi = synth.storage(w, psi)
+        self.offs, self.wdet = synth.det_offsets(w), synth.det_weight(w)
+        self.opt = oracle.build_pointing(pix, psi, self.offs, self.wdet, w.n_pix, stokes=stokes)
+        self.nc = self.opt.ncomp
+        self.pt = b.Pointing(torch.from_numpy(pix).to(DEV), torch.from_numpy(psi).to(DEV), self.offs, self.wdet,
+                             w.n_pix, stokes=stokes)
+        if kind == "toeplitz":
+            coeff, chunks = synth.toeplitz_coeff(w), synth.chunk_offsets(w)
+            self.noise = oracle.toeplitz_noise(coeff, chunks)
+            self.nz = b.Noise.toeplitz(coeff, chunks, DEV)
+        elif kind == "white":
+            self.noise = None
+            self.nz = b.Noise.white(self.wdet, DEV)
+        else:  # polynomial baselines of degree < 2 on 4001-sample intervals
+            n = self.opt.n_samples
+            ivals = np.array(sorted(set(range(0, n, 4001)) | {int(o) for o in self.offs} | {n}), dtype=np.int64)
+            self.noise = oracle.template_noise(ivals, np.full(ivals.size - 1, 2, dtype=np.int32))
+            self.nz = b.Noise.templates(self.wdet, ivals, 2, DEV)
+        m = np.random.default_rng(9).normal(size=self.nc * self.opt.n_kept) * 5.0
+        self.ds = []
+        for r in range(n_rhs):
+            wr = w.replace(config_id=w.config_id * 100 + r)
+            self.ds.append(synth.storage(w, oracle.apply_P(self.opt, m) + synth.noise(wr)))
+        self.tod = torch.from_numpy(np.stack(self.ds) if n_rhs > 1 else self.ds[0]).to(DEV)
+
+
+def _lockstep(p, ks, between=None, **opts):
+    """Step an eager and a recording solver of the same problem through the
+    chunk lengths ks, comparing their states after every step."""
+    b = _b()
+    eager = b.AsyncSolver(p.pt, p.nz, p.tod, graph=0, **opts)
+    rec = b.AsyncSolver(p.pt, p.nz, p.tod, graph=1, **opts)
+    steps = 0
+    for k in ks:
+        eager.step(k)
+        rec.step(k)
+        torch.cuda.synchronize()
+        if between is not None:
+            between()
+            torch.cuda.synchronize()
+        de, _, ie = eager.poll(with_info=True)
+        dr, _, ir = rec.poll(with_info=True)
+        steps += 1
+        assert de == dr, steps
+        for a, c in zip(ie, ir):
+            assert a["iters"] == c["iters"] and a["outer_iters"] == c["outer_iters"], (steps, a, c)
+            assert abs(a["rel_resid"] - c["rel_resid"]) <= 1e-12 + 1e-6 * abs(a["rel_resid"]), (steps, a, c)
+        if de:
+            break
+    return eager.finish(), rec.finish(), steps
+
+
+# templates in the Q, U form: the I, Q, U form leaves large-scale I modes
+# weakly constrained, and over its hundreds of iterations the rounding order
+# of the FP64 atomics alone moves the iterates of two eager runs apart
+@pytest.mark.parametrize("kind,mixed,stokes", [("toeplitz", 0, "IQU"), ("white", 0, "IQU"), ("templates", 0, "QU"),
+                                               ("toeplitz", 1, "IQU")])
+def test_replays_match_eager_steps(kind, mixed, stokes):
+    b = _b()
+    p = Problem(kind, stokes=stokes)
+    xr = torch.randn(p.nc * p.opt.n_kept, dtype=torch.float64, device=DEV)
+
+    def other_work():  # eager launches of the same library between replays
+        b.apply_A(p.pt, p.nz, xr)
+
+    e, r, steps = _lockstep(p, [4] * 400, between=other_work, tol=1e-10, mixed=mixed)
+    assert steps >= (1 if kind == "white" else 3)  # block-Jacobi is exact for white weights
+    assert e["info"][0]["converged"] == 1 and r["info"][0]["converged"] == 1
+    assert e["info"][0]["iters"] == r["info"][0]["iters"]
+    err = oracle.rel_l2_per_stokes(r["x"][0].cpu().numpy(), e["x"][0].cpu().numpy(), ncomp=p.nc)
+    assert np.all(err < 1e-9), err
+
+
+# (white weights: the first iteration is exact, the next one breaks down.
+# Templates: on this small scan the I, Q, U template problem amplifies
+# rounding differences about 100-fold every 5 iterations, eager launches
+# alike, so it is compared after 8.)
+@pytest.mark.parametrize("kind,k", [("toeplitz", 20), ("templates", 8)])
+def test_fixed_iterations_match_oracle(kind, k):
+    b = _b()
+    p = Problem(kind)
+    out = b.Solver(p.pt, p.nz, fixed_iter=k, tol=0.0, graph=1).solve(p.tod)
+    assert out["info"]["iters"] == k
+    _, _, x_ref = oracle.solve(p.opt, p.noise, p.ds[0], fixed_iters=k)
+    err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref)
+    assert np.all(err < 1e-10), err
+
+
+def test_chunk_length_changes_and_several_rhs():
+    p = Problem("toeplitz", n_rhs=3)
+    e, r, _ = _lockstep(p, [3, 5, 3, 8, 1, 5] * 60, tol=1e-10)
+    for i in range(3):
+        assert e["info"][i]["iters"] == r["info"][i]["iters"] and r["info"][i]["converged"] == 1
+        err = oracle.rel_l2_per_stokes(r["x"][i].cpu().numpy(), e["x"][i].cpu().numpy())
+        assert np.all(err < 1e-9), (i, err)
+
+
+def test_null_stream_solver():
+    b = _b()
+    p = Problem("toeplitz")
+    ref = b.Solver(p.pt, p.nz, tol=1e-10).solve(p.tod)
+    s = b.AsyncSolver(p.pt, p.nz, p.tod, stream=torch.cuda.default_stream(), tol=1e-10, graph=1)
+    for _ in range(400):
+        s.step(4)
+        torch.cuda.synchronize()
+        if s.poll()[0]:
+            break
+    out = s.finish()
+    assert out["info"][0]["converged"] == 1 and out["info"][0]["iters"] == ref["info"]["iters"]
+    err = oracle.rel_l2_per_stokes(out["x"][0].cpu().numpy(), ref["x"].cpu().numpy())
+    assert np.all(err < 1e-9), err
+
+
+def test_snapshot_restore_with_recorded_chunks():
+    b = _b()
+    p = Problem("toeplitz")
+    s = b.AsyncSolver(p.pt, p.nz, p.tod, tol=1e-10, graph=1)
+    for _ in range(3):
+        s.step(4)
+    snap = s.snapshot()
+
+    def run_to_end():
+        for _ in range(400):
+            s.step(4)
+            torch.cuda.synchronize()
+            if s.poll()[0]:
+                break
+        return s.finish()
+
+    first = run_to_end()
+    s.restore(snap)
+    second = run_to_end()
+    assert first["info"][0]["iters"] == second["info"][0]["iters"]
+    err = oracle.rel_l2_per_stokes(second["x"][0].cpu().numpy(), first["x"][0].cpu().numpy())
+    assert np.all(err < 1e-9), err
+
+
+def test_bad_graph_option():
+    b = _b()
+    p = Problem("white")
+    with pytest.raises(b.MapMakerError):
+        b.Solver(p.pt, p.nz, graph=2).solve(p.tod)
