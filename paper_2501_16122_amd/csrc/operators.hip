@@ -13,6 +13,7 @@
 #include "mm_internal.h"
 #include "sincos2.h"
 #include "stokes.h"
+#include "wave_runs.h"
 
 namespace mm {
 namespace {
@@ -98,16 +99,22 @@ __global__ __launch_bounds__(kOpThreads) void k_bin_tod(const PtTile* __restrict
   if (tl.kmax < tl.kmin) return;
   const int nb = zero_bins<NC>(bins, tl);
   const C w = kWeighted ? C(det_w[tl.det]) : C(1);
-  for (int i = threadIdx.x; i < tl.len; i += blockDim.x) {
-    const int64_t t = tl.start + i;
-    const int32_t k = sample_k[t];
-    if (k < 0) continue;
+  // whole wavefronts per round (the tile length is uniform over the block),
+  // so that runs of equal pixels are summed across lanes before the atomics
+  for (int i0 = 0; i0 < tl.len; i0 += blockDim.x) {
+    const int i = i0 + threadIdx.x;
+    const int64_t t = tl.start + (i < tl.len ? i : 0);
+    const int32_t kr = sample_k[t];
+    const int32_t k = i < tl.len ? kr : -1;
     C c, s;
     angle<NC>(psi, t, &c, &s);
     const C z = w * C(tod[t]);
     double o[NC];
     Stokes<NC>::terms(z, c, s, o);
-    bin_add<NC>(bins, nb, tl.kmin, k, o, q);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) o[j] = k >= 0 ? o[j] : 0.0;
+    const bool head = wave_run_sum<NC>(k, o);
+    if (head && k >= 0) bin_add<NC>(bins, nb, tl.kmin, k, o, q);
   }
   __syncthreads();
   flush_bins<NC>(bins, nb, tl.kmin, q);
