@@ -259,7 +259,7 @@ typedef struct {
                            global memory instead of staged in LDS, bit 2 = shorter tiles in
                            runs that carry the overlapping half-window from tile to tile
                            (needs stored pointing weights; never stages)                    */
-  int32_t graph;        /* 1: the first mm_solver_step of a given length k records its k
+  int32_t graph;        /* 1: the first mm_solver_step of a given length k > 0 records its k
                            iterations (operator and PCG launches) into a HIP graph and
                            every later step of that length replays it with one graph
                            launch on the solver's stream (recorded on a private stream,

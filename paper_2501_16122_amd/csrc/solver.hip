@@ -156,7 +156,7 @@ struct mm_solver_s {
     rb.done = &L.A.st[0].done;
     rb.done_stride = kPcgDoneStride;
     const int arith = mixed ? MM_F32 : MM_F64;
-    if (o.graph && !timing) {
+    if (o.graph && !timing && k > 0) {
       if (graph_k != k)
         if (int rc = record_chunk(k, rb, arith)) return rc;
       MM_HIP(hipGraphLaunch(gexec, s));

@@ -120,7 +120,7 @@ def test_fixed_iterations_match_oracle(kind, k):
 
 def test_chunk_length_changes_and_several_rhs():
     p = Problem("toeplitz", n_rhs=3)
-    e, r, _ = _lockstep(p, [3, 5, 3, 8, 1, 5] * 60, tol=1e-10)
+    e, r, _ = _lockstep(p, [3, 5, 0, 3, 8, 1, 5] * 60, tol=1e-10)
     for i in range(3):
         assert e["info"][i]["iters"] == r["info"][i]["iters"] and r["info"][i]["converged"] == 1
         err = oracle.rel_l2_per_stokes(r["x"][i].cpu().numpy(), e["x"][i].cpu().numpy())
