@@ -358,8 +358,10 @@ int mm_solver_destroy(mm_solver_t sv);
 
 /* Advance n resumable solvers together: the PCG iterations of Sec. II for
  * several independent map-making problems in shared launches.  Each of up to
- * k iterations is one persistent operator launch per noise kind over the
- * tiles of every member's right-hand sides (A = P^T N^-1 P, eq. (6)) and one
+ * k iterations is one operator launch per noise kind (white, band-Toeplitz or
+ * circulant, template-filtered) over the tiles, or template intervals, of
+ * every member's right-hand sides (A = P^T N^-1 P, eq. (6); A = P^T W P,
+ * eq. (4), for template-filtered weights) and one
  * launch per PCG vector step over all their vectors; for mixed-precision
  * members a pending outer refinement step runs first.  Members may differ in
  * size, pointing, noise model and tolerances; they must share one device,

@@ -324,7 +324,7 @@ constexpr int kMaxBatch = 16;
 
 // One slot of a batched operator launch: the fused A of one right-hand side.
 struct OpSlot {
-  const void* tiles;        // FftTile[] of the plan (band-Toeplitz) or PtTile[] (white)
+  const void* tiles;        // FftTile[] of the plan (band-Toeplitz), or the pointing's PtTile[]
   const void* ab;           // band-Toeplitz spectral weights of the plan
   const void* tw;           // band-Toeplitz twiddles of the plan
   const int32_t* sample_k;
@@ -334,6 +334,8 @@ struct OpSlot {
   const double* x;
   double* q;
   const int32_t* done;      // the slot is skipped while *done != 0 (null: never)
+  const void* iv;           // template intervals (TplInterval[])
+  int64_t n_pt_tiles;       // template slots: pointing tiles (for the detector of an interval)
   int32_t lambda;
   int32_t variant;          // band-Toeplitz operator variant (kOpNoStaging is honoured)
 };
@@ -349,6 +351,8 @@ static_assert(sizeof(OpBatch) <= 2048, "operator batch must stay a small kernel 
 // dtype / arith / weights / map form must be common to all slots of the launch.
 int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, int ncomp, hipStream_t s);
 int launch_white_batch(const OpBatch& b, int dtype, int arith, int ncomp, hipStream_t s);
+// weights: every slot has stored pointing weights usable in this arithmetic
+int launch_templates_batch(const OpBatch& b, int dtype, int arith, bool weights, int ncomp, hipStream_t s);
 
 // from_x0: start from the x already in place, with A x0 in q and
 // ||b - A x0||^2, ||b||^2 in each state's scratch0/scratch1 (launch_diff_norm)

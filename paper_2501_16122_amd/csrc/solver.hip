@@ -618,7 +618,6 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
     if (sv->mixed != s0->mixed || sv->pt->dtype != s0->pt->dtype || sv->pt->ncomp != s0->pt->ncomp)
       return fail(MM_EINVAL, "batch members must share the timeline dtype, precision mode and map form");
     if (sv->pt->device != s0->pt->device) return fail(MM_EINVAL, "batch members must share one device");
-    if (sv->nz->kind == 3) return fail(MM_EINVAL, "template-filtered weights are not batched");
     slots += sv->nrhs;
   }
   if (slots > kMaxBatch) return fail(MM_EINVAL, "more than 16 right-hand sides in one batch");
@@ -627,23 +626,28 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
   const int dtype = s0->pt->dtype;
   const int ncomp = s0->pt->ncomp;
   const int arith = mixed ? MM_F32 : MM_F64;
-  // stored weights only where every band-Toeplitz slot has usable ones
-  auto weights_ok = [&](int ar) {
+  // stored weights only where every band-Toeplitz (or every template) slot has usable ones
+  auto weights_ok = [&](int ar, bool tpl) {
     for (int32_t i = 0; i < n; ++i) {
       const mm_pointing_s* pt = solvers[i]->pt;
-      if (solvers[i]->nz->kind != 0 && !(pt->weights != nullptr && (ar == MM_F32 || pt->dtype == MM_F64)))
+      const int kind = solvers[i]->nz->kind;
+      if ((tpl ? kind == 3 : (kind == 1 || kind == 2)) &&
+          !(pt->weights != nullptr && (ar == MM_F32 || pt->dtype == MM_F64)))
         return false;
     }
     return true;
   };
-  const bool w_in = weights_ok(arith), w_out = weights_ok(MM_F64);
+  const bool w_in = weights_ok(arith, false), w_out = weights_ok(MM_F64, false);
+  const bool wt_in = weights_ok(arith, true), wt_out = weights_ok(MM_F64, true);
 
   PcgBatch pb;
-  OpBatch t_in, w_in_b, t_out, w_out_b;  // inner / outer operator slots, band-Toeplitz and white
+  // inner / outer operator slots: band-Toeplitz, white, template-filtered
+  OpBatch t_in, w_in_b, p_in, t_out, w_out_b, p_out;
   bool pending = false;
   auto add_op = [](OpBatch& b, const mm_solver_s* sv, int plan, const double* x, double* q, const int32_t* done) {
     const mm_pointing_s* pt = sv->pt;
     const mm_noise_s* nz = sv->nz;
+    if (nz->kind == 3 && pt->n_kept == 0) return;  // no unknowns: nothing to gather or scatter
     OpSlot& o = b.s[b.n];
     o = OpSlot{};
     o.sample_k = pt->sample_k;
@@ -654,7 +658,13 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
     o.done = done;
     o.variant = sv->variant;
     int64_t items;
-    if (nz->kind != 0) {
+    if (nz->kind == 3) {
+      o.tiles = pt->tiles;
+      o.n_pt_tiles = pt->n_tiles;
+      o.iv = nz->tpl;
+      o.det_w = nz->det_w;
+      items = pt->n_tiles > 0 ? nz->n_chunks : 0;
+    } else if (nz->kind != 0) {
       o.tiles = nz->tiles[plan];
       o.ab = nz->ab[plan];
       o.tw = nz->tw[plan];
@@ -693,8 +703,9 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
       p.A.max_iter = sv->o.max_iter;
       p.O.max_outer = sv->o.max_outer;
       const int plan_in = arith == MM_F64 ? 0 : 1;
-      add_op(sv->nz->kind != 0 ? t_in : w_in_b, sv, plan_in, p.A.p, p.A.q, &p.A.st->done);
-      add_op(sv->nz->kind != 0 ? t_out : w_out_b, sv, 0, p.O.xt, p.A.q, &p.O.os->skip);
+      const int kind = sv->nz->kind;
+      add_op(kind == 3 ? p_in : kind != 0 ? t_in : w_in_b, sv, plan_in, p.A.p, p.A.q, &p.A.st->done);
+      add_op(kind == 3 ? p_out : kind != 0 ? t_out : w_out_b, sv, 0, p.O.xt, p.A.q, &p.O.os->skip);
     }
   }
   if (mixed && pending) {
@@ -703,12 +714,14 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
     if (int rc = launch_outer_add_batch(pb, s)) return rc;
     if (int rc = launch_toeplitz_batch(t_out, dtype, MM_F64, w_out, ncomp, s)) return rc;
     if (int rc = launch_white_batch(w_out_b, dtype, MM_F64, ncomp, s)) return rc;
+    if (int rc = launch_templates_batch(p_out, dtype, MM_F64, wt_out, ncomp, s)) return rc;
     if (int rc = launch_outer_end_batch(pb, s)) return rc;
     for (int32_t i = 0; i < n; ++i) solvers[i]->outer_pending = false;
   }
   for (int32_t i = 0; i < k; ++i) {
     if (int rc = launch_toeplitz_batch(t_in, dtype, arith, w_in, ncomp, s)) return rc;
     if (int rc = launch_white_batch(w_in_b, dtype, arith, ncomp, s)) return rc;
+    if (int rc = launch_templates_batch(p_in, dtype, arith, wt_in, ncomp, s)) return rc;
     if (int rc = launch_pcg_iteration_tail_batch(pb, s)) return rc;
   }
   for (int32_t i = 0; i < n; ++i) {

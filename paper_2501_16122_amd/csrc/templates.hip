@@ -14,6 +14,7 @@
 // written as a timeline or scattered by P^T through LDS bins per batch of
 // 2048 samples (as the white fused operator does).  With y = P x the gather
 // is recomputed in the second pass instead of storing the timeline.
+#include <algorithm>
 #include <climits>
 
 #include "fft_lds.h"
@@ -82,23 +83,19 @@ __device__ __forceinline__ T wave_minmax(T v, bool is_min) {
   return v;
 }
 
+// One interval, the whole workgroup (every return below is uniform over it).
 // kIn: 1 = y = P x, 0 = y = tod_in.  kOut: 1 = q += P^T z, 0 = tod_out = z.
 // kW: 1 = stream the stored (cos 2psi, sin 2psi) pairs instead of psi.
 template <class S, class C, int NC, int kIn, int kOut, int kW>
-__global__ __launch_bounds__(kTplThreads) void k_templates(
-    const TplInterval* __restrict__ iv, const PtTile* __restrict__ tiles, int64_t n_tiles,
-    const double* __restrict__ det_w, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
-    const cpx<S>* __restrict__ wts, const double* __restrict__ x, const S* __restrict__ tin, S* __restrict__ tout,
-    double* __restrict__ q, RhsBatch rb) {
+__device__ __forceinline__ void templates_interval(
+    const TplInterval& I, const PtTile* __restrict__ tiles, int64_t n_tiles, const double* __restrict__ det_w,
+    const int32_t* __restrict__ sample_k, const S* __restrict__ psi, const cpx<S>* __restrict__ wts,
+    const double* __restrict__ x, const S* __restrict__ tin, S* __restrict__ tout, double* __restrict__ q) {
   constexpr int W = kTplThreads / 64;
   __shared__ double s_sum[kMaxTplOrder * W];
   __shared__ int32_t s_k[2 * W];
   __shared__ double s_w;
   __shared__ double bins[kOut == 1 ? NC * kTplBins : 1];
-  if (rb.done != nullptr && rb.done[(int64_t)blockIdx.y * rb.done_stride]) return;
-  if (x != nullptr) x += blockIdx.y * rb.vstride;
-  if (q != nullptr) q += blockIdx.y * rb.vstride;
-  const TplInterval I = iv[blockIdx.x];
   const int64_t a = I.start, n = I.end - I.start;
   if (n <= 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -280,6 +277,39 @@ __global__ __launch_bounds__(kTplThreads) void k_templates(
   }
 }
 
+// One interval (blockIdx.x) of one right-hand side (blockIdx.y) per workgroup.
+template <class S, class C, int NC, int kIn, int kOut, int kW>
+__global__ __launch_bounds__(kTplThreads) void k_templates(
+    const TplInterval* __restrict__ iv, const PtTile* __restrict__ tiles, int64_t n_tiles,
+    const double* __restrict__ det_w, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
+    const cpx<S>* __restrict__ wts, const double* __restrict__ x, const S* __restrict__ tin, S* __restrict__ tout,
+    double* __restrict__ q, RhsBatch rb) {
+  if (rb.done != nullptr && rb.done[(int64_t)blockIdx.y * rb.done_stride]) return;
+  if (x != nullptr) x += blockIdx.y * rb.vstride;
+  if (q != nullptr) q += blockIdx.y * rb.vstride;
+  templates_interval<S, C, NC, kIn, kOut, kW>(iv[blockIdx.x], tiles, n_tiles, det_w, sample_k, psi, wts, x, tin,
+                                              tout, q);
+}
+
+// Persistent form of q += P^T W P x over the intervals of several slots
+// (right-hand sides of different solves), numbered one after the other; a
+// slot whose done flag is set is skipped.
+template <class S, class C, int NC, int kW>
+__global__ __launch_bounds__(kTplThreads) void k_templates_batch(OpBatch b) {
+  const int64_t n_items = b.off[b.n];
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    int sl = 0;
+    for (int k = 1; k < b.n; ++k) sl = b.off[k] <= it ? k : sl;
+    const OpSlot& o = b.s[sl];
+    if (o.done == nullptr || *o.done == 0)
+      templates_interval<S, C, NC, 1, 1, kW>(static_cast<const TplInterval*>(o.iv)[it - b.off[sl]],
+                                             static_cast<const PtTile*>(o.tiles), o.n_pt_tiles, o.det_w,
+                                             o.sample_k, static_cast<const S*>(o.psi),
+                                             static_cast<const cpx<S>*>(o.wts), o.x, nullptr, nullptr, o.q);
+    __syncthreads();  // the next item reuses the shared memory
+  }
+}
+
 template <class S, class C, int NC, int kIn, int kOut, int kW>
 int launch_one(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tin, void* tout,
                double* q, const RhsBatch& rb, hipStream_t s) {
@@ -325,6 +355,33 @@ int launch_fused_templates(const mm_pointing_s* pt, const mm_noise_s* nz, const 
 int launch_ninv_templates(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
                           hipStream_t s) {
   return launch_nc<3, 0, 0>(pt, nz, nullptr, in, out, nullptr, arith, RhsBatch{}, s);
+}
+
+int launch_templates_batch(const OpBatch& b, int dtype, int arith, bool weights, int ncomp, hipStream_t s) {
+  if (b.n == 0) return MM_OK;
+  const int64_t n_items = b.off[b.n];
+  if (n_items == 0) return MM_OK;
+  // up to three 48 KiB-LDS workgroups per CU on 256 CUs
+  const dim3 g((unsigned)std::min<int64_t>(n_items, 3 * 256)), blk(kTplThreads);
+  return by_ncomp(ncomp, [&]<int NC>() -> int {
+    constexpr int kW1 = NC == 1 ? 0 : 1;  // the intensity-only form reads no angle
+    const bool w = kW1 == 1 && weights;
+    if (dtype == MM_F64) {
+      if (arith == MM_F64) {
+        if (w) hipLaunchKernelGGL((k_templates_batch<double, double, NC, kW1>), g, blk, 0, s, b);
+        else hipLaunchKernelGGL((k_templates_batch<double, double, NC, 0>), g, blk, 0, s, b);
+      } else {
+        if (w) hipLaunchKernelGGL((k_templates_batch<double, float, NC, kW1>), g, blk, 0, s, b);
+        else hipLaunchKernelGGL((k_templates_batch<double, float, NC, 0>), g, blk, 0, s, b);
+      }
+    } else {
+      if (arith == MM_F64) hipLaunchKernelGGL((k_templates_batch<float, double, NC, 0>), g, blk, 0, s, b);
+      else if (w) hipLaunchKernelGGL((k_templates_batch<float, float, NC, kW1>), g, blk, 0, s, b);
+      else hipLaunchKernelGGL((k_templates_batch<float, float, NC, 0>), g, blk, 0, s, b);
+    }
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+  });
 }
 
 }  // namespace mm

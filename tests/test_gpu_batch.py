@@ -57,6 +57,38 @@ def _members(precision):
     return [Member(w, r, precision) for w, r in MEMBERS]
 
 
+class TplMember:
+    """A member with template-filtered white weights: polynomial baselines
+    of degree < order marginalised on intervals of `length` samples."""
+
+    def __init__(self, w, n_rhs, precision, length, order, weights, stokes="IQU"):
+        b = _b()
+        w = w.replace(precision=precision)
+        self.w = w
+        pix, psi = synth.pointing(w)
+        psi = synth.storage(w, psi)
+        offs, wdet = synth.det_offsets(w), synth.det_weight(w)
+        self.opt = oracle.build_pointing(pix, psi, offs, wdet, w.n_pix, stokes=stokes)
+        ivals = np.array(sorted(set(range(0, self.opt.n_samples, length)) | {int(o) for o in offs}), dtype=np.int64)
+        self.noise = oracle.template_noise(ivals, order)
+        m = np.random.default_rng(w.config_id).normal(size=self.opt.ncomp * self.opt.n_kept) * 3.0
+        self.ds = [synth.storage(w, oracle.apply_P(self.opt, m) + synth.noise(w.replace(config_id=w.config_id * 100 + r)))
+                   for r in range(n_rhs)]
+        self.pt = b.Pointing(torch.from_numpy(pix).to(DEV), torch.from_numpy(psi).to(DEV), offs, wdet, w.n_pix,
+                             stokes=stokes)
+        if weights:
+            self.pt.attach_weights()
+        self.nz = b.Noise.templates(wdet, ivals, order, DEV)
+        self.tods = torch.from_numpy(np.stack(self.ds)).to(DEV)
+
+
+def _tpl_members(precision, stokes="IQU"):
+    return [TplMember(synth.Workload("batch_p64_2x60000", 986, 64, 64, 2, 60000, t_psi=900.0), 1, precision,
+                      5003, 3, True, stokes),
+            TplMember(synth.Workload("batch_p40_1x70000_x2", 987, 40, 40, 1, 70000, t_psi=700.0), 2, precision,
+                      3001, 2, False, stokes)]
+
+
 def _run_alone(mb, **opts):
     s = _b().AsyncSolver(mb.pt, mb.nz, mb.tods if mb.tods.shape[0] > 1 else mb.tods[0].contiguous(), **opts)
     while True:
@@ -106,6 +138,40 @@ def test_batch_fixed_iterations_match_alone_and_oracle():
             _, _, x_ref = oracle.solve(mb.opt, mb.noise, mb.ds[r].astype(np.float64), fixed_iters=k)
             err = oracle.rel_l2_per_stokes(x, x_ref)
             assert np.all(err < 1e-10), (mb.w.name, r, err)
+
+
+def test_batch_with_templates_fixed_iterations():
+    # template members beside band-Toeplitz and white ones; the I, Q, U
+    # template problems amplify rounding quickly, so they take few iterations
+    mbs = [Member(*MEMBERS[0], "f64"), Member(*MEMBERS[2], "f64")] + _tpl_members("f64")
+
+    def fixed(mb):
+        return {"fixed_iter": 6 if isinstance(mb, TplMember) else _fixed(mb)["fixed_iter"]}
+
+    outs = _run_batch(mbs, k=4, per_member=fixed, tol=0.0)
+    for mb, out in zip(mbs, outs):
+        k = fixed(mb)["fixed_iter"]
+        alone = _run_alone(mb, fixed_iter=k, tol=0.0)
+        for r in range(len(mb.ds)):
+            assert out["info"][r]["iters"] == k
+            x = out["x"][r].cpu().numpy()
+            err = oracle.rel_l2_per_stokes(x, alone["x"][r].cpu().numpy())
+            assert np.all(err < 1e-10), (mb.w.name, r, err)
+            _, _, x_ref = oracle.solve(mb.opt, mb.noise, mb.ds[r].astype(np.float64), fixed_iters=k)
+            err = oracle.rel_l2_per_stokes(x, x_ref)
+            assert np.all(err < 1e-10), (mb.w.name, r, err)
+
+
+def test_batch_templates_mixed_precision_matches_alone():
+    mbs = _tpl_members("f32", stokes="QU")
+    opts = dict(tol=1e-11, mixed=1, max_outer=20)
+    outs = _run_batch(mbs, k=8, **opts)
+    for mb, out in zip(mbs, outs):
+        alone = _run_alone(mb, **opts)
+        for r in range(len(mb.ds)):
+            assert out["info"][r]["converged"] == 1, (mb.w.name, out["info"][r])
+            err = oracle.rel_l2_per_stokes(out["x"][r].cpu().numpy(), alone["x"][r].cpu().numpy(), ncomp=2)
+            assert np.all(err < 1e-9), (mb.w.name, r, err)
 
 
 def test_batch_mixed_precision_matches_alone():

@@ -152,6 +152,3 @@ def test_argument_checks(setup):
         b.Noise.templates(setup.wdet, np.array([0, n]), 9, DEV)
     with pytest.raises(b.MapMakerError):
         b.Noise.templates(setup.wdet, np.array([3, n]), 1, DEV)
-    s1 = b.AsyncSolver(setup.pt, setup.nz, setup.t_d)
-    with pytest.raises(b.MapMakerError):
-        b.batch_step([s1], 2)
