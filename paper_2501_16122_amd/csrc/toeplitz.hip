@@ -647,7 +647,8 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
   int32_t kmin = INT32_MAX, kmax = -1, nmin = INT32_MAX, nmax = -1;
   constexpr int W = T / 64;
   // the compact-index ranges of the valid outputs (this tile) and of the
-  // samples that become the next tile's carried valid outputs
+  // samples that become the next tile's carried valid outputs (written out
+  // at both places: as one shared lambda it compiled to a slower schedule)
   if constexpr (!P::kLateReduce) {
 #pragma unroll
     for (int i = 0; i < 2 * E; ++i) {
