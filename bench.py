@@ -277,7 +277,7 @@ def batched_section(torch, b, synth, dev, n_solves=16):
     return res
 
 
-def serving_section(torch, b, synth, dev, n_req=24, rate=20.0):
+def serving_section(torch, b, synth, dev, n_req=100, rate=20.0):
     """A seeded Poisson stream of map-making requests of mixed sizes and
     noise models through the continuous-batching server (FP32 storage, FP64
     refinement to 1e-10) vs the same requests as serial plain FP64 solves."""
@@ -505,7 +505,7 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=3, help="timed FP32-refined steps (0 = skip)")
     ap.add_argument("--cpu-det", type=int, default=4, help="detectors in the oracle sample (0 = skip)")
     ap.add_argument("--multi-rhs", type=int, default=8, help="realisations in the multi-RHS measurement (0 = skip)")
-    ap.add_argument("--serve", type=int, default=24, help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--serve", type=int, default=100, help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--batch", type=int, default=16, help="uneven solves in the batched measurement (0 = skip)")
     ap.add_argument("--circulant", type=int, default=1, help="1 = also solve with circulant N^-1 (0 = skip)")
     ap.add_argument("--stokes", type=int, default=1, help="1 = also solve the QU-only and I-only forms (0 = skip)")
