@@ -21,6 +21,7 @@ import json
 import os
 import sys
 import time
+import traceback
 
 import numpy as np
 
@@ -624,19 +625,33 @@ def main():
         "roofline": roof,
     }
 
-    if args.circulant and w.toeplitz:
+    def guarded(key, fn, message):
+        """Run one optional section.  A failure is recorded in the JSON line
+        (traceback on stderr) instead of ending the run, so the headline
+        figures above are always printed."""
+        try:
+            result[key] = fn()
+            log(message(result[key]))
+        except Exception as e:  # reported, not swallowed
+            traceback.print_exc()
+            result[key] = {"error": f"{type(e).__name__}: {e}"}
+
+    def circulant():
         # the same workload with circulant N^-1 (the band filter on periodic
         # chunks): speed, and accuracy of both maps against the input sky
         nzc = b.Noise.circulant(coeff, chunks, dev)
-        step(t_psi, t_d, 0, nzc)
-        torch.cuda.synchronize()
-        c_times, c_infos = [], []
-        for i in range(2):
-            ts = time.perf_counter()
-            info_c, map_c = step(t_psi, t_d, 0, nzc, keep_map=True)
-            c_times.append(time.perf_counter() - ts)
-            c_infos.append(info_c)
-        _, map_t = step(t_psi, t_d, 0, None, keep_map=True)
+        try:
+            step(t_psi, t_d, 0, nzc)
+            torch.cuda.synchronize()
+            c_times, c_infos = [], []
+            for i in range(2):
+                ts = time.perf_counter()
+                info_c, map_c = step(t_psi, t_d, 0, nzc, keep_map=True)
+                c_times.append(time.perf_counter() - ts)
+                c_infos.append(info_c)
+            _, map_t = step(t_psi, t_d, 0, None, keep_map=True)
+        finally:
+            nzc.close()
         kept_np = kept.cpu().numpy()
         truth = m[kept_np]
 
@@ -646,7 +661,7 @@ def main():
 
         dm = (map_c - map_t).cpu().numpy().reshape(-1, 3)[kept_np]
         mt = map_t.cpu().numpy().reshape(-1, 3)[kept_np]
-        result["circulant"] = {
+        return {
             "time_to_map_ms": round(1e3 * float(np.median(c_times)), 3), "pcg_iters": c_infos[-1]["iters"],
             "operator_ms_avg": round(c_infos[-1]["op_ms"] / max(c_infos[-1]["op_launches"], 1), 4),
             "map_error_vs_input_sky_iqu": {"circulant": err(map_c), "band_toeplitz": err(map_t)},
@@ -654,21 +669,8 @@ def main():
                 round(float(np.linalg.norm(dm[:, i]) / np.linalg.norm(mt[:, i])), 6) for i in range(3)],
             "note": "same filter (4096 lags, tapered) on each 2^20-sample chunk taken as periodic; FP64, 1e-10; "
                     "map errors are relative L2 per Stokes of (GLS map - input sky) over kept pixels"}
-        nzc.close()
-        log(f"circulant: {result['circulant']['time_to_map_ms']} ms per map")
 
-    if args.templates and w.toeplitz:
-        result["templates"] = templates_section(torch, b, w, dev, t_pix, t_psi, t_d, t_m, noise, offs, wdet, nz,
-                                                kept, m, step)
-        log("templates: " + ", ".join(f"{k} {v['time_to_map_ms']} ms" for k, v in result["templates"].items()
-                                      if isinstance(v, dict)))
-
-    if args.stokes and w.toeplitz:
-        result["stokes_forms"] = stokes_section(torch, b, w, dev, t_pix, t_psi, t_m, noise, offs, wdet, nz, times)
-        log("map forms: " + ", ".join(f"{k} {v['time_to_map_ms']} ms" for k, v in result["stokes_forms"].items()
-                                        if isinstance(v, dict)))
-
-    if args.fp32_steps > 0:
+    def fp32_refined():
         psi32 = t_psi.float()
         d32 = t_d.float()
         torch.cuda.synchronize()
@@ -681,29 +683,43 @@ def main():
             f_times.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         ftm = float(np.median(f_times))
-        result["fp32_refined"] = {
+        return {
             "time_to_map_ms": {"p50": round(1e3 * ftm, 3), "p99": round(1e3 * float(np.percentile(f_times, 99)), 3)},
             "inner_iters": f_infos[-1]["iters"], "outer_iters": f_infos[-1]["outer_iters"],
             "final_true_rel_resid": max(i["true_rel_resid"] for i in f_infos),
             "speedup_vs_fp64": round(float(np.median(times)) / ftm, 3),
             "note": "psi and d rounded to FP32 once; inner PCG with FP32 timeline arithmetic, FP64 refinement"}
-        log(f"FP32-refined: {1e3 * ftm:.1f} ms per map")
 
+    def forms_line(name, r):
+        return name + ": " + ", ".join(f"{k} {v['time_to_map_ms']} ms" for k, v in r.items() if isinstance(v, dict))
+
+    if args.circulant and w.toeplitz:
+        guarded("circulant", circulant, lambda r: f"circulant: {r['time_to_map_ms']} ms per map")
+    if args.templates and w.toeplitz:
+        guarded("templates", lambda: templates_section(torch, b, w, dev, t_pix, t_psi, t_d, t_m, noise, offs, wdet,
+                                                       nz, kept, m, step),
+                lambda r: forms_line("templates", r))
+    if args.stokes and w.toeplitz:
+        guarded("stokes_forms", lambda: stokes_section(torch, b, w, dev, t_pix, t_psi, t_m, noise, offs, wdet, nz,
+                                                       times),
+                lambda r: forms_line("map forms", r))
+    if args.fp32_steps > 0:
+        guarded("fp32_refined", fp32_refined, lambda r: f"FP32-refined: {r['time_to_map_ms']['p50']:.1f} ms per map")
     if args.multi_rhs > 0:
         torch.cuda.empty_cache()
-        result["multi_rhs"] = multi_rhs_section(torch, b, synth, dev, args.multi_rhs)
-        log(f"multi-RHS: {result['multi_rhs']['time_to_maps_ms']} ms for {args.multi_rhs} maps")
+        guarded("multi_rhs", lambda: multi_rhs_section(torch, b, synth, dev, args.multi_rhs),
+                lambda r: f"multi-RHS: {r['time_to_maps_ms']} ms for {args.multi_rhs} maps")
         torch.cuda.empty_cache()
     if args.batch > 0:
-        result["batched"] = batched_section(torch, b, synth, dev, min(args.batch, 16))
-        log(f"batched: {result['batched']['time_to_all_maps_ms']} ms for {args.batch} maps")
+        guarded("batched", lambda: batched_section(torch, b, synth, dev, min(args.batch, 16)),
+                lambda r: f"batched: {r['time_to_all_maps_ms']} ms for {args.batch} maps")
     if args.serve > 0:
-        result["serving"] = serving_section(torch, b, synth, dev, args.serve)
-        log(f"serving: {result['serving']['solves_per_s']} solves/s")
+        guarded("serving", lambda: serving_section(torch, b, synth, dev, args.serve),
+                lambda r: f"serving: {r['solves_per_s']} solves/s")
     if args.cpu_det > 0:
         t0 = time.perf_counter()
-        result["cpu_baseline"] = cpu_baseline(w, pix, psi, d_host, min(args.cpu_det, w.n_det))
-        log(f"cpu baseline in {time.perf_counter() - t0:.1f} s")
+        guarded("cpu_baseline", lambda: cpu_baseline(w, pix, psi, d_host, min(args.cpu_det, w.n_det)),
+                lambda r: f"cpu baseline in {time.perf_counter() - t0:.1f} s")
 
     print(json.dumps(result))
 
