@@ -269,7 +269,15 @@ struct PcgState {
   uint32_t counter;
   int32_t pad_;
 };
-constexpr int kPcgBlocks = 512;   // fixed grid of the vector kernels (deterministic sums)
+constexpr int kPcgBlocks = 256;   // largest grid of the vector kernels (partial sums per block)
+// Grid of the vector kernels for a problem: fixed by its size, so its sums
+// are deterministic; larger grids spend more on the per-block partial sums
+// than they gain in memory parallelism (64 blocks for small maps, 256 at
+// 512^2 and beyond).
+inline int pcg_blocks(int32_t n_kept) {
+  const int g = n_kept / 1024;
+  return g < 64 ? 64 : (g > kPcgBlocks ? kPcgBlocks : g);
+}
 constexpr int kPcgThreads = 256;
 constexpr int32_t kPcgDoneStride = (int32_t)(sizeof(PcgState) / sizeof(int32_t));
 

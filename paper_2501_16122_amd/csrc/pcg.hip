@@ -9,9 +9,11 @@
 // alpha, beta, ||b||, the iteration count, a "done" flag) live in device
 // memory, so chunks of iterations are enqueued without host round trips and
 // every kernel of a slice returns at once when that slice is done.  Dot
-// products are deterministic: a fixed grid of kPcgBlocks blocks with a fixed
-// pixel assignment writes per-block partials and the last block to finish
-// (an atomic ticket) sums them in a fixed order.
+// products are deterministic: a grid fixed by the problem size
+// (pcg_blocks) with a fixed pixel assignment writes per-block partials and
+// the last block to finish (an atomic ticket) sums them in a fixed order.
+#include <algorithm>
+
 #include "mm_internal.h"
 
 namespace mm {
@@ -461,69 +463,78 @@ __global__ __launch_bounds__(kPcgThreads) void k_diff_norm(PcgArgs A, const doub
   }
 }
 
+dim3 grid(const PcgArgs& a, int nrhs) { return dim3(pcg_blocks(a.n_kept), nrhs); }
+
+// one grid for every slot of a batch: the largest any member would use
+dim3 grid(const PcgBatch& b) {
+  int g = 64;
+  for (int i = 0; i < b.n; ++i) g = std::max(g, pcg_blocks(b.s[i].A.n_kept));
+  return dim3(g, b.n);
+}
+
 }  // namespace
 
 int launch_pcg_init(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, double tol, int32_t max_iter,
                     int32_t fixed_iter, const OuterState* gate, hipStream_t s, bool from_x0) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a, pt->minv, tol, max_iter,
+  hipLaunchKernelGGL(k_pcg_init, grid(a, nrhs), dim3(kPcgThreads), 0, s, a, pt->minv, tol, max_iter,
                      fixed_iter, gate, (int32_t)from_x0);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
 int launch_pcg_iteration_tail(const mm_pointing_s* pt, const PcgArgs& a, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a);
-  hipLaunchKernelGGL(k_pcg_update, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a, pt->minv);
-  hipLaunchKernelGGL(k_pcg_direction, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a);
+  hipLaunchKernelGGL(k_pcg_alpha, grid(a, nrhs), dim3(kPcgThreads), 0, s, a);
+  hipLaunchKernelGGL(k_pcg_update, grid(a, nrhs), dim3(kPcgThreads), 0, s, a, pt->minv);
+  hipLaunchKernelGGL(k_pcg_direction, grid(a, nrhs), dim3(kPcgThreads), 0, s, a);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
 int launch_diff_norm(const PcgArgs& a, int nrhs, const double* x, const double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_diff_norm, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, a, x, y);
+  hipLaunchKernelGGL(k_diff_norm, grid(a, nrhs), dim3(kPcgThreads), 0, s, a, x, y);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
 int launch_outer_init(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s, bool from_x0) {
-  hipLaunchKernelGGL(k_outer_init, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, o, a, (int32_t)from_x0);
+  hipLaunchKernelGGL(k_outer_init, grid(a, nrhs), dim3(kPcgThreads), 0, s, o, a, (int32_t)from_x0);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
 int launch_outer_add(const OuterArgs& o, const PcgArgs& a, int nrhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_add, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, o, a);
+  hipLaunchKernelGGL(k_outer_add, grid(a, nrhs), dim3(kPcgThreads), 0, s, o, a);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
 int launch_outer_end(const OuterArgs& o, const PcgArgs& a, int nrhs, double tol, int32_t max_outer,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_end, dim3(kPcgBlocks, nrhs), dim3(kPcgThreads), 0, s, o, a, tol, max_outer);
+  hipLaunchKernelGGL(k_outer_end, grid(a, nrhs), dim3(kPcgThreads), 0, s, o, a, tol, max_outer);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
 int launch_pcg_iteration_tail_batch(const PcgBatch& b, hipStream_t s) {
   if (b.n == 0) return MM_OK;
-  hipLaunchKernelGGL(k_pcg_alpha_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
-  hipLaunchKernelGGL(k_pcg_update_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
-  hipLaunchKernelGGL(k_pcg_direction_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
+  hipLaunchKernelGGL(k_pcg_alpha_b, grid(b), dim3(kPcgThreads), 0, s, b);
+  hipLaunchKernelGGL(k_pcg_update_b, grid(b), dim3(kPcgThreads), 0, s, b);
+  hipLaunchKernelGGL(k_pcg_direction_b, grid(b), dim3(kPcgThreads), 0, s, b);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
 int launch_outer_add_batch(const PcgBatch& b, hipStream_t s) {
   if (b.n == 0) return MM_OK;
-  hipLaunchKernelGGL(k_outer_add_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
+  hipLaunchKernelGGL(k_outer_add_b, grid(b), dim3(kPcgThreads), 0, s, b);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
 int launch_outer_end_batch(const PcgBatch& b, hipStream_t s) {
   if (b.n == 0) return MM_OK;
-  hipLaunchKernelGGL(k_outer_end_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
-  hipLaunchKernelGGL(k_pcg_reinit_b, dim3(kPcgBlocks, b.n), dim3(kPcgThreads), 0, s, b);
+  hipLaunchKernelGGL(k_outer_end_b, grid(b), dim3(kPcgThreads), 0, s, b);
+  hipLaunchKernelGGL(k_pcg_reinit_b, grid(b), dim3(kPcgThreads), 0, s, b);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }

@@ -79,7 +79,7 @@ def footprint_bytes(w: synth.Workload, opts: b.SolveOpts, weights: bool) -> int:
     # solver vectors with every pixel kept (upper bound)
     n3 = 3 * w.n_pix
     hist = max(opts.max_iter, opts.fixed_iter) + opts.max_outer + 2
-    total += 9 * n3 * 8 + 4 * 2 * 512 * 8 + 8 * hist + 4096
+    total += 9 * n3 * 8 + 4 * 2 * 256 * 8 + 8 * hist + 4096
     return int(total)
 
 
