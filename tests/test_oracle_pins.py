@@ -424,6 +424,139 @@ def test_binned_config1_mask_margin():
 
 
 # ---------------------------------------------------------------------------
+# helpers every parity check rests on: the per-Stokes error metric, the
+# mask-decision margin and the expansion to the full grid
+# ---------------------------------------------------------------------------
+
+def _stokes_fixture():
+    """Six grid pixels, four kept; per-Stokes scales 1e2 (I), 1 (Q), 1e-3 (U)
+    so that the three per-component errors and a joint IQU norm differ by
+    orders of magnitude.  Masked rows 1 and 4 carry huge differences that
+    must not count."""
+    ref = np.array([[100.0, 1.0, 0.001],
+                    [7.0, 7.0, 7.0],
+                    [-200.0, 2.0, 0.002],
+                    [300.0, -1.0, 0.0],
+                    [7.0, 7.0, 7.0],
+                    [50.0, 0.5, -0.004]])
+    m = ref.copy()
+    m[0, 0] += 1.0          # I error 1
+    m[2, 1] += 0.02         # Q error 0.02
+    m[5, 2] += 1e-4         # U error 1e-4
+    m[1] += 1e6             # masked pixels: ignored
+    m[4] -= 1e6
+    kept = np.array([0, 2, 3, 5])
+    return m, ref, kept
+
+
+def test_rel_l2_per_stokes_closed_form():
+    # relative L2 per Stokes parameter over kept pixels (the design reading of
+    # the relative-L2 bar): by hand, I 1/sqrt(100^2+200^2+300^2+50^2),
+    # Q 0.02/sqrt(1+4+1+0.25) = 0.008, U 1e-4/sqrt(1e-6+4e-6+16e-6)
+    m, ref, kept = _stokes_fixture()
+    got = om.rel_l2_per_stokes(m.reshape(-1), ref.reshape(-1), kept=kept)
+    expect = [1.0 / math.sqrt(142500.0), 0.008, 1e-4 / math.sqrt(2.1e-5)]
+    assert got.shape == (3,)
+    assert np.allclose(got, expect, rtol=1e-12, atol=0)
+    # the same from an explicit loop over components and kept pixels
+    for j in range(3):
+        num = sum((m[p, j] - ref[p, j]) ** 2 for p in kept)
+        den = sum(ref[p, j] ** 2 for p in kept)
+        assert got[j] == pytest.approx(math.sqrt(num / den), rel=1e-13)
+    # a joint IQU norm would be I-dominated, orders of magnitude below U's
+    joint = math.sqrt(1.0 + 0.02 ** 2 + 1e-8) / math.sqrt(142500.0 + 6.25 + 2.1e-5)
+    assert got[2] > 5 * joint and got[1] > 2 * joint
+    # compact vectors (no kept selection) give the same values
+    got_c = om.rel_l2_per_stokes(m[kept].reshape(-1), ref[kept].reshape(-1))
+    assert np.allclose(got_c, expect, rtol=1e-12, atol=0)
+
+
+def test_rel_l2_per_stokes_forms_and_zero_reference():
+    m, ref, kept = _stokes_fixture()
+    # Q, U form: two values per pixel, in that order
+    qu = om.rel_l2_per_stokes(m[kept, 1:].reshape(-1), ref[kept, 1:].reshape(-1), ncomp=2)
+    assert np.allclose(qu, [0.008, 1e-4 / math.sqrt(2.1e-5)], rtol=1e-12, atol=0)
+    # I form: one value per pixel
+    i_only = om.rel_l2_per_stokes(m[kept, 0], ref[kept, 0], ncomp=1)
+    assert np.allclose(i_only, [1.0 / math.sqrt(142500.0)], rtol=1e-12, atol=0)
+    # an all-zero reference component reports the absolute error (3-4-5)
+    z_ref = np.zeros((2, 3))
+    z = np.zeros((2, 3))
+    z[0, 2], z[1, 2] = 3e-3, 4e-3
+    assert np.allclose(om.rel_l2_per_stokes(z.reshape(-1), z_ref.reshape(-1)), [0.0, 0.0, 5e-3], rtol=1e-13)
+
+
+def _margin_problem():
+    """Pixel 0: four samples at 2psi = 0, pi/2, pi, 3pi/2 from detectors of
+    weight 998, 1, 998, 1, so B = diag(1998, 1996, 2) and cond = 999 (4 hits).
+    Pixel 1: six samples at equispaced 2psi, cond = 2.  Pixel 2: unseen."""
+    psi0 = np.array([0.0, np.pi / 4, np.pi / 2, 3 * np.pi / 4])
+    psi1 = 0.5 * (0.2 + 2 * np.pi * np.arange(6) / 6)
+    pix = np.array([0, 0, 0, 0, 1, 1, 1, 1, 1, 1], np.int32)
+    psi = np.concatenate([psi0, psi1])
+    offs = np.array([0, 1, 2, 3, 4, 10])
+    wdet = np.array([998.0, 1.0, 998.0, 1.0, 1.0])
+    return pix, psi, offs, wdet
+
+
+def test_mask_margin_closed_forms():
+    # equispaced pixel alone: cond = 2, margin log10(1000 / 2) = log10(500)
+    K = 5
+    psi = 0.5 * (0.3 + 2 * np.pi * np.arange(K) / K)
+    pt = om.build_pointing(np.zeros(K, np.int32), psi, [0, K], [1.0], 1)
+    assert om.mask_margin(pt) == pytest.approx(math.log10(500.0), rel=1e-12)
+    # the axis-aligned pixel on either side of the threshold: cond 999 (kept)
+    # and 1001 (masked) are both log10(1000/999) resp. log10(1001/1000) away
+    for n0, cond in ((998, 999.0), (1000, 1001.0)):
+        pix, psi = _two_axis_pixel(n0, 1)
+        pt = om.build_pointing(pix, psi, [0, pix.size], [1.0], 1)
+        assert om.mask_margin(pt) == pytest.approx(abs(math.log10(cond / 1000.0)), rel=1e-6)
+    # several pixels: the smallest distance wins; pixels with fewer than
+    # min_hits hits (and unseen ones, cond = inf) take no part
+    pix, psi, offs, wdet = _margin_problem()
+    pt = om.build_pointing(pix, psi, offs, wdet, 3)
+    assert pt.cond[0] == pytest.approx(999.0, rel=1e-12) and pt.hits[0] == 4
+    assert pt.cond[1] == pytest.approx(2.0, rel=1e-12) and not np.isfinite(pt.cond[2])
+    assert om.mask_margin(pt) == pytest.approx(math.log10(1000.0 / 999.0), rel=1e-9)
+    assert om.mask_margin(pt, min_hits=5) == pytest.approx(math.log10(500.0), rel=1e-12)
+    # the threshold itself moves the distance: cond_max = 999 puts pixel 0 on it
+    assert om.mask_margin(pt, cond_max=999.0) == pytest.approx(0.0, abs=1e-12)
+    # no pixel qualifies: infinite margin
+    assert om.mask_margin(pt, min_hits=100) == np.inf
+
+
+def _expand_problem(stokes):
+    """Seven grid pixels: 0, 2, 3 and 5 seen six times at equispaced angles
+    (kept), 1 twice, 6 once, 4 never (masked: fewer than 3 hits in either
+    form)."""
+    eq = 0.5 * (0.1 + 2 * np.pi * np.arange(6) / 6)
+    pix, psi = [], []
+    for p, n in ((0, 6), (1, 2), (2, 6), (3, 6), (5, 6), (6, 1)):
+        pix += [p] * n
+        psi += list(eq[:n])
+    pix = np.array(pix, np.int32)
+    return om.build_pointing(pix, np.array(psi), [0, pix.size], [1.0], 7, min_hits=3, stokes=stokes)
+
+
+def test_expand_places_each_value():
+    # compact unknowns interleaved per kept pixel (eq. (8)'s s vector): kept
+    # pixel k holds (10k+1, 10k+2, 10k+3); every value lands at its grid
+    # pixel and component, masked pixels hold 0
+    pt = _expand_problem("IQU")
+    assert pt.kept.tolist() == [0, 2, 3, 5]
+    x = np.array([1, 2, 3, 11, 12, 13, 21, 22, 23, 31, 32, 33], float)
+    out = om.expand(pt, x)
+    expect = [[1, 2, 3], [0, 0, 0], [11, 12, 13], [21, 22, 23], [0, 0, 0], [31, 32, 33], [0, 0, 0]]
+    assert out.shape == (7, 3)
+    assert out.tolist() == expect
+    # the Q, U form: two values per pixel
+    pt2 = _expand_problem("QU")
+    assert pt2.kept.tolist() == [0, 2, 3, 5]
+    out2 = om.expand(pt2, np.array([1, 2, 11, 12, 21, 22, 31, 32], float))
+    assert out2.tolist() == [[1, 2], [0, 0], [11, 12], [21, 22], [0, 0], [31, 32], [0, 0]]
+
+
+# ---------------------------------------------------------------------------
 # planted mistakes: each must trip at least one pin above
 # ---------------------------------------------------------------------------
 
@@ -523,6 +656,71 @@ def test_planted_transposed_inverse_block(monkeypatch):
     monkeypatch.setattr(om, "apply_M", bad)
     assert not _run_pin(test_apply_M_is_inverse_block)
     monkeypatch.setattr(om, "apply_M", real)
+
+
+def test_planted_joint_iqu_norm(monkeypatch):
+    def joint(m, m_ref, kept=None, ncomp=3):
+        m = np.asarray(m, float).reshape(-1, ncomp)
+        r = np.asarray(m_ref, float).reshape(-1, ncomp)
+        if kept is not None:
+            m, r = m[kept], r[kept]
+        return np.full(ncomp, np.linalg.norm(m - r) / np.linalg.norm(r))
+
+    monkeypatch.setattr(om, "rel_l2_per_stokes", joint)
+    assert not _run_pin(test_rel_l2_per_stokes_closed_form)
+
+
+def test_planted_per_pixel_axis(monkeypatch):
+    def wrong_axis(m, m_ref, kept=None, ncomp=3):
+        m = np.asarray(m, float).reshape(-1, ncomp)
+        r = np.asarray(m_ref, float).reshape(-1, ncomp)
+        if kept is not None:
+            m, r = m[kept], r[kept]
+        return np.linalg.norm(m - r, axis=1) / np.linalg.norm(r, axis=1)
+
+    monkeypatch.setattr(om, "rel_l2_per_stokes", wrong_axis)
+    assert not _run_pin(test_rel_l2_per_stokes_closed_form)
+
+
+def test_planted_kept_ignored(monkeypatch):
+    real = om.rel_l2_per_stokes
+    monkeypatch.setattr(om, "rel_l2_per_stokes", lambda m, m_ref, kept=None, ncomp=3: real(m, m_ref, None, ncomp))
+    assert not _run_pin(test_rel_l2_per_stokes_closed_form)
+
+
+def test_planted_signed_margin(monkeypatch):
+    def signed(pt, cond_max=1e3, min_hits=None):
+        sel = (pt.hits >= (pt.ncomp if min_hits is None else min_hits)) & np.isfinite(pt.cond)
+        return float(np.min(np.log10(pt.cond[sel] / cond_max))) if np.any(sel) else np.inf
+
+    monkeypatch.setattr(om, "mask_margin", signed)
+    assert not _run_pin(test_mask_margin_closed_forms)
+
+
+def test_planted_margin_ignores_min_hits(monkeypatch):
+    real = om.mask_margin
+    monkeypatch.setattr(om, "mask_margin", lambda pt, cond_max=1e3, min_hits=None: real(pt, cond_max, 1))
+    assert not _run_pin(test_mask_margin_closed_forms)
+
+
+def test_planted_transposed_interleave(monkeypatch):
+    def transposed(pt, x):
+        out = np.zeros((pt.n_pix, pt.ncomp))
+        out[pt.kept] = np.asarray(x, float).reshape(pt.ncomp, -1).T
+        return out
+
+    monkeypatch.setattr(om, "expand", transposed)
+    assert not _run_pin(test_expand_places_each_value)
+
+
+def test_planted_expand_compact_positions(monkeypatch):
+    def compact_rows(pt, x):
+        out = np.zeros((pt.n_pix, pt.ncomp))
+        out[:pt.n_kept] = np.asarray(x, float).reshape(-1, pt.ncomp)
+        return out
+
+    monkeypatch.setattr(om, "expand", compact_rows)
+    assert not _run_pin(test_expand_places_each_value)
 
 
 # ---- circulant N^-1 per chunk (Sec. IV) ------------------------------------
