@@ -31,6 +31,11 @@ sys.path.insert(0, ROOT)
 METRIC = "TOD samples/s per PCG iter + time-to-map @1e-10 (FP64 vs FP32-refined); p99"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# algorithmic HBM bytes per timeline sample of one fused P^T N^-1 P launch:
+# int32 pixel index + FP64 angle (the map and the noise tables stay in cache)
+ALG_BYTES_PER_SAMPLE_F64 = 12.0
+# what the band-Toeplitz kernel streams instead: the index + stored FP64 (cos 2psi, sin 2psi)
+STREAMED_BYTES_PER_SAMPLE_TOEPLITZ = 20.0
 # source files of the dominant kernel (the fused band-Toeplitz A); a stored
 # counter summary is used only while these are unchanged
 KERNEL_SOURCES = ["paper_2501_16122_amd/csrc/toeplitz.hip", "paper_2501_16122_amd/csrc/fft_lds.h",
@@ -96,12 +101,114 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
     return round(gbs, 1)
 
 
-def cpu_baseline(w, pix, psi, d, n_det_sample):
-    """The FP64 oracle on the first n_det_sample detectors of the same
-    workload, single process: build + per-iteration time of A = P^T N^-1 P."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, pix, psi, d, n_det_sample, pool_workers):
+    """The FP64 oracle timed on the host's cores: (i) one process on the
+    first n_det_sample detectors of the workload; (ii) pool_workers processes,
+    one detector block each, summing their partial A = P^T N^-1 P vectors
+    (chunks never cross detectors, so the blocks are independent)."""
     from threadpoolctl import threadpool_limits
     with threadpool_limits(1):
-        return _cpu_baseline(w, pix, psi, d, n_det_sample)
+        single = _cpu_baseline(w, pix, psi, d, n_det_sample)
+    out = dict(single)
+    if pool_workers > 1:
+        pool = _cpu_pool_baseline(w, pix, psi, pool_workers)
+        out = dict(pool)
+        out["single_process"] = single
+    out["cpu_model"] = cpu_model()
+    out["host_cpu_count"] = os.cpu_count()
+    return out
+
+
+def _pool_worker(slot, pix, psi, det_offsets, det_weight, compact, kept, n_pix, coeff, chunk_offsets, x_raw,
+                 q_raw, n3, n_workers, go, done):
+    """One worker of the pooled oracle baseline: A x on its detector block,
+    with the compact pixel numbering of the whole sample, into its row of
+    the shared partial-sum array."""
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+    import oracle.mapmaking as oracle
+    c, s = oracle.pointing_weights(psi)
+    sub = oracle.Pointing(pix=pix, cos2=c, sin2=s, weight=oracle.sample_weights(det_offsets, det_weight),
+                          n_pix=n_pix, hits=None, blocks=None, cond=None, mask=None, kept=kept, compact=compact,
+                          minv=None, sample_k=compact[pix])
+    noise = oracle.toeplitz_noise(coeff, chunk_offsets)
+    x = np.frombuffer(x_raw, dtype=np.float64)
+    q = np.frombuffer(q_raw, dtype=np.float64).reshape(n_workers, n3)
+    done.put(("ready", slot))
+    while True:
+        if go.get() is None:
+            return
+        q[slot] = oracle.apply_A(sub, noise, x)
+        done.put(("done", slot))
+
+
+def _cpu_pool_baseline(w, pix, psi, n_workers):
+    import multiprocessing as mp
+
+    import oracle.mapmaking as oracle
+    from paper_2501_16122_amd import synth
+    nd = n_workers  # one detector per worker
+    ns = nd * w.n_samp
+    ws = w.replace(n_det=nd)
+    offs, wdet = synth.det_offsets(ws), synth.det_weight(ws)
+    t0 = time.perf_counter()
+    opt = oracle.build_pointing(pix[:ns], psi[:ns], offs, wdet, w.n_pix)
+    t_build = time.perf_counter() - t0
+    coeff = synth.toeplitz_coeff(ws)
+    n3 = 3 * opt.n_kept
+    ctx = mp.get_context("spawn")  # fresh interpreters: the workers never touch the GPU
+    x_raw = ctx.RawArray("d", n3)
+    q_raw = ctx.RawArray("d", n_workers * n3)
+    gos = [ctx.Queue() for _ in range(n_workers)]
+    done = ctx.Queue()
+    procs = []
+    for i in range(n_workers):
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        one = ws.replace(n_det=1)
+        procs.append(ctx.Process(target=_pool_worker, args=(
+            i, pix[lo:hi], psi[lo:hi], synth.det_offsets(one), wdet[i:i + 1], opt.compact, opt.kept, w.n_pix,
+            coeff, synth.chunk_offsets(one), x_raw, q_raw, n3, n_workers, gos[i], done)))
+    for p in procs:
+        p.start()
+    try:
+        for _ in range(n_workers):
+            done.get(timeout=600)
+        x = np.frombuffer(x_raw, dtype=np.float64)
+        q = np.frombuffer(q_raw, dtype=np.float64).reshape(n_workers, n3)
+        x[:] = np.random.default_rng(0).normal(size=n3)
+        reps = 0
+        t0 = time.perf_counter()
+        while reps < 3 or (time.perf_counter() - t0 < 10.0 and reps < 60):
+            for g in gos:
+                g.put(1)
+            for _ in range(n_workers):
+                done.get(timeout=600)
+            z = oracle.apply_M(opt, q.sum(axis=0))
+            x[:] = z / np.linalg.norm(z)
+            reps += 1
+        t_iter = (time.perf_counter() - t0) / reps
+    finally:
+        for g in gos:
+            g.put(None)
+        for p in procs:
+            p.join(timeout=60)
+    return {"value": ns / t_iter, "unit": "TOD samples/s per PCG iteration", "cores": n_workers, "kind": "oracle",
+            "sample": f"first {nd} of {w.n_det} detectors ({ns} samples) of the same workload, one detector per "
+                      f"process ({n_workers} processes, 1 thread each); {reps} applications of A = P^T N^-1 P "
+                      f"(partial vectors summed in shared memory) + M; oracle build of that sample "
+                      f"{t_build:.2f} s in one process",
+            "ms_per_iter": 1e3 * t_iter}
 
 
 def _cpu_baseline(w, pix, psi, d, n_det_sample):
@@ -278,19 +385,24 @@ def batched_section(torch, b, synth, dev, n_solves=16):
     return res
 
 
-def serving_section(torch, b, synth, dev, n_req=100, rate=20.0):
+def serving_section(torch, b, synth, dev, n_req=24, rate=20.0):
     """A seeded Poisson stream of map-making requests of mixed sizes and
     noise models through the continuous-batching server (FP32 storage, FP64
-    refinement to 1e-10) vs the same requests as serial plain FP64 solves."""
+    refinement to 1e-10) vs the same requests as serial plain FP64 solves.
+    Request sizes span the whole serving range: detectors 4-256, samples per
+    detector 2^18-2^23, grid side 64-1024 (each log-uniform), white noise
+    (binned scan, T_psi 200) or 1/f with the 4096-lag band-Toeplitz N^-1 on
+    2^20-sample chunks (GLS scan, T_psi 6000), 50/50; n_req is cut, not the
+    ranges."""
     from paper_2501_16122_amd import serve
 
     def sizes(rng, i):
-        side = serve.log_uniform_int(rng, 64, 512)
-        n_det = serve.log_uniform_int(rng, 4, 32)
-        n_samp = serve.log_uniform_int(rng, 1 << 18, 1 << 21)
+        side = serve.log_uniform_int(rng, 64, 1024)
+        n_det = serve.log_uniform_int(rng, 4, 256)
+        n_samp = serve.log_uniform_int(rng, 1 << 18, 1 << 23)
         toep = rng.uniform() < 0.5
-        return synth.Workload(f"req{i}", 5000 + i, side, side, n_det, n_samp, t_psi=1000.0,
-                              noise="oneoverf" if toep else "white", chunk=(1 << 18) if toep else 0,
+        return synth.Workload(f"req{i}", 5000 + i, side, side, n_det, n_samp, t_psi=6000.0 if toep else 200.0,
+                              noise="oneoverf" if toep else "white", chunk=(1 << 20) if toep else 0,
                               lam=4096 if toep else 0, precision="f32")
 
     def make_d(w, pix, psi):
@@ -304,7 +416,11 @@ def serving_section(torch, b, synth, dev, n_req=100, rate=20.0):
         return d
 
     t0 = time.perf_counter()
-    reqs = [serve.materialize(r, make_d) for r in serve.poisson_requests(n_req, rate, sizes, seed_id=5)]
+    reqs = []
+    for r in serve.poisson_requests(n_req, rate, sizes, seed_id=5):
+        reqs.append(serve.materialize(r, make_d))
+        log(f"serving: request {r.rid} ({r.workload.n_det} x {r.workload.n_samp} samples, "
+            f"{r.workload.width}^2, {r.workload.noise}) drawn")
     arrivals = np.array([r.arrival for r in reqs])
     n_samples = sum(r.workload.n_samples for r in reqs)
     log(f"serving: {n_req} requests, {n_samples} samples, inputs in {time.perf_counter() - t0:.1f} s")
@@ -361,6 +477,10 @@ def serving_section(torch, b, synth, dev, n_req=100, rate=20.0):
             "all_converged": ok,
             "serial_plain_fp64_solves_per_s": round(n_req / float(np.sum(service)), 3),
             "serial_plain_fp64_latency_ms": pct(serial_lat),
+            "ranges": "detectors 4-256, samples/detector 2^18-2^23, grid side 64-1024 (log-uniform), white or "
+                      "1/f band-Toeplitz (4096 lags, 2^20-sample chunks) 50/50; Poisson arrivals",
+            "request_samples_min_max": [min(r.workload.n_samples for r in reqs),
+                                        max(r.workload.n_samples for r in reqs)],
             "note": "solves/s: all requests queued at once (FP32 storage, FP64 refinement to 1e-10, up to 8 "
                     "overlapping solves, one stream each or batched steps); latency: the seeded Poisson arrivals "
                     "in real time; the top-level figures are the faster mode's. Serial baseline: "
@@ -505,8 +625,10 @@ def main():
     ap.add_argument("--workload", default="gls", choices=["gls", "shard", "binned"])
     ap.add_argument("--fp32-steps", type=int, default=3, help="timed FP32-refined steps (0 = skip)")
     ap.add_argument("--cpu-det", type=int, default=4, help="detectors in the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes of the pooled oracle baseline (one detector each; <= 1 = skip)")
     ap.add_argument("--multi-rhs", type=int, default=8, help="realisations in the multi-RHS measurement (0 = skip)")
-    ap.add_argument("--serve", type=int, default=100, help="requests in the serving measurement (0 = skip)")
+    ap.add_argument("--serve", type=int, default=24, help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--batch", type=int, default=16, help="uneven solves in the batched measurement (0 = skip)")
     ap.add_argument("--circulant", type=int, default=1, help="1 = also solve with circulant N^-1 (0 = skip)")
     ap.add_argument("--stokes", type=int, default=1, help="1 = also solve the QU-only and I-only forms (0 = skip)")
@@ -582,10 +704,13 @@ def main():
     op_ms = sum(i["op_ms"] for i in infos)
     op_n = sum(i["op_launches"] for i in infos)
     kernel_ms = op_ms / max(op_n, 1)
-    # streamed per sample: int32 compact index + FP64 (cos 2psi, sin 2psi) for
-    # the band-Toeplitz operator; int32 index + FP64 psi for the white one
-    alg_bytes = (20.0 if w.toeplitz else 12.0) * w.n_samples
+    # algorithmic bytes per sample of the fused iteration: the int32 pixel
+    # index and the FP64 angle psi (12 B), whatever the kernel streams
+    alg_bytes = ALG_BYTES_PER_SAMPLE_F64 * w.n_samples
     achieved_gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    # what the kernel actually streams per sample: the index and the stored
+    # FP64 (cos 2psi, sin 2psi) pair (band-Toeplitz), or the index and psi (white)
+    streamed = (STREAMED_BYTES_PER_SAMPLE_TOEPLITZ if w.toeplitz else ALG_BYTES_PER_SAMPLE_F64) * w.n_samples
     roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(),
             "kernel": ((f"k_toeplitz_carry<double,double,weights>" if infos[-1]["op_variant"] & 4
@@ -593,7 +718,10 @@ def main():
             if w.toeplitz else "k_fused_white<double,double>",
             "kernel_ms_avg": round(kernel_ms, 4), "launches": op_n,
             "op_variant": infos[-1]["op_variant"],
+            "algorithmic_bytes_per_sample": ALG_BYTES_PER_SAMPLE_F64,
             "algorithmic_bytes_per_launch": alg_bytes,
+            "streamed_bytes_per_launch": streamed,
+            "streamed_gbs": round(streamed / (kernel_ms * 1e-3) / 1e9, 1),
             "measured_copy_gbs": copy_bandwidth(torch, dev)}
     if w.toeplitz:
         flops = fft_flops_per_launch(w)
@@ -670,6 +798,20 @@ def main():
             "note": "same filter (4096 lags, tapered) on each 2^20-sample chunk taken as periodic; FP64, 1e-10; "
                     "map errors are relative L2 per Stokes of (GLS map - input sky) over kept pixels"}
 
+    def solve_x(psi_t, d_t, **opts):
+        # one map from these inputs; the compact solution on the host
+        pt = b.Pointing(t_pix, psi_t, offs, wdet, w.n_pix, w.min_hits, w.cond_max)
+        if w.toeplitz:
+            pt.attach_weights()
+        out = b.Solver(pt, nz, check_every=8, autotune=1, **opts).solve(d_t)
+        n_kept = pt.n_kept
+        pt.close()
+        return out["x"].cpu().numpy().reshape(-1, 3), out["info"], n_kept
+
+    def stokes_rel(x, ref):
+        # relative L2 error per Stokes parameter (I, Q, U) over kept pixels
+        return [float(np.linalg.norm(x[:, i] - ref[:, i]) / np.linalg.norm(ref[:, i])) for i in range(3)]
+
     def fp32_refined():
         psi32 = t_psi.float()
         d32 = t_d.float()
@@ -683,12 +825,40 @@ def main():
             f_times.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         ftm = float(np.median(f_times))
-        return {
+        res = {
             "time_to_map_ms": {"p50": round(1e3 * ftm, 3), "p99": round(1e3 * float(np.percentile(f_times, 99)), 3)},
             "inner_iters": f_infos[-1]["iters"], "outer_iters": f_infos[-1]["outer_iters"],
             "final_true_rel_resid": max(i["true_rel_resid"] for i in f_infos),
             "speedup_vs_fp64": round(float(np.median(times)) / ftm, 3),
-            "note": "psi and d rounded to FP32 once; inner PCG with FP32 timeline arithmetic, FP64 refinement"}
+            "note": "psi and d rounded to FP32 once; inner PCG with FP32 timeline arithmetic, FP64 refinement "
+                    "started from the block-Jacobi map"}
+        # accuracy, per Stokes (I, Q, U), against the FP64 map of the same
+        # FP32-rounded inputs solved to 1e-13 (the FP64 solver matches the
+        # oracle at fixed iteration counts on this scan's one-GPU share)
+        psi_up, d_up = psi32.double(), d32.double()
+        ref, ref_info, nk = solve_x(psi_up, d_up, tol=1e-13)
+        errs = {}
+        for key, psi_t, d_t, opts in (
+                ("fp32_before_refinement_from_zero", psi32, d32,
+                 dict(tol=1e-14, mixed=1, max_outer=1, inner_tol=1e-9, max_iter=400, bj_start=0)),
+                ("fp32_before_refinement_from_block_jacobi", psi32, d32,
+                 dict(tol=1e-14, mixed=1, max_outer=1, inner_tol=1e-9, max_iter=400, bj_start=1)),
+                ("fp32_refined_tol_1e-10", psi32, d32, dict(tol=1e-10, mixed=1)),
+                ("fp64_tol_1e-10", psi_up, d_up, dict(tol=1e-10)),
+                ("fp32_refined_tol_1e-13", psi32, d32, dict(tol=1e-13, mixed=1, max_outer=30))):
+            x, info, n_k = solve_x(psi_t, d_t, **opts)
+            assert n_k == nk
+            errs[key] = {"rel_l2_iqu": [float(f"{v:.3e}") for v in stokes_rel(x, ref)],
+                         "inner_iters": info["iters"], "outer_iters": info["outer_iters"],
+                         "true_rel_resid": info["true_rel_resid"]}
+        res["map_error_vs_fp64_ref"] = errs
+        res["reference"] = (f"FP64 solve of the FP32-rounded psi and d to 1e-13 ({ref_info['iters']} iterations, "
+                            f"true residual {ref_info['true_rel_resid']:.2e})")
+        res["error_note"] = ("before refinement: the FP32 inner solve alone (one outer step, inner tolerance 1e-9), "
+                             "from x = 0 or from the block-Jacobi map M b (one FP64 operator application for its "
+                             "residual); after refinement: the timed solve (to 1e-10), and one to 1e-13; "
+                             "fp64_tol_1e-10: the plain FP64 solve of the same inputs at the same tolerance")
+        return res
 
     def forms_line(name, r):
         return name + ": " + ", ".join(f"{k} {v['time_to_map_ms']} ms" for k, v in r.items() if isinstance(v, dict))
@@ -718,7 +888,8 @@ def main():
                 lambda r: f"serving: {r['solves_per_s']} solves/s")
     if args.cpu_det > 0:
         t0 = time.perf_counter()
-        guarded("cpu_baseline", lambda: cpu_baseline(w, pix, psi, d_host, min(args.cpu_det, w.n_det)),
+        guarded("cpu_baseline", lambda: cpu_baseline(w, pix, psi, d_host, min(args.cpu_det, w.n_det),
+                                                     min(args.cpu_workers, w.n_det) if w.toeplitz else 0),
                 lambda r: f"cpu baseline in {time.perf_counter() - t0:.1f} s")
 
     print(json.dumps(result))

@@ -77,7 +77,7 @@ typedef struct mm_noise_s* mm_noise_t;
 /* Message of the last failing call on this thread ("" if none). */
 const char* mm_last_error(void);
 
-/* ABI revision of this header (bumped on incompatible change): 4. */
+/* ABI revision of this header (bumped on incompatible change): 5. */
 int mm_abi_version(void);
 
 /* ------------------------------------------------------------------------
@@ -86,8 +86,10 @@ int mm_abi_version(void);
  * ------------------------------------------------------------------------ */
 
 /* Device workspace bytes that mm_pointing_build needs for a timeline of
- * n_samples samples over n_det detectors and a grid of n_pix pixels. */
-int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, size_t* bytes);
+ * n_samples samples over n_det detectors and a grid of n_pix pixels, with
+ * angles and timelines stored in `dtype` (MM_F64 or MM_F32; any other value
+ * fails with MM_EINVAL).  The same size serves every map form. */
+int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, int32_t dtype, size_t* bytes);
 
 /* Build the pointing handle (blocking: synchronises `stream` once to read
  * the number of kept pixels and the pixel-range check).
@@ -196,7 +198,8 @@ int mm_noise_circulant(const double* coeff_host, int32_t lambda, int32_t n_filt,
  * at apply time, MM_EINVAL).  A map component constant over whole intervals
  * (the I monopole with K_i >= 1) is then unconstrained; PCG started from 0
  * stays orthogonal to it.  The handle works with every operator and solve
- * entry point except mm_batch_step; the operator variants do not apply.
+ * entry point, mm_batch_step included (a batch may mix template-filtered,
+ * white and band-Toeplitz members); the operator variants do not apply.
  * Workspace: mm_noise_templates_workspace_size; copies its tables there and
  * synchronises `stream` once. */
 int mm_noise_templates_workspace_size(int32_t n_det, int64_t n_intervals, size_t* bytes);
@@ -221,7 +224,7 @@ int mm_apply_Ninv(mm_noise_t nz, mm_pointing_t pt, const void* tod_in, void* tod
  * on chip (registers for white noise, LDS for band-Toeplitz). */
 int mm_apply_A(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, void* stream);
 /* mm_apply_A with an explicit band-Toeplitz operator variant (the bits of
- * mm_solve_opts.op_variant, 0 <= variant < 8; ignored for white noise).
+ * mm_solve_opts.op_variant, 0 <= variant < 16; ignored for white noise).
  * Every variant computes the same sums up to the order of floating-point
  * atomics; this call lets a caller check or time one. */
 int mm_apply_A_variant(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, int32_t variant,
@@ -258,7 +261,11 @@ typedef struct {
                            order instead of the XCD-aware order, bit 1 = map read from
                            global memory instead of staged in LDS, bit 2 = shorter tiles in
                            runs that carry the overlapping half-window from tile to tile
-                           (needs stored pointing weights; never stages)                    */
+                           (needs stored pointing weights; never stages), bit 3 = plain
+                           tiles with two workgroups per CU, whose FFT exchanges pass real
+                           and imaginary parts through half the LDS in turn (FP64
+                           arithmetic; bits 1 and 2 do not apply), so the memory phases of
+                           one tile overlap the FFT of another; 0 <= op_variant < 16       */
   int32_t graph;        /* 1: the first mm_solver_step of a given length k > 0 records its k
                            iterations (operator and PCG launches) into a HIP graph and
                            every later step of that length replays it with one graph
@@ -269,6 +276,11 @@ typedef struct {
   const double* x0;     /* start vector (device, f64[n_rhs][nc * n_kept]) or NULL for x0 = 0;
                            the residual starts at b - A x0 (FP64), the mixed form refines from
                            x0; the solve's outputs do not alias it                           */
+  int32_t bj_start;     /* mixed form with x0 NULL: 1 (default) refines from the block-Jacobi
+                           map x0 = M b (eq. (7)), whose residual b - A x0 is formed in FP64;
+                           0 from x0 = 0.  The FP32 inner solves then work on corrections
+                           whose I component is no longer the sky's, so FP32 rounding of
+                           the I-dominated timeline leaks far less into Q and U            */
 } mm_solve_opts;
 
 typedef struct {
@@ -309,6 +321,14 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
 
 typedef struct mm_solver_s* mm_solver_t;
 
+/* Workspace bytes of a solver of n_rhs right-hand sides for a problem with
+ * at most n_kept_max kept pixels of ncomp values each (1, 2 or 3), without a
+ * pointing handle: what mm_solver_workspace_size returns once the pointing
+ * is built is never larger.  For sizing before the pointing exists, e.g.
+ * admission by device footprint.  Host only. */
+int mm_solver_workspace_bound(int32_t n_kept_max, int32_t ncomp, int32_t n_rhs, const mm_solve_opts* opts,
+                              size_t* bytes);
+
 int mm_solver_workspace_size(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const mm_solve_opts* opts,
                              size_t* bytes);
 
@@ -336,8 +356,8 @@ int mm_solver_poll(mm_solver_t sv, int32_t* done, int32_t* in_flight, mm_solve_i
 int mm_solver_finish(mm_solver_t sv, double* maps_out, double* x_out, mm_solve_info* info, double* history_host,
                      int32_t history_len);
 
-/* Checkpoint and resume (the solver state of the a9/a10 rows: preempting a
- * resumable solve to free its workspace, or resuming it elsewhere).
+/* Checkpoint and resume of a resumable solve (preempting it to free its
+ * workspace, or resuming it elsewhere).
  * mm_solver_snapshot_size: bytes of a snapshot (a small header plus the
  * solver's share of its workspace).  mm_solver_snapshot (blocking: waits
  * for the solver's stream) copies the state after the last enqueued step

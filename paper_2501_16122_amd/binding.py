@@ -33,7 +33,7 @@ _psz = _c.POINTER(_c.c_size_t)
 class SolveOpts(_c.Structure):
     _fields_ = [("tol", _f64), ("max_iter", _i32), ("fixed_iter", _i32), ("check_every", _i32),
                 ("mixed", _i32), ("max_outer", _i32), ("inner_tol", _f64), ("timing", _i32),
-                ("autotune", _i32), ("op_variant", _i32), ("graph", _i32), ("x0", _vp)]
+                ("autotune", _i32), ("op_variant", _i32), ("graph", _i32), ("x0", _vp), ("bj_start", _i32)]
 
 
 class SolveInfo(_c.Structure):
@@ -49,7 +49,7 @@ class SolveInfo(_c.Structure):
 SIGNATURES = {
     "mm_last_error": (_c.c_char_p, []),
     "mm_abi_version": (_c.c_int, []),
-    "mm_pointing_workspace_size": (_c.c_int, [_i64, _i32, _i32, _psz]),
+    "mm_pointing_workspace_size": (_c.c_int, [_i64, _i32, _i32, _i32, _psz]),
     "mm_pointing_build": (_c.c_int, [_vp, _vp, _i32, _i64, _pi64, _i32, _pf64, _i32, _i32, _f64, _vp, _sz, _vp,
                                      _c.POINTER(_vp)]),
     "mm_pointing_build_stokes": (_c.c_int, [_vp, _vp, _i32, _i64, _pi64, _i32, _pf64, _i32, _i32, _i32, _f64, _vp,
@@ -80,6 +80,7 @@ SIGNATURES = {
     "mm_solve_workspace_size": (_c.c_int, [_vp, _vp, _c.POINTER(SolveOpts), _psz]),
     "mm_solve": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.POINTER(SolveOpts), _c.POINTER(SolveInfo), _pf64, _i32,
                             _vp, _sz, _vp]),
+    "mm_solver_workspace_bound": (_c.c_int, [_i32, _i32, _i32, _c.POINTER(SolveOpts), _psz]),
     "mm_solver_workspace_size": (_c.c_int, [_vp, _vp, _i32, _c.POINTER(SolveOpts), _psz]),
     "mm_solver_create": (_c.c_int, [_vp, _vp, _i32, _vp, _c.POINTER(SolveOpts), _vp, _sz, _vp, _c.POINTER(_vp)]),
     "mm_solver_step": (_c.c_int, [_vp, _i32]),
@@ -208,7 +209,7 @@ class Pointing:
         w = np.ascontiguousarray(det_weight, dtype=np.float64)
         n_det = offs.size - 1
         sz = _c.c_size_t()
-        _check(lib.mm_pointing_workspace_size(n, n_det, int(n_pix), _c.byref(sz)))
+        _check(lib.mm_pointing_workspace_size(n, n_det, int(n_pix), self.dtype, _c.byref(sz)))
         self.workspace = torch.empty(max(1, sz.value), dtype=torch.uint8, device=pix.device)
         h = _vp()
         _check(lib.mm_pointing_build_stokes(_ptr(pix), _ptr(psi), self.dtype, n, offs.ctypes.data_as(_pi64), n_det,

@@ -165,10 +165,11 @@ extern "C" {
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
 
-int mm_abi_version(void) { return 4; }
+int mm_abi_version(void) { return 5; }
 
-int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, size_t* bytes) {
+int mm_pointing_workspace_size(int64_t n_samples, int32_t n_det, int32_t n_pix, int32_t dtype, size_t* bytes) {
   if (!bytes || n_samples < 0 || n_det <= 0 || n_pix <= 0) return fail(MM_EINVAL, "bad pointing sizes");
+  if (!valid_dtype(dtype)) return fail(MM_EINVAL, "dtype must be MM_F64 or MM_F32");
   // worst case tile count: every detector may add one partial tile
   const int64_t n_tiles = n_samples / kTileSamples + n_det;
   Carver cv(nullptr, 0);
@@ -206,7 +207,7 @@ int mm_pointing_build_stokes(const int32_t* pix, const void* psi, int32_t dtype,
       return fail(MM_EINVAL, "detector weights must be finite and >= 0");
   }
   size_t need = 0;
-  mm_pointing_workspace_size(n_samples, n_det, n_pix, &need);
+  mm_pointing_workspace_size(n_samples, n_det, n_pix, dtype, &need);
   if (ws_bytes < need) return fail(MM_ENOSPC, "pointing workspace too small");
   hipStream_t s = as_stream(stream);
 

@@ -227,7 +227,12 @@ int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const vo
 // consecutive tiles and reuses the P x of the overlap instead of gathering
 // it again (never staged; tile order as bit kOpLinearOrder says; only with
 // stored pointing weights, else the plain tiles are used).
-constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpCarry = 4, kOpVariants = 8;
+// Bit kOpHalfLds runs plain tiles with two workgroups per CU: the FFT
+// exchanges go through half the LDS (real parts, then imaginary parts), so
+// the memory phases of one tile overlap the FFT of another (FP64 arithmetic;
+// tile order as bit kOpLinearOrder says; bits kOpNoStaging and kOpCarry do
+// not apply).
+constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpCarry = 4, kOpHalfLds = 8, kOpVariants = 16;
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
                           double* q, int arith, const RhsBatch& rb, hipStream_t s, int32_t variant = 0);
 // template-filtered white weights (noise kind 3)
@@ -271,10 +276,11 @@ struct PcgState {
 };
 constexpr int kPcgBlocks = 256;   // largest grid of the vector kernels (partial sums per block)
 // Grid of the vector kernels for a problem: fixed by its size, so its sums
-// are deterministic; larger grids spend more on the per-block partial sums
+// are deterministic (a batched launch spans the largest member's grid, and
+// each member uses only its own count of blocks); larger grids spend more on the per-block partial sums
 // than they gain in memory parallelism (64 blocks for small maps, 256 at
 // 512^2 and beyond).
-inline int pcg_blocks(int32_t n_kept) {
+__host__ __device__ inline int pcg_blocks(int32_t n_kept) {
   const int g = n_kept / 1024;
   return g < 64 ? 64 : (g > kPcgBlocks ? kPcgBlocks : g);
 }

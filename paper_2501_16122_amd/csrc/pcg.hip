@@ -9,9 +9,12 @@
 // alpha, beta, ||b||, the iteration count, a "done" flag) live in device
 // memory, so chunks of iterations are enqueued without host round trips and
 // every kernel of a slice returns at once when that slice is done.  Dot
-// products are deterministic: a grid fixed by the problem size
+// products are deterministic: a block count fixed by the problem size
 // (pcg_blocks) with a fixed pixel assignment writes per-block partials and
 // the last block to finish (an atomic ticket) sums them in a fixed order.
+// A batched launch spans the largest member's block count; blocks past a
+// member's own count return at once, so a member's sums, and its iterates,
+// are the same alone and in any batch.
 #include <algorithm>
 
 #include "mm_internal.h"
@@ -46,20 +49,21 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
 
 // Write this block's two partials; returns true in every thread of the last
 // block of the slice, whose thread 0 then holds the slice totals in (a, b).
-__device__ bool grid_sum2(double& a, double& b, double* partials, uint32_t* counter, double* sh, bool* s_last) {
+__device__ bool grid_sum2(double& a, double& b, double* partials, uint32_t* counter, double* sh, bool* s_last,
+                          int nblk) {
   block_sum2(a, b, sh);
   if (threadIdx.x == 0) {
     partials[blockIdx.x] = a;
     partials[kPcgBlocks + blockIdx.x] = b;
     __threadfence();
     const uint32_t ticket = atomicAdd(counter, 1u);
-    *s_last = ticket == gridDim.x - 1;
+    *s_last = ticket == (uint32_t)nblk - 1;
   }
   __syncthreads();
   if (!*s_last) return false;
   __threadfence();
   double pa = 0.0, pb = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
     pa += partials[i];
     pb += partials[kPcgBlocks + i];
   }
@@ -100,13 +104,14 @@ struct Slice {
   int32_t hist_len;
   int32_t ncomp;  // values per kept pixel
   int64_t n;      // ncomp * n_kept values per vector
+  int32_t nblk;   // blocks that work on this right-hand side (pcg_blocks)
 };
 
 __device__ __forceinline__ Slice slice(const PcgArgs& a, int y) {
   const int64_t o = (int64_t)y * a.vstride;
   return Slice{a.x + o, a.r + o, a.z + o, a.p + o, a.q + o, a.b + o,
                a.partials + (int64_t)y * 2 * kPcgBlocks, a.st + y, a.hist + (int64_t)y * a.hist_len,
-               a.n_kept, a.hist_len, a.ncomp, (int64_t)a.ncomp * a.n_kept};
+               a.n_kept, a.hist_len, a.ncomp, (int64_t)a.ncomp * a.n_kept, pcg_blocks(a.n_kept)};
 }
 
 // The outer refinement vectors and state of one right-hand side.
@@ -135,7 +140,7 @@ template <int NC>
 __device__ __forceinline__ void pcg_init_sums(const Slice& S, const double* __restrict__ minv, bool from_x0,
                                               bool zero_b, double& bb, double& rz) {
   constexpr int NB = NC * (NC + 1) / 2;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)S.nblk * blockDim.x) {
     double bv[NC], rv[NC], zv[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -165,6 +170,7 @@ __device__ __forceinline__ void pcg_init_sums(const Slice& S, const double* __re
 __device__ __forceinline__ void pcg_init_body(const Slice& S, const double* __restrict__ minv, double tol,
                                               int32_t max_iter, int32_t fixed_iter, const OuterState* gate,
                                               bool from_x0 = false) {
+  if ((int)blockIdx.x >= S.nblk) return;
   if (gate != nullptr && (gate->done || gate->skip)) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
@@ -174,7 +180,7 @@ __device__ __forceinline__ void pcg_init_body(const Slice& S, const double* __re
   if (S.ncomp == 3) pcg_init_sums<3>(S, minv, from_x0, zero_b, bb, rz);
   else if (S.ncomp == 2) pcg_init_sums<2>(S, minv, from_x0, zero_b, bb, rz);
   else pcg_init_sums<1>(S, minv, from_x0, zero_b, bb, rz);
-  if (!grid_sum2(bb, rz, S.partials, &S.st->counter, sh, &s_last)) return;
+  if (!grid_sum2(bb, rz, S.partials, &S.st->counter, sh, &s_last, S.nblk)) return;
   if (threadIdx.x == 0) {
     PcgState* st = S.st;
     const double bnorm = sqrt(bb);
@@ -186,26 +192,28 @@ __device__ __forceinline__ void pcg_init_body(const Slice& S, const double* __re
     st->rel = rel;
     st->tol = tol;
     st->iter = 0;
-    st->breakdown = 0;
     st->max_iter = max_iter;
     st->fixed_iter = fixed_iter;
-    const bool met = rel <= tol;
+    // a non-finite right-hand side, start residual or r.z is a breakdown
+    const bool bad = !isfinite(bb) || !isfinite(rz) || !isfinite(rel);
+    st->breakdown = bad ? 1 : 0;
+    const bool met = !bad && rel <= tol;
     st->converged = met ? 1 : 0;
-    st->done = (bnorm == 0.0 || (fixed_iter <= 0 && met) || (fixed_iter <= 0 && max_iter <= 0)) ? 1 : 0;
+    st->done = (bad || bnorm == 0.0 || (fixed_iter <= 0 && met) || (fixed_iter <= 0 && max_iter <= 0)) ? 1 : 0;
     if (S.hist_len > 0) S.hist[0] = rel;
   }
 }
 
 // alpha = rho / p.q (breakdown if p.q <= 0 or not finite)
 __device__ __forceinline__ void pcg_alpha_body(const Slice& S) {
-  if (S.st->done) return;
+  if ((int)blockIdx.x >= S.nblk || S.st->done) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   double pq = 0.0, unused = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
-       i += (int64_t)gridDim.x * blockDim.x)
+       i += (int64_t)S.nblk * blockDim.x)
     pq += S.p[i] * S.q[i];
-  if (!grid_sum2(pq, unused, S.partials, &S.st->counter, sh, &s_last)) return;
+  if (!grid_sum2(pq, unused, S.partials, &S.st->counter, sh, &s_last, S.nblk)) return;
   if (threadIdx.x == 0) {
     if (!(pq > 0.0) || isinf(pq)) {
       S.st->breakdown = 1;
@@ -221,7 +229,7 @@ template <int NC>
 __device__ __forceinline__ void pcg_update_sums(const Slice& S, const double* __restrict__ minv, double alpha,
                                                 double& rr, double& rz) {
   constexpr int NB = NC * (NC + 1) / 2;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_kept; k += (int64_t)S.nblk * blockDim.x) {
     double rv[NC], zv[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -244,7 +252,7 @@ __device__ __forceinline__ void pcg_update_sums(const Slice& S, const double* __
 }
 
 __device__ __forceinline__ void pcg_update_body(const Slice& S, const double* __restrict__ minv) {
-  if (S.st->done) return;
+  if ((int)blockIdx.x >= S.nblk || S.st->done) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   const double alpha = S.st->alpha;
@@ -252,7 +260,7 @@ __device__ __forceinline__ void pcg_update_body(const Slice& S, const double* __
   if (S.ncomp == 3) pcg_update_sums<3>(S, minv, alpha, rr, rz);
   else if (S.ncomp == 2) pcg_update_sums<2>(S, minv, alpha, rr, rz);
   else pcg_update_sums<1>(S, minv, alpha, rr, rz);
-  if (!grid_sum2(rr, rz, S.partials, &S.st->counter, sh, &s_last)) return;
+  if (!grid_sum2(rr, rz, S.partials, &S.st->counter, sh, &s_last, S.nblk)) return;
   if (threadIdx.x == 0) {
     PcgState* st = S.st;
     const int it = st->iter + 1;
@@ -281,10 +289,10 @@ __device__ __forceinline__ void pcg_update_body(const Slice& S, const double* __
 
 // p = z + beta p, q = 0 (the next operator launch accumulates into q)
 __device__ __forceinline__ void pcg_direction_body(const Slice& S) {
-  if (S.st->done) return;
+  if ((int)blockIdx.x >= S.nblk || S.st->done) return;
   const double beta = S.st->beta;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+       i += (int64_t)S.nblk * blockDim.x) {
     S.p[i] = S.z[i] + beta * S.p[i];
     S.q[i] = 0.0;
   }
@@ -297,6 +305,7 @@ __device__ __forceinline__ void pcg_direction_body(const Slice& S) {
 // scratch1 ||b64||^2, so rt = b64 - A64 x0; ||rt||^2 (sum 2) gives the
 // starting residual.
 __device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S, bool from_x0 = false) {
+  if ((int)blockIdx.x >= S.nblk) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   const int64_t n3 = S.n;
@@ -308,7 +317,7 @@ __device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S,
   // with b64 = 0 (||b64||^2 in the inner scratch1, see launch_diff_norm) the solution is 0
   const bool zero_b = from_x0 && !(S.st->scratch1 > 0.0);
   double bb = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += (int64_t)S.nblk * blockDim.x) {
     const double v = O.b64[i];
     const double r = from_x0 && !zero_b ? v - S.q[i] : v;
     if (!from_x0 || zero_b) O.xt[i] = 0.0;
@@ -316,17 +325,19 @@ __device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S,
     bb += v * v;
     rr += r * r;
   }
-  if (!grid_sum2(bb, rr, O.partials, &O.os->counter, sh, &s_last)) return;
+  if (!grid_sum2(bb, rr, O.partials, &O.os->counter, sh, &s_last, S.nblk)) return;
   if (threadIdx.x == 0) {
     OuterState* os = O.os;
     os->bnorm = sqrt(bb);
     os->rel = os->bnorm > 0.0 ? (from_x0 ? sqrt(rr) / os->bnorm : 1.0) : 0.0;
     os->iters = 0;
     os->inner_total = 0;
-    os->converged = os->bnorm == 0.0 ? 1 : 0;
-    os->done = os->bnorm == 0.0 ? 1 : 0;
+    // a non-finite right-hand side or start residual is a breakdown
+    const bool bad = !isfinite(bb) || !isfinite(rr);
+    os->converged = (!bad && os->bnorm == 0.0) ? 1 : 0;
+    os->done = (bad || os->bnorm == 0.0) ? 1 : 0;
     os->skip = 0;  // the first inner solve may start
-    os->breakdown = 0;
+    os->breakdown = bad ? 1 : 0;
   }
 }
 
@@ -334,6 +345,7 @@ __device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S,
 // still open takes an outer step: xt += x; q := 0 (A64 xt accumulates into
 // q next).  Any other right-hand side is marked skip.
 __device__ __forceinline__ void outer_add_body(const OSlice& O, const Slice& S) {
+  if ((int)blockIdx.x >= S.nblk) return;
   OuterState* os = O.os;
   const PcgState* st = S.st;
   const bool act = st->done && !os->done;
@@ -342,7 +354,7 @@ __device__ __forceinline__ void outer_add_body(const OSlice& O, const Slice& S) 
     return;
   }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+       i += (int64_t)S.nblk * blockDim.x) {
     O.xt[i] += S.x[i];
     S.q[i] = 0.0;
   }
@@ -355,18 +367,19 @@ __device__ __forceinline__ void outer_add_body(const OSlice& O, const Slice& S) 
 
 // rt = b64 - q (q = A64 xt), ||rt|| / ||b64||, the outer stopping test.
 __device__ __forceinline__ void outer_end_body(const OSlice& O, const Slice& S, double tol, int32_t max_outer) {
+  if ((int)blockIdx.x >= S.nblk) return;
   OuterState* os = O.os;
   if (os->skip) return;
   __shared__ double sh[16];
   __shared__ bool s_last;
   double rr = 0.0, unused = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+       i += (int64_t)S.nblk * blockDim.x) {
     const double v = O.b64[i] - S.q[i];
     O.rt[i] = v;
     rr += v * v;
   }
-  if (!grid_sum2(rr, unused, O.partials, &os->counter, sh, &s_last)) return;
+  if (!grid_sum2(rr, unused, O.partials, &os->counter, sh, &s_last, S.nblk)) return;
   if (threadIdx.x == 0) {
     const int it = os->iters + 1;
     os->iters = it;
@@ -448,15 +461,16 @@ __global__ __launch_bounds__(kPcgThreads) void k_diff_norm(PcgArgs A, const doub
   __shared__ double sh[16];
   __shared__ bool s_last;
   Slice S = slice(A, blockIdx.y);
+  if ((int)blockIdx.x >= S.nblk) return;
   const int64_t off = (int64_t)blockIdx.y * A.vstride;
   double dd = 0.0, aa = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+       i += (int64_t)S.nblk * blockDim.x) {
     const double d = a[off + i] - b[off + i];
     dd += d * d;
     aa += a[off + i] * a[off + i];
   }
-  if (!grid_sum2(dd, aa, S.partials, &S.st->counter, sh, &s_last)) return;
+  if (!grid_sum2(dd, aa, S.partials, &S.st->counter, sh, &s_last, S.nblk)) return;
   if (threadIdx.x == 0) {
     S.st->scratch0 = dd;
     S.st->scratch1 = aa;

@@ -77,6 +77,7 @@ int check_opts(const mm_solve_opts& o) {
   if (o.mixed && o.fixed_iter > 0) return fail(MM_EINVAL, "fixed_iter is not available with mixed precision");
   if (o.op_variant < 0 || o.op_variant >= kOpVariants) return fail(MM_EINVAL, "op_variant out of range");
   if (o.graph != 0 && o.graph != 1) return fail(MM_EINVAL, "graph must be 0 or 1");
+  if (o.bj_start != 0 && o.bj_start != 1) return fail(MM_EINVAL, "bj_start must be 0 or 1");
   return MM_OK;
 }
 
@@ -240,6 +241,8 @@ struct mm_solver_s {
     int32_t best_v = 0;
     for (int32_t v = 0; v < kOpVariants && rc == MM_OK; ++v) {
       if ((v & kOpCarry) && (v & kOpNoStaging)) continue;  // the carrying form never stages
+      // the two-per-CU form: FP64 arithmetic, plain tiles, never staged
+      if ((v & kOpHalfLds) && (arith != MM_F64 || (v & (kOpCarry | kOpNoStaging)))) continue;
       if ((rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s, v))) break;
       if ((e = hipEventRecord(e0, s)) != hipSuccess) { rc = hip_fail(e, "tuner event"); break; }
       for (int r = 0; r < 2 && rc == MM_OK; ++r) rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s, v);
@@ -349,6 +352,7 @@ int mm_solve_opts_default(mm_solve_opts* o) {
   o->op_variant = 0;
   o->graph = 0;
   o->x0 = nullptr;
+  o->bj_start = 1;
   return MM_OK;
 }
 
@@ -362,6 +366,19 @@ int mm_solver_workspace_size(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, con
   Carver cv(nullptr, 0);
   Layout L;
   *bytes = carve(cv, pt->n_kept, pt->ncomp, n_rhs, o, &L);
+  return MM_OK;
+}
+
+int mm_solver_workspace_bound(int32_t n_kept_max, int32_t ncomp, int32_t n_rhs, const mm_solve_opts* opts,
+                              size_t* bytes) {
+  if (!bytes || n_kept_max < 0 || n_rhs < 1 || ncomp < 1 || ncomp > 3)
+    return fail(MM_EINVAL, "bad solver workspace bound query");
+  mm_solve_opts o;
+  mm_solve_opts_default(&o);
+  if (opts) o = *opts;
+  Carver cv(nullptr, 0);
+  Layout L;
+  *bytes = carve(cv, n_kept_max, ncomp, n_rhs, o, &L);
   return MM_OK;
 }
 
@@ -422,12 +439,20 @@ int mm_solver_create(mm_pointing_t pt, mm_noise_t nz, int32_t n_rhs, const void*
     const char* t = static_cast<const char*>(tod) + (size_t)r * esz * (size_t)pt->n_samples;
     if (int rc = rhs_impl(pt, nz, t, rhs_dst + r * sv->n3, MM_F64, sv->s)) return bail(rc);
   }
-  const bool from_x0 = o.x0 != nullptr;
+  // the mixed form refines from the block-Jacobi map M b unless the caller
+  // gives a start vector or asks for x0 = 0
+  const bool bj = sv->mixed && o.x0 == nullptr && o.bj_start != 0;
+  const bool from_x0 = o.x0 != nullptr || bj;
   if (from_x0) {
     // start vector: x (FP64 solve) or xt (outer FP64 refinement) = x0, and
     // q = A64 x0 in FP64 arithmetic; then ||b - A x0||^2, ||b||^2
     double* xs = sv->mixed ? sv->L.O.xt : sv->L.A.x;
-    MM_HIP(hipMemcpyAsync(xs, o.x0, sizeof(double) * sv->n3 * n_rhs, hipMemcpyDeviceToDevice, sv->s));
+    if (bj) {
+      for (int32_t r = 0; r < n_rhs; ++r)
+        if (int rc = launch_apply_M(pt, rhs_dst + r * sv->n3, xs + r * sv->n3, sv->s)) return bail(rc);
+    } else {
+      MM_HIP(hipMemcpyAsync(xs, o.x0, sizeof(double) * sv->n3 * n_rhs, hipMemcpyDeviceToDevice, sv->s));
+    }
     if (int rc = launch_fill(sv->L.A.q, sv->n3 * n_rhs, 0.0, sv->s)) return bail(rc);
     RhsBatch rb;
     rb.nrhs = n_rhs;

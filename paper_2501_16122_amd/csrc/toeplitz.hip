@@ -276,7 +276,8 @@ __device__ __forceinline__ bool src_pos(int pos, int ilo, int ihi, bool wrap, in
 }
 
 
-template <class S, class C, int kW, int NC, bool kKeepK, bool kKeepW = false>
+template <class S, class C, int kW, int NC, bool kKeepK, bool kKeepW = false, int kSlots = Lds<C, NC>::kBinSlots,
+          int kBatch = Plan<C>::kScatterBatch>
 __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, const int32_t* kk,
                                              const int32_t* __restrict__ sk, const S* __restrict__ ps0,
                                              const cpx<S>* __restrict__ w0, int32_t vlo, int32_t vhi, int32_t kmin,
@@ -285,8 +286,8 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
   using P = Plan<C>;
   using F = Fft<C>;
   using A = Angle<C, S, kW>;
-  constexpr int N = P::N, T = P::T, E = N / T, GS = P::kScatterBatch;
-  constexpr int kTBinSlots = Lds<C, NC>::kBinSlots;
+  constexpr int N = P::N, T = P::T, E = N / T, GS = kBatch;
+  constexpr int kTBinSlots = kSlots;
   constexpr bool kAng = Stokes<NC>::kAngle;
   const int tid = threadIdx.x;
   for (int32_t wlo = kmin; wlo <= kmax; wlo += kTBinSlots) {
@@ -821,6 +822,287 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(
                                          tod_in, tod_out, q, variant);
 }
 
+// ---------------------------------------------------------------------------
+// Two workgroups per CU (operator variant bit kOpHalfLds).  The FFT state of
+// a tile lives in registers, and each LDS exchange of the Stockham passes
+// moves the real parts of all values first and the imaginary parts second,
+// so the exchange buffer holds N scalars instead of N complex values (68 KiB
+// for the FP64 plan).  Two such workgroups fit one CU's LDS, and with at
+// most 128 VGPRs per thread their 16 waves fit the register file: the
+// memory-bound gather and scatter of one tile overlap the FFT of the other,
+// which a single 136 KiB workgroup per CU cannot do.  Plain tiles only: the
+// whole window is gathered (its halo is read again through L2 by the
+// neighbouring tile, which the XCD-aware order keeps on the same L2).
+// ---------------------------------------------------------------------------
+
+// padded scalar index of the half buffer (one pad scalar every 16)
+__device__ __forceinline__ int hpad(int i) { return i + (i >> 4); }
+template <int N>
+constexpr int hlds_elems() { return N + N / 16; }
+
+template <class C, int kComp>
+__device__ __forceinline__ C& comp(cpx<C>& a) {
+  if constexpr (kComp == 0) return a.x;
+  else return a.y;
+}
+
+// Component kComp of every value of pass (R, Ns) to its output position.
+template <class C, int N, int T, int R, int Ns, int kComp>
+__device__ __forceinline__ void hstore(C* buf, cpx<C>* v) {
+  constexpr int BPT = N / T / R;
+  const int tid = fft_tid();
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int j = tid + b * T;
+    const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
+#pragma unroll
+    for (int q = 0; q < R; ++q) buf[hpad(base + q * Ns)] = comp<C, kComp>(v[b * R + q]);
+  }
+}
+
+// Component kComp of the inputs of a pass of radix R.
+template <class C, int N, int T, int R, int kComp>
+__device__ __forceinline__ void hload(const C* buf, cpx<C>* v) {
+  constexpr int BPT = N / T / R;
+  const int tid = fft_tid();
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int j = tid + b * T;
+#pragma unroll
+    for (int m = 0; m < R; ++m) comp<C, kComp>(v[b * R + m]) = buf[hpad(j + m * (N / R))];
+  }
+}
+
+// Every register value complete here: the compiler may not sink the
+// arithmetic that produces a component past the LDS round that stores the
+// other one (which would keep a pass's intermediates live instead).
+template <class C, int E>
+__device__ __forceinline__ void settle(cpx<C>* v) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) asm volatile("" : "+v"(v[e].x), "+v"(v[e].y));
+}
+
+// Exchange between pass (R, Ns) and the next pass (radix R2): real parts,
+// then imaginary parts, through the same half buffer.
+template <class C, int N, int T, int R, int Ns, int R2>
+__device__ __forceinline__ void hexchange(C* buf, cpx<C>* v) {
+  settle<C, N / T>(v);
+  __syncthreads();
+  hstore<C, N, T, R, Ns, 0>(buf, v);
+  __syncthreads();
+  hload<C, N, T, R2, 0>(buf, v);
+  __syncthreads();
+  hstore<C, N, T, R, Ns, 1>(buf, v);
+  __syncthreads();
+  hload<C, N, T, R2, 1>(buf, v);
+}
+
+template <class C, int N, int T, bool kFwd, int Ns, int R>
+__device__ __forceinline__ void hpasses(C* buf, cpx<C>* v, const cpx<C>* __restrict__ tw) {
+  pass_compute<C, N, T, R, Ns, kFwd>(v, tw);
+}
+template <class C, int N, int T, bool kFwd, int Ns, int R, int R2, int... Rest>
+__device__ __forceinline__ void hpasses(C* buf, cpx<C>* v, const cpx<C>* __restrict__ tw) {
+  pass_compute<C, N, T, R, Ns, kFwd>(v, tw);
+  hexchange<C, N, T, R, Ns, R2>(buf, v);
+  hpasses<C, N, T, kFwd, Ns * R, R2, Rest...>(buf, v, tw);
+}
+
+// The FP64 middle step (see middle_r2) through the half buffer: v holds the
+// outputs of the last forward pass (radix 16, span 256) on entry and the
+// inputs of the first inverse pass (radix 16) on return.  Thread t takes the
+// bin quadruples (j, j + H, m, m + H) with j = t + T r, m = H - j, one
+// component per LDS round, computes them in registers and scatters the
+// results to 2j, 2j + 1, 2m, 2m + 1.  Bins 0 and H pair with themselves:
+// the slot j = 0 uses them as its own mirrors, and its m side takes the
+// self-paired quadruple m = Q instead, so no thread branches.
+template <int N, int T>
+__device__ __forceinline__ void hmiddle(double* buf, cpx<double>* v, const cpx<double>* __restrict__ abf,
+                                        const cpx<double>* __restrict__ tw) {
+  constexpr int H = N / 2, Q = H / 2, PPT = Q / T;
+  static_assert(PPT * T == Q && 4 * PPT == N / T, "quadruples must fill the registers");
+  settle<double, N / T>(v);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    __syncthreads();
+    if (c == 0) hstore<double, N, T, 16, 256, 0>(buf, v);
+    else hstore<double, N, T, 16, 256, 1>(buf, v);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      const int j = fft_tid() + T * r, m = j == 0 ? Q : H - j;
+      (c == 0 ? v[4 * r + 0].x : v[4 * r + 0].y) = buf[hpad(j)];
+      (c == 0 ? v[4 * r + 1].x : v[4 * r + 1].y) = buf[hpad(j + H)];
+      (c == 0 ? v[4 * r + 2].x : v[4 * r + 2].y) = buf[hpad(m)];
+      (c == 0 ? v[4 * r + 3].x : v[4 * r + 3].y) = buf[hpad(m + H)];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int j = fft_tid() + T * r;
+    const bool j0 = j == 0;  // bins 0 and H pair with themselves; this slot's m side takes m = Q
+    const int m = j0 ? Q : H - j;
+    const cpx<double> t = tw[j];
+    const cpx<double> tm = j0 ? cpx<double>{0.0, -1.0} : cpx<double>{-t.x, t.y};  // w^m
+    const cpx<double> wb = cmul(t, v[4 * r + 1]), wd = cmul(tm, v[4 * r + 3]);
+    const cpx<double> zj = cadd(v[4 * r], wb), zj2 = csub(v[4 * r], wb);
+    const cpx<double> zm = cadd(v[4 * r + 2], wd), zm2 = csub(v[4 * r + 2], wd);
+    const cpx<double> xj = spec(abf[j], zj, j0 ? zj : zm2), xjh = spec(abf[j + H], zj2, j0 ? zj2 : zm);
+    const cpx<double> xm = spec(abf[m], zm, j0 ? zm2 : zj2), xmh = spec(abf[m + H], zm2, j0 ? zm : zj);
+    v[4 * r + 0] = cadd(xj, xjh);
+    v[4 * r + 1] = csub(xj, xjh);
+    v[4 * r + 2] = cadd(xm, xmh);
+    v[4 * r + 3] = csub(xm, xmh);
+  }
+  settle<double, N / T>(v);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      const int j = fft_tid() + T * r, m = j == 0 ? Q : H - j;
+      buf[hpad(2 * j)] = c == 0 ? v[4 * r + 0].x : v[4 * r + 0].y;
+      buf[hpad(2 * j + 1)] = c == 0 ? v[4 * r + 1].x : v[4 * r + 1].y;
+      buf[hpad(2 * m)] = c == 0 ? v[4 * r + 2].x : v[4 * r + 2].y;
+      buf[hpad(2 * m + 1)] = c == 0 ? v[4 * r + 3].x : v[4 * r + 3].y;
+    }
+    __syncthreads();
+    if (c == 0) hload<double, N, T, 16, 0>(buf, v);
+    else hload<double, N, T, 16, 1>(buf, v);
+  }
+}
+
+// Batches of the two-per-CU kernel: smaller than the one-per-CU plan's, so
+// that a batch of loads and the 16 register values fit 128 VGPRs.
+template <class C>
+struct HPlan {
+  static constexpr int N = Plan<C>::N, T = Plan<C>::T;
+  static constexpr int kGatherBatch = 2;   // entries (sample pairs) per load batch
+  static constexpr int kScatterBatch = 2;
+  static constexpr int kWavesPerEU = 4;    // two 512-thread workgroups per CU
+};
+
+template <class S, class C, int kW, int NC>
+__device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t lambda, const cpx<C>* __restrict__ abf,
+                                                   const cpx<C>* __restrict__ tw,
+                                                   const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
+                                                   const cpx<S>* __restrict__ wts, const double* __restrict__ x,
+                                                   double* __restrict__ q) {
+  using P = HPlan<C>;
+  using A = Angle<C, S, kW>;
+  constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch;
+  constexpr bool kAng = Stokes<NC>::kAngle;
+  constexpr int kSlots = (hlds_elems<N>() * (int)sizeof(C) / 8) / NC / 64 * 64;
+  static_assert(E % G == 0, "gather batches must tile the elements");
+  static_assert(E == 16, "the half-buffer FFT is written for 16 values per thread");
+  __shared__ C buf[hlds_elems<N>()];
+  __shared__ int32_t s_red[2 * (T / 64)];
+
+  const int64_t in0 = tl.out_start - (lambda - 1);
+  const int32_t vlo = lambda - 1;
+  const int32_t vhi = vlo + (int32_t)(tl.out_end - tl.out_start);
+  const int32_t ilo = (int32_t)(tl.chunk_start > in0 ? tl.chunk_start - in0 : 0);
+  const int32_t ihi = (int32_t)(tl.chunk_end - in0 < L ? tl.chunk_end - in0 : L);
+  const bool wrap = tl.wrap != 0;
+  const int32_t clen = (int32_t)(tl.chunk_end - tl.chunk_start);
+  const int32_t* __restrict__ sk = sample_k + in0;
+  const S* __restrict__ ps0 = (kAng && kW == 0) ? psi + in0 : nullptr;
+  const cpx<S>* __restrict__ w0 = (kAng && kW == 1) ? wts + in0 : nullptr;
+  const int tid = threadIdx.x;
+
+  // ---- gather P x over the whole window, element e of this thread packing
+  // window samples 2n, 2n+1 with n = tid + T e
+  cpx<C> v[E];
+  int32_t kmin = INT32_MAX, kmax = -1;  // compact-index window of the valid outputs
+  int tdep = tid;
+#pragma unroll
+  for (int e0 = 0; e0 < E; e0 += G) {
+    // one batch of loads in flight at a time: the positions of a batch are
+    // computed from a thread id that waits for the previous batch's last
+    // value, so the compiler cannot issue the loads of several batches at
+    // once and hold them beside the 16 register values
+    __builtin_amdgcn_sched_barrier(0);
+    if (e0 > 0) asm volatile("" : "+v"(tdep) : "v"(v[e0 - 1].y));
+    int32_t ks[2 * G];
+    typename A::type ps[2 * G];
+#pragma unroll
+    for (int i = 0; i < 2 * G; ++i) {
+      const int pos = 2 * (tdep + T * (e0 + i / 2)) + (i & 1);
+      int sp;
+      const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+      const int pa = ok ? sp : ilo;  // ilo: inside the chunk, always in bounds
+      const int32_t kr = sk[pa];
+      ks[i] = ok ? kr : -1;
+      ps[i] = kAng ? A::load(ps0, w0, pa) : A::zero();
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * G; ++i) {
+      const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
+      const int32_t k = ks[i];
+      C c = C(0), s = C(0);
+      if constexpr (kAng) A::eval(ps[i], &c, &s);
+      const C val = k >= 0 ? Stokes<NC>::project(x + NC * (int64_t)(k >= 0 ? k : 0), c, s) : C(0);
+      if (i & 1) v[e0 + i / 2].y = val;
+      else v[e0 + i / 2].x = val;
+      if (k >= 0 && pos >= vlo && pos < vhi) {
+        kmin = k < kmin ? k : kmin;
+        kmax = k > kmax ? k : kmax;
+      }
+    }
+  }
+  kmin = wave_min(kmin);
+  kmax = wave_max(kmax);
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6] = kmin;
+    s_red[T / 64 + (tid >> 6)] = kmax;
+  }
+
+  // ---- forward FFT, spectral step, inverse FFT (outputs in registers)
+  hpasses<C, N, T, true, 1, 16, 16, 16>(buf, v, tw);
+  hmiddle<N, T>(buf, v, abf, tw);
+  hpasses<C, N, T, false, 2, 16, 16, 16>(buf, v, tw);
+
+  // ---- P^T through LDS bins in the half buffer
+  __syncthreads();  // every thread is done reading buf; s_red is complete
+  kmin = s_red[0];
+  kmax = s_red[T / 64];
+#pragma unroll
+  for (int w = 1; w < T / 64; ++w) {
+    kmin = s_red[w] < kmin ? s_red[w] : kmin;
+    kmax = s_red[T / 64 + w] > kmax ? s_red[T / 64 + w] : kmax;
+  }
+  if (kmax < kmin) return;
+  scatter_bins<S, C, kW, NC, false, false, kSlots, P::kScatterBatch>(v, reinterpret_cast<double*>(buf), nullptr, sk,
+                                                                     ps0, w0, vlo, vhi, kmin, kmax, q);
+}
+
+// One plain tile of one right-hand side per workgroup, two workgroups per
+// CU; tiles mapped to workgroups as in k_toeplitz.
+template <class S, class C, int kW, int NC>
+__global__ __launch_bounds__(HPlan<C>::T, HPlan<C>::kWavesPerEU) void k_toeplitz_half(
+    const FftTile* __restrict__ tiles, int64_t n_tiles, int32_t lambda, const cpx<C>* __restrict__ ab,
+    const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
+    const cpx<S>* __restrict__ wts, const double* __restrict__ x, double* __restrict__ q, RhsBatch rb,
+    int32_t variant) {
+  int64_t tile;
+  int rhs;
+  if (variant & kOpLinearOrder) {
+    tile = blockIdx.x / rb.nrhs;
+    rhs = (int)(blockIdx.x % rb.nrhs);
+  } else {
+    const int64_t per_xcd = (n_tiles + 7) / 8;
+    const int64_t local = blockIdx.x / 8;
+    tile = (int64_t)(blockIdx.x % 8) * per_xcd + local / rb.nrhs;
+    rhs = (int)(local % rb.nrhs);
+  }
+  if (tile >= n_tiles) return;
+  if (rb.done != nullptr && rb.done[(int64_t)rhs * rb.done_stride]) return;
+  x += rhs * rb.vstride;
+  q += rhs * rb.vstride;
+  const FftTile tl = tiles[tile];
+  toeplitz_tile_half<S, C, kW, NC>(tl, lambda, ab + (int64_t)tl.filter * HPlan<C>::N, tw, sample_k, psi, wts, x, q);
+}
+
 // One launch over the tiles of several slots (right-hand sides of different
 // solves).  Every slot's tiles are split into 8 contiguous parts and XCD x
 // takes part x of every slot, one after the other: each XCD then gets an
@@ -877,6 +1159,15 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
     }
   }
   const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8) * rb.nrhs;
+  if constexpr (kIn == 1 && kOut == 1 && std::is_same<C, double>::value) {
+    if (variant & kOpHalfLds) {
+      hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC>), dim3(grid), dim3(HPlan<C>::T), 0, s, nz->tiles[a],
+                         nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
+                         pt->sample_k, (const S*)pt->psi, (const cpx<S>*)pt->weights, x, q, rb, variant);
+      MM_HIP(hipGetLastError());
+      return MM_OK;
+    }
+  }
   hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW, NC>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
                      nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
                      pt ? pt->sample_k : nullptr, pt ? (const S*)pt->psi : nullptr,

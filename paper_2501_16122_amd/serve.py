@@ -67,7 +67,8 @@ def footprint_bytes(w: synth.Workload, opts: b.SolveOpts, weights: bool) -> int:
     if weights:
         total += 2 * n * esz
     sz = b._c.c_size_t()
-    b._check(lib.mm_pointing_workspace_size(n, w.n_det, w.n_pix, b._c.byref(sz)))
+    b._check(lib.mm_pointing_workspace_size(n, w.n_det, w.n_pix, b.MM_F32 if w.precision == "f32" else b.MM_F64,
+                                            b._c.byref(sz)))
     total += sz.value
     if w.toeplitz:
         offs = synth.chunk_offsets(w)
@@ -76,10 +77,9 @@ def footprint_bytes(w: synth.Workload, opts: b.SolveOpts, weights: bool) -> int:
         total += sz.value
     else:
         total += 8 * w.n_det
-    # solver vectors with every pixel kept (upper bound)
-    n3 = 3 * w.n_pix
-    hist = max(opts.max_iter, opts.fixed_iter) + opts.max_outer + 2
-    total += 9 * n3 * 8 + 4 * 2 * 256 * 8 + 8 * hist + 4096
+    # solver vectors, state and history with every pixel kept (the library's bound)
+    b._check(lib.mm_solver_workspace_bound(w.n_pix, 3, 1, b._c.byref(opts), b._c.byref(sz)))
+    total += sz.value
     return int(total)
 
 

@@ -39,12 +39,14 @@ def test_binding_covers_every_declared_symbol():
 @pytest.mark.skipif(not os.path.exists(binding.LIB_PATH), reason="library not built")
 def test_host_only_calls():
     lib = binding.load()
-    assert lib.mm_abi_version() == 4
+    assert lib.mm_abi_version() == 5
     sz = ctypes.c_size_t()
-    assert lib.mm_pointing_workspace_size(1 << 20, 4, 4096, ctypes.byref(sz)) == 0
+    assert lib.mm_pointing_workspace_size(1 << 20, 4, 4096, binding.MM_F64, ctypes.byref(sz)) == 0
     assert sz.value > 4 * (1 << 20)
-    assert lib.mm_pointing_workspace_size(10, 0, 4096, ctypes.byref(sz)) == binding.MM_EINVAL
+    assert lib.mm_pointing_workspace_size(10, 0, 4096, binding.MM_F64, ctypes.byref(sz)) == binding.MM_EINVAL
     assert b"bad" in lib.mm_last_error()
+    assert lib.mm_pointing_workspace_size(10, 1, 4096, 7, ctypes.byref(sz)) == binding.MM_EINVAL
+    assert b"dtype" in lib.mm_last_error()
     opts = binding.SolveOpts()
     assert lib.mm_solve_opts_default(ctypes.byref(opts)) == 0
     assert opts.tol == 1e-10 and opts.max_iter == 2000

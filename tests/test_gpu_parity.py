@@ -11,6 +11,7 @@ import pytest
 
 import oracle.mapmaking as oracle
 from paper_2501_16122_amd import synth
+from parity_util import err as rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -28,13 +29,6 @@ DEV = "cuda:0"
 # 3*2^16 + 777 samples, chunks of 2^15 + 123 samples, a 128^2 grid
 RAGGED = synth.Workload("ragged_128x128_3x197385", 931, 128, 128, 3, 3 * (1 << 16) + 777, t_psi=1500.0,
                         noise="oneoverf", chunk=(1 << 15) + 123, lam=512)
-
-
-def rel_err(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    den = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
 
 
 class Problem:
@@ -90,7 +84,7 @@ def _check_build(P):
     assert np.array_equal(out["compact"].cpu().numpy(), o.compact.astype(np.int32))
     assert np.array_equal(out["kept"].cpu().numpy(), o.kept.astype(np.int32))
     minv = out["minv"].cpu().numpy()
-    assert rel_err(minv, o.minv) < 1e-12
+    assert rel_err(minv, o.minv, 9) < 1e-12
 
 
 def test_build_bit_exact_ragged(ragged):
@@ -153,7 +147,7 @@ def test_P_PT_white_ninv(ragged):
     yp = b.apply_P(P.pt, tx).cpu().numpy()
     assert rel_err(yp, oracle.apply_P(P.opt, x)) < 1e-14
     q = b.apply_PT(P.pt, ty).cpu().numpy()
-    assert rel_err(q, oracle.apply_PT(P.opt, y)) < 1e-13
+    assert rel_err(q, oracle.apply_PT(P.opt, y), 3) < 1e-13
     nzw = b.Noise.white(P.wdet * np.array([1.0, 0.5, 2.0]), DEV)
     z = b.apply_Ninv(nzw, P.pt, ty).cpu().numpy()
     wt = np.repeat(P.wdet * np.array([1.0, 0.5, 2.0]), np.diff(P.offs))
@@ -169,7 +163,7 @@ def test_fused_white_matches_oracle(binned):
     P = binned
     x = np.random.default_rng(12).normal(size=3 * P.opt.n_kept)
     q = b.apply_A(P.pt, P.nz, torch.from_numpy(x).to(DEV)).cpu().numpy()
-    assert rel_err(q, oracle.apply_A(P.opt, None, x)) < 1e-13
+    assert rel_err(q, oracle.apply_A(P.opt, None, x), 3) < 1e-13
 
 
 @pytest.mark.parametrize("lam", [1, 7, 64, 512, 4096])
@@ -221,14 +215,14 @@ def test_fused_toeplitz_and_rhs_match_oracle(ragged):
     P = ragged
     x = np.random.default_rng(13).normal(size=3 * P.opt.n_kept)
     q = b.apply_A(P.pt, P.nz, torch.from_numpy(x).to(DEV)).cpu().numpy()
-    assert rel_err(q, oracle.apply_A(P.opt, P.noise, x)) < 1e-12
+    assert rel_err(q, oracle.apply_A(P.opt, P.noise, x), 3) < 1e-12
     bb = b.rhs(P.pt, P.nz, P.t_d).cpu().numpy()
-    assert rel_err(bb, oracle.rhs(P.opt, P.noise, P.d)) < 1e-12
+    assert rel_err(bb, oracle.rhs(P.opt, P.noise, P.d), 3) < 1e-12
     # the fused pass equals the composition of the standalone operators
     y = b.apply_P(P.pt, torch.from_numpy(x).to(DEV))
     z = b.apply_Ninv(P.nz, P.pt, y)
     q2 = b.apply_PT(P.pt, z).cpu().numpy()
-    assert rel_err(q, q2) < 1e-13
+    assert rel_err(q, q2, 3) < 1e-13
 
 
 def test_apply_M_and_expand(ragged):
@@ -236,7 +230,7 @@ def test_apply_M_and_expand(ragged):
     P = ragged
     r = np.random.default_rng(14).normal(size=3 * P.opt.n_kept)
     z = b.apply_M(P.pt, torch.from_numpy(r).to(DEV)).cpu().numpy()
-    assert rel_err(z, oracle.apply_M(P.opt, r)) < 1e-13
+    assert rel_err(z, oracle.apply_M(P.opt, r), 3) < 1e-13
     full = b.expand_map(P.pt, torch.from_numpy(r).to(DEV)).cpu().numpy().reshape(-1, 3)
     assert np.array_equal(full, oracle.expand(P.opt, r))
 
@@ -295,9 +289,9 @@ def test_fused_toeplitz_with_stored_weights(ragged):
         bb = b.rhs(P.pt, P.nz, P.t_d).cpu().numpy()
     finally:
         P.pt.detach_weights()
-    assert rel_err(q1, oracle.apply_A(P.opt, P.noise, x)) < 1e-12
-    assert rel_err(q1, q0) < 1e-13
-    assert rel_err(bb, oracle.rhs(P.opt, P.noise, P.d)) < 1e-12
+    assert rel_err(q1, oracle.apply_A(P.opt, P.noise, x), 3) < 1e-12
+    assert rel_err(q1, q0, 3) < 1e-13
+    assert rel_err(bb, oracle.rhs(P.opt, P.noise, P.d), 3) < 1e-12
 
 
 def _mixed_problem(w):
@@ -326,14 +320,18 @@ def test_precision_form_toeplitz_refined():
     b = _b()
     P = _mixed_problem(RAGGED)
     P.pt.attach_weights()
-    # FP32 operator alone (one outer step, inner solve run to FP32 accuracy)
-    one = b.Solver(P.pt, P.nz, tol=1e-14, mixed=1, max_outer=1, inner_tol=1e-6).solve(P.t_d)
+    # FP32 operator alone (one outer step, inner solve run to FP32 accuracy),
+    # from x = 0 and from the block-Jacobi map M b (whose residual is FP64)
     _, _, x_ref = oracle.solve(P.opt, P.noise, P.d, tol=1e-14)
-    err_fp32 = oracle.rel_l2_per_stokes(one["x"].cpu().numpy(), x_ref)
-    # reported, not a parity bar: FP32 FFT round-off on the I-dominated
-    # timeline (sigma_I = 100 vs 1 for Q, U) leaks ~1e-7 * 100 into Q/U
-    print("FP32-operator map error before refinement (I, Q, U):", err_fp32)
-    assert np.all(err_fp32 < 1e-3)
+    errs = {}
+    for bj in (0, 1):
+        one = b.Solver(P.pt, P.nz, tol=1e-14, mixed=1, max_outer=1, inner_tol=1e-9, max_iter=400,
+                       bj_start=bj).solve(P.t_d)
+        errs[bj] = oracle.rel_l2_per_stokes(one["x"].cpu().numpy(), x_ref)
+    # FP32 rounding of the I-dominated timeline (sigma_I = 100 vs 1 for Q, U)
+    # and of the FP32 (cos 2psi, sin 2psi) leaks ~eps_32 * 100 into Q/U
+    print("FP32-operator map error before refinement (I, Q, U): from 0", errs[0], "from M b", errs[1])
+    assert np.all(errs[0] < 1e-3) and np.all(errs[1] < 1e-3)
     # refined to a tight FP64 residual: the map matches the FP64 oracle
     out = b.Solver(P.pt, P.nz, tol=1e-13, mixed=1, max_outer=20).solve(P.t_d, history=True)
     info = out["info"]
@@ -367,8 +365,13 @@ def test_fused_toeplitz_wide_window_matches_oracle():
     x = np.random.default_rng(21).normal(size=3 * o.n_kept)
     tx = torch.from_numpy(x).to(DEV)
     q_ref = oracle.apply_A(o, P.noise, x)
-    assert rel_err(b.apply_A(P.pt, P.nz, tx).cpu().numpy(), q_ref) < 1e-12
-    # FP32 timeline arithmetic (32768-sample tiles, more passes): FP32 rounding only
-    assert rel_err(b.apply_A(P.pt, P.nz, tx, arith="f32").cpu().numpy(), q_ref) < 1e-5
+    # plain tiles (0), and halo-carrying segments (4, 5): 2^23 samples in 8192-
+    # sample carry strides make 1024 carrying tiles, i.e. segments of 4 tiles
+    # on 256 CUs, so the carried P x and index ranges are exercised, with
+    # several bin passes per tile
+    for v in (0, 4, 5, 8, 9):
+        assert rel_err(b.apply_A(P.pt, P.nz, tx, variant=v).cpu().numpy(), q_ref, 3) < 1e-12, v
+        # FP32 timeline arithmetic (32768-sample tiles, more passes): FP32 rounding only
+        assert rel_err(b.apply_A(P.pt, P.nz, tx, arith="f32", variant=v).cpu().numpy(), q_ref, 3) < 1e-5, v
     bb = b.rhs(P.pt, P.nz, P.t_d).cpu().numpy()
-    assert rel_err(bb, oracle.rhs(o, P.noise, P.d)) < 1e-12
+    assert rel_err(bb, oracle.rhs(o, P.noise, P.d), 3) < 1e-12

@@ -8,6 +8,7 @@ import pytest
 
 import oracle.mapmaking as oracle
 from paper_2501_16122_amd import synth
+from parity_util import err as rel
 
 pytestmark = pytest.mark.gpu
 
@@ -21,12 +22,6 @@ W = synth.Workload("tpl_128x128_3x197385", 951, 128, 128, 3, 3 * (1 << 16) + 777
 def _b():
     from paper_2501_16122_amd import binding
     return binding
-
-
-def rel(a, b):
-    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
-    d = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
 
 
 def intervals(w, length=5003):
@@ -85,17 +80,17 @@ def test_fused_operator_and_rhs(setup):
     x = np.random.default_rng(2).normal(size=setup.nc * o.n_kept)
     tx = torch.from_numpy(x).to(DEV)
     ref = oracle.apply_A(o, setup.noise, x)
-    assert rel(b.apply_A(setup.pt, setup.nz, tx).cpu(), ref) < 1e-12
-    assert rel(b.apply_A(setup.pt, setup.nz, tx, arith="f32").cpu(), ref) < 1e-5
+    assert rel(b.apply_A(setup.pt, setup.nz, tx).cpu(), ref, setup.nc) < 1e-12
+    assert rel(b.apply_A(setup.pt, setup.nz, tx, arith="f32").cpu(), ref, setup.nc) < 1e-5
     Q = b.apply_A_multi(setup.pt, setup.nz, torch.stack([tx, -tx]).contiguous()).cpu().numpy()
-    assert rel(Q[0], ref) < 1e-12 and rel(Q[1], -ref) < 1e-12
-    assert rel(b.rhs(setup.pt, setup.nz, setup.t_d).cpu(), oracle.rhs(o, setup.noise, setup.d)) < 1e-12
+    assert rel(Q[0], ref, setup.nc) < 1e-12 and rel(Q[1], -ref, setup.nc) < 1e-12
+    assert rel(b.rhs(setup.pt, setup.nz, setup.t_d).cpu(), oracle.rhs(o, setup.noise, setup.d), setup.nc) < 1e-12
     # the same with stored pointing weights streamed instead of psi
     setup.pt.attach_weights()
     try:
-        assert rel(b.apply_A(setup.pt, setup.nz, tx).cpu(), ref) < 1e-12
-        assert rel(b.apply_A(setup.pt, setup.nz, tx, arith="f32").cpu(), ref) < 1e-5
-        assert rel(b.rhs(setup.pt, setup.nz, setup.t_d).cpu(), oracle.rhs(o, setup.noise, setup.d)) < 1e-12
+        assert rel(b.apply_A(setup.pt, setup.nz, tx).cpu(), ref, setup.nc) < 1e-12
+        assert rel(b.apply_A(setup.pt, setup.nz, tx, arith="f32").cpu(), ref, setup.nc) < 1e-5
+        assert rel(b.rhs(setup.pt, setup.nz, setup.t_d).cpu(), oracle.rhs(o, setup.noise, setup.d), setup.nc) < 1e-12
     finally:
         setup.pt.detach_weights()
 
