@@ -34,8 +34,9 @@ FP64_PEAK_TFLOPS = 78.6
 # algorithmic HBM bytes per timeline sample of one fused P^T N^-1 P launch:
 # int32 pixel index + FP64 angle (the map and the noise tables stay in cache)
 ALG_BYTES_PER_SAMPLE_F64 = 12.0
-# what the band-Toeplitz kernel streams instead: the index + stored FP64 (cos 2psi, sin 2psi)
-STREAMED_BYTES_PER_SAMPLE_TOEPLITZ = 20.0
+# what the band-Toeplitz kernel reads per sample and pass: the index + the
+# stored FP64 tangent tan psi (the row's cos/sin are rebuilt from it)
+STREAMED_BYTES_PER_SAMPLE_TOEPLITZ = 12.0
 # source files of the dominant kernel (the fused band-Toeplitz A); a stored
 # counter summary is used only while these are unchanged
 KERNEL_SOURCES = ["paper_2501_16122_amd/csrc/toeplitz.hip", "paper_2501_16122_amd/csrc/fft_lds.h",

@@ -138,11 +138,15 @@ int mm_pointing_info(mm_pointing_t pt, int32_t* n_kept, int64_t* n_samples, int3
 int mm_pointing_export(mm_pointing_t pt, int32_t* hits, uint8_t* mask, int32_t* compact,
                        int32_t* kept, double* minv, void* stream);
 
-/* Precompute the pointing elements (cos 2psi_t, sin 2psi_t) of eq. (8) once
- * (Sec. III-A) into caller memory and let the band-Toeplitz operators stream
- * them instead of evaluating sin/cos from psi three times per sample:
- *   weights   dtype[2 * n_samples] device, interleaved (cos, sin) per sample,
- *             same dtype as psi; borrowed until detached or destroyed
+/* Precompute the pointing elements of eq. (8) once (Sec. III-A) into caller
+ * memory, and let the band-Toeplitz and template operators stream them
+ * instead of evaluating sin/cos from psi each time they need a row:
+ *   weights   dtype[n_samples] device, same dtype as psi: u_t = tan psi_t,
+ *             from which the kernels rebuild the row's (cos 2psi_t, sin 2psi_t)
+ *             = ((1 - u^2), 2u) / (1 + u^2) with a few multiplies (the
+ *             half-angle substitution; u is finite for every finite stored
+ *             angle, and a relative error e in u moves 2psi by at most e);
+ *             borrowed until detached or destroyed
  * Stored weights serve arithmetic no finer than their dtype (FP32 weights are
  * not used by FP64 arithmetic).  weights = NULL detaches.  Stream-ordered.
  * The intensity-only form has no weights (MM_EINVAL). */
@@ -312,6 +316,7 @@ int mm_solve_workspace_size(mm_pointing_t pt, mm_noise_t nz, const mm_solve_opts
 int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, double* x_out,
              const mm_solve_opts* opts, mm_solve_info* info, double* history_host, int32_t history_len,
              void* workspace, size_t ws_bytes, void* stream);
+
 
 /* ------------------------------------------------------------------------
  * Resumable solves: one or several right-hand sides sharing a pointing and a

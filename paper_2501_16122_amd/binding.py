@@ -240,14 +240,15 @@ class Pointing:
                 "minv": minv[:nc * nc * self.n_kept].view(-1, nc, nc)}
 
     def attach_weights(self, stream=None):
-        """Precompute (cos 2psi, sin 2psi) per sample into a device tensor the
-        handle keeps; the band-Toeplitz operators then stream it.  The
-        intensity-only form reads no angle: nothing to attach (None)."""
+        """Precompute the pointing weight u = tan(psi) of every sample into a
+        device tensor the handle keeps; the band-Toeplitz and template
+        operators then stream it and rebuild (cos 2psi, sin 2psi) from it.
+        The intensity-only form reads no angle: nothing to attach (None)."""
         torch = _torch()
         if self.ncomp == 1:
             self.weights = None
             return None
-        self.weights = torch.empty(2 * max(1, self.n_samples), dtype=self.tod_dtype, device=self.device)
+        self.weights = torch.empty(max(1, self.n_samples), dtype=self.tod_dtype, device=self.device)
         _check(load().mm_pointing_attach_weights(self.handle, _ptr(self.weights), _stream(stream)))
         return self.weights
 

@@ -220,15 +220,16 @@ __global__ __launch_bounds__(kOpThreads) void k_ninv_white(const PtTile* __restr
   }
 }
 
-// (cos 2psi_t, sin 2psi_t) of every sample, stored as a pair of S
+// The stored pointing weight of every sample: u = tan psi_t (sin psi / cos
+// psi in FP64, rounded to S), from which the kernels rebuild (cos 2psi_t,
+// sin 2psi_t) by the half-angle substitution (from_tangent).
 template <class S>
 __global__ __launch_bounds__(kOpThreads) void k_weights(const S* __restrict__ psi, S* __restrict__ w, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
-    S c, s;
-    sincos2<S>(psi[t], &c, &s);
-    w[2 * t] = c;
-    w[2 * t + 1] = s;
+    double s, c;
+    sincos_x(double(psi[t]), &s, &c);
+    w[t] = S(s / c);
   }
 }
 

@@ -104,4 +104,32 @@ __device__ __forceinline__ void sincos2(S psi, C* c, C* s) {
   sincos_x(2.0 * double(psi), s, c);
 }
 
+// 1 / d for d >= 1: the hardware estimate refined by Newton steps
+// r <- r + r (1 - d r), each of which squares the relative error.
+__device__ __forceinline__ double recip_ge1(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ float recip_ge1(float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  return fmaf(r, fmaf(-d, r, 1.0f), r);
+}
+
+// (cos 2psi, sin 2psi) from the stored tangent u = tan psi, by the
+// half-angle (Weierstrass) substitution: cos 2psi = (1 - u^2) / (1 + u^2),
+// sin 2psi = 2u / (1 + u^2).  u is finite for every stored angle (no FP64 or
+// FP32 number is an odd multiple of pi/2), a relative error e in u moves the
+// angle 2psi by at most e, and 1 + u^2 >= 1 keeps the reciprocal well
+// conditioned: a few multiplies instead of a reduction and two polynomials.
+template <class C, class S>
+__device__ __forceinline__ void from_tangent(S u, C* c, C* s) {
+  const C v = C(u);
+  const C v2 = v * v;
+  const C r = recip_ge1(C(1) + v2);
+  *c = (C(1) - v2) * r;
+  *s = (v + v) * r;
+}
+
 }  // namespace mm

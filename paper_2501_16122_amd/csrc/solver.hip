@@ -798,3 +798,4 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
 }
 
 }  // extern "C"
+

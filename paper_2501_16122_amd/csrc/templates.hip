@@ -89,7 +89,7 @@ __device__ __forceinline__ T wave_minmax(T v, bool is_min) {
 template <class S, class C, int NC, int kIn, int kOut, int kW>
 __device__ __forceinline__ void templates_interval(
     const TplInterval& I, const PtTile* __restrict__ tiles, int64_t n_tiles, const double* __restrict__ det_w,
-    const int32_t* __restrict__ sample_k, const S* __restrict__ psi, const cpx<S>* __restrict__ wts,
+    const int32_t* __restrict__ sample_k, const S* __restrict__ psi, const S* __restrict__ wts,
     const double* __restrict__ x, const S* __restrict__ tin, S* __restrict__ tout, double* __restrict__ q) {
   constexpr int W = kTplThreads / 64;
   __shared__ double s_sum[kMaxTplOrder * W];
@@ -122,7 +122,6 @@ __device__ __forceinline__ void templates_interval(
   constexpr bool kAng = Stokes<NC>::kAngle && (kIn == 1 || kOut == 1);
   auto load_batch = [&](int64_t i0, int32_t* kb, C* yb, C* cb, C* sb) {
     S ang[kTplJ];
-    cpx<S> cs[kTplJ];
     S tv[kTplJ];
     // loads past the end of the interval read its last sample instead (in
     // bounds, unconditional, then discarded)
@@ -136,17 +135,14 @@ __device__ __forceinline__ void templates_interval(
         const int32_t kr = sample_k[t];
         kb[j] = ok ? kr : -1;
       }
-      if constexpr (kAng && kW == 1) cs[j] = wts[t];
+      if constexpr (kAng && kW == 1) ang[j] = wts[t];
       if constexpr (kAng && kW == 0) ang[j] = psi[t];
       if constexpr (kIn == 0) tv[j] = tin[t];
     }
 #pragma unroll
     for (int j = 0; j < kTplJ; ++j) {
       C c = C(0), sn = C(0);
-      if constexpr (kAng && kW == 1) {
-        c = C(cs[j].x);
-        sn = C(cs[j].y);
-      }
+      if constexpr (kAng && kW == 1) from_tangent<C, S>(ang[j], &c, &sn);
       if constexpr (kAng && kW == 0)
         if (kb[j] >= 0) sincos2<C>(ang[j], &c, &sn);
       cb[j] = c;
@@ -282,7 +278,7 @@ template <class S, class C, int NC, int kIn, int kOut, int kW>
 __global__ __launch_bounds__(kTplThreads) void k_templates(
     const TplInterval* __restrict__ iv, const PtTile* __restrict__ tiles, int64_t n_tiles,
     const double* __restrict__ det_w, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
-    const cpx<S>* __restrict__ wts, const double* __restrict__ x, const S* __restrict__ tin, S* __restrict__ tout,
+    const S* __restrict__ wts, const double* __restrict__ x, const S* __restrict__ tin, S* __restrict__ tout,
     double* __restrict__ q, RhsBatch rb) {
   if (rb.done != nullptr && rb.done[(int64_t)blockIdx.y * rb.done_stride]) return;
   if (x != nullptr) x += blockIdx.y * rb.vstride;
@@ -305,7 +301,7 @@ __global__ __launch_bounds__(kTplThreads) void k_templates_batch(OpBatch b) {
       templates_interval<S, C, NC, 1, 1, kW>(static_cast<const TplInterval*>(o.iv)[it - b.off[sl]],
                                              static_cast<const PtTile*>(o.tiles), o.n_pt_tiles, o.det_w,
                                              o.sample_k, static_cast<const S*>(o.psi),
-                                             static_cast<const cpx<S>*>(o.wts), o.x, nullptr, nullptr, o.q);
+                                             static_cast<const S*>(o.wts), o.x, nullptr, nullptr, o.q);
     __syncthreads();  // the next item reuses the shared memory
   }
 }
@@ -315,7 +311,7 @@ int launch_one(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, c
                double* q, const RhsBatch& rb, hipStream_t s) {
   const dim3 g((unsigned)nz->n_chunks, rb.nrhs), b(kTplThreads);
   hipLaunchKernelGGL((k_templates<S, C, NC, kIn, kOut, kW>), g, b, 0, s, nz->tpl, pt->tiles, pt->n_tiles, nz->det_w,
-                     pt->sample_k, (const S*)pt->psi, (const cpx<S>*)pt->weights, x, (const S*)tin, (S*)tout, q,
+                     pt->sample_k, (const S*)pt->psi, (const S*)pt->weights, x, (const S*)tin, (S*)tout, q,
                      rb);
   MM_HIP(hipGetLastError());
   return MM_OK;

@@ -231,26 +231,19 @@ struct Fft<float> {
   }
 };
 
-// (cos 2psi_t, sin 2psi_t) in arithmetic C: from the stored pair when kW,
-// else from psi.
+// (cos 2psi_t, sin 2psi_t) in arithmetic C: from the stored tangent
+// tan psi_t when kW, else from psi.
 template <class C, class S, int kW>
 struct Angle {
-  using type = typename std::conditional<kW == 1, cpx<S>, S>::type;
-  static __device__ __forceinline__ type load(const S* __restrict__ psi, const cpx<S>* __restrict__ w, int32_t t) {
+  using type = S;
+  static __device__ __forceinline__ type load(const S* __restrict__ psi, const S* __restrict__ w, int32_t t) {
     if constexpr (kW == 1) return w[t];
     else return psi[t];
   }
-  static __device__ __forceinline__ type zero() {
-    if constexpr (kW == 1) return cpx<S>{S(0), S(0)};
-    else return S(0);
-  }
+  static __device__ __forceinline__ type zero() { return S(0); }
   static __device__ __forceinline__ void eval(type a, C* c, C* s) {
-    if constexpr (kW == 1) {
-      *c = C(a.x);
-      *s = C(a.y);
-    } else {
-      sincos2<C>(a, c, s);
-    }
+    if constexpr (kW == 1) from_tangent<C, S>(a, c, s);
+    else sincos2<C>(a, c, s);
   }
 };
 
@@ -280,7 +273,7 @@ template <class S, class C, int kW, int NC, bool kKeepK, bool kKeepW = false, in
           int kBatch = Plan<C>::kScatterBatch>
 __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, const int32_t* kk,
                                              const int32_t* __restrict__ sk, const S* __restrict__ ps0,
-                                             const cpx<S>* __restrict__ w0, int32_t vlo, int32_t vhi, int32_t kmin,
+                                             const S* __restrict__ w0, int32_t vlo, int32_t vhi, int32_t kmin,
                                              int32_t kmax, double* __restrict__ q,
                                              const typename Angle<C, S, kW>::type* wk = nullptr) {
   using P = Plan<C>;
@@ -390,7 +383,7 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
 template <class S, class C, int kIn, int kOut, int kW, int NC>
 __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda, const cpx<C>* __restrict__ abf,
                                               const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k,
-                                              const S* __restrict__ psi, const cpx<S>* __restrict__ wts,
+                                              const S* __restrict__ psi, const S* __restrict__ wts,
                                               const double* __restrict__ x, const S* __restrict__ tod_in,
                                               S* __restrict__ tod_out, double* __restrict__ q, int32_t variant) {
   using P = Plan<C>;
@@ -414,7 +407,7 @@ __device__ __forceinline__ void toeplitz_tile(const FftTile& tl, int32_t lambda,
   // tile-based views indexed by window position (only the chunk is read)
   const int32_t* __restrict__ sk = sample_k != nullptr ? sample_k + in0 : nullptr;
   const S* __restrict__ ps0 = (kAng && kW == 0 && psi != nullptr) ? psi + in0 : nullptr;
-  const cpx<S>* __restrict__ w0 = (kAng && kW == 1 && wts != nullptr) ? wts + in0 : nullptr;
+  const S* __restrict__ w0 = (kAng && kW == 1 && wts != nullptr) ? wts + in0 : nullptr;
   const S* __restrict__ tin = tod_in != nullptr ? tod_in + in0 : nullptr;
   S* __restrict__ tout = tod_out != nullptr ? tod_out + in0 : nullptr;
   const int tid = threadIdx.x;
@@ -602,7 +595,7 @@ template <class S, class C, int kW, int NC>
 __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t lambda,
                                                     const cpx<C>* __restrict__ abf, const cpx<C>* __restrict__ tw,
                                                     const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
-                                                    const cpx<S>* __restrict__ wts, const double* __restrict__ x,
+                                                    const S* __restrict__ wts, const double* __restrict__ x,
                                                     double* __restrict__ q, cpx<C>* carry, bool have, int32_t& cmin,
                                                     int32_t& cmax) {
   using P = Plan<C>;
@@ -627,7 +620,7 @@ __device__ __forceinline__ void toeplitz_tile_carry(const FftTile& tl, int32_t l
   const int32_t clen = (int32_t)(tl.chunk_end - tl.chunk_start);
   const int32_t* __restrict__ sk = sample_k + in0;
   const S* __restrict__ ps0 = (kAng && kW == 0) ? psi + in0 : nullptr;
-  const cpx<S>* __restrict__ w0 = (kAng && kW == 1) ? wts + in0 : nullptr;
+  const S* __restrict__ w0 = (kAng && kW == 1) ? wts + in0 : nullptr;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));  // per-tile offsets: not hoisted out of the segment loop
 
@@ -763,7 +756,7 @@ template <class S, class C, int kW, int NC>
 __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_carry(
     const FftTile* __restrict__ tiles, const CarrySeg* __restrict__ segs, int64_t n_segs, int32_t lambda,
     const cpx<C>* __restrict__ ab, const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k,
-    const S* __restrict__ psi, const cpx<S>* __restrict__ wts, const double* __restrict__ x, double* __restrict__ q,
+    const S* __restrict__ psi, const S* __restrict__ wts, const double* __restrict__ x, double* __restrict__ q,
     RhsBatch rb, int32_t variant) {
   int64_t seg;
   int rhs;
@@ -800,7 +793,7 @@ template <class S, class C, int kIn, int kOut, int kW, int NC>
 __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(
     const FftTile* __restrict__ tiles, int64_t n_tiles, int32_t lambda, const cpx<C>* __restrict__ ab,
     const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
-    const cpx<S>* __restrict__ wts, const double* __restrict__ x, const S* __restrict__ tod_in,
+    const S* __restrict__ wts, const double* __restrict__ x, const S* __restrict__ tod_in,
     S* __restrict__ tod_out, double* __restrict__ q, RhsBatch rb, int32_t variant) {
   int64_t tile;
   int rhs;
@@ -986,7 +979,7 @@ template <class S, class C, int kW, int NC>
 __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t lambda, const cpx<C>* __restrict__ abf,
                                                    const cpx<C>* __restrict__ tw,
                                                    const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
-                                                   const cpx<S>* __restrict__ wts, const double* __restrict__ x,
+                                                   const S* __restrict__ wts, const double* __restrict__ x,
                                                    double* __restrict__ q) {
   using P = HPlan<C>;
   using A = Angle<C, S, kW>;
@@ -1007,7 +1000,7 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   const int32_t clen = (int32_t)(tl.chunk_end - tl.chunk_start);
   const int32_t* __restrict__ sk = sample_k + in0;
   const S* __restrict__ ps0 = (kAng && kW == 0) ? psi + in0 : nullptr;
-  const cpx<S>* __restrict__ w0 = (kAng && kW == 1) ? wts + in0 : nullptr;
+  const S* __restrict__ w0 = (kAng && kW == 1) ? wts + in0 : nullptr;
   const int tid = threadIdx.x;
 
   // ---- gather P x over the whole window, element e of this thread packing
@@ -1082,7 +1075,7 @@ template <class S, class C, int kW, int NC>
 __global__ __launch_bounds__(HPlan<C>::T, HPlan<C>::kWavesPerEU) void k_toeplitz_half(
     const FftTile* __restrict__ tiles, int64_t n_tiles, int32_t lambda, const cpx<C>* __restrict__ ab,
     const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
-    const cpx<S>* __restrict__ wts, const double* __restrict__ x, double* __restrict__ q, RhsBatch rb,
+    const S* __restrict__ wts, const double* __restrict__ x, double* __restrict__ q, RhsBatch rb,
     int32_t variant) {
   int64_t tile;
   int rhs;
@@ -1136,7 +1129,7 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_ba
   toeplitz_tile<S, C, 1, 1, kW, NC>(tl, o.lambda,
                                     static_cast<const cpx<C>*>(o.ab) + (int64_t)tl.filter * Plan<C>::N,
                                     static_cast<const cpx<C>*>(o.tw), o.sample_k, static_cast<const S*>(o.psi),
-                                    static_cast<const cpx<S>*>(o.wts), o.x, nullptr, nullptr, o.q, o.variant);
+                                    static_cast<const S*>(o.wts), o.x, nullptr, nullptr, o.q, o.variant);
 }
 
 template <class S, class C, int kIn, int kOut, int kW, int NC>
@@ -1153,7 +1146,7 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
       hipLaunchKernelGGL((k_toeplitz_carry<S, C, kW, NC>), dim3(g), dim3(Plan<C>::T), 0, s, nz->ctiles[a],
                          nz->csegs[a], nz->n_csegs[a], nz->lambda, (const cpx<C>*)nz->ab[a],
                          (const cpx<C>*)nz->tw[a], pt->sample_k, (const S*)pt->psi,
-                         (const cpx<S>*)pt->weights, x, q, rb, variant);
+                         (const S*)pt->weights, x, q, rb, variant);
       MM_HIP(hipGetLastError());
       return MM_OK;
     }
@@ -1163,7 +1156,7 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
     if (variant & kOpHalfLds) {
       hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC>), dim3(grid), dim3(HPlan<C>::T), 0, s, nz->tiles[a],
                          nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
-                         pt->sample_k, (const S*)pt->psi, (const cpx<S>*)pt->weights, x, q, rb, variant);
+                         pt->sample_k, (const S*)pt->psi, (const S*)pt->weights, x, q, rb, variant);
       MM_HIP(hipGetLastError());
       return MM_OK;
     }
@@ -1171,7 +1164,7 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
   hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW, NC>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
                      nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
                      pt ? pt->sample_k : nullptr, pt ? (const S*)pt->psi : nullptr,
-                     pt ? (const cpx<S>*)pt->weights : nullptr, x, (const S*)tod_in, (S*)tod_out, q, rb, variant);
+                     pt ? (const S*)pt->weights : nullptr, x, (const S*)tod_in, (S*)tod_out, q, rb, variant);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }

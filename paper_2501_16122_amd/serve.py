@@ -65,7 +65,7 @@ def footprint_bytes(w: synth.Workload, opts: b.SolveOpts, weights: bool) -> int:
     n = w.n_samples
     total = n * (4 + esz + esz)                      # pix, psi, d
     if weights:
-        total += 2 * n * esz
+        total += n * esz                              # stored tangent per sample
     sz = b._c.c_size_t()
     b._check(lib.mm_pointing_workspace_size(n, w.n_det, w.n_pix, b.MM_F32 if w.precision == "f32" else b.MM_F64,
                                             b._c.byref(sz)))

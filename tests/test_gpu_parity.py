@@ -282,9 +282,12 @@ def test_fused_toeplitz_with_stored_weights(ragged):
     q0 = b.apply_A(P.pt, P.nz, tx).cpu().numpy()
     P.pt.attach_weights()
     try:
-        w = P.pt.weights.cpu().numpy().reshape(-1, 2)
-        assert np.max(np.abs(w[:, 0] - P.opt.cos2)) < 1e-15
-        assert np.max(np.abs(w[:, 1] - P.opt.sin2)) < 1e-15
+        # the stored weight is u = tan psi; the row's (cos 2psi, sin 2psi)
+        # is ((1 - u^2), 2u) / (1 + u^2)
+        u = P.pt.weights.cpu().numpy()
+        assert u.shape == (P.w.n_samples,)
+        assert np.max(np.abs((1 - u * u) / (1 + u * u) - P.opt.cos2)) < 2e-15
+        assert np.max(np.abs(2 * u / (1 + u * u) - P.opt.sin2)) < 2e-15
         q1 = b.apply_A(P.pt, P.nz, tx).cpu().numpy()
         bb = b.rhs(P.pt, P.nz, P.t_d).cpu().numpy()
     finally:
