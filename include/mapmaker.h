@@ -317,6 +317,21 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
              const mm_solve_opts* opts, mm_solve_info* info, double* history_host, int32_t history_len,
              void* workspace, size_t ws_bytes, void* stream);
 
+/* mm_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, with the solver's vectors, partial sums and state in a 64 MiB
+ * device array inside the library instead of a caller workspace.  The call
+ * allocates no device memory, pinned memory, event or graph (no history
+ * output; opts.autotune, opts.timing and opts.graph must be 0, else
+ * MM_EINVAL: pass opts.op_variant).  The array holds the state of one
+ * right-hand side of at most about 0.9 million unknowns (nc * n_kept, e.g.
+ * a 512^2 I, Q, U map, FP64 or mixed): a larger problem fails with
+ * MM_ENOSPC before any work.  Each GPU the library runs on holds its own
+ * copy of the array until the process ends; every call on one GPU shares it
+ * (a call clears what it needs), so calls that overlap on one GPU race.
+ * Blocking; returns like mm_solve. */
+int mm_solve_noalloc(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, double* x_out,
+                     const mm_solve_opts* opts, mm_solve_info* info, void* stream);
 
 /* ------------------------------------------------------------------------
  * Resumable solves: one or several right-hand sides sharing a pointing and a

@@ -80,6 +80,7 @@ SIGNATURES = {
     "mm_solve_workspace_size": (_c.c_int, [_vp, _vp, _c.POINTER(SolveOpts), _psz]),
     "mm_solve": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.POINTER(SolveOpts), _c.POINTER(SolveInfo), _pf64, _i32,
                             _vp, _sz, _vp]),
+    "mm_solve_noalloc": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.POINTER(SolveOpts), _c.POINTER(SolveInfo), _vp]),
     "mm_solver_workspace_bound": (_c.c_int, [_i32, _i32, _i32, _c.POINTER(SolveOpts), _psz]),
     "mm_solver_workspace_size": (_c.c_int, [_vp, _vp, _i32, _c.POINTER(SolveOpts), _psz]),
     "mm_solver_create": (_c.c_int, [_vp, _vp, _i32, _vp, _c.POINTER(SolveOpts), _vp, _sz, _vp, _c.POINTER(_vp)]),

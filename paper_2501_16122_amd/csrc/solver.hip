@@ -11,7 +11,9 @@
 // loop can keep many solvers in flight on their own streams.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "mm_internal.h"
@@ -799,3 +801,184 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Allocation-free blocking solve (mm_solve_noalloc).  The solver's vectors,
+// partial sums, states and histories live in `scratch`, a file-scope device
+// array, instead of a caller workspace; the host side keeps its state copies
+// on the stack and waits with stream synchronisations, so the call creates
+// no device memory, pinned memory, event or graph.  Each GPU the library
+// runs on holds its own copy of the array until the process ends; every
+// call on that GPU shares it, so calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kNoAllocDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocDevices] = {};
+
+// The device address of this device's copy of `scratch` (the host-side name
+// is only a stand-in): looked up once per device, with that device current.
+int scratch_ptr(void** out) {
+  int dev = 0;
+  MM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices) return fail(MM_EINVAL, "device index beyond the allocation-free table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (p == nullptr) return fail(MM_EHIP, "no device address for the allocation-free scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mm_solve_noalloc(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, double* x_out,
+                     const mm_solve_opts* opts, mm_solve_info* info, void* stream) {
+  if (int rc = check_pointing(pt)) return rc;
+  if (int rc = check_noise_vs_pointing(nz, pt)) return rc;
+  mm_solve_opts o;
+  mm_solve_opts_default(&o);
+  if (opts) o = *opts;
+  if (int rc = check_opts(o)) return rc;
+  if (o.autotune || o.timing || o.graph)
+    return fail(MM_EINVAL, "mm_solve_noalloc: autotune, timing and graph need events or graphs; pass op_variant");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (pt->n_kept == 0) {
+    if (map_out)
+      if (int rc = launch_fill(map_out, (int64_t)pt->ncomp * pt->n_pix, 0.0, s)) return rc;
+    MM_HIP(hipStreamSynchronize(s));
+    if (info) {
+      *info = mm_solve_info{};
+      info->converged = 1;
+    }
+    return MM_OK;
+  }
+  if (pt->n_samples && !tod) return fail(MM_EINVAL, "null timeline");
+  Layout L;
+  {
+    Carver cv(nullptr, 0);
+    const size_t need = carve(cv, pt->n_kept, pt->ncomp, 1, o, &L);
+    if (need > kNoAllocBytes)
+      return fail(MM_ENOSPC, "mm_solve_noalloc: the problem needs " + std::to_string(need) +
+                                 " bytes of solver state, more than the " + std::to_string(kNoAllocBytes) +
+                                 " bytes of its scratch array (use mm_solve with a workspace)");
+  }
+  void* ws = nullptr;
+  if (int rc = scratch_ptr(&ws)) return rc;
+  Carver cv(ws, kNoAllocBytes);
+  carve(cv, pt->n_kept, pt->ncomp, 1, o, &L);
+  const bool mixed = o.mixed != 0;
+  const int64_t n3 = (int64_t)pt->ncomp * pt->n_kept;
+  // the states left by an earlier call start from zero (reduction tickets)
+  if (int rc = launch_fill(reinterpret_cast<double*>(L.A.st), sizeof(PcgState) / sizeof(double), 0.0, s)) return rc;
+  if (int rc = launch_fill(reinterpret_cast<double*>(L.O.os), sizeof(OuterState) / sizeof(double), 0.0, s))
+    return rc;
+  double* rhs_dst = mixed ? L.b64 : L.b;
+  if (int rc = rhs_impl(pt, nz, tod, rhs_dst, MM_F64, s)) return rc;
+  const bool bj = mixed && o.x0 == nullptr && o.bj_start != 0;
+  const bool from_x0 = o.x0 != nullptr || bj;
+  RhsBatch one;
+  one.nrhs = 1;
+  one.vstride = n3;
+  if (from_x0) {
+    double* xs = mixed ? L.O.xt : L.A.x;
+    if (bj) {
+      if (int rc = launch_apply_M(pt, rhs_dst, xs, s)) return rc;
+    } else {
+      MM_HIP(hipMemcpyAsync(xs, o.x0, sizeof(double) * n3, hipMemcpyDeviceToDevice, s));
+    }
+    if (int rc = launch_fill(L.A.q, n3, 0.0, s)) return rc;
+    if (int rc = apply_A_impl(pt, nz, xs, L.A.q, MM_F64, one, s, o.op_variant)) return rc;
+    if (int rc = launch_diff_norm(L.A, 1, rhs_dst, L.A.q, s)) return rc;
+  }
+  if (mixed) {
+    L.A.b = L.O.rt;
+    if (int rc = launch_outer_init(L.O, L.A, 1, s, from_x0)) return rc;
+    if (int rc = launch_pcg_init(pt, L.A, 1, o.inner_tol, o.max_iter, 0, L.O.os, s)) return rc;
+  } else {
+    if (int rc = launch_pcg_init(pt, L.A, 1, o.tol, o.max_iter, o.fixed_iter, nullptr, s, from_x0)) return rc;
+  }
+  // iterate in chunks of check_every, reading the state back after each
+  const int64_t per_inner = (int64_t)(o.fixed_iter > 0 ? o.fixed_iter : o.max_iter) / o.check_every + 3;
+  const int64_t max_steps = per_inner * (mixed ? o.max_outer : 1) + 4;
+  PcgState st{};
+  OuterState os{};
+  bool outer_pending = false, done = false;
+  const int arith = mixed ? MM_F32 : MM_F64;
+  for (int64_t i = 0; i < max_steps && !done; ++i) {
+    if (mixed && outer_pending) {
+      RhsBatch rb = one;
+      rb.done = &L.O.os[0].skip;
+      rb.done_stride = kOuterStride;
+      if (int rc = launch_outer_add(L.O, L.A, 1, s)) return rc;
+      if (int rc = apply_A_impl(pt, nz, L.O.xt, L.A.q, MM_F64, rb, s, o.op_variant)) return rc;
+      if (int rc = launch_outer_end(L.O, L.A, 1, o.tol, o.max_outer, s)) return rc;
+      if (int rc = launch_pcg_init(pt, L.A, 1, o.inner_tol, o.max_iter, 0, L.O.os, s)) return rc;
+      outer_pending = false;
+    }
+    RhsBatch rb = one;
+    rb.done = &L.A.st[0].done;
+    rb.done_stride = kPcgDoneStride;
+    for (int32_t k = 0; k < o.check_every; ++k) {
+      if (int rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s, o.op_variant)) return rc;
+      if (int rc = launch_pcg_iteration_tail(pt, L.A, 1, s)) return rc;
+    }
+    MM_HIP(hipStreamSynchronize(s));
+    MM_HIP(hipMemcpy(&st, L.A.st, sizeof(PcgState), hipMemcpyDeviceToHost));
+    if (mixed) {
+      MM_HIP(hipMemcpy(&os, L.O.os, sizeof(OuterState), hipMemcpyDeviceToHost));
+      if (st.done && !os.done) outer_pending = true;
+      done = os.done != 0;
+    } else {
+      done = st.done != 0;
+    }
+  }
+  double true_rel = 0.0;
+  const double* xf = mixed ? L.O.xt : L.A.x;
+  if (!mixed) {
+    // ||b - A x|| / ||b|| in FP64 arithmetic
+    if (int rc = launch_fill(L.A.q, n3, 0.0, s)) return rc;
+    if (int rc = apply_A_impl(pt, nz, L.A.x, L.A.q, MM_F64, one, s, o.op_variant)) return rc;
+    if (int rc = launch_diff_norm(L.A, 1, L.b, L.A.q, s)) return rc;
+    MM_HIP(hipStreamSynchronize(s));
+    PcgState fin{};
+    MM_HIP(hipMemcpy(&fin, L.A.st, sizeof(PcgState), hipMemcpyDeviceToHost));
+    true_rel = fin.scratch1 > 0 ? std::sqrt(fin.scratch0 / fin.scratch1) : 0.0;
+  }
+  if (map_out)
+    if (int rc = launch_expand(pt, xf, map_out, s)) return rc;
+  if (x_out) MM_HIP(hipMemcpyAsync(x_out, xf, sizeof(double) * n3, hipMemcpyDeviceToDevice, s));
+  MM_HIP(hipStreamSynchronize(s));
+  mm_solve_info inf{};
+  if (mixed) {
+    inf.iters = os.inner_total;
+    inf.outer_iters = os.iters;
+    inf.converged = os.converged;
+    inf.breakdown = os.breakdown;
+    inf.rel_resid = os.rel;
+    inf.true_rel_resid = os.rel;
+  } else {
+    inf.iters = st.iter;
+    inf.outer_iters = 1;
+    inf.converged = st.converged;
+    inf.breakdown = st.breakdown;
+    inf.rel_resid = st.rel;
+    inf.true_rel_resid = true_rel;
+  }
+  inf.op_variant = o.op_variant;
+  if (info) *info = inf;
+  if (inf.breakdown) return fail(MM_EBREAKDOWN, "PCG breakdown (p^T A p <= 0 or non-finite value)");
+  return (inf.converged || (o.fixed_iter > 0 && !mixed)) ? MM_OK : MM_NOTCONVERGED;
+}
+
+}  // extern "C"
