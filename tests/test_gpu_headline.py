@@ -127,6 +127,11 @@ def test_headline_fp32_refined(shard32):
         err0 = oracle.rel_l2_per_stokes(one["x"].cpu().numpy(), x_ref)
         print(f"FP32 map before refinement (start {'M b' if bj else '0'}, {one['info']['iters']} inner "
               f"iterations), rel L2 (I, Q, U): {err0}", flush=True)
+        # from the block-Jacobi map (the default), the FP32 inner solve alone
+        # is within 1e-6 per Stokes of the FP64 map (measured ~7.5e-7 for Q,
+        # U); from 0, FP32 rounding of the I-dominated timeline leaks ~1e-5
+        # into Q and U
+        assert np.all(err0 < (1e-6 if bj else 1e-4)), (bj, err0)
     # refined to an FP64 residual of 1e-14
     out = b.Solver(s.pt, s.nz, tol=1e-14, mixed=1, max_outer=30).solve(s.t_d)
     i = out["info"]
