@@ -714,9 +714,10 @@ def main():
     streamed = (STREAMED_BYTES_PER_SAMPLE_TOEPLITZ if w.toeplitz else ALG_BYTES_PER_SAMPLE_F64) * w.n_samples
     roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(),
-            "kernel": ((f"k_toeplitz_carry<double,double,weights>" if infos[-1]["op_variant"] & 4
-                        else "k_toeplitz<double,double,gather,scatter,weights>") + " (fused P^T N^-1 P)")
-            if w.toeplitz else "k_fused_white<double,double>",
+            "kernel": ((("k_toeplitz_half<double,double,weights>" if infos[-1]["op_variant"] & 8 else
+                          "k_toeplitz_carry<double,double,weights>" if infos[-1]["op_variant"] & 4
+                          else "k_toeplitz<double,double,gather,scatter,weights>") + " (fused P^T N^-1 P)")
+                       if w.toeplitz else "k_fused_white<double,double>"),
             "kernel_ms_avg": round(kernel_ms, 4), "launches": op_n,
             "op_variant": infos[-1]["op_variant"],
             "algorithmic_bytes_per_sample": ALG_BYTES_PER_SAMPLE_F64,

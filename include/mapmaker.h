@@ -267,9 +267,9 @@ typedef struct {
                            runs that carry the overlapping half-window from tile to tile
                            (needs stored pointing weights; never stages), bit 3 = plain
                            tiles with two workgroups per CU, whose FFT exchanges pass real
-                           and imaginary parts through half the LDS in turn (FP64
-                           arithmetic; bits 1 and 2 do not apply), so the memory phases of
-                           one tile overlap the FFT of another; 0 <= op_variant < 16       */
+                           and imaginary parts through half the LDS in turn (bits 1 and 2
+                           do not apply), so the memory phases of one tile overlap the
+                           FFT of another; 0 <= op_variant < 16                             */
   int32_t graph;        /* 1: the first mm_solver_step of a given length k > 0 records its k
                            iterations (operator and PCG launches) into a HIP graph and
                            every later step of that length replays it with one graph

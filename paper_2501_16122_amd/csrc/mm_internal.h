@@ -229,9 +229,8 @@ int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const vo
 // stored pointing weights, else the plain tiles are used).
 // Bit kOpHalfLds runs plain tiles with two workgroups per CU: the FFT
 // exchanges go through half the LDS (real parts, then imaginary parts), so
-// the memory phases of one tile overlap the FFT of another (FP64 arithmetic;
-// tile order as bit kOpLinearOrder says; bits kOpNoStaging and kOpCarry do
-// not apply).
+// the memory phases of one tile overlap the FFT of another (tile order as
+// bit kOpLinearOrder says; bits kOpNoStaging and kOpCarry do not apply).
 constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpCarry = 4, kOpHalfLds = 8, kOpVariants = 16;
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
                           double* q, int arith, const RhsBatch& rb, hipStream_t s, int32_t variant = 0);

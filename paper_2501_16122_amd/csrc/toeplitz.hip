@@ -968,6 +968,62 @@ __device__ __forceinline__ void hmiddle(double* buf, cpx<double>* v, const cpx<d
   }
 }
 
+// The FP32 plan's spectral step through the half buffer (N = 16384, radix
+// 32 32 16): v holds the outputs of the last forward pass (radix 16, span
+// N/16, natural order) on entry and the inputs of the first inverse pass
+// (radix 16) on return.  Thread t takes the bin pairs (k, N - k), k = t + T r,
+// one component per LDS round, forms X_k = alpha_k Z_k + i beta_k
+// conj(Z_{N-k}) and X_{N-k} likewise in registers, and scatters them back.
+// Bins 0 and N/2 pair with themselves: the slot k = 0 uses Z_0 as its own
+// mirror, and its second half takes the bin N/2 (also its own mirror).
+template <class C>
+__device__ __forceinline__ cpx<C> spec_t(cpx<C> ab, cpx<C> z, cpx<C> zr) {
+  return {ab.x * z.x + ab.y * zr.y, ab.x * z.y + ab.y * zr.x};
+}
+
+template <int N, int T>
+__device__ __forceinline__ void hmiddle32(float* buf, cpx<float>* v, const cpx<float>* __restrict__ abf) {
+  constexpr int H = N / 2, PPT = H / T;
+  static_assert(2 * PPT == N / T, "bin pairs must fill the registers");
+  settle<float, N / T>(v);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    __syncthreads();
+    if (c == 0) hstore<float, N, T, 16, N / 16, 0>(buf, v);
+    else hstore<float, N, T, 16, N / 16, 1>(buf, v);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      const int k = fft_tid() + T * r, m = k == 0 ? H : N - k;
+      (c == 0 ? v[2 * r].x : v[2 * r].y) = buf[hpad(k)];
+      (c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y) = buf[hpad(m)];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int k = fft_tid() + T * r;
+    const bool k0 = k == 0;
+    const int m = k0 ? H : N - k;
+    const cpx<float> zk = v[2 * r], zm = v[2 * r + 1];
+    v[2 * r] = spec_t(abf[k], zk, k0 ? zk : zm);
+    v[2 * r + 1] = spec_t(abf[m], zm, k0 ? zm : zk);
+  }
+  settle<float, N / T>(v);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      const int k = fft_tid() + T * r, m = k == 0 ? H : N - k;
+      buf[hpad(k)] = c == 0 ? v[2 * r].x : v[2 * r].y;
+      buf[hpad(m)] = c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y;
+    }
+    __syncthreads();
+    if (c == 0) hload<float, N, T, 16, 0>(buf, v);
+    else hload<float, N, T, 16, 1>(buf, v);
+  }
+}
+
 // Batches of the two-per-CU kernel: smaller than the one-per-CU plan's, so
 // that a batch of loads and the 16 register values fit 128 VGPRs.
 template <class C>
@@ -976,6 +1032,15 @@ struct HPlan {
   static constexpr int kGatherBatch = 2;   // entries (sample pairs) per load batch
   static constexpr int kScatterBatch = 2;
   static constexpr int kWavesPerEU = 4;    // two 512-thread workgroups per CU
+};
+// FP32: 32 values per thread, indices loaded again in the gather batches, so
+// longer batches keep as many loads in flight
+template <>
+struct HPlan<float> {
+  static constexpr int N = Plan<float>::N, T = Plan<float>::T;
+  static constexpr int kGatherBatch = 4;
+  static constexpr int kScatterBatch = 4;
+  static constexpr int kWavesPerEU = 4;
 };
 
 template <class S, class C, int kW, int NC>
@@ -990,7 +1055,12 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   constexpr bool kAng = Stokes<NC>::kAngle;
   constexpr int kSlots = (hlds_elems<N>() * (int)sizeof(C) / 8) / NC / 64 * 64;
   static_assert(E % G == 0, "gather batches must tile the elements");
-  static_assert(E == 16, "the half-buffer FFT is written for 16 values per thread");
+  static_assert((E == 16 && std::is_same<C, double>::value) || (E == 32 && std::is_same<C, float>::value),
+                "the half-buffer plans: FP64 16 values per thread, FP32 32");
+  // FP64 keeps every window index in registers from the first round of
+  // loads to the gather; FP32 (twice the samples per thread) has no room and
+  // loads them again in the gather batches
+  constexpr bool kKeepIdx = E == 16;
   __shared__ C buf[hlds_elems<N>()];
   __shared__ int32_t s_red[4 * (T / 64)];
 
@@ -1006,28 +1076,36 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   const S* __restrict__ w0 = (kAng && kW == 1) ? wts + in0 : nullptr;
   const int tid = threadIdx.x;
 
-  // ---- (1) compact indices of every window sample, in one round of loads
-  // (element e of this thread packs window samples 2n, 2n+1, n = tid + T e),
-  // and their ranges: the whole window (map staging) and the valid outputs
-  int32_t kk[2 * E];
-#pragma unroll
-  for (int i = 0; i < 2 * E; ++i) {
-    const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
-    int sp;
-    const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
-    const int32_t kr = sk[ok ? sp : ilo];  // ilo: inside the chunk, always in bounds
-    kk[i] = ok ? kr : -1;
-  }
+  // ---- (1) compact indices of every window sample, in rounds of 32 loads
+  // per thread (element e of this thread packs window samples 2n, 2n+1,
+  // n = tid + T e), and their ranges: the whole window (map staging) and
+  // the valid outputs
+  constexpr int kPre = kKeepIdx ? 2 * E : 1;
+  int32_t kk[kPre];
   int32_t amin = INT32_MAX, amax = -1, kmin = INT32_MAX, kmax = -1;
 #pragma unroll
-  for (int i = 0; i < 2 * E; ++i) {
-    const int pos = 2 * (tid + T * (i / 2)) + (i & 1);
-    if (kk[i] >= 0) {
-      amin = kk[i] < amin ? kk[i] : amin;
-      amax = kk[i] > amax ? kk[i] : amax;
-      if (pos >= vlo && pos < vhi) {
-        kmin = kk[i] < kmin ? kk[i] : kmin;
-        kmax = kk[i] > kmax ? kk[i] : kmax;
+  for (int h = 0; h < 2 * E; h += 32) {
+    int32_t kr32[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const int pos = 2 * (tid + T * ((h + i) / 2)) + (i & 1);
+      int sp;
+      const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
+      const int32_t kr = sk[ok ? sp : ilo];  // ilo: inside the chunk, always in bounds
+      kr32[i] = ok ? kr : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const int pos = 2 * (tid + T * ((h + i) / 2)) + (i & 1);
+      const int32_t k = kr32[i];
+      if constexpr (kKeepIdx) kk[h + i] = k;
+      if (k >= 0) {
+        amin = k < amin ? k : amin;
+        amax = k > amax ? k : amax;
+        if (pos >= vlo && pos < vhi) {
+          kmin = k < kmin ? k : kmin;
+          kmax = k > kmax ? k : kmax;
+        }
       }
     }
   }
@@ -1091,16 +1169,23 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
       __builtin_amdgcn_sched_barrier(0);
       if (e0 > 0) asm volatile("" : "+v"(tdep) : "v"(v[e0 - 1].y));
       typename A::type ps[2 * G];
+      int32_t kb[2 * G];
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
         const int pos = 2 * (tdep + T * (e0 + i / 2)) + (i & 1);
         int sp;
         const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
         ps[i] = kAng ? A::load(ps0, w0, ok ? sp : ilo) : A::zero();
+        if constexpr (kKeepIdx) {
+          kb[i] = kk[2 * e0 + i];
+        } else {
+          const int32_t kr = sk[ok ? sp : ilo];
+          kb[i] = ok ? kr : -1;
+        }
       }
 #pragma unroll
       for (int i = 0; i < 2 * G; ++i) {
-        const int32_t k = kk[2 * e0 + i];
+        const int32_t k = kb[i];
         const int32_t ka = k >= 0 ? k : kfill;
         C c = C(0), s = C(0);
         if constexpr (kAng) A::eval(ps[i], &c, &s);
@@ -1118,9 +1203,15 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   __syncthreads();  // the FFT reuses the staging area; s_red[0, 2W) holds the valid range
 
   // ---- forward FFT, spectral step, inverse FFT (outputs in registers)
-  hpasses<C, N, T, true, 1, 16, 16, 16>(buf, v, tw);
-  hmiddle<N, T>(buf, v, abf, tw);
-  hpasses<C, N, T, false, 2, 16, 16, 16>(buf, v, tw);
+  if constexpr (std::is_same<C, double>::value) {
+    hpasses<C, N, T, true, 1, 16, 16, 16>(buf, v, tw);
+    hmiddle<N, T>(buf, v, abf, tw);
+    hpasses<C, N, T, false, 2, 16, 16, 16>(buf, v, tw);
+  } else {
+    hpasses<C, N, T, true, 1, 32, 32, 16>(buf, v, tw);
+    hmiddle32<N, T>(buf, v, abf);
+    hpasses<C, N, T, false, 1, 16, 32, 32>(buf, v, tw);
+  }
 
   // ---- P^T through LDS bins in the half buffer
   __syncthreads();  // every thread is done reading buf
@@ -1219,7 +1310,7 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
     }
   }
   const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8) * rb.nrhs;
-  if constexpr (kIn == 1 && kOut == 1 && std::is_same<C, double>::value) {
+  if constexpr (kIn == 1 && kOut == 1) {
     if (variant & kOpHalfLds) {
       hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC>), dim3(grid), dim3(HPlan<C>::T), 0, s, nz->tiles[a],
                          nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],

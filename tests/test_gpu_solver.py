@@ -229,7 +229,7 @@ def test_operator_variants_agree_and_autotune():
     pt32.attach_weights()
     out = b.Solver(pt32, nz32, tol=1e-12, mixed=1, max_outer=20, autotune=1).solve(
         torch.from_numpy(ds32[0]).to(DEV))
-    assert out["info"]["converged"] == 1 and 0 <= out["info"]["op_variant"] < 8  # no two-per-CU FP32 form
+    assert out["info"]["converged"] == 1 and 0 <= out["info"]["op_variant"] < 16
     _, _, x_ref = oracle.solve(opt32, noise32, ds32[0].astype(np.float64), tol=1e-13)
     err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref)
     assert np.all(err < 1e-9), err
