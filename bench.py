@@ -42,7 +42,7 @@ STREAMED_BYTES_PER_SAMPLE_TOEPLITZ = 12.0
 KERNEL_SOURCES = ["paper_2501_16122_amd/csrc/toeplitz.hip", "paper_2501_16122_amd/csrc/fft_lds.h",
                   "paper_2501_16122_amd/csrc/stokes.h",
                   "paper_2501_16122_amd/csrc/sincos2.h"]
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_toeplitz_fused_f64_gls512.counters.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_toeplitz_half_f64_gls512.counters.json")
 
 
 def log(msg):
@@ -72,15 +72,15 @@ def fft_flops_per_launch(w, n_fft=8192):
     return tiles * per_tile + 6 * w.n_samples
 
 
-def stored_traffic():
+def stored_traffic(kernel):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+    was taken on the current kernel sources and for this kernel."""
     try:
         with open(COUNTERS_FILE) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
-    if c.get("kernel_source_hash") != kernel_source_hash():
+    if c.get("kernel_source_hash") != kernel_source_hash() or c.get("kernel") != kernel:
         return None
     return c.get("hbm_bytes_per_launch")
 
@@ -561,7 +561,7 @@ def templates_section(torch, b, w, dev, t_pix, t_psi, t_d, t_m, noise, offs, wde
     out["note"] = ("1/f data; W = white weights with polynomial baselines (degree < 3) marginalised on each "
                    "2^16-sample interval instead of the band-Toeplitz N^-1; FP64 to 1e-10 with stored pointing "
                    "weights, pointing build included; map errors relative L2 per Stokes over kept pixels (I mean "
-                   "removed); the operator reads the index and the (cos, sin) pair in each of its two passes")
+                   "removed); the operator reads the index and the stored half-angle tangent in each of its two passes")
     return out
 
 
@@ -571,7 +571,9 @@ def stokes_section(torch, b, w, dev, t_pix, t_psi, t_m, noise, offs, wdet, nz, i
     components of the sky plus the same noise, FP64 to 1e-10."""
     out = {}
     t_noise = torch.from_numpy(noise).to(dev)
-    for form, cols, bps in (("QU", [1, 2], 20.0), ("I", [0], 4.0)):
+    # bytes per sample each form's operator streams: the index and the FP64
+    # tangent (Q, U), the index alone (I)
+    for form, cols, bps in (("QU", [1, 2], 12.0), ("I", [0], 4.0)):
         psi_f = None if form == "I" else t_psi
         pt0 = b.Pointing(t_pix, psi_f, offs, wdet, w.n_pix, stokes=form, tod_dtype=torch.float64)
         kept = pt0.export()["kept"].long()
@@ -681,7 +683,7 @@ def main():
     def step(psi_t, d_t, mixed, noise=None, keep_map=False):
         pt = b.Pointing(t_pix, psi_t, offs, wdet, w.n_pix, w.min_hits, w.cond_max)
         if w.toeplitz:
-            pt.attach_weights()  # precomputed (cos 2psi, sin 2psi), part of the build
+            pt.attach_weights()  # stored half-angle tangents, part of the build
         s = b.Solver(pt, noise if noise is not None else nz, tol=1e-10, mixed=mixed, timing=1, check_every=8,
                      autotune=1)
         out = s.solve(d_t)
@@ -710,10 +712,14 @@ def main():
     alg_bytes = ALG_BYTES_PER_SAMPLE_F64 * w.n_samples
     achieved_gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
     # what the kernel actually streams per sample: the index and the stored
-    # FP64 (cos 2psi, sin 2psi) pair (band-Toeplitz), or the index and psi (white)
+    # FP64 half-angle tangent (band-Toeplitz), or the index and psi (white)
     streamed = (STREAMED_BYTES_PER_SAMPLE_TOEPLITZ if w.toeplitz else ALG_BYTES_PER_SAMPLE_F64) * w.n_samples
+    v_last = infos[-1]["op_variant"]
+    prof_name = ("k_toeplitz_half<double, double, 1, 3>" if v_last & 8 else
+                 "k_toeplitz_carry<double, double, 1, 3>" if v_last & 4 else None)
     roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": stored_traffic(),
+            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic(prof_name) if w.toeplitz and prof_name else None,
             "kernel": ((("k_toeplitz_half<double,double,weights>" if infos[-1]["op_variant"] & 8 else
                           "k_toeplitz_carry<double,double,weights>" if infos[-1]["op_variant"] & 4
                           else "k_toeplitz<double,double,gather,scatter,weights>") + " (fused P^T N^-1 P)")
