@@ -228,7 +228,7 @@ int mm_apply_Ninv(mm_noise_t nz, mm_pointing_t pt, const void* tod_in, void* tod
  * on chip (registers for white noise, LDS for band-Toeplitz). */
 int mm_apply_A(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, void* stream);
 /* mm_apply_A with an explicit band-Toeplitz operator variant (the bits of
- * mm_solve_opts.op_variant, 0 <= variant < 16; ignored for white noise).
+ * mm_solve_opts.op_variant, 0 <= variant < 32; ignored for white noise).
  * Every variant computes the same sums up to the order of floating-point
  * atomics; this call lets a caller check or time one. */
 int mm_apply_A_variant(mm_pointing_t pt, mm_noise_t nz, const double* x, double* q, int32_t arith, int32_t variant,
@@ -269,7 +269,10 @@ typedef struct {
                            tiles with two workgroups per CU, whose FFT exchanges pass real
                            and imaginary parts through half the LDS in turn (bits 1 and 2
                            do not apply), so the memory phases of one tile overlap the
-                           FFT of another; 0 <= op_variant < 16                             */
+                           FFT of another, bit 4 = in FP64 arithmetic, plain tiles of the
+                           16384-point plan (the FP32 plan's tile length), one 1024-thread
+                           workgroup per CU with half-LDS exchanges (bits 1 to 3 do not
+                           apply; ignored in FP32 arithmetic); 0 <= op_variant < 32        */
   int32_t graph;        /* 1: the first mm_solver_step of a given length k > 0 records its k
                            iterations (operator and PCG launches) into a HIP graph and
                            every later step of that length replays it with one graph

@@ -163,6 +163,9 @@ struct mm_noise_s {
   int64_t n_csegs[2] = {0, 0};
   void* ab[2] = {nullptr, nullptr};  // [n_filt][N] pairs (alpha_k, beta_k)
   void* tw[2] = {nullptr, nullptr};  // [N] exp(-2 pi i k / N)
+  // FP64 tables of the 16384-point plan (its tiles are the FP32 plan's)
+  void* ab64l = nullptr;
+  void* tw64l = nullptr;
   // operator variants picked by the autotuner, per problem shape
   struct Tuned {
     int64_t n_samples;
@@ -231,7 +234,13 @@ int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const vo
 // exchanges go through half the LDS (real parts, then imaginary parts), so
 // the memory phases of one tile overlap the FFT of another (tile order as
 // bit kOpLinearOrder says; bits kOpNoStaging and kOpCarry do not apply).
-constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpCarry = 4, kOpHalfLds = 8, kOpVariants = 16;
+// Bit kOpLongPlan (FP64 arithmetic only; ignored in FP32) runs plain tiles
+// of the 16384-point plan, the FP32 plan's tile length (75% of each window
+// valid at lambda = 4096 instead of 50%), one 1024-thread workgroup per CU
+// with the exchanges through a half buffer (tile order as bit
+// kOpLinearOrder says; the other bits do not apply).
+constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpCarry = 4, kOpHalfLds = 8, kOpLongPlan = 16,
+                  kOpVariants = 32;
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,
                           double* q, int arith, const RhsBatch& rb, hipStream_t s, int32_t variant = 0);
 // template-filtered white weights (noise kind 3)

@@ -1,7 +1,8 @@
 // Tables of the band-Toeplitz noise weighting (the correlated N^-1 of
 // eq. (5), one finite band section per stationary chunk): the overlap-save
 // tiles of each FFT plan, the spectral weights (alpha_k, beta_k) of every
-// filter, and the twiddle factors.
+// filter, and the twiddle factors (FP64 tables for the FP64 plan and, in
+// FP64 too, for the 16384-point plan that FP64 arithmetic may also run).
 //
 // The symbol of the symmetric band filter at the L frequencies of a plan,
 //   H_k = c_0 + 2 sum_{tau=1}^{lambda-1} c_tau cos(2 pi k tau / L),  k = 0..N,
@@ -139,6 +140,8 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   d_ab[1] = cv.take<cpx<float>>((size_t)nf * kFftN32);
   d_tw[0] = cv.take<cpx<double>>(kFftN64);
   d_tw[1] = cv.take<cpx<float>>(kFftN32);
+  cpx<double>* d_ab64l = cv.take<cpx<double>>((size_t)nf * kFftN32);
+  cpx<double>* d_tw64l = cv.take<cpx<double>>(kFftN32);
   // build-time staging: coefficients, cosine table, symbol
   double* d_coeff = cv.take<double>((size_t)nf * lam);
   double* d_cos = cv.take<double>(kCosLen);
@@ -151,13 +154,15 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   for (int j = 0; j < kCosLen; ++j) cos_t[j] = std::cos(2.0 * M_PI * (double)j / (double)kCosLen);
   std::vector<cpx<double>> tw64(kFftN64);
   std::vector<cpx<float>> tw32(kFftN32);
+  std::vector<cpx<double>> tw64l(kFftN32);
   for (int k = 0; k < kFftN64; ++k) {
     const double th = -2.0 * M_PI * (double)k / (double)kFftN64;
     tw64[k] = {std::cos(th), std::sin(th)};
   }
   for (int k = 0; k < kFftN32; ++k) {
     const double th = -2.0 * M_PI * (double)k / (double)kFftN32;
-    tw32[k] = {(float)std::cos(th), (float)std::sin(th)};
+    tw64l[k] = {std::cos(th), std::sin(th)};
+    tw32[k] = {(float)tw64l[k].x, (float)tw64l[k].y};
   }
   for (int a = 0; a < 2; ++a) {
     if (!tiles[a].empty())
@@ -177,6 +182,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   MM_HIP(hipMemcpyAsync(d_cos, cos_t.data(), cos_t.size() * sizeof(double), hipMemcpyHostToDevice, s));
   MM_HIP(hipMemcpyAsync(d_tw[0], tw64.data(), tw64.size() * sizeof(tw64[0]), hipMemcpyHostToDevice, s));
   MM_HIP(hipMemcpyAsync(d_tw[1], tw32.data(), tw32.size() * sizeof(tw32[0]), hipMemcpyHostToDevice, s));
+  MM_HIP(hipMemcpyAsync(d_tw64l, tw64l.data(), tw64l.size() * sizeof(tw64l[0]), hipMemcpyHostToDevice, s));
   for (int a = 0; a < 2; ++a) {
     const int n = Ns[a];
     const int step = kCosLen / (2 * n);
@@ -187,9 +193,13 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     if (a == 0)
       hipLaunchKernelGGL(k_spectral_weights<double>, dim3((n + 255) / 256, nf), dim3(256), 0, s, (const double*)d_H,
                          (const double*)d_cos, step, n, (cpx<double>*)d_ab[0]);
-    else
+    else {
       hipLaunchKernelGGL(k_spectral_weights<float>, dim3((n + 255) / 256, nf), dim3(256), 0, s, (const double*)d_H,
                          (const double*)d_cos, step, n, (cpx<float>*)d_ab[1]);
+      MM_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_spectral_weights<double>, dim3((n + 255) / 256, nf), dim3(256), 0, s,
+                         (const double*)d_H, (const double*)d_cos, step, n, d_ab64l);
+    }
     MM_HIP(hipGetLastError());
   }
   // the host staging vectors die on return: wait for the copies
@@ -198,6 +208,8 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     nz->ab[a] = d_ab[a];
     nz->tw[a] = d_tw[a];
   }
+  nz->ab64l = d_ab64l;
+  nz->tw64l = d_tw64l;
   return MM_OK;
 }
 

@@ -51,6 +51,7 @@ struct Plan;
 template <>
 struct Plan<double> {
   static constexpr int N = kFftN64, T = 512, kMinBlocks = 1;
+  static constexpr int kROut = 16;         // radix of the last inverse pass
   static constexpr int kGatherBatch = 8;   // entries (sample pairs) per load batch
   static constexpr int kScatterBatch = 8;
   static constexpr int kCarryElems = 8, kKeepW0 = 5, kKeepW1 = 11;
@@ -59,6 +60,7 @@ struct Plan<double> {
 template <>
 struct Plan<float> {
   static constexpr int N = kFftN32, T = 512, kMinBlocks = 1;
+  static constexpr int kROut = 32;
   static constexpr int kGatherBatch = 8;
   static constexpr int kScatterBatch = 4;
   static constexpr int kCarryElems = 8, kKeepW0 = 0, kKeepW1 = 0;
@@ -269,15 +271,16 @@ __device__ __forceinline__ bool src_pos(int pos, int ilo, int ihi, bool wrap, in
 }
 
 
+// G: the plan whose register layout v has (N, T, last inverse radix kROut,
+// kKeepW0/kKeepW1, kPairMerge).
 template <class S, class C, int kW, int NC, bool kKeepK, bool kKeepW = false, int kSlots = Lds<C, NC>::kBinSlots,
-          int kBatch = Plan<C>::kScatterBatch>
+          int kBatch = Plan<C>::kScatterBatch, class G = Plan<C>>
 __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, const int32_t* kk,
                                              const int32_t* __restrict__ sk, const S* __restrict__ ps0,
                                              const S* __restrict__ w0, int32_t vlo, int32_t vhi, int32_t kmin,
                                              int32_t kmax, double* __restrict__ q,
                                              const typename Angle<C, S, kW>::type* wk = nullptr) {
-  using P = Plan<C>;
-  using F = Fft<C>;
+  using P = G;
   using A = Angle<C, S, kW>;
   constexpr int N = P::N, T = P::T, E = N / T, GS = kBatch;
   constexpr int kTBinSlots = kSlots;
@@ -327,7 +330,7 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
       if constexpr (P::kPairMerge) {
 #pragma unroll
         for (int i = 0; i < 2 * GS; i += 2) {
-          const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
+          const cpx<C> o = v[slot_of<N, T, P::kROut>(e0 + i / 2)];
           C c0 = C(0), s0 = C(0), c1 = C(0), s1 = C(0);
           if constexpr (kAng) {
             A::eval(ps[i], &c0, &s0);
@@ -353,7 +356,7 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
       } else {
 #pragma unroll
         for (int i = 0; i < 2 * GS; ++i) {
-          const cpx<C> o = v[slot_of<N, T, F::ROut>(e0 + i / 2)];
+          const cpx<C> o = v[slot_of<N, T, P::kROut>(e0 + i / 2)];
           const C z = (i & 1) ? o.y : o.x;
           C c = C(0), s = C(0);
           if constexpr (kAng) A::eval(ps[i], &c, &s);
@@ -981,16 +984,16 @@ __device__ __forceinline__ cpx<C> spec_t(cpx<C> ab, cpx<C> z, cpx<C> zr) {
   return {ab.x * z.x + ab.y * zr.y, ab.x * z.y + ab.y * zr.x};
 }
 
-template <int N, int T>
-__device__ __forceinline__ void hmiddle32(float* buf, cpx<float>* v, const cpx<float>* __restrict__ abf) {
+template <class C, int N, int T>
+__device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* __restrict__ abf) {
   constexpr int H = N / 2, PPT = H / T;
   static_assert(2 * PPT == N / T, "bin pairs must fill the registers");
-  settle<float, N / T>(v);
+  settle<C, N / T>(v);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     __syncthreads();
-    if (c == 0) hstore<float, N, T, 16, N / 16, 0>(buf, v);
-    else hstore<float, N, T, 16, N / 16, 1>(buf, v);
+    if (c == 0) hstore<C, N, T, 16, N / 16, 0>(buf, v);
+    else hstore<C, N, T, 16, N / 16, 1>(buf, v);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < PPT; ++r) {
@@ -1004,11 +1007,11 @@ __device__ __forceinline__ void hmiddle32(float* buf, cpx<float>* v, const cpx<f
     const int k = fft_tid() + T * r;
     const bool k0 = k == 0;
     const int m = k0 ? H : N - k;
-    const cpx<float> zk = v[2 * r], zm = v[2 * r + 1];
+    const cpx<C> zk = v[2 * r], zm = v[2 * r + 1];
     v[2 * r] = spec_t(abf[k], zk, k0 ? zk : zm);
     v[2 * r + 1] = spec_t(abf[m], zm, k0 ? zm : zk);
   }
-  settle<float, N / T>(v);
+  settle<C, N / T>(v);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     __syncthreads();
@@ -1019,37 +1022,53 @@ __device__ __forceinline__ void hmiddle32(float* buf, cpx<float>* v, const cpx<f
       buf[hpad(m)] = c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y;
     }
     __syncthreads();
-    if (c == 0) hload<float, N, T, 16, 0>(buf, v);
-    else hload<float, N, T, 16, 1>(buf, v);
+    if (c == 0) hload<C, N, T, 16, 0>(buf, v);
+    else hload<C, N, T, 16, 1>(buf, v);
   }
 }
 
-// Batches of the two-per-CU kernel: smaller than the one-per-CU plan's, so
-// that a batch of loads and the 16 register values fit 128 VGPRs.
+// Plans of the half-buffer kernel.  Batches are smaller than the
+// one-per-CU plan's, so that a batch of loads and the 16 register values
+// fit 128 VGPRs.  kFft: 0 = FP64 8192 points (forward 16, 16, 16, the last
+// radix 2 folded into the spectral step), 1 = 16384 points (forward
+// 32, 32, 16 in FP32, 16, 8, 8, 16 in FP64; the spectral step on bin pairs).
 template <class C>
 struct HPlan {
-  static constexpr int N = Plan<C>::N, T = Plan<C>::T;
+  static constexpr int N = Plan<C>::N, T = Plan<C>::T, kROut = Plan<C>::kROut, kFft = 0;
   static constexpr int kGatherBatch = 2;   // entries (sample pairs) per load batch
   static constexpr int kScatterBatch = 2;
   static constexpr int kWavesPerEU = 4;    // two 512-thread workgroups per CU
+  static constexpr int kKeepW0 = 0, kKeepW1 = 0;
+  static constexpr bool kPairMerge = Plan<C>::kPairMerge;
 };
 // FP32: 32 values per thread, indices loaded again in the gather batches, so
 // longer batches keep as many loads in flight
 template <>
 struct HPlan<float> {
-  static constexpr int N = Plan<float>::N, T = Plan<float>::T;
+  static constexpr int N = Plan<float>::N, T = Plan<float>::T, kROut = Plan<float>::kROut, kFft = 1;
   static constexpr int kGatherBatch = 4;
   static constexpr int kScatterBatch = 4;
   static constexpr int kWavesPerEU = 4;
+  static constexpr int kKeepW0 = 0, kKeepW1 = 0;
+  static constexpr bool kPairMerge = Plan<float>::kPairMerge;
+};
+// FP64 on the 16384-point tiles: 1024 threads x 16 values, one workgroup
+// (16 waves, 4 per SIMD) per CU, the 136 KiB half buffer.
+struct HPlanL64 {
+  static constexpr int N = kFftN32, T = 1024, kROut = 16, kFft = 1;
+  static constexpr int kGatherBatch = 2;
+  static constexpr int kScatterBatch = 2;
+  static constexpr int kWavesPerEU = 4;
+  static constexpr int kKeepW0 = 0, kKeepW1 = 0;
+  static constexpr bool kPairMerge = true;
 };
 
-template <class S, class C, int kW, int NC>
+template <class S, class C, int kW, int NC, class P>
 __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t lambda, const cpx<C>* __restrict__ abf,
                                                    const cpx<C>* __restrict__ tw,
                                                    const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
                                                    const S* __restrict__ wts, const double* __restrict__ x,
                                                    double* __restrict__ q) {
-  using P = HPlan<C>;
   using A = Angle<C, S, kW>;
   constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch;
   constexpr bool kAng = Stokes<NC>::kAngle;
@@ -1203,13 +1222,18 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   __syncthreads();  // the FFT reuses the staging area; s_red[0, 2W) holds the valid range
 
   // ---- forward FFT, spectral step, inverse FFT (outputs in registers)
-  if constexpr (std::is_same<C, double>::value) {
+  static_assert(P::kFft == (N == 8192 ? 0 : 1) && (N == 8192 || N == 16384), "plan and length");
+  if constexpr (P::kFft == 0) {
     hpasses<C, N, T, true, 1, 16, 16, 16>(buf, v, tw);
     hmiddle<N, T>(buf, v, abf, tw);
     hpasses<C, N, T, false, 2, 16, 16, 16>(buf, v, tw);
+  } else if constexpr (std::is_same<C, double>::value) {
+    hpasses<C, N, T, true, 1, 16, 8, 8, 16>(buf, v, tw);
+    hmiddle_pairs<C, N, T>(buf, v, abf);
+    hpasses<C, N, T, false, 1, 16, 8, 8, 16>(buf, v, tw);
   } else {
     hpasses<C, N, T, true, 1, 32, 32, 16>(buf, v, tw);
-    hmiddle32<N, T>(buf, v, abf);
+    hmiddle_pairs<C, N, T>(buf, v, abf);
     hpasses<C, N, T, false, 1, 16, 32, 32>(buf, v, tw);
   }
 
@@ -1223,14 +1247,14 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
     kmax = s_red[W + w] > kmax ? s_red[W + w] : kmax;
   }
   if (kmax < kmin) return;
-  scatter_bins<S, C, kW, NC, false, false, kSlots, P::kScatterBatch>(v, reinterpret_cast<double*>(buf), nullptr, sk,
+  scatter_bins<S, C, kW, NC, false, false, kSlots, P::kScatterBatch, P>(v, reinterpret_cast<double*>(buf), nullptr, sk,
                                                                      ps0, w0, vlo, vhi, kmin, kmax, q);
 }
 
 // One plain tile of one right-hand side per workgroup, two workgroups per
 // CU; tiles mapped to workgroups as in k_toeplitz.
-template <class S, class C, int kW, int NC>
-__global__ __launch_bounds__(HPlan<C>::T, HPlan<C>::kWavesPerEU) void k_toeplitz_half(
+template <class S, class C, int kW, int NC, class P>
+__global__ __launch_bounds__(P::T, P::kWavesPerEU) void k_toeplitz_half(
     const FftTile* __restrict__ tiles, int64_t n_tiles, int32_t lambda, const cpx<C>* __restrict__ ab,
     const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
     const S* __restrict__ wts, const double* __restrict__ x, double* __restrict__ q, RhsBatch rb,
@@ -1251,7 +1275,7 @@ __global__ __launch_bounds__(HPlan<C>::T, HPlan<C>::kWavesPerEU) void k_toeplitz
   x += rhs * rb.vstride;
   q += rhs * rb.vstride;
   const FftTile tl = tiles[tile];
-  toeplitz_tile_half<S, C, kW, NC>(tl, lambda, ab + (int64_t)tl.filter * HPlan<C>::N, tw, sample_k, psi, wts, x, q);
+  toeplitz_tile_half<S, C, kW, NC, P>(tl, lambda, ab + (int64_t)tl.filter * P::N, tw, sample_k, psi, wts, x, q);
 }
 
 // One launch over the tiles of several slots (right-hand sides of different
@@ -1295,6 +1319,18 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
              double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
+  // the 16384-point FP64 plan (bit kOpLongPlan) before any other bit
+  if constexpr (kIn == 1 && kOut == 1 && std::is_same<C, double>::value) {
+    if (variant & kOpLongPlan) {
+      if (nz->n_tiles[1] == 0) return MM_OK;
+      const int64_t g = 8 * ((nz->n_tiles[1] + 7) / 8) * rb.nrhs;
+      hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, HPlanL64>), dim3(g), dim3(HPlanL64::T), 0, s, nz->tiles[1],
+                         nz->n_tiles[1], nz->lambda, (const cpx<C>*)nz->ab64l, (const cpx<C>*)nz->tw64l,
+                         pt->sample_k, (const S*)pt->psi, (const S*)pt->weights, x, q, rb, variant);
+      MM_HIP(hipGetLastError());
+      return MM_OK;
+    }
+  }
   // the halo-carrying form streams stored weights (with psi it spills), or
   // no angle at all (intensity only)
   if constexpr (kIn == 1 && kOut == 1 && (kW == 1 || NC == 1)) {
@@ -1312,7 +1348,7 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
   const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8) * rb.nrhs;
   if constexpr (kIn == 1 && kOut == 1) {
     if (variant & kOpHalfLds) {
-      hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC>), dim3(grid), dim3(HPlan<C>::T), 0, s, nz->tiles[a],
+      hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, HPlan<C>>), dim3(grid), dim3(HPlan<C>::T), 0, s, nz->tiles[a],
                          nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
                          pt->sample_k, (const S*)pt->psi, (const S*)pt->weights, x, q, rb, variant);
       MM_HIP(hipGetLastError());

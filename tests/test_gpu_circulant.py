@@ -77,7 +77,7 @@ def test_circulant_fused_operator_all_variants(prob):
     x = np.random.default_rng(7).normal(size=3 * opt.n_kept)
     ref = oracle.apply_A(opt, noise, x)
     tx = torch.from_numpy(x).to(DEV)
-    for v in list(range(8)) + [8, 9]:
+    for v in list(range(8)) + [8, 9, 16, 17]:
         assert rel(b.apply_A(pt, nz, tx, variant=v).cpu().numpy(), ref, 3) < 1e-12, v
         assert rel(b.apply_A(pt, nz, tx, arith="f32", variant=v).cpu().numpy(), ref, 3) < 1e-5, v
     bb = b.rhs(pt, nz, torch.from_numpy(d).to(DEV)).cpu().numpy()

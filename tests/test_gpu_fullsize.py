@@ -65,7 +65,7 @@ def _oracle_rows(opt, coeff, chunks, x, sel):
     return q[sel], len(cidx)
 
 
-@pytest.mark.parametrize("variant", [0, 2, 5, 8])
+@pytest.mark.parametrize("variant", [0, 2, 5, 8, 16])
 def test_full_size_operator_sampled_pixels(full, variant):
     b = _b()
     w, pix, psi, opt, pt, nz, coeff, chunks = full
@@ -130,7 +130,7 @@ def test_full_size_forms_build_and_sampled_pixels(full_form):
                               weight=opt.weight[idx], sample_k=opt.sample_k[idx])
     ref = oracle.apply_A(sub, oracle.toeplitz_noise(coeff, np.concatenate([[0], np.cumsum(lens)])), x)
     ref = ref.reshape(-1, nc)[sel]
-    for v in (0, 5, 8):
+    for v in (0, 5, 8, 16):
         q = b.apply_A(pt, nz, torch.from_numpy(x).to(DEV), variant=v).cpu().numpy().reshape(-1, nc)
         err = np.abs(q[sel] - ref).max() / np.abs(ref).max()
         assert err < 1e-12, (v, err)

@@ -11,7 +11,8 @@ operator runs in the launch configuration of the full-size problem (full
   <= 1e-10 relative L2 over kept pixels.  Parity is taken at a fixed k
   because a solve stopped at residual tol is ~kappa * tol away from the
   exact map, not tol.  Checked in the halo-carrying variant (5), plain
-  tiles (0), plain tiles two workgroups per CU (8), and with the autotuner.
+  tiles (0), plain tiles two workgroups per CU (8), the 16384-point FP64
+  plan (16), and with the autotuner.
 * FP32 storage, FP32 timeline arithmetic, FP64 refinement: solved to an
   FP64 residual of 1e-14, the map equals the oracle's map of the same
   (FP32-rounded) inputs solved to 1e-14, per Stokes <= 1e-10.  The map of
@@ -98,7 +99,7 @@ def test_headline_fp64_fixed_iterations(shard64):
     _, info_k, x_ref = oracle.solve(s.opt, s.noise, s.d, fixed_iters=K_FIXED)
     print(f"oracle {K_FIXED} iterations: {time.time() - t0:.1f} s, residual {info_k.history[-1]:.3e}", flush=True)
     runs = [("variant 5", dict(op_variant=5)), ("variant 0", dict(op_variant=0)), ("variant 8", dict(op_variant=8)),
-            ("autotuned", dict(autotune=1))]
+            ("variant 16", dict(op_variant=16)), ("autotuned", dict(autotune=1))]
     for name, kw in runs:
         out = b.Solver(s.pt, s.nz, fixed_iter=K_FIXED, **kw).solve(s.t_d, history=True)
         assert out["info"]["iters"] == K_FIXED

@@ -372,7 +372,7 @@ def test_fused_toeplitz_wide_window_matches_oracle():
     # sample carry strides make 1024 carrying tiles, i.e. segments of 4 tiles
     # on 256 CUs, so the carried P x and index ranges are exercised, with
     # several bin passes per tile
-    for v in (0, 4, 5, 8, 9):
+    for v in (0, 4, 5, 8, 9, 16):
         assert rel_err(b.apply_A(P.pt, P.nz, tx, variant=v).cpu().numpy(), q_ref, 3) < 1e-12, v
         # FP32 timeline arithmetic (32768-sample tiles, more passes): FP32 rounding only
         assert rel_err(b.apply_A(P.pt, P.nz, tx, arith="f32", variant=v).cpu().numpy(), q_ref, 3) < 1e-5, v

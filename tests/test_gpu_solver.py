@@ -210,26 +210,26 @@ def test_operator_variants_agree_and_autotune():
     pt.attach_weights()
     td = torch.from_numpy(ds[0]).to(DEV)
     ref = b.Solver(pt, nz, tol=1e-12).solve(td)
-    for v in list(range(8)) + [8, 9]:
+    for v in list(range(8)) + [8, 9, 16, 17]:
         out = b.Solver(pt, nz, tol=1e-12, op_variant=v).solve(td)
         assert out["info"]["op_variant"] == v
         err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), ref["x"].cpu().numpy())
         assert np.all(err < 1e-10), (v, err)
     tuned = b.Solver(pt, nz, tol=1e-12, autotune=1).solve(td)
-    assert 0 <= tuned["info"]["op_variant"] < 16
+    assert 0 <= tuned["info"]["op_variant"] < 32
     err = oracle.rel_l2_per_stokes(tuned["x"].cpu().numpy(), ref["x"].cpu().numpy())
     assert np.all(err < 1e-10), err
     again = b.Solver(pt, nz, tol=1e-12, autotune=1).solve(td)  # remembered by the noise handle
     assert again["info"]["op_variant"] == tuned["info"]["op_variant"]
     with pytest.raises(b.MapMakerError):
-        b.Solver(pt, nz, op_variant=16).solve(td)
+        b.Solver(pt, nz, op_variant=32).solve(td)
     # the FP32 inner operator with refinement, tuned
     w32 = SMALL_T.replace(precision="f32")
     pt32, nz32, opt32, noise32, ds32 = _device_problem(w32)
     pt32.attach_weights()
     out = b.Solver(pt32, nz32, tol=1e-12, mixed=1, max_outer=20, autotune=1).solve(
         torch.from_numpy(ds32[0]).to(DEV))
-    assert out["info"]["converged"] == 1 and 0 <= out["info"]["op_variant"] < 16
+    assert out["info"]["converged"] == 1 and 0 <= out["info"]["op_variant"] < 32
     _, _, x_ref = oracle.solve(opt32, noise32, ds32[0].astype(np.float64), tol=1e-13)
     err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref)
     assert np.all(err < 1e-9), err
@@ -240,7 +240,7 @@ LONG4096 = synth.Workload("long_128x128_2x2^18_lam4096", 962, 128, 128, 2, 1 << 
                           noise="oneoverf", chunk=(1 << 17) + 777, lam=4096)
 
 
-@pytest.mark.parametrize("variant", list(range(8)) + [8, 9])
+@pytest.mark.parametrize("variant", list(range(8)) + [8, 9, 16])
 @pytest.mark.parametrize("w", [SMALL_T, LONG4096], ids=["small", "long4096"])
 def test_operator_variants_fixed_iteration_parity(w, variant):
     """Each operator variant, through a fixed number of PCG iterations,

@@ -104,7 +104,7 @@ def test_fused_operators_all_variants(form):
     assert rel(b.apply_A(form.pt, form.white, tx).cpu(), ref_w, form.nc) < 1e-13
     assert rel(b.apply_A(form.pt, form.white, tx, arith="f32").cpu(), ref_w, form.nc) < 1e-5
     ref = oracle.apply_A(o, form.noise, x)
-    for v in list(range(8)) + [8, 9]:
+    for v in list(range(8)) + [8, 9, 16, 17]:
         assert rel(b.apply_A(form.pt, form.nz, tx, variant=v).cpu(), ref, form.nc) < 1e-12, v
         assert rel(b.apply_A(form.pt, form.nz, tx, arith="f32", variant=v).cpu(), ref, form.nc) < 1e-5, v
     X = torch.stack([tx, 2.0 * tx]).contiguous()
