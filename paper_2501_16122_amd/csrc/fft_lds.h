@@ -136,6 +136,10 @@ __device__ __forceinline__ int fft_tid() {
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 template <int N>
 constexpr int lds_elems() { return N + N / 16; }
+// lds_pad(i + d) - lds_pad(i) for d a multiple of 16, or d = q Ns with Ns
+// dividing 16 and i mod 16 < Ns: one padded address per butterfly, the other
+// inputs or outputs at constant offsets from it.
+constexpr int lds_step(int d) { return d + (d >> 4); }
 
 // Twiddle by w^(m k), then DFT, for the BPT butterflies held in v.
 template <class C, int N, int T, int R, int Ns, bool kFwd>
@@ -166,25 +170,27 @@ __device__ __forceinline__ void pass_compute(cpx<C>* v, const cpx<C>* __restrict
 template <class C, int N, int T, int R, int Ns>
 __device__ __forceinline__ void pass_store(cpx<C>* buf, const cpx<C>* v) {
   constexpr int BPT = N / T / R;
+  static_assert(Ns % 16 == 0 || (16 % Ns == 0 && (Ns * R) % 16 == 0), "offsets q Ns must keep the pad count");
   const int tid = fft_tid();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     const int j = tid + b * T;
-    const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
+    const int pb = lds_pad((j / Ns) * Ns * R + (j & (Ns - 1)));
 #pragma unroll
-    for (int q = 0; q < R; ++q) buf[lds_pad(base + q * Ns)] = v[b * R + q];
+    for (int q = 0; q < R; ++q) buf[pb + lds_step(q * Ns)] = v[b * R + q];
   }
 }
 
 template <class C, int N, int T, int R>
 __device__ __forceinline__ void pass_load(const cpx<C>* buf, cpx<C>* v) {
   constexpr int BPT = N / T / R;
+  static_assert((N / R) % 16 == 0, "input stride must keep the pad count");
   const int tid = fft_tid();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int j = tid + b * T;
+    const int pj = lds_pad(tid + b * T);
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[b * R + m] = buf[lds_pad(j + m * (N / R))];
+    for (int m = 0; m < R; ++m) v[b * R + m] = buf[pj + lds_step(m * (N / R))];
   }
 }
 

@@ -270,6 +270,21 @@ __device__ __forceinline__ bool src_pos(int pos, int ilo, int ihi, bool wrap, in
   return in || (wrap && pos < ihi + lam1);
 }
 
+// src_pos with the wrap known at compile time, and sp always a position
+// inside the chunk (the load address for a position that holds none): for a
+// chunk that does not wrap, the position clamped into [ilo, ihi).
+template <bool kWrap>
+__device__ __forceinline__ bool win_pos(int pos, int ilo, int ihi, int clen, int lam1, int& sp) {
+  if constexpr (kWrap) {
+    const bool ok = src_pos(pos, ilo, ihi, true, clen, lam1, sp);
+    sp = ok ? sp : ilo;
+    return ok;
+  } else {
+    sp = min(max(pos, ilo), ihi - 1);
+    return (uint32_t)(pos - ilo) < (uint32_t)(ihi - ilo);
+  }
+}
+
 
 // G: the plan whose register layout v has (N, T, last inverse radix kROut,
 // kKeepW0/kKeepW1, kPairMerge).
@@ -309,16 +324,16 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
 #pragma unroll
       for (int i = 0; i < 2 * GS; ++i) {
         const int pos = 2 * (tidp + T * (e0 + i / 2)) + (i & 1);
-        const bool valid = pos >= vlo && pos < vhi;
-        const int posa = valid ? pos : vlo;  // a valid output: its loads are always in bounds
+        const bool valid = (uint32_t)(pos - vlo) < (uint32_t)(vhi - vlo);
+        const int posa = min(max(pos, vlo), vhi - 1);  // a valid output: its loads are always in bounds
         int32_t k;
         if constexpr (kKeepK) k = valid ? kk[2 * e0 + i] : -1;
         else {
           const int32_t kr = skp[posa];
           k = valid ? kr : -1;
         }
-        const int32_t rel = k - wlo;
-        ks[i] = (k >= 0 && rel < nb && rel >= 0) ? rel : -1;
+        const int32_t rel = k - wlo;  // k = -1 (none) gives rel < 0
+        ks[i] = (uint32_t)rel < (uint32_t)nb ? rel : -1;
         const int e = e0 + i / 2;
         if (!kAng)
           ps[i] = A::zero();
@@ -838,6 +853,11 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz(
 __device__ __forceinline__ int hpad(int i) { return i + (i >> 4); }
 template <int N>
 constexpr int hlds_elems() { return N + N / 16; }
+// hpad(i + d) - hpad(i) for the offsets d the exchanges use: d a multiple of
+// 16, or d = q Ns with Ns dividing 16 and i mod Ns = i mod 16 < Ns (the low
+// bits of i then never carry into the pad count).  With it each thread forms
+// one padded address per butterfly and reaches the rest by constant offsets.
+constexpr int hstep(int d) { return d + (d >> 4); }
 
 template <class C, int kComp>
 __device__ __forceinline__ C& comp(cpx<C>& a) {
@@ -850,12 +870,13 @@ template <class C, int N, int T, int R, int Ns, int kComp>
 __device__ __forceinline__ void hstore(C* buf, cpx<C>* v) {
   constexpr int BPT = N / T / R;
   const int tid = fft_tid();
+  static_assert(Ns % 16 == 0 || (16 % Ns == 0 && (Ns * R) % 16 == 0), "offsets q Ns must keep the pad count");
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     const int j = tid + b * T;
-    const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
+    const int pb = hpad((j / Ns) * Ns * R + (j & (Ns - 1)));
 #pragma unroll
-    for (int q = 0; q < R; ++q) buf[hpad(base + q * Ns)] = comp<C, kComp>(v[b * R + q]);
+    for (int q = 0; q < R; ++q) buf[pb + hstep(q * Ns)] = comp<C, kComp>(v[b * R + q]);
   }
 }
 
@@ -864,11 +885,12 @@ template <class C, int N, int T, int R, int kComp>
 __device__ __forceinline__ void hload(const C* buf, cpx<C>* v) {
   constexpr int BPT = N / T / R;
   const int tid = fft_tid();
+  static_assert((N / R) % 16 == 0, "input stride must keep the pad count");
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int j = tid + b * T;
+    const int pj = hpad(tid + b * T);
 #pragma unroll
-    for (int m = 0; m < R; ++m) comp<C, kComp>(v[b * R + m]) = buf[hpad(j + m * (N / R))];
+    for (int m = 0; m < R; ++m) comp<C, kComp>(v[b * R + m]) = buf[pj + hstep(m * (N / R))];
   }
 }
 
@@ -927,19 +949,26 @@ __device__ __forceinline__ void hmiddle(double* buf, cpx<double>* v, const cpx<d
     if (c == 0) hstore<double, N, T, 16, 256, 0>(buf, v);
     else hstore<double, N, T, 16, 256, 1>(buf, v);
     __syncthreads();
+    // j = t + T r and m = H - j (m = Q for j = 0): padded addresses from
+    // those of t and H - t by constant offsets
+    const int t = fft_tid();
+    const int pj = hpad(t), pmh = hpad(H - t), pm0 = t == 0 ? hpad(Q) : pmh;
 #pragma unroll
     for (int r = 0; r < PPT; ++r) {
-      const int j = fft_tid() + T * r, m = j == 0 ? Q : H - j;
-      (c == 0 ? v[4 * r + 0].x : v[4 * r + 0].y) = buf[hpad(j)];
-      (c == 0 ? v[4 * r + 1].x : v[4 * r + 1].y) = buf[hpad(j + H)];
-      (c == 0 ? v[4 * r + 2].x : v[4 * r + 2].y) = buf[hpad(m)];
-      (c == 0 ? v[4 * r + 3].x : v[4 * r + 3].y) = buf[hpad(m + H)];
+      const int aj = pj + hstep(T * r), am = r == 0 ? pm0 : pmh - hstep(T * r);
+      (c == 0 ? v[4 * r + 0].x : v[4 * r + 0].y) = buf[aj];
+      (c == 0 ? v[4 * r + 1].x : v[4 * r + 1].y) = buf[aj + hstep(H)];
+      (c == 0 ? v[4 * r + 2].x : v[4 * r + 2].y) = buf[am];
+      (c == 0 ? v[4 * r + 3].x : v[4 * r + 3].y) = buf[am + hstep(H)];
     }
   }
+  const int t0 = fft_tid();
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
-    const int j = fft_tid() + T * r;
-    const bool j0 = j == 0;  // bins 0 and H pair with themselves; this slot's m side takes m = Q
+    const int j = t0 + T * r;
+    // bins 0 and H pair with themselves; this slot's m side takes m = Q (only
+    // thread 0's first slot: r > 0 never holds j = 0)
+    const bool j0 = r == 0 && t0 == 0;
     const int m = j0 ? Q : H - j;
     const cpx<double> t = tw[j];
     const cpx<double> tm = j0 ? cpx<double>{0.0, -1.0} : cpx<double>{-t.x, t.y};  // w^m
@@ -957,13 +986,16 @@ __device__ __forceinline__ void hmiddle(double* buf, cpx<double>* v, const cpx<d
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     __syncthreads();
+    // 2j, 2m even: 2j + 1 and 2m + 1 sit one scalar further
+    const int t = fft_tid();
+    const int pj = hpad(2 * t), pmh = hpad(2 * (H - t)), pm0 = t == 0 ? hpad(2 * Q) : pmh;
 #pragma unroll
     for (int r = 0; r < PPT; ++r) {
-      const int j = fft_tid() + T * r, m = j == 0 ? Q : H - j;
-      buf[hpad(2 * j)] = c == 0 ? v[4 * r + 0].x : v[4 * r + 0].y;
-      buf[hpad(2 * j + 1)] = c == 0 ? v[4 * r + 1].x : v[4 * r + 1].y;
-      buf[hpad(2 * m)] = c == 0 ? v[4 * r + 2].x : v[4 * r + 2].y;
-      buf[hpad(2 * m + 1)] = c == 0 ? v[4 * r + 3].x : v[4 * r + 3].y;
+      const int aj = pj + hstep(2 * T * r), am = r == 0 ? pm0 : pmh - hstep(2 * T * r);
+      buf[aj] = c == 0 ? v[4 * r + 0].x : v[4 * r + 0].y;
+      buf[aj + 1] = c == 0 ? v[4 * r + 1].x : v[4 * r + 1].y;
+      buf[am] = c == 0 ? v[4 * r + 2].x : v[4 * r + 2].y;
+      buf[am + 1] = c == 0 ? v[4 * r + 3].x : v[4 * r + 3].y;
     }
     __syncthreads();
     if (c == 0) hload<double, N, T, 16, 0>(buf, v);
@@ -995,17 +1027,20 @@ __device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* _
     if (c == 0) hstore<C, N, T, 16, N / 16, 0>(buf, v);
     else hstore<C, N, T, 16, N / 16, 1>(buf, v);
     __syncthreads();
+    // k = t + T r and m = N - k (m = H for k = 0)
+    const int t = fft_tid();
+    const int pk = hpad(t), pmh = hpad(N - t), pm0 = t == 0 ? hpad(H) : pmh;
 #pragma unroll
     for (int r = 0; r < PPT; ++r) {
-      const int k = fft_tid() + T * r, m = k == 0 ? H : N - k;
-      (c == 0 ? v[2 * r].x : v[2 * r].y) = buf[hpad(k)];
-      (c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y) = buf[hpad(m)];
+      (c == 0 ? v[2 * r].x : v[2 * r].y) = buf[pk + hstep(T * r)];
+      (c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y) = buf[r == 0 ? pm0 : pmh - hstep(T * r)];
     }
   }
+  const int t0 = fft_tid();
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
-    const int k = fft_tid() + T * r;
-    const bool k0 = k == 0;
+    const int k = t0 + T * r;
+    const bool k0 = r == 0 && t0 == 0;  // r > 0 never holds k = 0
     const int m = k0 ? H : N - k;
     const cpx<C> zk = v[2 * r], zm = v[2 * r + 1];
     v[2 * r] = spec_t(abf[k], zk, k0 ? zk : zm);
@@ -1015,11 +1050,12 @@ __device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* _
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     __syncthreads();
+    const int t = fft_tid();
+    const int pk = hpad(t), pmh = hpad(N - t), pm0 = t == 0 ? hpad(H) : pmh;
 #pragma unroll
     for (int r = 0; r < PPT; ++r) {
-      const int k = fft_tid() + T * r, m = k == 0 ? H : N - k;
-      buf[hpad(k)] = c == 0 ? v[2 * r].x : v[2 * r].y;
-      buf[hpad(m)] = c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y;
+      buf[pk + hstep(T * r)] = c == 0 ? v[2 * r].x : v[2 * r].y;
+      buf[r == 0 ? pm0 : pmh - hstep(T * r)] = c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y;
     }
     __syncthreads();
     if (c == 0) hload<C, N, T, 16, 0>(buf, v);
@@ -1035,6 +1071,7 @@ __device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* _
 template <class C>
 struct HPlan {
   static constexpr int N = Plan<C>::N, T = Plan<C>::T, kROut = Plan<C>::kROut, kFft = 0;
+  static constexpr bool kKeepIdx = true;   // window indices in registers from the first loads to the gather
   static constexpr int kGatherBatch = 2;   // entries (sample pairs) per load batch
   static constexpr int kScatterBatch = 2;
   static constexpr int kWavesPerEU = 4;    // two 512-thread workgroups per CU
@@ -1046,6 +1083,7 @@ struct HPlan {
 template <>
 struct HPlan<float> {
   static constexpr int N = Plan<float>::N, T = Plan<float>::T, kROut = Plan<float>::kROut, kFft = 1;
+  static constexpr bool kKeepIdx = false;
   static constexpr int kGatherBatch = 4;
   static constexpr int kScatterBatch = 4;
   static constexpr int kWavesPerEU = 4;
@@ -1056,6 +1094,7 @@ struct HPlan<float> {
 // (16 waves, 4 per SIMD) per CU, the 136 KiB half buffer.
 struct HPlanL64 {
   static constexpr int N = kFftN32, T = 1024, kROut = 16, kFft = 1;
+  static constexpr bool kKeepIdx = true;
   static constexpr int kGatherBatch = 2;
   static constexpr int kScatterBatch = 2;
   static constexpr int kWavesPerEU = 4;
@@ -1063,7 +1102,7 @@ struct HPlanL64 {
   static constexpr bool kPairMerge = true;
 };
 
-template <class S, class C, int kW, int NC, class P>
+template <class S, class C, int kW, int NC, class P, bool kWrap>
 __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t lambda, const cpx<C>* __restrict__ abf,
                                                    const cpx<C>* __restrict__ tw,
                                                    const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
@@ -1079,7 +1118,8 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   // FP64 keeps every window index in registers from the first round of
   // loads to the gather; FP32 (twice the samples per thread) has no room and
   // loads them again in the gather batches
-  constexpr bool kKeepIdx = E == 16;
+  constexpr bool kKeepIdx = P::kKeepIdx;
+  static_assert(!kKeepIdx || E == 16, "indices kept for 16 values per thread");
   __shared__ C buf[hlds_elems<N>()];
   __shared__ int32_t s_red[4 * (T / 64)];
 
@@ -1088,7 +1128,6 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   const int32_t vhi = vlo + (int32_t)(tl.out_end - tl.out_start);
   const int32_t ilo = (int32_t)(tl.chunk_start > in0 ? tl.chunk_start - in0 : 0);
   const int32_t ihi = (int32_t)(tl.chunk_end - in0 < L ? tl.chunk_end - in0 : L);
-  const bool wrap = tl.wrap != 0;
   const int32_t clen = (int32_t)(tl.chunk_end - tl.chunk_start);
   const int32_t* __restrict__ sk = sample_k + in0;
   const S* __restrict__ ps0 = (kAng && kW == 0) ? psi + in0 : nullptr;
@@ -1101,7 +1140,10 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   // the valid outputs
   constexpr int kPre = kKeepIdx ? 2 * E : 1;
   int32_t kk[kPre];
-  int32_t amin = INT32_MAX, amax = -1, kmin = INT32_MAX, kmax = -1;
+  // minima as unsigned: the index -1 (no sample, or a masked pixel) is then
+  // the largest value and drops out of min and max alike, without branches
+  uint32_t amin_u = UINT32_MAX, kmin_u = UINT32_MAX;
+  int32_t amax = -1, kmax = -1;
 #pragma unroll
   for (int h = 0; h < 2 * E; h += 32) {
     int32_t kr32[32];
@@ -1109,8 +1151,8 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
     for (int i = 0; i < 32; ++i) {
       const int pos = 2 * (tid + T * ((h + i) / 2)) + (i & 1);
       int sp;
-      const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
-      const int32_t kr = sk[ok ? sp : ilo];  // ilo: inside the chunk, always in bounds
+      const bool ok = win_pos<kWrap>(pos, ilo, ihi, clen, vlo, sp);
+      const int32_t kr = sk[sp];
       kr32[i] = ok ? kr : -1;
     }
 #pragma unroll
@@ -1118,16 +1160,14 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
       const int pos = 2 * (tid + T * ((h + i) / 2)) + (i & 1);
       const int32_t k = kr32[i];
       if constexpr (kKeepIdx) kk[h + i] = k;
-      if (k >= 0) {
-        amin = k < amin ? k : amin;
-        amax = k > amax ? k : amax;
-        if (pos >= vlo && pos < vhi) {
-          kmin = k < kmin ? k : kmin;
-          kmax = k > kmax ? k : kmax;
-        }
-      }
+      amin_u = min(amin_u, (uint32_t)k);
+      amax = max(amax, k);
+      const int32_t kv = (uint32_t)(pos - vlo) < (uint32_t)(vhi - vlo) ? k : -1;
+      kmin_u = min(kmin_u, (uint32_t)kv);
+      kmax = max(kmax, kv);
     }
   }
+  int32_t amin = (int32_t)min(amin_u, (uint32_t)INT32_MAX), kmin = (int32_t)min(kmin_u, (uint32_t)INT32_MAX);
   constexpr int W = T / 64;
   amin = wave_min(amin);
   amax = wave_max(amax);
@@ -1193,12 +1233,13 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
       for (int i = 0; i < 2 * G; ++i) {
         const int pos = 2 * (tdep + T * (e0 + i / 2)) + (i & 1);
         int sp;
-        const bool ok = src_pos(pos, ilo, ihi, wrap, clen, vlo, sp);
-        ps[i] = kAng ? A::load(ps0, w0, ok ? sp : ilo) : A::zero();
+        const bool ok = win_pos<kWrap>(pos, ilo, ihi, clen, vlo, sp);
+        ps[i] = kAng ? A::load(ps0, w0, sp) : A::zero();
         if constexpr (kKeepIdx) {
           kb[i] = kk[2 * e0 + i];
+          (void)ok;
         } else {
-          const int32_t kr = sk[ok ? sp : ilo];
+          const int32_t kr = sk[sp];
           kb[i] = ok ? kr : -1;
         }
       }
@@ -1253,7 +1294,7 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
 
 // One plain tile of one right-hand side per workgroup, two workgroups per
 // CU; tiles mapped to workgroups as in k_toeplitz.
-template <class S, class C, int kW, int NC, class P>
+template <class S, class C, int kW, int NC, class P, bool kWrap>
 __global__ __launch_bounds__(P::T, P::kWavesPerEU) void k_toeplitz_half(
     const FftTile* __restrict__ tiles, int64_t n_tiles, int32_t lambda, const cpx<C>* __restrict__ ab,
     const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
@@ -1275,7 +1316,8 @@ __global__ __launch_bounds__(P::T, P::kWavesPerEU) void k_toeplitz_half(
   x += rhs * rb.vstride;
   q += rhs * rb.vstride;
   const FftTile tl = tiles[tile];
-  toeplitz_tile_half<S, C, kW, NC, P>(tl, lambda, ab + (int64_t)tl.filter * P::N, tw, sample_k, psi, wts, x, q);
+  toeplitz_tile_half<S, C, kW, NC, P, kWrap>(tl, lambda, ab + (int64_t)tl.filter * P::N, tw, sample_k, psi, wts, x,
+                                             q);
 }
 
 // One launch over the tiles of several slots (right-hand sides of different
@@ -1314,6 +1356,26 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_ba
                                     static_cast<const S*>(o.wts), o.x, nullptr, nullptr, o.q, o.variant);
 }
 
+// A half-buffer kernel over the given tiles; circulant chunks (their tiles
+// wrap) take the instantiation with the wrap-around positions.
+template <class S, class C, int kW, int NC, class P>
+int launch_half(const mm_pointing_s* pt, const mm_noise_s* nz, const FftTile* tiles, int64_t n_tiles,
+                const void* ab, const void* tw, const double* x, double* q, const RhsBatch& rb, hipStream_t s,
+                int32_t variant) {
+  if (n_tiles == 0) return MM_OK;
+  const int64_t g = 8 * ((n_tiles + 7) / 8) * rb.nrhs;
+  if (nz->kind == 2)
+    hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, P, true>), dim3(g), dim3(P::T), 0, s, tiles, n_tiles,
+                       nz->lambda, (const cpx<C>*)ab, (const cpx<C>*)tw, pt->sample_k, (const S*)pt->psi,
+                       (const S*)pt->weights, x, q, rb, variant);
+  else
+    hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, P, false>), dim3(g), dim3(P::T), 0, s, tiles, n_tiles,
+                       nz->lambda, (const cpx<C>*)ab, (const cpx<C>*)tw, pt->sample_k, (const S*)pt->psi,
+                       (const S*)pt->weights, x, q, rb, variant);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
 template <class S, class C, int kIn, int kOut, int kW, int NC>
 int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod_in, void* tod_out,
              double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
@@ -1321,15 +1383,9 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
   if (nz->n_tiles[a] == 0) return MM_OK;
   // the 16384-point FP64 plan (bit kOpLongPlan) before any other bit
   if constexpr (kIn == 1 && kOut == 1 && std::is_same<C, double>::value) {
-    if (variant & kOpLongPlan) {
-      if (nz->n_tiles[1] == 0) return MM_OK;
-      const int64_t g = 8 * ((nz->n_tiles[1] + 7) / 8) * rb.nrhs;
-      hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, HPlanL64>), dim3(g), dim3(HPlanL64::T), 0, s, nz->tiles[1],
-                         nz->n_tiles[1], nz->lambda, (const cpx<C>*)nz->ab64l, (const cpx<C>*)nz->tw64l,
-                         pt->sample_k, (const S*)pt->psi, (const S*)pt->weights, x, q, rb, variant);
-      MM_HIP(hipGetLastError());
-      return MM_OK;
-    }
+    if (variant & kOpLongPlan)
+      return launch_half<S, C, kW, NC, HPlanL64>(pt, nz, nz->tiles[1], nz->n_tiles[1], nz->ab64l, nz->tw64l, x, q, rb,
+                                                 s, variant);
   }
   // the halo-carrying form streams stored weights (with psi it spills), or
   // no angle at all (intensity only)
@@ -1347,13 +1403,9 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
   }
   const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8) * rb.nrhs;
   if constexpr (kIn == 1 && kOut == 1) {
-    if (variant & kOpHalfLds) {
-      hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, HPlan<C>>), dim3(grid), dim3(HPlan<C>::T), 0, s, nz->tiles[a],
-                         nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
-                         pt->sample_k, (const S*)pt->psi, (const S*)pt->weights, x, q, rb, variant);
-      MM_HIP(hipGetLastError());
-      return MM_OK;
-    }
+    if (variant & kOpHalfLds)
+      return launch_half<S, C, kW, NC, HPlan<C>>(pt, nz, nz->tiles[a], nz->n_tiles[a], nz->ab[a], nz->tw[a], x, q, rb,
+                                                 s, variant);
   }
   hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW, NC>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
                      nz->n_tiles[a], nz->lambda, (const cpx<C>*)nz->ab[a], (const cpx<C>*)nz->tw[a],
