@@ -235,12 +235,26 @@ struct Fft<float> {
 
 // (cos 2psi_t, sin 2psi_t) in arithmetic C: from the stored tangent
 // tan psi_t when kW, else from psi.
+// base[i] for a window offset i as a 32-bit unsigned byte offset from a
+// wave-uniform base (one shift per load instead of a 64-bit address).  Only
+// for offsets known to be >= 0: a circulant chunk's wrapped positions can
+// lie before the window start (negative offsets), and those take base[i].
+template <class T>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, int32_t i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)i * (uint32_t)sizeof(T));
+}
+
 template <class C, class S, int kW>
 struct Angle {
   using type = S;
   static __device__ __forceinline__ type load(const S* __restrict__ psi, const S* __restrict__ w, int32_t t) {
     if constexpr (kW == 1) return w[t];
     else return psi[t];
+  }
+  // the same for an offset t >= 0
+  static __device__ __forceinline__ type load_nn(const S* __restrict__ psi, const S* __restrict__ w, int32_t t) {
+    if constexpr (kW == 1) return ld_off(w, t);
+    else return ld_off(psi, t);
   }
   static __device__ __forceinline__ type zero() { return S(0); }
   static __device__ __forceinline__ void eval(type a, C* c, C* s) {
@@ -280,7 +294,7 @@ __device__ __forceinline__ bool win_pos(int pos, int ilo, int ihi, int clen, int
     sp = ok ? sp : ilo;
     return ok;
   } else {
-    sp = min(max(pos, ilo), ihi - 1);
+    sp = max(min(pos, ihi - 1), ilo);  // >= ilo >= 0 whatever the bounds
     return (uint32_t)(pos - ilo) < (uint32_t)(ihi - ilo);
   }
 }
@@ -303,12 +317,12 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
   const int tid = threadIdx.x;
   for (int32_t wlo = kmin; wlo <= kmax; wlo += kTBinSlots) {
     const int nb = kmax - wlo + 1 < kTBinSlots ? kmax - wlo + 1 : kTBinSlots;
-    // opaque copies of the index view and thread id: keep the per-sample
-    // offsets and loads inside the pass instead of 2E of them hoisted and
-    // held live across all passes
-    const int32_t* skp = sk;
+    // an opaque copy of the thread id: keeps the per-sample offsets and
+    // loads inside the pass instead of 2E of them hoisted and held live
+    // across all passes (the index view itself stays a global pointer, so
+    // its loads stay global loads)
     int tidp = tid;
-    asm volatile("" : "+s"(skp), "+v"(tidp));
+    asm volatile("" : "+v"(tidp));
     for (int i = tid; i < nb; i += T)
 #pragma unroll
       for (int c = 0; c < NC; ++c) bins[c * kTBinSlots + i] = 0.0;
@@ -325,11 +339,12 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
       for (int i = 0; i < 2 * GS; ++i) {
         const int pos = 2 * (tidp + T * (e0 + i / 2)) + (i & 1);
         const bool valid = (uint32_t)(pos - vlo) < (uint32_t)(vhi - vlo);
-        const int posa = min(max(pos, vlo), vhi - 1);  // a valid output: its loads are always in bounds
+        // a valid output (>= vlo >= 0): its loads are always in bounds
+        const int posa = max(min(pos, vhi - 1), vlo);
         int32_t k;
         if constexpr (kKeepK) k = valid ? kk[2 * e0 + i] : -1;
         else {
-          const int32_t kr = skp[posa];
+          const int32_t kr = ld_off(sk, posa);  // posa >= vlo >= 0
           k = valid ? kr : -1;
         }
         const int32_t rel = k - wlo;  // k = -1 (none) gives rel < 0
@@ -340,7 +355,7 @@ __device__ __forceinline__ void scatter_bins(const cpx<C>* v, double* bins, cons
         else if (kKeepW && e >= P::kKeepW0 && e < P::kKeepW1)
           ps[i] = wk[2 * (e - P::kKeepW0) + (i & 1)];
         else
-          ps[i] = A::load(ps0, w0, posa);
+          ps[i] = A::load_nn(ps0, w0, posa);  // posa >= vlo >= 0
       }
       if constexpr (P::kPairMerge) {
 #pragma unroll
@@ -1152,7 +1167,8 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
       const int pos = 2 * (tid + T * ((h + i) / 2)) + (i & 1);
       int sp;
       const bool ok = win_pos<kWrap>(pos, ilo, ihi, clen, vlo, sp);
-      const int32_t kr = sk[sp];
+      // without wrap, sp lies in [ilo, ihi): a non-negative offset
+      const int32_t kr = kWrap ? sk[sp] : ld_off(sk, sp);
       kr32[i] = ok ? kr : -1;
     }
 #pragma unroll
@@ -1234,12 +1250,12 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
         const int pos = 2 * (tdep + T * (e0 + i / 2)) + (i & 1);
         int sp;
         const bool ok = win_pos<kWrap>(pos, ilo, ihi, clen, vlo, sp);
-        ps[i] = kAng ? A::load(ps0, w0, sp) : A::zero();
+        ps[i] = kAng ? (kWrap ? A::load(ps0, w0, sp) : A::load_nn(ps0, w0, sp)) : A::zero();
         if constexpr (kKeepIdx) {
           kb[i] = kk[2 * e0 + i];
           (void)ok;
         } else {
-          const int32_t kr = sk[sp];
+          const int32_t kr = kWrap ? sk[sp] : ld_off(sk, sp);
           kb[i] = ok ? kr : -1;
         }
       }
