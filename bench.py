@@ -42,7 +42,7 @@ STREAMED_BYTES_PER_SAMPLE_TOEPLITZ = 12.0
 KERNEL_SOURCES = ["paper_2501_16122_amd/csrc/toeplitz.hip", "paper_2501_16122_amd/csrc/fft_lds.h",
                   "paper_2501_16122_amd/csrc/stokes.h",
                   "paper_2501_16122_amd/csrc/sincos2.h"]
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_toeplitz_half_f64_gls512.counters.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_toeplitz_long_f64_gls512.counters.json")
 
 
 def log(msg):
@@ -715,15 +715,15 @@ def main():
     # FP64 half-angle tangent (band-Toeplitz), or the index and psi (white)
     streamed = (STREAMED_BYTES_PER_SAMPLE_TOEPLITZ if w.toeplitz else ALG_BYTES_PER_SAMPLE_F64) * w.n_samples
     v_last = infos[-1]["op_variant"]
-    prof_name = ("k_toeplitz_half<double, double, 1, 3>" if v_last & 8 else
-                 "k_toeplitz_carry<double, double, 1, 3>" if v_last & 4 else None)
+    # the dominant kernel as rocprofv3 names it (namespace dropped)
+    prof_name = ("k_toeplitz_half<double, double, 1, 3, HPlanL64, false>" if v_last & 16 else
+                 "k_toeplitz_half<double, double, 1, 3, HPlan<double>, false>" if v_last & 8 else
+                 "k_toeplitz_carry<double, double, 1, 3>" if v_last & 4 else
+                 "k_toeplitz<double, double, 1, 1, 1, 3>")
     roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
             "traffic": stored_traffic(prof_name) if w.toeplitz and prof_name else None,
-            "kernel": ((("k_toeplitz_half<double,double,weights>" if infos[-1]["op_variant"] & 8 else
-                          "k_toeplitz_carry<double,double,weights>" if infos[-1]["op_variant"] & 4
-                          else "k_toeplitz<double,double,gather,scatter,weights>") + " (fused P^T N^-1 P)")
-                       if w.toeplitz else "k_fused_white<double,double>"),
+            "kernel": (prof_name + " (fused P^T N^-1 P)") if w.toeplitz else "k_fused_white<double,double>",
             "kernel_ms_avg": round(kernel_ms, 4), "launches": op_n,
             "op_variant": infos[-1]["op_variant"],
             "algorithmic_bytes_per_sample": ALG_BYTES_PER_SAMPLE_F64,
