@@ -59,10 +59,11 @@ def kernel_source_hash() -> str:
 
 
 def fft_flops_per_launch(w, n_fft=8192):
-    """Algorithmic flops of one fused P^T T P launch: per overlap-save tile
-    two complex N-point FFTs at 5 N log2 N, the bin-pair spectral multiply
-    (8 N), and per timeline sample of the tile window P (4) and, per valid
-    sample, P^T (6)."""
+    """Algorithmic flops of one fused P^T T P launch with an n_fft-point
+    complex plan (windows of 2 n_fft samples): per overlap-save tile two
+    complex FFTs at 5 N log2 N, the bin-pair spectral multiply (8 N), and
+    per timeline sample of the tile window P (4) and, per valid sample,
+    P^T (6)."""
     L = 2 * n_fft
     V = L - 2 * (w.lam - 1)
     tiles_per_chunk = -(-w.chunk // V)
@@ -732,7 +733,8 @@ def main():
             "streamed_gbs": round(streamed / (kernel_ms * 1e-3) / 1e9, 1),
             "measured_copy_gbs": copy_bandwidth(torch, dev)}
     if w.toeplitz:
-        flops = fft_flops_per_launch(w)
+        # the FFT work of the plan the launch ran (16384 points with bit 4)
+        flops = fft_flops_per_launch(w, 16384 if v_last & 16 else 8192)
         tf = flops / (kernel_ms * 1e-3) / 1e12
         roof["fp64_tflops"] = round(tf, 2)
         roof["fp64_frac"] = round(tf / FP64_PEAK_TFLOPS, 4)
