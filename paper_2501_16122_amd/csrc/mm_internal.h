@@ -351,7 +351,7 @@ struct OpSlot {
   const void* tw;           // band-Toeplitz twiddles of the plan
   const int32_t* sample_k;
   const void* psi;
-  const void* wts;          // stored (cos 2psi, sin 2psi) or null
+  const void* wts;          // stored tangents tan psi, or null
   const double* det_w;      // white noise weights
   const double* x;
   double* q;
@@ -359,7 +359,7 @@ struct OpSlot {
   const void* iv;           // template intervals (TplInterval[])
   int64_t n_pt_tiles;       // template slots: pointing tiles (for the detector of an interval)
   int32_t lambda;
-  int32_t variant;          // band-Toeplitz operator variant (kOpNoStaging is honoured)
+  int32_t wrap;             // band-Toeplitz: 1 for circulant chunks (their tiles wrap)
 };
 struct OpBatch {
   int32_t n = 0;

@@ -685,7 +685,6 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
     o.x = x;
     o.q = q;
     o.done = done;
-    o.variant = sv->variant;
     int64_t items;
     if (nz->kind == 3) {
       o.tiles = pt->tiles;
@@ -698,6 +697,7 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
       o.ab = nz->ab[plan];
       o.tw = nz->tw[plan];
       o.lambda = nz->lambda;
+      o.wrap = nz->kind == 2 ? 1 : 0;
       items = nz->n_tiles[plan];
     } else {
       o.tiles = pt->tiles;

@@ -1337,13 +1337,15 @@ __global__ __launch_bounds__(P::T, P::kWavesPerEU) void k_toeplitz_half(
 }
 
 // One launch over the tiles of several slots (right-hand sides of different
-// solves).  Every slot's tiles are split into 8 contiguous parts and XCD x
-// takes part x of every slot, one after the other: each XCD then gets an
-// equal share of every solve (tiles of different solves differ in cost) and
-// still walks neighbouring tiles of one solve together.  A slot whose done
-// flag is set is skipped.
-template <class S, class C, int kW, int NC>
-__global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_batch(OpBatch b) {
+// solves), through the two-per-CU half-buffer tile.  Every slot's tiles are
+// split into 8 contiguous parts and XCD x takes part x of every slot, one
+// after the other: each XCD then gets an equal share of every solve (tiles
+// of different solves differ in cost) and still walks neighbouring tiles of
+// one solve together.  A slot whose done flag is set is skipped, and so is
+// one whose chunks wrap differently from kWrap (circulant and band slots of
+// one batch take one launch each).
+template <class S, class C, int kW, int NC, bool kWrap>
+__global__ __launch_bounds__(HPlan<C>::T, HPlan<C>::kWavesPerEU) void k_toeplitz_batch(OpBatch b) {
   const int x = blockIdx.x % 8;
   int64_t j = blockIdx.x / 8;  // position in XCD x's list
   int sl = -1;
@@ -1364,12 +1366,13 @@ __global__ __launch_bounds__(Plan<C>::T, Plan<C>::kMinBlocks) void k_toeplitz_ba
   }
   if (sl < 0) return;
   const OpSlot& o = b.s[sl];
+  if ((o.wrap != 0) != kWrap) return;
   if (o.done != nullptr && *o.done != 0) return;
   const FftTile tl = static_cast<const FftTile*>(o.tiles)[idx];
-  toeplitz_tile<S, C, 1, 1, kW, NC>(tl, o.lambda,
-                                    static_cast<const cpx<C>*>(o.ab) + (int64_t)tl.filter * Plan<C>::N,
-                                    static_cast<const cpx<C>*>(o.tw), o.sample_k, static_cast<const S*>(o.psi),
-                                    static_cast<const S*>(o.wts), o.x, nullptr, nullptr, o.q, o.variant);
+  toeplitz_tile_half<S, C, kW, NC, HPlan<C>, kWrap>(
+      tl, o.lambda, static_cast<const cpx<C>*>(o.ab) + (int64_t)tl.filter * HPlan<C>::N,
+      static_cast<const cpx<C>*>(o.tw), o.sample_k, static_cast<const S*>(o.psi), static_cast<const S*>(o.wts), o.x,
+      o.q);
 }
 
 // A half-buffer kernel over the given tiles; circulant chunks (their tiles
@@ -1469,23 +1472,27 @@ int dispatch(const mm_pointing_s* pt, const mm_noise_s* nz, int dtype, int arith
 }
 
 template <int NC>
-int launch_batch_nc(const OpBatch& b, dim3 grid, int dtype, int arith, bool weights, hipStream_t s) {
-  const int T = arith == MM_F64 ? Plan<double>::T : Plan<float>::T;
+int launch_batch_nc(const OpBatch& b, dim3 grid, int dtype, int arith, bool weights, bool wrap, hipStream_t s) {
+  const int T = arith == MM_F64 ? HPlan<double>::T : HPlan<float>::T;
   constexpr int kW1 = NC == 1 ? 0 : 1;  // no weights without an angle
+  auto go = [&]<class S, class C, int kW>() {
+    if (wrap) hipLaunchKernelGGL((k_toeplitz_batch<S, C, kW, NC, true>), grid, dim3(T), 0, s, b);
+    else hipLaunchKernelGGL((k_toeplitz_batch<S, C, kW, NC, false>), grid, dim3(T), 0, s, b);
+  };
   if (dtype == MM_F64) {
     if (arith == MM_F64) {
-      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<double, double, kW1, NC>), grid, dim3(T), 0, s, b);
-      else hipLaunchKernelGGL((k_toeplitz_batch<double, double, 0, NC>), grid, dim3(T), 0, s, b);
+      if (weights) go.template operator()<double, double, kW1>();
+      else go.template operator()<double, double, 0>();
     } else {
-      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<double, float, kW1, NC>), grid, dim3(T), 0, s, b);
-      else hipLaunchKernelGGL((k_toeplitz_batch<double, float, 0, NC>), grid, dim3(T), 0, s, b);
+      if (weights) go.template operator()<double, float, kW1>();
+      else go.template operator()<double, float, 0>();
     }
   } else {
     if (arith == MM_F64) {
-      hipLaunchKernelGGL((k_toeplitz_batch<float, double, 0, NC>), grid, dim3(T), 0, s, b);
+      go.template operator()<float, double, 0>();
     } else {
-      if (weights) hipLaunchKernelGGL((k_toeplitz_batch<float, float, kW1, NC>), grid, dim3(T), 0, s, b);
-      else hipLaunchKernelGGL((k_toeplitz_batch<float, float, 0, NC>), grid, dim3(T), 0, s, b);
+      if (weights) go.template operator()<float, float, kW1>();
+      else go.template operator()<float, float, 0>();
     }
   }
   MM_HIP(hipGetLastError());
@@ -1501,7 +1508,16 @@ int launch_toeplitz_batch(const OpBatch& b, int dtype, int arith, bool weights, 
   for (int k = 0; k < b.n; ++k) per_xcd += (b.off[k + 1] - b.off[k] + 7) / 8;
   if (per_xcd == 0) return MM_OK;
   const dim3 grid((unsigned)(8 * per_xcd));
-  return by_ncomp(ncomp, [&]<int NC>() -> int { return launch_batch_nc<NC>(b, grid, dtype, arith, weights, s); });
+  bool any_wrap = false, any_band = false;
+  for (int k = 0; k < b.n; ++k) (b.s[k].wrap ? any_wrap : any_band) = true;
+  for (const bool wrap : {false, true}) {
+    if (!(wrap ? any_wrap : any_band)) continue;
+    if (int rc = by_ncomp(ncomp, [&]<int NC>() -> int {
+          return launch_batch_nc<NC>(b, grid, dtype, arith, weights, wrap, s);
+        }))
+      return rc;
+  }
+  return MM_OK;
 }
 
 int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const void* in, void* out, int arith,
