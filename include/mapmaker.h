@@ -269,10 +269,10 @@ typedef struct {
                            tiles with two workgroups per CU, whose FFT exchanges pass real
                            and imaginary parts through half the LDS in turn (bits 1 and 2
                            do not apply), so the memory phases of one tile overlap the
-                           FFT of another, bit 4 = in FP64 arithmetic, plain tiles of the
-                           16384-point plan (the FP32 plan's tile length), one 1024-thread
-                           workgroup per CU with half-LDS exchanges (bits 1 to 3 do not
-                           apply; ignored in FP32 arithmetic); 0 <= op_variant < 32        */
+                           FFT of another, bit 4 = plain tiles of the arithmetic's longer
+                           plan (FP64: 16384 points, the FP32 plan's tile length; FP32:
+                           32768 points), one 1024-thread workgroup per CU with half-LDS
+                           exchanges (bits 1 to 3 do not apply); 0 <= op_variant < 32      */
   int32_t graph;        /* 1: the first mm_solver_step of a given length k > 0 records its k
                            iterations (operator and PCG launches) into a HIP graph and
                            every later step of that length replays it with one graph

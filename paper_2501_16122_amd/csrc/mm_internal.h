@@ -86,6 +86,7 @@ static_assert(sizeof(TplInterval) == 24, "TplInterval layout");
 // FP32: L = 2^15 (16384 complex floats = 128 KiB of LDS).
 constexpr int kFftN64 = 8192;
 constexpr int kFftN32 = 16384;
+constexpr int kFftN32L = 32768;  // the longer FP32 plan
 constexpr int kMaxLambda = 4096;
 
 // Carves aligned sub-buffers out of one caller workspace.
@@ -166,6 +167,11 @@ struct mm_noise_s {
   // FP64 tables of the 16384-point plan (its tiles are the FP32 plan's)
   void* ab64l = nullptr;
   void* tw64l = nullptr;
+  // the 32768-point FP32 plan: its tiles and FP32 tables
+  mm::FftTile* tiles32l = nullptr;
+  int64_t n_tiles32l = 0;
+  void* ab32l = nullptr;
+  void* tw32l = nullptr;
   // operator variants picked by the autotuner, per problem shape
   struct Tuned {
     int64_t n_samples;
@@ -234,11 +240,12 @@ int launch_ninv_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const vo
 // exchanges go through half the LDS (real parts, then imaginary parts), so
 // the memory phases of one tile overlap the FFT of another (tile order as
 // bit kOpLinearOrder says; bits kOpNoStaging and kOpCarry do not apply).
-// Bit kOpLongPlan (FP64 arithmetic only; ignored in FP32) runs plain tiles
-// of the 16384-point plan, the FP32 plan's tile length (75% of each window
-// valid at lambda = 4096 instead of 50%), one 1024-thread workgroup per CU
-// with the exchanges through a half buffer (tile order as bit
-// kOpLinearOrder says; the other bits do not apply).
+// Bit kOpLongPlan runs plain tiles of the arithmetic's longer plan: in FP64
+// 16384 points, the FP32 plan's tile length (75% of each window valid at
+// lambda = 4096 instead of 50%); in FP32 32768 points (87.5% instead of
+// 75%); one 1024-thread workgroup per CU with the exchanges through a half
+// buffer (tile order as bit kOpLinearOrder says; the other bits do not
+// apply).
 constexpr int32_t kOpLinearOrder = 1, kOpNoStaging = 2, kOpCarry = 4, kOpHalfLds = 8, kOpLongPlan = 16,
                   kOpVariants = 32;
 int launch_fused_toeplitz(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, const void* tod,

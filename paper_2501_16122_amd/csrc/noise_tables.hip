@@ -1,8 +1,9 @@
 // Tables of the band-Toeplitz noise weighting (the correlated N^-1 of
 // eq. (5), one finite band section per stationary chunk): the overlap-save
 // tiles of each FFT plan, the spectral weights (alpha_k, beta_k) of every
-// filter, and the twiddle factors (FP64 tables for the FP64 plan and, in
-// FP64 too, for the 16384-point plan that FP64 arithmetic may also run).
+// filter, and the twiddle factors: the FP64 8192-point plan, the 16384-point
+// plan (FP32 tables, and FP64 ones for FP64 arithmetic's longer plan), and
+// the 32768-point FP32 plan.
 //
 // The symbol of the symmetric band filter at the L frequencies of a plan,
 //   H_k = c_0 + 2 sum_{tau=1}^{lambda-1} c_tau cos(2 pi k tau / L),  k = 0..N,
@@ -22,9 +23,9 @@ namespace {
 
 // cos(2 pi j / kCosLen), j < kCosLen; a plan of length L reads every
 // (kCosLen / L)-th entry.
-constexpr int kCosLen = 2 * kFftN32;
+constexpr int kCosLen = 2 * kFftN32L;
 static_assert((kCosLen & (kCosLen - 1)) == 0, "cosine table length must be a power of two");
-static_assert(kCosLen % (2 * kFftN64) == 0, "FP64 plan length must divide the table");
+static_assert(kCosLen % (2 * kFftN64) == 0 && kCosLen % (2 * kFftN32) == 0, "plan lengths must divide the table");
 
 __global__ void __launch_bounds__(256) k_symbol(const double* __restrict__ coeff, int lam,
                                                 const double* __restrict__ cos_t, int step, int n,
@@ -91,6 +92,16 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     }
     nz->n_tiles[a] = (int64_t)tiles[a].size();
   }
+  std::vector<FftTile> tiles_l;  // the 32768-point FP32 plan
+  {
+    const int64_t V = 2 * (int64_t)kFftN32L - 2 * (int64_t)(lam - 1);
+    for (int64_t c = 0; c < nz->n_chunks; ++c) {
+      const int64_t c0 = nz->chunk_offsets[c], c1 = nz->chunk_offsets[c + 1];
+      for (int64_t o = c0; o < c1; o += V)
+        tiles_l.push_back(FftTile{o, o + V < c1 ? o + V : c1, c0, c1, nz->chunk_filter[c], wrap});
+    }
+    nz->n_tiles32l = (int64_t)tiles_l.size();
+  }
   // halo-carrying tiles (kCarryStride samples apart) and their segments.  Longer segments
   // gather fewer halos; the segment length is the longest (up to
   // kSegTiles) that still gives every CU a segment, and each chunk's tiles
@@ -128,6 +139,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   }
   FftTile* d_tiles[2];
   for (int a = 0; a < 2; ++a) d_tiles[a] = cv.take<FftTile>(tiles[a].size());
+  FftTile* d_tiles_l = cv.take<FftTile>(tiles_l.size());
   FftTile* d_ctiles[2];
   CarrySeg* d_csegs[2];
   for (int a = 0; a < 2; ++a) {
@@ -142,10 +154,12 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   d_tw[1] = cv.take<cpx<float>>(kFftN32);
   cpx<double>* d_ab64l = cv.take<cpx<double>>((size_t)nf * kFftN32);
   cpx<double>* d_tw64l = cv.take<cpx<double>>(kFftN32);
+  cpx<float>* d_ab32l = cv.take<cpx<float>>((size_t)nf * kFftN32L);
+  cpx<float>* d_tw32l = cv.take<cpx<float>>(kFftN32L);
   // build-time staging: coefficients, cosine table, symbol
   double* d_coeff = cv.take<double>((size_t)nf * lam);
   double* d_cos = cv.take<double>(kCosLen);
-  double* d_H = cv.take<double>((size_t)nf * (kFftN32 + 1));
+  double* d_H = cv.take<double>((size_t)nf * (kFftN32L + 1));
   if (bytes_needed) *bytes_needed = cv.used;
   if (ws == nullptr) return MM_OK;
   if (!cv.fits()) return fail(MM_ENOSPC, "noise workspace too small");
@@ -155,6 +169,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   std::vector<cpx<double>> tw64(kFftN64);
   std::vector<cpx<float>> tw32(kFftN32);
   std::vector<cpx<double>> tw64l(kFftN32);
+  std::vector<cpx<float>> tw32l(kFftN32L);
   for (int k = 0; k < kFftN64; ++k) {
     const double th = -2.0 * M_PI * (double)k / (double)kFftN64;
     tw64[k] = {std::cos(th), std::sin(th)};
@@ -163,6 +178,10 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     const double th = -2.0 * M_PI * (double)k / (double)kFftN32;
     tw64l[k] = {std::cos(th), std::sin(th)};
     tw32[k] = {(float)tw64l[k].x, (float)tw64l[k].y};
+  }
+  for (int k = 0; k < kFftN32L; ++k) {
+    const double th = -2.0 * M_PI * (double)k / (double)kFftN32L;
+    tw32l[k] = {(float)std::cos(th), (float)std::sin(th)};
   }
   for (int a = 0; a < 2; ++a) {
     if (!tiles[a].empty())
@@ -183,6 +202,9 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   MM_HIP(hipMemcpyAsync(d_tw[0], tw64.data(), tw64.size() * sizeof(tw64[0]), hipMemcpyHostToDevice, s));
   MM_HIP(hipMemcpyAsync(d_tw[1], tw32.data(), tw32.size() * sizeof(tw32[0]), hipMemcpyHostToDevice, s));
   MM_HIP(hipMemcpyAsync(d_tw64l, tw64l.data(), tw64l.size() * sizeof(tw64l[0]), hipMemcpyHostToDevice, s));
+  MM_HIP(hipMemcpyAsync(d_tw32l, tw32l.data(), tw32l.size() * sizeof(tw32l[0]), hipMemcpyHostToDevice, s));
+  if (!tiles_l.empty())
+    MM_HIP(hipMemcpyAsync(d_tiles_l, tiles_l.data(), tiles_l.size() * sizeof(FftTile), hipMemcpyHostToDevice, s));
   for (int a = 0; a < 2; ++a) {
     const int n = Ns[a];
     const int step = kCosLen / (2 * n);
@@ -202,6 +224,16 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     }
     MM_HIP(hipGetLastError());
   }
+  {
+    const int n = kFftN32L;
+    const int step = kCosLen / (2 * n);
+    hipLaunchKernelGGL(k_symbol, dim3((n + 1 + 255) / 256, nf), dim3(256), 0, s, (const double*)d_coeff, lam,
+                       (const double*)d_cos, step, n, d_H);
+    MM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_spectral_weights<float>, dim3((n + 255) / 256, nf), dim3(256), 0, s, (const double*)d_H,
+                       (const double*)d_cos, step, n, d_ab32l);
+    MM_HIP(hipGetLastError());
+  }
   // the host staging vectors die on return: wait for the copies
   MM_HIP(hipStreamSynchronize(s));
   for (int a = 0; a < 2; ++a) {
@@ -210,6 +242,9 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   }
   nz->ab64l = d_ab64l;
   nz->tw64l = d_tw64l;
+  nz->tiles32l = d_tiles_l;
+  nz->ab32l = d_ab32l;
+  nz->tw32l = d_tw32l;
   return MM_OK;
 }
 

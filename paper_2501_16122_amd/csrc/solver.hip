@@ -245,8 +245,8 @@ struct mm_solver_s {
       if ((v & kOpCarry) && (v & kOpNoStaging)) continue;  // the carrying form never stages
       // the two-per-CU form: plain tiles, never staged
       if ((v & kOpHalfLds) && (v & (kOpCarry | kOpNoStaging))) continue;
-      // the 16384-point FP64 plan: FP64 arithmetic, plain tiles, never staged
-      if ((v & kOpLongPlan) && (arith != MM_F64 || (v & (kOpCarry | kOpNoStaging | kOpHalfLds)))) continue;
+      // the longer plan: plain tiles, never staged
+      if ((v & kOpLongPlan) && (v & (kOpCarry | kOpNoStaging | kOpHalfLds))) continue;
       if ((rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s, v))) break;
       if ((e = hipEventRecord(e0, s)) != hipSuccess) { rc = hip_fail(e, "tuner event"); break; }
       for (int r = 0; r < 2 && rc == MM_OK; ++r) rc = apply_A_impl(pt, nz, L.A.p, L.A.q, arith, rb, s, v);

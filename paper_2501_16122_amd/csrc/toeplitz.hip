@@ -1031,7 +1031,7 @@ __device__ __forceinline__ cpx<C> spec_t(cpx<C> ab, cpx<C> z, cpx<C> zr) {
   return {ab.x * z.x + ab.y * zr.y, ab.x * z.y + ab.y * zr.x};
 }
 
-template <class C, int N, int T>
+template <class C, int N, int T, int RL = 16, int RF = 16>
 __device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* __restrict__ abf) {
   constexpr int H = N / 2, PPT = H / T;
   static_assert(2 * PPT == N / T, "bin pairs must fill the registers");
@@ -1039,8 +1039,8 @@ __device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* _
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     __syncthreads();
-    if (c == 0) hstore<C, N, T, 16, N / 16, 0>(buf, v);
-    else hstore<C, N, T, 16, N / 16, 1>(buf, v);
+    if (c == 0) hstore<C, N, T, RL, N / RL, 0>(buf, v);
+    else hstore<C, N, T, RL, N / RL, 1>(buf, v);
     __syncthreads();
     // k = t + T r and m = N - k (m = H for k = 0)
     const int t = fft_tid();
@@ -1073,8 +1073,8 @@ __device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* _
       buf[r == 0 ? pm0 : pmh - hstep(T * r)] = c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y;
     }
     __syncthreads();
-    if (c == 0) hload<C, N, T, 16, 0>(buf, v);
-    else hload<C, N, T, 16, 1>(buf, v);
+    if (c == 0) hload<C, N, T, RF, 0>(buf, v);
+    else hload<C, N, T, RF, 1>(buf, v);
   }
 }
 
@@ -1082,7 +1082,8 @@ __device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* _
 // one-per-CU plan's, so that a batch of loads and the 16 register values
 // fit 128 VGPRs.  kFft: 0 = FP64 8192 points (forward 16, 16, 16, the last
 // radix 2 folded into the spectral step), 1 = 16384 points (forward
-// 32, 32, 16 in FP32, 16, 8, 8, 16 in FP64; the spectral step on bin pairs).
+// 32, 32, 16 in FP32, 16, 8, 8, 16 in FP64; the spectral step on bin pairs),
+// 2 = 32768 points in FP32 (forward 32, 32, 32; bin pairs).
 template <class C>
 struct HPlan {
   static constexpr int N = Plan<C>::N, T = Plan<C>::T, kROut = Plan<C>::kROut, kFft = 0;
@@ -1104,6 +1105,17 @@ struct HPlan<float> {
   static constexpr int kWavesPerEU = 4;
   static constexpr int kKeepW0 = 0, kKeepW1 = 0;
   static constexpr bool kPairMerge = Plan<float>::kPairMerge;
+};
+// FP32 on 32768-point tiles (65536-sample windows): 1024 threads x 32
+// values, forward 32, 32, 32, one workgroup per CU, the 136 KiB half buffer.
+struct HPlanL32 {
+  static constexpr int N = kFftN32L, T = 1024, kROut = 32, kFft = 2;
+  static constexpr bool kKeepIdx = false;
+  static constexpr int kGatherBatch = 4;
+  static constexpr int kScatterBatch = 4;
+  static constexpr int kWavesPerEU = 4;
+  static constexpr int kKeepW0 = 0, kKeepW1 = 0;
+  static constexpr bool kPairMerge = false;
 };
 // FP64 on the 16384-point tiles: 1024 threads x 16 values, one workgroup
 // (16 waves, 4 per SIMD) per CU, the 136 KiB half buffer.
@@ -1279,7 +1291,8 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   __syncthreads();  // the FFT reuses the staging area; s_red[0, 2W) holds the valid range
 
   // ---- forward FFT, spectral step, inverse FFT (outputs in registers)
-  static_assert(P::kFft == (N == 8192 ? 0 : 1) && (N == 8192 || N == 16384), "plan and length");
+  static_assert(P::kFft == (N == 8192 ? 0 : N == 16384 ? 1 : 2) && (N == 8192 || N == 16384 || N == 32768),
+                "plan and length");
   if constexpr (P::kFft == 0) {
     hpasses<C, N, T, true, 1, 16, 16, 16>(buf, v, tw);
     hmiddle<N, T>(buf, v, abf, tw);
@@ -1288,10 +1301,14 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
     hpasses<C, N, T, true, 1, 16, 8, 8, 16>(buf, v, tw);
     hmiddle_pairs<C, N, T>(buf, v, abf);
     hpasses<C, N, T, false, 1, 16, 8, 8, 16>(buf, v, tw);
-  } else {
+  } else if constexpr (P::kFft == 1) {
     hpasses<C, N, T, true, 1, 32, 32, 16>(buf, v, tw);
     hmiddle_pairs<C, N, T>(buf, v, abf);
     hpasses<C, N, T, false, 1, 16, 32, 32>(buf, v, tw);
+  } else {
+    hpasses<C, N, T, true, 1, 32, 32, 32>(buf, v, tw);
+    hmiddle_pairs<C, N, T, 32, 32>(buf, v, abf);
+    hpasses<C, N, T, false, 1, 32, 32, 32>(buf, v, tw);
   }
 
   // ---- P^T through LDS bins in the half buffer
@@ -1400,11 +1417,16 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
              double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
-  // the 16384-point FP64 plan (bit kOpLongPlan) before any other bit
-  if constexpr (kIn == 1 && kOut == 1 && std::is_same<C, double>::value) {
-    if (variant & kOpLongPlan)
-      return launch_half<S, C, kW, NC, HPlanL64>(pt, nz, nz->tiles[1], nz->n_tiles[1], nz->ab64l, nz->tw64l, x, q, rb,
-                                                 s, variant);
+  // the longer plan of the arithmetic (bit kOpLongPlan) before any other bit
+  if constexpr (kIn == 1 && kOut == 1) {
+    if (variant & kOpLongPlan) {
+      if constexpr (std::is_same<C, double>::value)
+        return launch_half<S, C, kW, NC, HPlanL64>(pt, nz, nz->tiles[1], nz->n_tiles[1], nz->ab64l, nz->tw64l, x, q,
+                                                   rb, s, variant);
+      else
+        return launch_half<S, C, kW, NC, HPlanL32>(pt, nz, nz->tiles32l, nz->n_tiles32l, nz->ab32l, nz->tw32l, x, q,
+                                                   rb, s, variant);
+    }
   }
   // the halo-carrying form streams stored weights (with psi it spills), or
   // no angle at all (intensity only)
