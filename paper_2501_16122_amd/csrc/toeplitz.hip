@@ -1129,12 +1129,14 @@ struct HPlanL64 {
   static constexpr bool kPairMerge = true;
 };
 
-template <class S, class C, int kW, int NC, class P, bool kWrap>
+// kIn: 1 = the timeline is P x, gathered from the map x; 0 = the timeline
+// is tod (the right-hand side P^T N^-1 d).
+template <class S, class C, int kW, int NC, class P, bool kWrap, int kIn = 1>
 __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t lambda, const cpx<C>* __restrict__ abf,
                                                    const cpx<C>* __restrict__ tw,
                                                    const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
                                                    const S* __restrict__ wts, const double* __restrict__ x,
-                                                   double* __restrict__ q) {
+                                                   double* __restrict__ q, const S* __restrict__ tod = nullptr) {
   using A = Angle<C, S, kW>;
   constexpr int N = P::N, T = P::T, E = N / T, L = 2 * N, G = P::kGatherBatch;
   constexpr bool kAng = Stokes<NC>::kAngle;
@@ -1145,7 +1147,7 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   // FP64 keeps every window index in registers from the first round of
   // loads to the gather; FP32 (twice the samples per thread) has no room and
   // loads them again in the gather batches
-  constexpr bool kKeepIdx = P::kKeepIdx;
+  constexpr bool kKeepIdx = P::kKeepIdx && kIn == 1;
   static_assert(!kKeepIdx || E == 16, "indices kept for 16 values per thread");
   __shared__ C buf[hlds_elems<N>()];
   __shared__ int32_t s_red[4 * (T / 64)];
@@ -1220,7 +1222,7 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   double* xs = reinterpret_cast<double*>(buf);
   constexpr int kXPix = hlds_elems<N>() * (int)sizeof(C) / 8 / NC;
   const int xspan = amax - amin + 1;
-  const bool staged = amax >= amin && xspan <= kXPix;
+  const bool staged = kIn == 1 && amax >= amin && xspan <= kXPix;
   if (staged) {
     const double* __restrict__ xw = x + NC * (int64_t)amin;
     const int nx = NC * xspan;
@@ -1286,8 +1288,36 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
       }
     }
   };
-  if (staged) gather(std::true_type{});
-  else gather(std::false_type{});
+  if constexpr (kIn == 1) {
+    if (staged) gather(std::true_type{});
+    else gather(std::false_type{});
+  } else {
+    // the timeline itself, zero at positions that hold no sample of the chunk
+    const S* __restrict__ d0 = tod + in0;
+    int tdep = tid;
+#pragma unroll
+    for (int e0 = 0; e0 < E; e0 += G) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (e0 > 0) asm volatile("" : "+v"(tdep) : "v"(v[e0 - 1].y));
+      S dv[2 * G];
+      bool okv[2 * G];
+#pragma unroll
+      for (int i = 0; i < 2 * G; ++i) {
+        const int pos = 2 * (tdep + T * (e0 + i / 2)) + (i & 1);
+        int sp;
+        okv[i] = win_pos<kWrap>(pos, ilo, ihi, clen, vlo, sp);
+        dv[i] = kWrap ? d0[sp] : ld_off(d0, sp);
+      }
+#pragma unroll
+      for (int i = 0; i < 2 * G; ++i) {
+        const C val = okv[i] ? C(dv[i]) : C(0);
+        if (i & 1) v[e0 + i / 2].y = val;
+        else v[e0 + i / 2].x = val;
+      }
+    }
+    (void)amin;
+    (void)amax;
+  }
   __syncthreads();  // the FFT reuses the staging area; s_red[0, 2W) holds the valid range
 
   // ---- forward FFT, spectral step, inverse FFT (outputs in registers)
@@ -1327,12 +1357,12 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
 
 // One plain tile of one right-hand side per workgroup, two workgroups per
 // CU; tiles mapped to workgroups as in k_toeplitz.
-template <class S, class C, int kW, int NC, class P, bool kWrap>
+template <class S, class C, int kW, int NC, class P, bool kWrap, int kIn>
 __global__ __launch_bounds__(P::T, P::kWavesPerEU) void k_toeplitz_half(
     const FftTile* __restrict__ tiles, int64_t n_tiles, int32_t lambda, const cpx<C>* __restrict__ ab,
     const cpx<C>* __restrict__ tw, const int32_t* __restrict__ sample_k, const S* __restrict__ psi,
     const S* __restrict__ wts, const double* __restrict__ x, double* __restrict__ q, RhsBatch rb,
-    int32_t variant) {
+    int32_t variant, const S* __restrict__ tod) {
   int64_t tile;
   int rhs;
   if (variant & kOpLinearOrder) {
@@ -1349,8 +1379,8 @@ __global__ __launch_bounds__(P::T, P::kWavesPerEU) void k_toeplitz_half(
   x += rhs * rb.vstride;
   q += rhs * rb.vstride;
   const FftTile tl = tiles[tile];
-  toeplitz_tile_half<S, C, kW, NC, P, kWrap>(tl, lambda, ab + (int64_t)tl.filter * P::N, tw, sample_k, psi, wts, x,
-                                             q);
+  toeplitz_tile_half<S, C, kW, NC, P, kWrap, kIn>(tl, lambda, ab + (int64_t)tl.filter * P::N, tw, sample_k, psi,
+                                                  wts, x, q, tod);
 }
 
 // One launch over the tiles of several slots (right-hand sides of different
@@ -1394,20 +1424,20 @@ __global__ __launch_bounds__(HPlan<C>::T, HPlan<C>::kWavesPerEU) void k_toeplitz
 
 // A half-buffer kernel over the given tiles; circulant chunks (their tiles
 // wrap) take the instantiation with the wrap-around positions.
-template <class S, class C, int kW, int NC, class P>
+template <class S, class C, int kW, int NC, class P, int kIn = 1>
 int launch_half(const mm_pointing_s* pt, const mm_noise_s* nz, const FftTile* tiles, int64_t n_tiles,
                 const void* ab, const void* tw, const double* x, double* q, const RhsBatch& rb, hipStream_t s,
-                int32_t variant) {
+                int32_t variant, const void* tod = nullptr) {
   if (n_tiles == 0) return MM_OK;
   const int64_t g = 8 * ((n_tiles + 7) / 8) * rb.nrhs;
   if (nz->kind == 2)
-    hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, P, true>), dim3(g), dim3(P::T), 0, s, tiles, n_tiles,
+    hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, P, true, kIn>), dim3(g), dim3(P::T), 0, s, tiles, n_tiles,
                        nz->lambda, (const cpx<C>*)ab, (const cpx<C>*)tw, pt->sample_k, (const S*)pt->psi,
-                       (const S*)pt->weights, x, q, rb, variant);
+                       (const S*)pt->weights, x, q, rb, variant, (const S*)tod);
   else
-    hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, P, false>), dim3(g), dim3(P::T), 0, s, tiles, n_tiles,
+    hipLaunchKernelGGL((k_toeplitz_half<S, C, kW, NC, P, false, kIn>), dim3(g), dim3(P::T), 0, s, tiles, n_tiles,
                        nz->lambda, (const cpx<C>*)ab, (const cpx<C>*)tw, pt->sample_k, (const S*)pt->psi,
-                       (const S*)pt->weights, x, q, rb, variant);
+                       (const S*)pt->weights, x, q, rb, variant, (const S*)tod);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
@@ -1417,6 +1447,11 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
              double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
+  // the right-hand side P^T N^-1 d: plain tiles through the half buffer,
+  // two workgroups per CU
+  if constexpr (kIn == 0 && kOut == 1)
+    return launch_half<S, C, kW, NC, HPlan<C>, 0>(pt, nz, nz->tiles[a], nz->n_tiles[a], nz->ab[a], nz->tw[a], nullptr,
+                                                  q, rb, s, variant, tod_in);
   // the longer plan of the arithmetic (bit kOpLongPlan) before any other bit
   if constexpr (kIn == 1 && kOut == 1) {
     if (variant & kOpLongPlan) {
