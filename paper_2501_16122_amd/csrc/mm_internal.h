@@ -321,6 +321,7 @@ struct PcgArgs {
 struct OuterState {
   double bnorm;
   double rel;
+  double target;        // the outer tolerance, once the first outer step has ended (0 before)
   int32_t iters;        // outer steps taken
   int32_t inner_total;  // inner PCG iterations of finished inner solves
   int32_t converged;

@@ -172,6 +172,11 @@ __device__ __forceinline__ void pcg_init_body(const Slice& S, const double* __re
                                               bool from_x0 = false) {
   if ((int)blockIdx.x >= S.nblk) return;
   if (gate != nullptr && (gate->done || gate->skip)) return;
+  // an inner solve of the refinement goes no deeper than the outer
+  // tolerance needs: relative to its right-hand side r_k it must reach
+  // tol ||b|| / ||r_k||, with a factor 2 to spare, and never less deep than
+  // the inner tolerance
+  if (gate != nullptr && gate->target > 0.0 && gate->rel > 0.0) tol = fmax(tol, 0.5 * gate->target / gate->rel);
   __shared__ double sh[16];
   __shared__ bool s_last;
   double bb = 0.0, rz = 0.0;
@@ -338,6 +343,7 @@ __device__ __forceinline__ void outer_init_body(const OSlice& O, const Slice& S,
     os->done = (bad || os->bnorm == 0.0) ? 1 : 0;
     os->skip = 0;  // the first inner solve may start
     os->breakdown = bad ? 1 : 0;
+    os->target = 0.0;  // set when an outer step ends
   }
 }
 
@@ -385,6 +391,7 @@ __device__ __forceinline__ void outer_end_body(const OSlice& O, const Slice& S, 
     os->iters = it;
     const double rel = sqrt(rr) / os->bnorm;
     os->rel = rel;
+    os->target = tol;
     if (it < O.hist_len) O.hist[it] = rel;
     if (rel <= tol) {
       os->converged = 1;
