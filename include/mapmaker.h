@@ -260,7 +260,10 @@ typedef struct {
   int32_t timing;       /* 1: time each iteration and its A kernel with HIP events       */
   int32_t autotune;     /* 1: time the band-Toeplitz operator variants on this problem at
                            solver creation and keep the fastest (remembered by the noise
-                           handle per problem size); 0: use op_variant                       */
+                           handle per problem size, and across the process's noise handles
+                           per size class: same device, storage, arithmetic, right-hand
+                           sides, values per pixel, band and noise kind, and sample count
+                           rounded down to a power of two); 0: use op_variant            */
   int32_t op_variant;   /* variant when not autotuned (default 0): bit 0 = tiles in launch
                            order instead of the XCD-aware order, bit 1 = map read from
                            global memory instead of staged in LDS, bit 2 = shorter tiles in

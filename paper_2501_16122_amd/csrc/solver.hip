@@ -39,6 +39,30 @@ struct Layout {
 };
 
 int32_t inner_hist_len(const mm_solve_opts& o) { return std::max<int32_t>(1, (o.fixed_iter > 0 ? o.fixed_iter : o.max_iter) + 1); }
+// Operator variants chosen by the tuner, shared by every noise handle of the
+// process: problems on one device whose sample counts round down to the same
+// power of two, with the same storage, arithmetic, right-hand sides, values
+// per pixel, band and noise kind, take the first such problem's choice.  A
+// stream of similar problems (a server's requests, each with handles of its
+// own) then times the variants once per size class instead of once per
+// problem; the variants are within a few percent of each other inside one.
+struct TuneClass {
+  int device;
+  int32_t log2n, dtype, arith, nrhs, ncomp, lambda, kind;
+  bool operator==(const TuneClass& o) const {
+    return device == o.device && log2n == o.log2n && dtype == o.dtype && arith == o.arith && nrhs == o.nrhs &&
+           ncomp == o.ncomp && lambda == o.lambda && kind == o.kind;
+  }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneClass, int32_t>> g_tune_cache;
+
+TuneClass tune_class(const mm_pointing_s* pt, const mm_noise_s* nz, int arith, int nrhs) {
+  int32_t log2n = -1;
+  for (int64_t n = pt->n_samples; n > 0; n >>= 1) ++log2n;
+  return TuneClass{nz->device, log2n, pt->dtype, arith, nrhs, pt->ncomp, nz->lambda, nz->kind};
+}
+
 int32_t outer_hist_len(const mm_solve_opts& o) { return std::max<int32_t>(1, o.max_outer + 1); }
 
 size_t carve(Carver& cv, int32_t n_kept, int32_t ncomp, int32_t nrhs, const mm_solve_opts& o, Layout* L) {
@@ -219,7 +243,8 @@ struct mm_solver_s {
   // Autotuner: time each variant of the fused band-Toeplitz operator on
   // this problem (one warm-up and two timed launches on the current search
   // direction, into q, which is cleared afterwards) and keep the fastest.
-  // The choice is remembered by the noise handle for this problem shape.
+  // The choice is remembered by the noise handle for this problem shape,
+  // and across the process's handles for its size class (tune_class).
   int tune() {
     const int arith = mixed ? MM_F32 : MM_F64;
     for (const auto& t : nz->tuned)
@@ -228,6 +253,17 @@ struct mm_solver_s {
         variant = t.variant;
         return MM_OK;
       }
+    const TuneClass cls = tune_class(pt, nz, arith, nrhs);
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      for (const auto& c : g_tune_cache)
+        if (c.first == cls) {
+          variant = c.second;
+          nz->tuned.push_back(
+              mm_noise_s::Tuned{pt->n_samples, pt->n_kept, pt->dtype, arith, nrhs, variant, pt->ncomp});
+          return MM_OK;
+        }
+    }
     RhsBatch rb;
     rb.nrhs = nrhs;
     rb.vstride = n3;
@@ -268,6 +304,12 @@ struct mm_solver_s {
     if ((rc = launch_fill(L.A.q, n3 * nrhs, 0.0, s))) return rc;
     variant = best_v;
     nz->tuned.push_back(mm_noise_s::Tuned{pt->n_samples, pt->n_kept, pt->dtype, arith, nrhs, best_v, pt->ncomp});
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      bool have = false;
+      for (const auto& c : g_tune_cache) have = have || c.first == cls;
+      if (!have) g_tune_cache.emplace_back(cls, best_v);
+    }
     return MM_OK;
   }
 

@@ -176,13 +176,15 @@ def test_batch_templates_mixed_precision_matches_alone():
 
 def test_batch_mixed_precision_matches_alone():
     mbs = _members("f32")
-    opts = dict(tol=1e-12, mixed=1, max_outer=20)
+    # converged maps are compared: each is within kappa * residual of the
+    # exact map (kappa(MA) ~ 1e2), so both solve to 1e-13 for a 1e-10 bar
+    opts = dict(tol=1e-13, mixed=1, max_outer=20)
     outs = _run_batch(mbs, k=8, **opts)
     for mb, out in zip(mbs, outs):
         alone = _run_alone(mb, **opts)
         for r in range(len(mb.ds)):
             assert out["info"][r]["converged"] == 1, (mb.w.name, out["info"][r])
-            assert out["info"][r]["true_rel_resid"] <= 1e-12
+            assert out["info"][r]["true_rel_resid"] <= 1e-13
             err = oracle.rel_l2_per_stokes(out["x"][r].cpu().numpy(), alone["x"][r].cpu().numpy())
             assert np.all(err < 1e-10), (mb.w.name, r, err)
             hits = mb.pt.export()["hits"].cpu().numpy()
