@@ -717,8 +717,8 @@ def main():
     streamed = (STREAMED_BYTES_PER_SAMPLE_TOEPLITZ if w.toeplitz else ALG_BYTES_PER_SAMPLE_F64) * w.n_samples
     v_last = infos[-1]["op_variant"]
     # the dominant kernel as rocprofv3 names it (namespace dropped)
-    prof_name = ("k_toeplitz_half<double, double, 1, 3, HPlanL64, false>" if v_last & 16 else
-                 "k_toeplitz_half<double, double, 1, 3, HPlan<double>, false>" if v_last & 8 else
+    prof_name = ("k_toeplitz_half<double, double, 1, 3, HPlanL64, false, 1>" if v_last & 16 else
+                 "k_toeplitz_half<double, double, 1, 3, HPlan<double>, false, 1>" if v_last & 8 else
                  "k_toeplitz_carry<double, double, 1, 3>" if v_last & 4 else
                  "k_toeplitz<double, double, 1, 1, 1, 3>")
     roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
