@@ -15,6 +15,12 @@ or batched, where every tick enqueues one shared step for all active solves
 (mm_batch_step: one operator launch per iteration over the tiles of every
 solve, one launch per PCG vector step over all of them) on a single stream.
 
+Admission (the upload, the builds, the solver's creation) runs on builder
+threads of their own by default (prefetch, two builders): while requests'
+arrays cross PCIe and their handles are built, the scheduler keeps the
+active solves supplied with work.  The library's calls release the
+interpreter lock.
+
 All computation runs in libmapmaker's kernels; this module only schedules.
 """
 from __future__ import annotations
@@ -22,6 +28,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import math
+import threading
 import time
 from typing import Callable, Optional
 
@@ -128,7 +135,8 @@ class Server:
     """Admit, advance and retire map-making solves with overlapping work."""
 
     def __init__(self, device="cuda:0", hbm_budget: Optional[int] = None, max_slots: int = 8, k_chunk: int = 8,
-                 n_streams: int = 8, use_weights: bool = True, batched: bool = False, **solve_opts):
+                 n_streams: int = 8, use_weights: bool = True, batched: bool = False, prefetch: bool = True,
+                 builders: int = 2, **solve_opts):
         import torch
         self.dev = torch.device(device)
         if hbm_budget is None:
@@ -155,6 +163,14 @@ class Server:
         self.peak_slots = 0
         self.peak_bytes = 0
         self.depth = 0  # batched mode: shared steps in flight
+        # the builder thread (prefetch): admission state shared with it
+        self.prefetch = prefetch
+        self.builders = max(1, builders)
+        self._lock = threading.Lock()
+        self._ready: collections.deque = collections.deque()  # built, not yet active
+        self._building = 0
+        self._stop = False
+        self._err: Optional[BaseException] = None
 
     def submit(self, req: Request):
         self.pending.append(req)
@@ -182,6 +198,49 @@ class Server:
             self.peak_slots = max(self.peak_slots, len(self.active))
             self.peak_bytes = max(self.peak_bytes, self.in_use)
 
+    def _reserve(self, now_rel: float):
+        """Under the lock: the next request to build, its memory reserved, or
+        None (none has arrived, no slot is free, or memory must free up)."""
+        if not self.pending or len(self.active) + self._building + len(self._ready) >= self.max_slots:
+            return None
+        req = self.pending[0]
+        if req.arrival > now_rel:
+            return None
+        fp = self._fp(req)
+        if fp > self.budget:
+            raise MemoryError(f"request {req.rid} needs {fp} bytes, more than the whole budget")
+        if self.in_use + fp > self.budget:
+            return None
+        self.pending.popleft()
+        self.in_use += fp
+        self.peak_bytes = max(self.peak_bytes, self.in_use)
+        self._building += 1
+        return req, fp
+
+    def _builder(self, t0: float):
+        """Builder thread: admit and build requests one at a time."""
+        try:
+            while True:
+                with self._lock:
+                    if self._stop:
+                        return
+                    got = self._reserve(time.perf_counter() - t0)
+                if got is None:
+                    time.sleep(0.0005)
+                    continue
+                req, fp = got
+                stream = self.streams[req.rid % len(self.streams)]
+                slot = _Slot(req, self.dev, stream, self.opts, self.use_weights, time.perf_counter() - t0)
+                slot.fp = fp
+                slot.depth = 0
+                with self._lock:
+                    self._building -= 1
+                    self._ready.append(slot)
+        except BaseException as e:  # reported by the scheduler loop
+            with self._lock:
+                self._err = e
+                self._stop = True
+
     def run(self, requests=None, realtime=True, on_result=None):
         """Serve ``requests`` (sorted by arrival); returns the results in
         completion order.  With realtime=False arrival times are ignored and
@@ -191,6 +250,8 @@ class Server:
                 r.arrival = 0.0
             self.submit(r)
         t0 = time.perf_counter()
+        if self.prefetch:
+            return self._run_prefetch(t0, on_result)
         while self.pending or self.active:
             now = time.perf_counter()
             self._admit(now, t0)
@@ -223,12 +284,62 @@ class Server:
                 time.sleep(0.0002)
         return self.results
 
+    def _run_prefetch(self, t0, on_result):
+        """The scheduler loop with admission on the builder thread."""
+        self._stop = False
+        ths = [threading.Thread(target=self._builder, args=(t0,), daemon=True) for _ in range(self.builders)]
+        for th in ths:
+            th.start()
+        try:
+            while True:
+                with self._lock:
+                    if self._err is not None:
+                        raise self._err
+                    while self._ready:
+                        self.active.append(self._ready.popleft())
+                    self.peak_slots = max(self.peak_slots, len(self.active))
+                    busy = bool(self.pending or self.active or self._building)
+                if not busy:
+                    break
+                if not self.active:
+                    time.sleep(0.0005)
+                    continue
+                if self.batched:
+                    self._tick_batched(t0, on_result)
+                    continue
+                progressed = False
+                still = []
+                for slot in list(self.active):
+                    done, in_flight = slot.solver.poll()
+                    if done:
+                        self._retire(slot, t0, on_result)
+                        progressed = True
+                        continue
+                    still.append(slot)
+                    if not in_flight:
+                        slot.depth = 0
+                    if slot.depth < 2:  # at most two chunks queued per solve
+                        slot.solver.step(self.k_chunk)
+                        slot.depth += 1
+                        progressed = True
+                with self._lock:
+                    self.active = still
+                if not progressed:
+                    time.sleep(0.0002)
+        finally:
+            with self._lock:
+                self._stop = True
+            for th in ths:
+                th.join()
+        return self.results
+
     def _retire(self, slot, t0, on_result):
         out = slot.solver.finish()
         w = slot.req.workload
         res = Result(slot.req.rid, out["maps"][0].cpu().numpy().reshape(w.n_pix, 3), out["info"][0],
                      slot.req.arrival, slot.admitted, time.perf_counter() - t0)
-        self.in_use -= slot.fp
+        with self._lock:
+            self.in_use -= slot.fp
         slot.release()
         self.results.append(res)
         if on_result:
@@ -239,14 +350,15 @@ class Server:
         enqueue one shared step of k iterations for all the others (at most two
         steps in flight)."""
         still, in_flight = [], False
-        for slot in self.active:
+        for slot in list(self.active):
             done, flight = slot.solver.poll()
             if done:
                 self._retire(slot, t0, on_result)
             else:
                 still.append(slot)
                 in_flight = in_flight or flight
-        self.active = still
+        with self._lock:
+            self.active = still
         if not in_flight:
             self.depth = 0
         if still and self.depth < 2:
