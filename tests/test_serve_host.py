@@ -23,19 +23,22 @@ class _Tracker:
 
 
 class _FakeSolver:
-    """Done after a number of steps; each step is 'in flight' until polled."""
+    """Done after a number of steps and a minimum wall time (ten times a
+    build's, so that solves overlap); each step is 'in flight' until polled."""
 
-    def __init__(self, n_steps, n_pix):
+    def __init__(self, n_steps, n_pix, seconds):
         self.left = n_steps
         self.in_flight = False
         self.n_pix = n_pix
+        self.until = time.perf_counter() + seconds
 
     def step(self, k):
         self.left -= 1
         self.in_flight = True
 
     def poll(self):
-        done, flight = self.left <= 0, self.in_flight
+        done = self.left <= 0 and time.perf_counter() >= self.until
+        flight = self.in_flight
         self.in_flight = False
         return done, flight
 
@@ -56,7 +59,7 @@ def _install(monkeypatch, build_s=0.002, fail_rid=None):
             time.sleep(build_s)
             self.req = req
             self.admitted = now
-            self.solver = _FakeSolver(1 + req.rid % 3, req.workload.n_pix)
+            self.solver = _FakeSolver(1 + req.rid % 3, req.workload.n_pix, 10 * build_s)
             with tr.lock:
                 tr.live += 1
                 tr.peak_live = max(tr.peak_live, tr.live)
