@@ -45,6 +45,29 @@ KERNEL_SOURCES = ["paper_2501_16122_amd/csrc/toeplitz.hip", "paper_2501_16122_am
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_toeplitz_long_f64_gls512.counters.json")
 
 
+def source_commit() -> str:
+    """The checked-out commit of the repository, with '+dirty' when the
+    tracked sources differ from it, or 'unknown' outside a git checkout."""
+    import subprocess
+    try:
+        sha = subprocess.run(["git", "-C", ROOT, "rev-parse", "HEAD"], capture_output=True, text=True,
+                             timeout=10).stdout.strip()
+        dirty = subprocess.run(["git", "-C", ROOT, "status", "--porcelain", "--untracked-files=no"],
+                               capture_output=True, text=True, timeout=10).stdout.strip()
+    except (OSError, subprocess.SubprocessError):
+        return "unknown"
+    return (sha + ("+dirty" if dirty else "")) if sha else "unknown"
+
+
+def append_record(path: str, result: dict) -> None:
+    """One JSONL line per run: the result line, the source commit, the kernel
+    sources' hash and the time (UTC)."""
+    rec = {"time_utc": time.strftime("%Y-%m-%dT%H:%M:%SZ", time.gmtime()), "commit": source_commit(),
+           "kernel_source_hash": kernel_source_hash(), "argv": sys.argv[1:], "result": result}
+    with open(path, "a") as f:
+        f.write(json.dumps(rec) + "\n")
+
+
 def log(msg):
     sys.stderr.write(f"[bench {time.strftime('%H:%M:%S')}] {msg}\n")
     sys.stderr.flush()
@@ -638,6 +661,8 @@ def main():
     ap.add_argument("--stokes", type=int, default=1, help="1 = also solve the QU-only and I-only forms (0 = skip)")
     ap.add_argument("--templates", type=int, default=1,
                     help="1 = also solve with polynomial baselines marginalised instead of N^-1 (0 = skip)")
+    ap.add_argument("--record", default=None,
+                    help="also append the result, with the source commit and the time, as one line to this JSONL file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: single-GPU only (asked for --gpus {args.gpus}); sharding the timeline across "
@@ -903,6 +928,8 @@ def main():
                 lambda r: f"cpu baseline in {time.perf_counter() - t0:.1f} s")
 
     print(json.dumps(result))
+    if args.record:
+        append_record(args.record, result)
 
 
 if __name__ == "__main__":
