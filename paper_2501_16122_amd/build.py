@@ -63,5 +63,47 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+# sources whose object the sanitized build takes from the regular build: they
+# hold only kernels and their launch wrappers, which no host-only check
+# reaches, and their device pass takes minutes
+SANITIZE_REUSE = ("toeplitz.hip",)
+
+
+def build_host_sanitized(out_dir: str) -> str:
+    """libmapmaker with its host code under AddressSanitizer and
+    UndefinedBehaviorSanitizer (device code built as usual, never run), as
+    out_dir/libmapmaker_hostsan.so, for checks of the entry points that need
+    no GPU: size queries, option and argument checks, error paths.  The
+    objects of SANITIZE_REUSE come unsanitized from the regular build, which
+    must exist.  Loading the library needs the compiler's shared ASan
+    runtime, e.g. through an executable linked with -fsanitize=address
+    -shared-libsan."""
+    os.makedirs(out_dir, exist_ok=True)
+    reused = [os.path.join(BUILD, s.replace(".hip", ".o")) for s in SANITIZE_REUSE]
+    for o in reused:
+        if not os.path.exists(o):
+            raise FileNotFoundError(f"{o}: run the regular build first")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+    flags = [f for f in CFLAGS if f != "-O3"] + ["-O1", "-g", "-fno-omit-frame-pointer", *san]
+
+    def one(src):
+        obj = os.path.join(out_dir, src.replace(".hip", ".hostsan.o"))
+        cmd = [HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{' '.join(cmd)}\n{r.stderr}")
+        return obj
+
+    srcs = [s for s in sources() if s not in SANITIZE_REUSE]
+    with concurrent.futures.ThreadPoolExecutor(max(1, min(len(srcs), os.cpu_count() or 1, 8))) as ex:
+        objs = list(ex.map(one, srcs))
+    lib = os.path.join(out_dir, "libmapmaker_hostsan.so")
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", *san, "-shared-libsan", "-o", lib, *objs, *reused]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stderr}")
+    return lib
+
+
 if __name__ == "__main__":
     build()
