@@ -164,7 +164,8 @@ struct mm_noise_s {
   int64_t n_csegs[2] = {0, 0};
   void* ab[2] = {nullptr, nullptr};  // [n_filt][N] pairs (alpha_k, beta_k)
   void* tw[2] = {nullptr, nullptr};  // [N] exp(-2 pi i k / N)
-  // FP64 tables of the 16384-point plan (its tiles are the FP32 plan's)
+  // FP64 tables of the 16384-point plan (its tiles are the FP32 plan's);
+  // its weights in region-major order: bin k1 + 16 k2 at k1 * 1024 + k2
   void* ab64l = nullptr;
   void* tw64l = nullptr;
   // the 32768-point FP32 plan: its tiles and FP32 tables

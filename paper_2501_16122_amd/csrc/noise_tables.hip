@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) k_symbol(const double* __restrict__ coeff
 template <class C>
 __global__ void __launch_bounds__(256) k_spectral_weights(const double* __restrict__ H,
                                                           const double* __restrict__ cos_t, int step, int n,
-                                                          cpx<C>* __restrict__ ab) {
+                                                          cpx<C>* __restrict__ ab, int region_major) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const double* h = H + (size_t)blockIdx.y * (n + 1);
@@ -69,7 +69,9 @@ __global__ void __launch_bounds__(256) k_spectral_weights(const double* __restri
   const double ct = cos_t[i];
   const double st = cos_t[(i + 3 * (kCosLen / 4)) & (kCosLen - 1)];
   const double L = 2.0 * n;
-  ab[(size_t)blockIdx.y * n + k] = cpx<C>{(C)((S - D * st) / L), (C)(D * ct / L)};
+  // region-major order (the four-step plan): bin k1 + 16 k2 at k1 n/16 + k2
+  const int at = region_major ? (k & 15) * (n >> 4) + (k >> 4) : k;
+  ab[(size_t)blockIdx.y * n + at] = cpx<C>{(C)((S - D * st) / L), (C)(D * ct / L)};
 }
 
 }  // namespace
@@ -214,13 +216,13 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     MM_HIP(hipGetLastError());
     if (a == 0)
       hipLaunchKernelGGL(k_spectral_weights<double>, dim3((n + 255) / 256, nf), dim3(256), 0, s, (const double*)d_H,
-                         (const double*)d_cos, step, n, (cpx<double>*)d_ab[0]);
+                         (const double*)d_cos, step, n, (cpx<double>*)d_ab[0], 0);
     else {
       hipLaunchKernelGGL(k_spectral_weights<float>, dim3((n + 255) / 256, nf), dim3(256), 0, s, (const double*)d_H,
-                         (const double*)d_cos, step, n, (cpx<float>*)d_ab[1]);
+                         (const double*)d_cos, step, n, (cpx<float>*)d_ab[1], 0);
       MM_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_spectral_weights<double>, dim3((n + 255) / 256, nf), dim3(256), 0, s,
-                         (const double*)d_H, (const double*)d_cos, step, n, d_ab64l);
+                         (const double*)d_H, (const double*)d_cos, step, n, d_ab64l, 1);
     }
     MM_HIP(hipGetLastError());
   }
@@ -231,7 +233,7 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
                        (const double*)d_cos, step, n, d_H);
     MM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_spectral_weights<float>, dim3((n + 255) / 256, nf), dim3(256), 0, s, (const double*)d_H,
-                       (const double*)d_cos, step, n, d_ab32l);
+                       (const double*)d_cos, step, n, d_ab32l, 0);
     MM_HIP(hipGetLastError());
   }
   // the host staging vectors die on return: wait for the copies

@@ -1078,6 +1078,204 @@ __device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* _
   }
 }
 
+// ---------------------------------------------------------------------------
+// The 16384-point FP64 transform as a four-step split (Bailey's
+// decomposition N = 16 * 1024; Van Loan, Sec. 3.3): with n = n2 + 1024 n1
+// and k = k1 + 16 k2,
+//   X[k1 + 16 k2] = sum_n2 W_1024^(n2 k2) W_N^(n2 k1) sum_n1 x[n2 + 1024 n1] W_16^(n1 k1).
+// Thread t = n2 holds x[t + 1024 n1] (the gather's layout), so the 16-point
+// DFTs and the twiddles W_N^(t k1) run in its registers; one transpose
+// through the half buffer hands the sequence of each k1 to wave k1, whose
+// 64 lanes then run a 1024-point Stockham transform (radix 16, 8, 8) in
+// their own region of the buffer.  Only the transpose needs the whole
+// workgroup: the exchanges inside a wave's transform order themselves
+// (a wave's LDS operations complete in issue order), so the 16 waves meet
+// at 10 barriers per transform pair instead of 32.  The inverse runs
+// the same steps backwards.  The spectral step pairs bin k with N - k, held
+// by wave (16 - k1) mod 16, through the buffer in region-major order (bin
+// k1 + 16 k2 at region k1, position k2); each thread then forms its own
+// bins' outputs in place.
+// ---------------------------------------------------------------------------
+constexpr int kFsN = 16384, kFsM = 1024, kFsReg = kFsM + kFsM / 16;  // region: 1088 scalars
+
+// orders this wave's LDS operations around it (no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// slot of local element lane + 64 e after a wave transform's last pass
+// (radix 8, two butterflies per lane)
+__device__ constexpr int fs_slot_out(int e) { return (e % 2) * 8 + e / 2; }
+
+// One pass (radix R, span Ns) of a wave's 1024-point transform: lane `ln`
+// holds butterflies j = ln + 64 b; twiddles W_(Ns R)^k = W_N^(k N / (Ns R))
+// from the N-point table.
+template <class C, int R, int Ns, bool kFwd>
+__device__ __forceinline__ void fs_pass(cpx<C>* v, const cpx<C>* __restrict__ tw, int ln) {
+  constexpr int BPT = 16 / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    cpx<C>* a = v + b * R;
+    if (Ns > 1) {
+      const int k = (ln + 64 * b) & (Ns - 1);
+      cpx<C> w1 = tw[k * (kFsN / (Ns * R))];
+      if (!kFwd) w1.y = -w1.y;
+      cpx<C> w = w1;
+#pragma unroll
+      for (int m = 1; m < R; ++m) {
+        a[m] = cmul(a[m], w);
+        if (m + 1 < R) w = cmul(w, w1);
+      }
+    }
+    dft_reg<C, R, kFwd>(a);
+  }
+}
+
+// Exchange inside one wave's region between pass (R, Ns) and a pass of
+// radix R2, one component per round.
+template <class C, int R, int Ns, int R2>
+__device__ __forceinline__ void fs_exchange(C* reg, cpx<C>* v, int ln) {
+  static_assert(Ns % 16 == 0 || (16 % Ns == 0 && (Ns * R) % 16 == 0), "offsets q Ns must keep the pad count");
+  static_assert((kFsM / R2) % 16 == 0, "input stride must keep the pad count");
+  constexpr int BPT = 16 / R, BPT2 = 16 / R2;
+  settle<C, 16>(v);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    wave_sync();
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int j = ln + 64 * b;
+      const int pb = hpad((j / Ns) * Ns * R + (j & (Ns - 1)));
+#pragma unroll
+      for (int q = 0; q < R; ++q) reg[pb + hstep(q * Ns)] = c == 0 ? v[b * R + q].x : v[b * R + q].y;
+    }
+    wave_sync();
+#pragma unroll
+    for (int b = 0; b < BPT2; ++b) {
+      const int pj = hpad(ln + 64 * b);
+#pragma unroll
+      for (int m = 0; m < R2; ++m) (c == 0 ? v[b * R2 + m].x : v[b * R2 + m].y) = reg[pj + hstep(m * (kFsM / R2))];
+    }
+  }
+}
+
+// A wave's 1024-point transform, natural order in (slot e = element
+// ln + 64 e) and out (slot fs_slot_out(e)).
+template <class C, bool kFwd>
+__device__ __forceinline__ void fs_wave_fft(C* reg, cpx<C>* v, const cpx<C>* __restrict__ tw, int ln) {
+  fs_pass<C, 16, 1, kFwd>(v, tw, ln);
+  fs_exchange<C, 16, 1, 8>(reg, v, ln);
+  fs_pass<C, 8, 16, kFwd>(v, tw, ln);
+  fs_exchange<C, 8, 16, 8>(reg, v, ln);
+  fs_pass<C, 8, 128, kFwd>(v, tw, ln);
+}
+
+// v *= W_N^(+-t k1) for slot k1, by powers of the thread's twiddle
+template <class C, bool kFwd>
+__device__ __forceinline__ void fs_twiddle(cpx<C>* v, const cpx<C>* __restrict__ tw, int t) {
+  cpx<C> w1 = tw[t];
+  if (!kFwd) w1.y = -w1.y;
+  cpx<C> w = w1;
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) {
+    v[k1] = cmul(v[k1], w);
+    if (k1 + 1 < 16) w = cmul(w, w1);
+  }
+}
+
+// Forward transform: on entry slot e of thread t holds element t + 1024 e;
+// on return slot fs_slot_out(e) of lane ln in wave w holds bin
+// w + 16 (ln + 64 e).  The caller has synchronized the workgroup since the
+// buffer's last use.
+template <class C>
+__device__ __forceinline__ void fs_forward(C* buf, cpx<C>* v, const cpx<C>* __restrict__ tw) {
+  const int t = fft_tid();
+  const int ln = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+  dft_reg<C, 16, true>(v);
+  fs_twiddle<C, true>(v, tw, t);
+  settle<C, 16>(v);
+  const int pt = hpad(t), pl = w * kFsReg + hpad(ln);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (c > 0) __syncthreads();  // every wave has read the first round
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) buf[k1 * kFsReg + pt] = c == 0 ? v[k1].x : v[k1].y;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; ++m) (c == 0 ? v[m].x : v[m].y) = buf[pl + 68 * m];
+  }
+  fs_wave_fft<C, true>(buf + w * kFsReg, v, tw, ln);
+}
+
+// Spectral step on the forward layout: bin k = w + 16 k2 (k2 = ln + 64 e)
+// becomes spec_t(ab_k, Z_k, Z_(N-k)); its mirror sits at region
+// (16 - w) mod 16, position 1023 - k2 (for w = 0: 1024 - k2, and bin 0 is
+// its own mirror).  abp holds the weights in the same region-major order.
+// On return slot e holds bin w + 16 (ln + 64 e), the inverse's input layout.
+template <class C>
+__device__ __forceinline__ void fs_middle(C* buf, cpx<C>* v, const cpx<C>* __restrict__ abp) {
+  const int t = fft_tid();
+  const int ln = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int pl = w * kFsReg + hpad(ln);
+  const int pm = w != 0 ? ((16 - w) * kFsReg + hpad(1023 - ln)) : hpad(1024 - ln);
+  const int pm0 = (w == 0 && ln == 0) ? 0 : pm;
+  settle<C, 16>(v);
+  C zrx[16];
+  cpx<C> o[16];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    // a wave writes only its own region, which no other wave has used since
+    // the last barrier in the first round; in the second its mirror wave
+    // must have read the first
+    if (c > 0) __syncthreads();
+    else wave_sync();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) buf[pl + 68 * e] = c == 0 ? v[fs_slot_out(e)].x : v[fs_slot_out(e)].y;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const C zr = buf[e == 0 ? pm0 : pm - 68 * e];
+      if (c == 0) {
+        zrx[e] = zr;
+      } else {
+        const cpx<C> ab = abp[w * kFsM + ln + 64 * e];
+        const cpx<C> z = v[fs_slot_out(e)];
+        o[e] = cpx<C>{ab.x * z.x + ab.y * zr, ab.x * z.y + ab.y * zrx[e]};
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = o[e];
+  __syncthreads();  // the mirror wave has read this wave's region
+}
+
+// Inverse transform from the spectral step's layout; on return slot n1 of
+// thread t holds element t + 1024 n1.
+template <class C>
+__device__ __forceinline__ void fs_inverse(C* buf, cpx<C>* v, const cpx<C>* __restrict__ tw) {
+  const int t = fft_tid();
+  const int ln = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+  fs_wave_fft<C, false>(buf + w * kFsReg, v, tw, ln);
+  settle<C, 16>(v);
+  const int pt = hpad(t), pl = w * kFsReg + hpad(ln);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    // the first round writes the wave's own region, used since the last
+    // barrier by this wave alone
+    if (c > 0) __syncthreads();
+    else wave_sync();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) buf[pl + 68 * e] = c == 0 ? v[fs_slot_out(e)].x : v[fs_slot_out(e)].y;
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) (c == 0 ? v[k1].x : v[k1].y) = buf[k1 * kFsReg + pt];
+  }
+  fs_twiddle<C, false>(v, tw, t);
+  dft_reg<C, 16, false>(v);
+}
+
 // Plans of the half-buffer kernel.  Batches are smaller than the
 // one-per-CU plan's, so that a batch of loads and the 16 register values
 // fit 128 VGPRs.  kFft: 0 = FP64 8192 points (forward 16, 16, 16, the last
@@ -1120,7 +1318,7 @@ struct HPlanL32 {
 // FP64 on the 16384-point tiles: 1024 threads x 16 values, one workgroup
 // (16 waves, 4 per SIMD) per CU, the 136 KiB half buffer.
 struct HPlanL64 {
-  static constexpr int N = kFftN32, T = 1024, kROut = 16, kFft = 1;
+  static constexpr int N = kFftN32, T = 1024, kROut = 16, kFft = 3;
   static constexpr bool kKeepIdx = true;
   static constexpr int kGatherBatch = 2;
   static constexpr int kScatterBatch = 2;
@@ -1321,16 +1519,18 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   __syncthreads();  // the FFT reuses the staging area; s_red[0, 2W) holds the valid range
 
   // ---- forward FFT, spectral step, inverse FFT (outputs in registers)
-  static_assert(P::kFft == (N == 8192 ? 0 : N == 16384 ? 1 : 2) && (N == 8192 || N == 16384 || N == 32768),
+  static_assert((P::kFft == 3 ? N == kFsN && T == 1024 && std::is_same<C, double>::value
+                              : P::kFft == (N == 8192 ? 0 : N == 16384 ? 1 : 2)) &&
+                    (N == 8192 || N == 16384 || N == 32768),
                 "plan and length");
-  if constexpr (P::kFft == 0) {
+  if constexpr (P::kFft == 3) {
+    fs_forward<C>(buf, v, tw);
+    fs_middle<C>(buf, v, abf);
+    fs_inverse<C>(buf, v, tw);
+  } else if constexpr (P::kFft == 0) {
     hpasses<C, N, T, true, 1, 16, 16, 16>(buf, v, tw);
     hmiddle<N, T>(buf, v, abf, tw);
     hpasses<C, N, T, false, 2, 16, 16, 16>(buf, v, tw);
-  } else if constexpr (std::is_same<C, double>::value) {
-    hpasses<C, N, T, true, 1, 16, 8, 8, 16>(buf, v, tw);
-    hmiddle_pairs<C, N, T>(buf, v, abf);
-    hpasses<C, N, T, false, 1, 16, 8, 8, 16>(buf, v, tw);
   } else if constexpr (P::kFft == 1) {
     hpasses<C, N, T, true, 1, 32, 32, 16>(buf, v, tw);
     hmiddle_pairs<C, N, T>(buf, v, abf);
