@@ -86,6 +86,11 @@ static_assert(sizeof(TplInterval) == 24, "TplInterval layout");
 // FP32: L = 2^15 (16384 complex floats = 128 KiB of LDS).
 constexpr int kFftN64 = 8192;
 constexpr int kFftN32 = 16384;
+// spectral-weight order of the two-per-CU half-buffer plans, FP64 and FP32:
+// the number of region-major sequences of the four-step split, or 0 for the
+// natural order of the Stockham passes (the FP64 plan: its four-step form
+// spilled registers and ran slower)
+constexpr int kHalfRegions[2] = {0, 32};
 constexpr int kFftN32L = 32768;  // the longer FP32 plan
 constexpr int kMaxLambda = 4096;
 
@@ -163,12 +168,16 @@ struct mm_noise_s {
   mm::CarrySeg* csegs[2] = {nullptr, nullptr};
   int64_t n_csegs[2] = {0, 0};
   void* ab[2] = {nullptr, nullptr};  // [n_filt][N] pairs (alpha_k, beta_k)
+  // the same in the order of the two-per-CU half-buffer plans: region-major
+  // (bin k1 + E k2 at k1 N/E + k2, E = kHalfRegions[a]) or, for E = 0, ab[a]
+  void* abr[2] = {nullptr, nullptr};
   void* tw[2] = {nullptr, nullptr};  // [N] exp(-2 pi i k / N)
   // FP64 tables of the 16384-point plan (its tiles are the FP32 plan's);
   // its weights in region-major order: bin k1 + 16 k2 at k1 * 1024 + k2
   void* ab64l = nullptr;
   void* tw64l = nullptr;
-  // the 32768-point FP32 plan: its tiles and FP32 tables
+  // the 32768-point FP32 plan: its tiles and FP32 tables (weights in
+  // region-major order: bin k1 + 32 k2 at k1 * 1024 + k2)
   mm::FftTile* tiles32l = nullptr;
   int64_t n_tiles32l = 0;
   void* ab32l = nullptr;

@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) k_symbol(const double* __restrict__ coeff
 template <class C>
 __global__ void __launch_bounds__(256) k_spectral_weights(const double* __restrict__ H,
                                                           const double* __restrict__ cos_t, int step, int n,
-                                                          cpx<C>* __restrict__ ab, int region_major) {
+                                                          cpx<C>* __restrict__ ab, int regions) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const double* h = H + (size_t)blockIdx.y * (n + 1);
@@ -69,8 +69,9 @@ __global__ void __launch_bounds__(256) k_spectral_weights(const double* __restri
   const double ct = cos_t[i];
   const double st = cos_t[(i + 3 * (kCosLen / 4)) & (kCosLen - 1)];
   const double L = 2.0 * n;
-  // region-major order (the four-step plan): bin k1 + 16 k2 at k1 n/16 + k2
-  const int at = region_major ? (k & 15) * (n >> 4) + (k >> 4) : k;
+  // region-major order (the four-step plans): bin k1 + E k2 at k1 n/E + k2
+  // for E = regions (a power of two)
+  const int at = regions ? (k & (regions - 1)) * (n / regions) + k / regions : k;
   ab[(size_t)blockIdx.y * n + at] = cpx<C>{(C)((S - D * st) / L), (C)(D * ct / L)};
 }
 
@@ -154,6 +155,9 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
   d_ab[1] = cv.take<cpx<float>>((size_t)nf * kFftN32);
   d_tw[0] = cv.take<cpx<double>>(kFftN64);
   d_tw[1] = cv.take<cpx<float>>(kFftN32);
+  void* d_abr[2];
+  d_abr[0] = kHalfRegions[0] ? cv.take<cpx<double>>((size_t)nf * kFftN64) : d_ab[0];
+  d_abr[1] = kHalfRegions[1] ? cv.take<cpx<float>>((size_t)nf * kFftN32) : d_ab[1];
   cpx<double>* d_ab64l = cv.take<cpx<double>>((size_t)nf * kFftN32);
   cpx<double>* d_tw64l = cv.take<cpx<double>>(kFftN32);
   cpx<float>* d_ab32l = cv.take<cpx<float>>((size_t)nf * kFftN32L);
@@ -214,15 +218,25 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
     hipLaunchKernelGGL(k_symbol, dim3((n + 1 + 255) / 256, nf), dim3(256), 0, s, (const double*)d_coeff, lam,
                        (const double*)d_cos, step, n, d_H);
     MM_HIP(hipGetLastError());
-    if (a == 0)
+    if (a == 0) {
       hipLaunchKernelGGL(k_spectral_weights<double>, dim3((n + 255) / 256, nf), dim3(256), 0, s, (const double*)d_H,
                          (const double*)d_cos, step, n, (cpx<double>*)d_ab[0], 0);
-    else {
+      MM_HIP(hipGetLastError());
+      if (kHalfRegions[0])
+        hipLaunchKernelGGL(k_spectral_weights<double>, dim3((n + 255) / 256, nf), dim3(256), 0, s,
+                           (const double*)d_H, (const double*)d_cos, step, n, (cpx<double>*)d_abr[0],
+                           kHalfRegions[0]);
+    } else {
       hipLaunchKernelGGL(k_spectral_weights<float>, dim3((n + 255) / 256, nf), dim3(256), 0, s, (const double*)d_H,
                          (const double*)d_cos, step, n, (cpx<float>*)d_ab[1], 0);
       MM_HIP(hipGetLastError());
+      if (kHalfRegions[1])
+        hipLaunchKernelGGL(k_spectral_weights<float>, dim3((n + 255) / 256, nf), dim3(256), 0, s,
+                           (const double*)d_H, (const double*)d_cos, step, n, (cpx<float>*)d_abr[1],
+                           kHalfRegions[1]);
+      MM_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_spectral_weights<double>, dim3((n + 255) / 256, nf), dim3(256), 0, s,
-                         (const double*)d_H, (const double*)d_cos, step, n, d_ab64l, 1);
+                         (const double*)d_H, (const double*)d_cos, step, n, d_ab64l, n / 1024);
     }
     MM_HIP(hipGetLastError());
   }
@@ -233,13 +247,14 @@ int prepare_toeplitz_tables(mm_noise_s* nz, const double* coeff_host, void* ws, 
                        (const double*)d_cos, step, n, d_H);
     MM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_spectral_weights<float>, dim3((n + 255) / 256, nf), dim3(256), 0, s, (const double*)d_H,
-                       (const double*)d_cos, step, n, d_ab32l, 0);
+                       (const double*)d_cos, step, n, d_ab32l, n / 1024);
     MM_HIP(hipGetLastError());
   }
   // the host staging vectors die on return: wait for the copies
   MM_HIP(hipStreamSynchronize(s));
   for (int a = 0; a < 2; ++a) {
     nz->ab[a] = d_ab[a];
+    nz->abr[a] = d_abr[a];
     nz->tw[a] = d_tw[a];
   }
   nz->ab64l = d_ab64l;

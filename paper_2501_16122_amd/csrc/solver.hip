@@ -736,7 +736,7 @@ int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k) {
       items = pt->n_tiles > 0 ? nz->n_chunks : 0;
     } else if (nz->kind != 0) {
       o.tiles = nz->tiles[plan];
-      o.ab = nz->ab[plan];
+      o.ab = nz->abr[plan];  // the half-buffer tile's region-major weights
       o.tw = nz->tw[plan];
       o.lambda = nz->lambda;
       o.wrap = nz->kind == 2 ? 1 : 0;

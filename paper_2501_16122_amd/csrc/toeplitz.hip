@@ -1018,85 +1018,34 @@ __device__ __forceinline__ void hmiddle(double* buf, cpx<double>* v, const cpx<d
   }
 }
 
-// The FP32 plan's spectral step through the half buffer (N = 16384, radix
-// 32 32 16): v holds the outputs of the last forward pass (radix 16, span
-// N/16, natural order) on entry and the inputs of the first inverse pass
-// (radix 16) on return.  Thread t takes the bin pairs (k, N - k), k = t + T r,
-// one component per LDS round, forms X_k = alpha_k Z_k + i beta_k
-// conj(Z_{N-k}) and X_{N-k} likewise in registers, and scatters them back.
-// Bins 0 and N/2 pair with themselves: the slot k = 0 uses Z_0 as its own
-// mirror, and its second half takes the bin N/2 (also its own mirror).
-template <class C>
-__device__ __forceinline__ cpx<C> spec_t(cpx<C> ab, cpx<C> z, cpx<C> zr) {
-  return {ab.x * z.x + ab.y * zr.y, ab.x * z.y + ab.y * zr.x};
-}
-
-template <class C, int N, int T, int RL = 16, int RF = 16>
-__device__ __forceinline__ void hmiddle_pairs(C* buf, cpx<C>* v, const cpx<C>* __restrict__ abf) {
-  constexpr int H = N / 2, PPT = H / T;
-  static_assert(2 * PPT == N / T, "bin pairs must fill the registers");
-  settle<C, N / T>(v);
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    __syncthreads();
-    if (c == 0) hstore<C, N, T, RL, N / RL, 0>(buf, v);
-    else hstore<C, N, T, RL, N / RL, 1>(buf, v);
-    __syncthreads();
-    // k = t + T r and m = N - k (m = H for k = 0)
-    const int t = fft_tid();
-    const int pk = hpad(t), pmh = hpad(N - t), pm0 = t == 0 ? hpad(H) : pmh;
-#pragma unroll
-    for (int r = 0; r < PPT; ++r) {
-      (c == 0 ? v[2 * r].x : v[2 * r].y) = buf[pk + hstep(T * r)];
-      (c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y) = buf[r == 0 ? pm0 : pmh - hstep(T * r)];
-    }
-  }
-  const int t0 = fft_tid();
-#pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    const int k = t0 + T * r;
-    const bool k0 = r == 0 && t0 == 0;  // r > 0 never holds k = 0
-    const int m = k0 ? H : N - k;
-    const cpx<C> zk = v[2 * r], zm = v[2 * r + 1];
-    v[2 * r] = spec_t(abf[k], zk, k0 ? zk : zm);
-    v[2 * r + 1] = spec_t(abf[m], zm, k0 ? zm : zk);
-  }
-  settle<C, N / T>(v);
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    __syncthreads();
-    const int t = fft_tid();
-    const int pk = hpad(t), pmh = hpad(N - t), pm0 = t == 0 ? hpad(H) : pmh;
-#pragma unroll
-    for (int r = 0; r < PPT; ++r) {
-      buf[pk + hstep(T * r)] = c == 0 ? v[2 * r].x : v[2 * r].y;
-      buf[r == 0 ? pm0 : pmh - hstep(T * r)] = c == 0 ? v[2 * r + 1].x : v[2 * r + 1].y;
-    }
-    __syncthreads();
-    if (c == 0) hload<C, N, T, RF, 0>(buf, v);
-    else hload<C, N, T, RF, 1>(buf, v);
-  }
-}
-
 // ---------------------------------------------------------------------------
-// The 16384-point FP64 transform as a four-step split (Bailey's
-// decomposition N = 16 * 1024; Van Loan, Sec. 3.3): with n = n2 + 1024 n1
-// and k = k1 + 16 k2,
-//   X[k1 + 16 k2] = sum_n2 W_1024^(n2 k2) W_N^(n2 k1) sum_n1 x[n2 + 1024 n1] W_16^(n1 k1).
-// Thread t = n2 holds x[t + 1024 n1] (the gather's layout), so the 16-point
+// The half-buffer plans' transforms as a four-step split (Bailey's
+// decomposition N = E * M with E = N/T values per thread and M = T; Van
+// Loan, Sec. 3.3): with n = n2 + M n1 and k = k1 + E k2,
+//   X[k1 + E k2] = sum_n2 W_M^(n2 k2) W_N^(n2 k1) sum_n1 x[n2 + M n1] W_E^(n1 k1).
+// Thread t = n2 holds x[t + M n1] (the gather's layout), so the E-point
 // DFTs and the twiddles W_N^(t k1) run in its registers; one transpose
-// through the half buffer hands the sequence of each k1 to wave k1, whose
-// 64 lanes then run a 1024-point Stockham transform (radix 16, 8, 8) in
-// their own region of the buffer.  Only the transpose needs the whole
-// workgroup: the exchanges inside a wave's transform order themselves
-// (a wave's LDS operations complete in issue order), so the 16 waves meet
-// at 10 barriers per transform pair instead of 32.  The inverse runs
-// the same steps backwards.  The spectral step pairs bin k with N - k, held
-// by wave (16 - k1) mod 16, through the buffer in region-major order (bin
-// k1 + 16 k2 at region k1, position k2); each thread then forms its own
-// bins' outputs in place.
+// through the half buffer hands the E sequences of length M to the T/64
+// waves, S = E / (T/64) sequences each, whose 64 lanes then run M-point
+// Stockham transforms (radix 16, 8, 8 for M = 1024; 8, 8, 8 for M = 512)
+// in the wave's own region of the buffer.  Only the transposes need the
+// whole workgroup: the exchanges inside a wave's transforms order
+// themselves (a wave's LDS operations complete in issue order), so the
+// waves meet at 10 barriers per transform pair instead of 2 per pass.  The
+// inverse runs the same steps backwards.  The spectral step pairs bin k
+// with N - k through the buffer in region-major order (bin k1 + E k2 at
+// sequence k1, position k2); each thread then forms its own bins' outputs
+// in place.  Its weights come in the same region-major order.
 // ---------------------------------------------------------------------------
-constexpr int kFsN = 16384, kFsM = 1024, kFsReg = kFsM + kFsM / 16;  // region: 1088 scalars
+template <class C, int N, int T>
+struct Fs {
+  static constexpr int E = N / T, M = T, W = T / 64, S = E / W, V = M / 64;
+  static constexpr int MR = M + M / 16;  // one sequence's padded scalars
+  static_assert(S * W == E && V == W && (M == 1024 || M == 512), "four-step shape");
+  // slot of local element ln + 64 e after a wave transform's last pass
+  // (radix 8)
+  static constexpr int slot_out(int e) { return (e % (V / 8)) * 8 + e / (V / 8); }
+};
 
 // orders this wave's LDS operations around it (no workgroup barrier)
 __device__ __forceinline__ void wave_sync() {
@@ -1105,22 +1054,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// slot of local element lane + 64 e after a wave transform's last pass
-// (radix 8, two butterflies per lane)
-__device__ constexpr int fs_slot_out(int e) { return (e % 2) * 8 + e / 2; }
-
-// One pass (radix R, span Ns) of a wave's 1024-point transform: lane `ln`
-// holds butterflies j = ln + 64 b; twiddles W_(Ns R)^k = W_N^(k N / (Ns R))
-// from the N-point table.
-template <class C, int R, int Ns, bool kFwd>
+// One pass (radix R, span Ns) of a wave's transform of V values per lane:
+// lane `ln` holds butterflies j = ln + 64 b; twiddles
+// W_(Ns R)^k = W_N^(k N / (Ns R)) from the N-point table.
+template <class C, int N, int V, int R, int Ns, bool kFwd>
 __device__ __forceinline__ void fs_pass(cpx<C>* v, const cpx<C>* __restrict__ tw, int ln) {
-  constexpr int BPT = 16 / R;
+  constexpr int BPT = V / R;
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     cpx<C>* a = v + b * R;
     if (Ns > 1) {
       const int k = (ln + 64 * b) & (Ns - 1);
-      cpx<C> w1 = tw[k * (kFsN / (Ns * R))];
+      cpx<C> w1 = tw[k * (N / (Ns * R))];
       if (!kFwd) w1.y = -w1.y;
       cpx<C> w = w1;
 #pragma unroll
@@ -1133,14 +1078,16 @@ __device__ __forceinline__ void fs_pass(cpx<C>* v, const cpx<C>* __restrict__ tw
   }
 }
 
-// Exchange inside one wave's region between pass (R, Ns) and a pass of
-// radix R2, one component per round.
-template <class C, int R, int Ns, int R2>
+// Exchange inside one sequence's region between pass (R, Ns) and a pass of
+// radix R2, one component per round.  Ns and Ns R are powers of two, so an
+// output's offset q Ns from its butterfly's first output never moves it
+// across more pads than hstep counts.
+template <class C, int M, int V, int R, int Ns, int R2>
 __device__ __forceinline__ void fs_exchange(C* reg, cpx<C>* v, int ln) {
-  static_assert(Ns % 16 == 0 || (16 % Ns == 0 && (Ns * R) % 16 == 0), "offsets q Ns must keep the pad count");
-  static_assert((kFsM / R2) % 16 == 0, "input stride must keep the pad count");
-  constexpr int BPT = 16 / R, BPT2 = 16 / R2;
-  settle<C, 16>(v);
+  static_assert(Ns % 16 == 0 || 16 % Ns == 0, "offsets q Ns must keep the pad count");
+  static_assert((M / R2) % 16 == 0, "input stride must keep the pad count");
+  constexpr int BPT = V / R, BPT2 = V / R2;
+  settle<C, V>(v);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     wave_sync();
@@ -1156,132 +1103,167 @@ __device__ __forceinline__ void fs_exchange(C* reg, cpx<C>* v, int ln) {
     for (int b = 0; b < BPT2; ++b) {
       const int pj = hpad(ln + 64 * b);
 #pragma unroll
-      for (int m = 0; m < R2; ++m) (c == 0 ? v[b * R2 + m].x : v[b * R2 + m].y) = reg[pj + hstep(m * (kFsM / R2))];
+      for (int m = 0; m < R2; ++m) (c == 0 ? v[b * R2 + m].x : v[b * R2 + m].y) = reg[pj + hstep(m * (M / R2))];
     }
   }
 }
 
-// A wave's 1024-point transform, natural order in (slot e = element
-// ln + 64 e) and out (slot fs_slot_out(e)).
-template <class C, bool kFwd>
+// A wave's M-point transform of one sequence, natural order in (slot e =
+// element ln + 64 e) and out (slot Fs::slot_out(e)).
+template <class C, int N, int M, int V, bool kFwd>
 __device__ __forceinline__ void fs_wave_fft(C* reg, cpx<C>* v, const cpx<C>* __restrict__ tw, int ln) {
-  fs_pass<C, 16, 1, kFwd>(v, tw, ln);
-  fs_exchange<C, 16, 1, 8>(reg, v, ln);
-  fs_pass<C, 8, 16, kFwd>(v, tw, ln);
-  fs_exchange<C, 8, 16, 8>(reg, v, ln);
-  fs_pass<C, 8, 128, kFwd>(v, tw, ln);
+  if constexpr (M == 1024) {
+    fs_pass<C, N, V, 16, 1, kFwd>(v, tw, ln);
+    fs_exchange<C, M, V, 16, 1, 8>(reg, v, ln);
+    fs_pass<C, N, V, 8, 16, kFwd>(v, tw, ln);
+    fs_exchange<C, M, V, 8, 16, 8>(reg, v, ln);
+    fs_pass<C, N, V, 8, 128, kFwd>(v, tw, ln);
+  } else {
+    fs_pass<C, N, V, 8, 1, kFwd>(v, tw, ln);
+    fs_exchange<C, M, V, 8, 1, 8>(reg, v, ln);
+    fs_pass<C, N, V, 8, 8, kFwd>(v, tw, ln);
+    fs_exchange<C, M, V, 8, 8, 8>(reg, v, ln);
+    fs_pass<C, N, V, 8, 64, kFwd>(v, tw, ln);
+  }
 }
 
-// v *= W_N^(+-t k1) for slot k1, by powers of the thread's twiddle
-template <class C, bool kFwd>
+// v[k1] *= W_N^(+-t k1), by powers of the thread's twiddle
+template <class C, int E, bool kFwd>
 __device__ __forceinline__ void fs_twiddle(cpx<C>* v, const cpx<C>* __restrict__ tw, int t) {
   cpx<C> w1 = tw[t];
   if (!kFwd) w1.y = -w1.y;
   cpx<C> w = w1;
 #pragma unroll
-  for (int k1 = 1; k1 < 16; ++k1) {
+  for (int k1 = 1; k1 < E; ++k1) {
     v[k1] = cmul(v[k1], w);
-    if (k1 + 1 < 16) w = cmul(w, w1);
+    if (k1 + 1 < E) w = cmul(w, w1);
   }
 }
 
-// Forward transform: on entry slot e of thread t holds element t + 1024 e;
-// on return slot fs_slot_out(e) of lane ln in wave w holds bin
-// w + 16 (ln + 64 e).  The caller has synchronized the workgroup since the
-// buffer's last use.
-template <class C>
+// Forward transform: on entry slot e of thread t holds element t + M e; on
+// return slot s V + Fs::slot_out(e) of lane ln in wave w holds bin
+// k1 + E (ln + 64 e) with k1 = w S + s.  The caller has synchronized the
+// workgroup since the buffer's last use.
+template <class C, int N, int T>
 __device__ __forceinline__ void fs_forward(C* buf, cpx<C>* v, const cpx<C>* __restrict__ tw) {
+  using F = Fs<C, N, T>;
   const int t = fft_tid();
   const int ln = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
-  dft_reg<C, 16, true>(v);
-  fs_twiddle<C, true>(v, tw, t);
-  settle<C, 16>(v);
-  const int pt = hpad(t), pl = w * kFsReg + hpad(ln);
+  dft_reg<C, F::E, true>(v);
+  fs_twiddle<C, F::E, true>(v, tw, t);
+  settle<C, F::E>(v);
+  const int pt = hpad(t), pl = w * F::S * F::MR + hpad(ln);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     if (c > 0) __syncthreads();  // every wave has read the first round
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) buf[k1 * kFsReg + pt] = c == 0 ? v[k1].x : v[k1].y;
+    for (int k1 = 0; k1 < F::E; ++k1) buf[k1 * F::MR + pt] = c == 0 ? v[k1].x : v[k1].y;
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 16; ++m) (c == 0 ? v[m].x : v[m].y) = buf[pl + 68 * m];
+    for (int s = 0; s < F::S; ++s)
+#pragma unroll
+      for (int m = 0; m < F::V; ++m)
+        (c == 0 ? v[s * F::V + m].x : v[s * F::V + m].y) = buf[pl + s * F::MR + 68 * m];
   }
-  fs_wave_fft<C, true>(buf + w * kFsReg, v, tw, ln);
+#pragma unroll
+  for (int s = 0; s < F::S; ++s)
+    fs_wave_fft<C, N, F::M, F::V, true>(buf + (w * F::S + s) * F::MR, v + s * F::V, tw, ln);
 }
 
-// Spectral step on the forward layout: bin k = w + 16 k2 (k2 = ln + 64 e)
-// becomes spec_t(ab_k, Z_k, Z_(N-k)); its mirror sits at region
-// (16 - w) mod 16, position 1023 - k2 (for w = 0: 1024 - k2, and bin 0 is
-// its own mirror).  abp holds the weights in the same region-major order.
-// On return slot e holds bin w + 16 (ln + 64 e), the inverse's input layout.
-template <class C>
+// Spectral step on the forward layout: bin k = k1 + E k2 (k2 = ln + 64 e)
+// becomes X_k = alpha_k Z_k + i beta_k conj(Z_(N-k)) (the real-data
+// packing's spectral step); its mirror sits in sequence E - k1 at
+// position M - 1 - k2 (for k1 = 0: sequence 0, position M - k2, and bin 0
+// is its own mirror).  abp holds the weights in the same region-major order.
+// On return slot s V + e holds bin k1 + E (ln + 64 e), the inverse's input
+// layout.
+template <class C, int N, int T>
 __device__ __forceinline__ void fs_middle(C* buf, cpx<C>* v, const cpx<C>* __restrict__ abp) {
+  using F = Fs<C, N, T>;
   const int t = fft_tid();
   const int ln = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int pl = w * kFsReg + hpad(ln);
-  const int pm = w != 0 ? ((16 - w) * kFsReg + hpad(1023 - ln)) : hpad(1024 - ln);
-  const int pm0 = (w == 0 && ln == 0) ? 0 : pm;
-  settle<C, 16>(v);
-  C zrx[16];
-  cpx<C> o[16];
+  const int pl = w * F::S * F::MR + hpad(ln);
+  settle<C, F::E>(v);
+  C zrx[F::E];
+  cpx<C> o[F::E];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    // a wave writes only its own region, which no other wave has used since
-    // the last barrier in the first round; in the second its mirror wave
-    // must have read the first
+    // a wave writes only its own sequences, which no other wave has used
+    // since the last barrier in the first round; in the second the mirror
+    // waves must have read the first
     if (c > 0) __syncthreads();
     else wave_sync();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) buf[pl + 68 * e] = c == 0 ? v[fs_slot_out(e)].x : v[fs_slot_out(e)].y;
+    for (int s = 0; s < F::S; ++s)
+#pragma unroll
+      for (int e = 0; e < F::V; ++e) {
+        const cpx<C> z = v[s * F::V + F::slot_out(e)];
+        buf[pl + s * F::MR + 68 * e] = c == 0 ? z.x : z.y;
+      }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const C zr = buf[e == 0 ? pm0 : pm - 68 * e];
-      if (c == 0) {
-        zrx[e] = zr;
-      } else {
-        const cpx<C> ab = abp[w * kFsM + ln + 64 * e];
-        const cpx<C> z = v[fs_slot_out(e)];
-        o[e] = cpx<C>{ab.x * z.x + ab.y * zr, ab.x * z.y + ab.y * zrx[e]};
+    for (int s = 0; s < F::S; ++s) {
+      const int k1 = w * F::S + s;
+      const int pm = k1 != 0 ? (F::E - k1) * F::MR + hpad(F::M - 1 - ln) : hpad(F::M - ln);
+      const int pm0 = (k1 == 0 && ln == 0) ? 0 : pm;
+#pragma unroll
+      for (int e = 0; e < F::V; ++e) {
+        const int i = s * F::V + e;
+        const C zr = buf[e == 0 ? pm0 : pm - 68 * e];
+        if (c == 0) {
+          zrx[i] = zr;
+        } else {
+          const cpx<C> ab = abp[k1 * F::M + ln + 64 * e];
+          const cpx<C> z = v[s * F::V + F::slot_out(e)];
+          o[i] = cpx<C>{ab.x * z.x + ab.y * zr, ab.x * z.y + ab.y * zrx[i]};
+        }
       }
     }
   }
 #pragma unroll
-  for (int e = 0; e < 16; ++e) v[e] = o[e];
-  __syncthreads();  // the mirror wave has read this wave's region
+  for (int i = 0; i < F::E; ++i) v[i] = o[i];
+  __syncthreads();  // the mirror waves have read this wave's sequences
 }
 
 // Inverse transform from the spectral step's layout; on return slot n1 of
-// thread t holds element t + 1024 n1.
-template <class C>
+// thread t holds element t + M n1.
+template <class C, int N, int T>
 __device__ __forceinline__ void fs_inverse(C* buf, cpx<C>* v, const cpx<C>* __restrict__ tw) {
+  using F = Fs<C, N, T>;
   const int t = fft_tid();
   const int ln = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
-  fs_wave_fft<C, false>(buf + w * kFsReg, v, tw, ln);
-  settle<C, 16>(v);
-  const int pt = hpad(t), pl = w * kFsReg + hpad(ln);
+#pragma unroll
+  for (int s = 0; s < F::S; ++s)
+    fs_wave_fft<C, N, F::M, F::V, false>(buf + (w * F::S + s) * F::MR, v + s * F::V, tw, ln);
+  settle<C, F::E>(v);
+  const int pt = hpad(t), pl = w * F::S * F::MR + hpad(ln);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    // the first round writes the wave's own region, used since the last
+    // the first round writes the wave's own sequences, used since the last
     // barrier by this wave alone
     if (c > 0) __syncthreads();
     else wave_sync();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) buf[pl + 68 * e] = c == 0 ? v[fs_slot_out(e)].x : v[fs_slot_out(e)].y;
+    for (int s = 0; s < F::S; ++s)
+#pragma unroll
+      for (int e = 0; e < F::V; ++e) {
+        const cpx<C> u = v[s * F::V + F::slot_out(e)];
+        buf[pl + s * F::MR + 68 * e] = c == 0 ? u.x : u.y;
+      }
     __syncthreads();
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) (c == 0 ? v[k1].x : v[k1].y) = buf[k1 * kFsReg + pt];
+    for (int k1 = 0; k1 < F::E; ++k1) (c == 0 ? v[k1].x : v[k1].y) = buf[k1 * F::MR + pt];
   }
-  fs_twiddle<C, false>(v, tw, t);
-  dft_reg<C, 16, false>(v);
+  fs_twiddle<C, F::E, false>(v, tw, t);
+  dft_reg<C, F::E, false>(v);
 }
 
 // Plans of the half-buffer kernel.  Batches are smaller than the
 // one-per-CU plan's, so that a batch of loads and the 16 register values
-// fit 128 VGPRs.  kFft: 0 = FP64 8192 points (forward 16, 16, 16, the last
-// radix 2 folded into the spectral step), 1 = 16384 points (forward
-// 32, 32, 16 in FP32, 16, 8, 8, 16 in FP64; the spectral step on bin pairs),
-// 2 = 32768 points in FP32 (forward 32, 32, 32; bin pairs).
+// fit 128 VGPRs.  kFft: 3 = the four-step split (fs_forward), its spectral
+// weights in region-major order; 0 = Stockham passes through the whole
+// buffer, FP64 8192 points (forward 16, 16, 16, the last radix 2 folded
+// into the spectral step; weights in natural order).
 template <class C>
 struct HPlan {
   static constexpr int N = Plan<C>::N, T = Plan<C>::T, kROut = Plan<C>::kROut, kFft = 0;
@@ -1296,7 +1278,7 @@ struct HPlan {
 // longer batches keep as many loads in flight
 template <>
 struct HPlan<float> {
-  static constexpr int N = Plan<float>::N, T = Plan<float>::T, kROut = Plan<float>::kROut, kFft = 1;
+  static constexpr int N = Plan<float>::N, T = Plan<float>::T, kROut = Plan<float>::kROut, kFft = 3;
   static constexpr bool kKeepIdx = false;
   static constexpr int kGatherBatch = 4;
   static constexpr int kScatterBatch = 4;
@@ -1304,10 +1286,13 @@ struct HPlan<float> {
   static constexpr int kKeepW0 = 0, kKeepW1 = 0;
   static constexpr bool kPairMerge = Plan<float>::kPairMerge;
 };
+static_assert((HPlan<double>::kFft == 3 ? HPlan<double>::N / HPlan<double>::T : 0) == kHalfRegions[0] &&
+                  (HPlan<float>::kFft == 3 ? HPlan<float>::N / HPlan<float>::T : 0) == kHalfRegions[1],
+              "weight order of the two-per-CU plans");
 // FP32 on 32768-point tiles (65536-sample windows): 1024 threads x 32
-// values, forward 32, 32, 32, one workgroup per CU, the 136 KiB half buffer.
+// values, one workgroup per CU, the 136 KiB half buffer.
 struct HPlanL32 {
-  static constexpr int N = kFftN32L, T = 1024, kROut = 32, kFft = 2;
+  static constexpr int N = kFftN32L, T = 1024, kROut = 32, kFft = 3;
   static constexpr bool kKeepIdx = false;
   static constexpr int kGatherBatch = 4;
   static constexpr int kScatterBatch = 4;
@@ -1519,26 +1504,16 @@ __device__ __forceinline__ void toeplitz_tile_half(const FftTile& tl, int32_t la
   __syncthreads();  // the FFT reuses the staging area; s_red[0, 2W) holds the valid range
 
   // ---- forward FFT, spectral step, inverse FFT (outputs in registers)
-  static_assert((P::kFft == 3 ? N == kFsN && T == 1024 && std::is_same<C, double>::value
-                              : P::kFft == (N == 8192 ? 0 : N == 16384 ? 1 : 2)) &&
-                    (N == 8192 || N == 16384 || N == 32768),
+  static_assert(P::kFft == 3 || (P::kFft == 0 && N == 8192 && std::is_same<C, double>::value),
                 "plan and length");
   if constexpr (P::kFft == 3) {
-    fs_forward<C>(buf, v, tw);
-    fs_middle<C>(buf, v, abf);
-    fs_inverse<C>(buf, v, tw);
+    fs_forward<C, N, T>(buf, v, tw);
+    fs_middle<C, N, T>(buf, v, abf);
+    fs_inverse<C, N, T>(buf, v, tw);
   } else if constexpr (P::kFft == 0) {
     hpasses<C, N, T, true, 1, 16, 16, 16>(buf, v, tw);
     hmiddle<N, T>(buf, v, abf, tw);
     hpasses<C, N, T, false, 2, 16, 16, 16>(buf, v, tw);
-  } else if constexpr (P::kFft == 1) {
-    hpasses<C, N, T, true, 1, 32, 32, 16>(buf, v, tw);
-    hmiddle_pairs<C, N, T>(buf, v, abf);
-    hpasses<C, N, T, false, 1, 16, 32, 32>(buf, v, tw);
-  } else {
-    hpasses<C, N, T, true, 1, 32, 32, 32>(buf, v, tw);
-    hmiddle_pairs<C, N, T, 32, 32>(buf, v, abf);
-    hpasses<C, N, T, false, 1, 32, 32, 32>(buf, v, tw);
   }
 
   // ---- P^T through LDS bins in the half buffer
@@ -1650,7 +1625,7 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
   // the right-hand side P^T N^-1 d: plain tiles through the half buffer,
   // two workgroups per CU
   if constexpr (kIn == 0 && kOut == 1)
-    return launch_half<S, C, kW, NC, HPlan<C>, 0>(pt, nz, nz->tiles[a], nz->n_tiles[a], nz->ab[a], nz->tw[a], nullptr,
+    return launch_half<S, C, kW, NC, HPlan<C>, 0>(pt, nz, nz->tiles[a], nz->n_tiles[a], nz->abr[a], nz->tw[a], nullptr,
                                                   q, rb, s, variant, tod_in);
   // the longer plan of the arithmetic (bit kOpLongPlan) before any other bit
   if constexpr (kIn == 1 && kOut == 1) {
@@ -1680,7 +1655,7 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
   const int64_t grid = 8 * ((nz->n_tiles[a] + 7) / 8) * rb.nrhs;
   if constexpr (kIn == 1 && kOut == 1) {
     if (variant & kOpHalfLds)
-      return launch_half<S, C, kW, NC, HPlan<C>>(pt, nz, nz->tiles[a], nz->n_tiles[a], nz->ab[a], nz->tw[a], x, q, rb,
+      return launch_half<S, C, kW, NC, HPlan<C>>(pt, nz, nz->tiles[a], nz->n_tiles[a], nz->abr[a], nz->tw[a], x, q, rb,
                                                  s, variant);
   }
   hipLaunchKernelGGL((k_toeplitz<S, C, kIn, kOut, kW, NC>), dim3(grid), dim3(Plan<C>::T), 0, s, nz->tiles[a],
