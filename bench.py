@@ -640,7 +640,7 @@ def stokes_section(torch, b, w, dev, t_pix, t_psi, t_m, noise, offs, wdet, nz, i
     torch.cuda.empty_cache()
     out["note"] = ("same scan, noise and band-Toeplitz N^-1 as the headline workload; each form solves d = P m + n "
                    "with its own columns of P and components of the sky, FP64 to 1e-10, pointing build included; "
-                   "bytes per sample streamed by the fused operator: QU 4 (index) + 16 (cos, sin), I 4 (index only)")
+                   "bytes per sample streamed by the fused operator: QU 4 (index) + 8 (stored half-angle tangent), I 4 (index only)")
     return out
 
 
