@@ -21,6 +21,10 @@ arrays cross PCIe and their handles are built, the scheduler keeps the
 active solves supplied with work.  The library's calls release the
 interpreter lock.
 
+``Server.cancel(rid)`` withdraws a request at any stage: a queued one is
+dropped; one being built, or active, stops at the next scheduler tick once
+the work already queued on its stream has finished, and its memory is freed.
+
 All computation runs in libmapmaker's kernels; this module only schedules.
 """
 from __future__ import annotations
@@ -110,6 +114,7 @@ class _Slot:
         w = req.workload
         self.req = req
         self.admitted = now
+        self.stream = stream
         with torch.cuda.stream(stream):
             self.t_pix = torch.from_numpy(req.pix).to(dev, non_blocking=False)
             self.t_psi = torch.from_numpy(req.psi).to(dev, non_blocking=False)
@@ -171,14 +176,72 @@ class Server:
         self._building = 0
         self._stop = False
         self._err: Optional[BaseException] = None
+        # cancellation: requested rids, and (rid, stage, seconds after the
+        # start) of every request withdrawn ("queued", "built" or "active")
+        self._cancel: set = set()
+        self.cancelled: list = []
+        self._t0 = time.perf_counter()
 
     def submit(self, req: Request):
         self.pending.append(req)
+
+    def cancel(self, rid: int) -> None:
+        """Withdraw request ``rid`` (thread-safe; a finished or unknown rid is
+        ignored).  It appears in ``cancelled`` instead of the results."""
+        with self._lock:
+            self._cancel.add(rid)
+
+    def _drop_cancelled(self):
+        """Under the lock: drop cancelled requests from the queue and from the
+        built ones not yet active; returns the slots that must be released."""
+        if not self._cancel:
+            return []
+        now = time.perf_counter() - self._t0
+        keep = collections.deque()
+        for r in self.pending:
+            if r.rid in self._cancel:
+                self.cancelled.append((r.rid, "queued", now))
+            else:
+                keep.append(r)
+        self.pending = keep
+        gone, ready = [], collections.deque()
+        for sl in self._ready:
+            (gone if sl.req.rid in self._cancel else ready).append(sl)
+        self._ready = ready
+        for sl in gone:
+            self.cancelled.append((sl.req.rid, "built", now))
+        return gone
+
+    def _release_cancelled(self, slot, stage=None):
+        """Free a withdrawn slot once the work queued on its stream is done
+        (its solver may still have chunks of iterations in flight)."""
+        sync = getattr(getattr(slot, "stream", None), "synchronize", None)
+        if sync is not None:
+            sync()
+        slot.release()
+        with self._lock:
+            self.in_use -= slot.fp
+            if stage is not None:
+                self.cancelled.append((slot.req.rid, stage, time.perf_counter() - self._t0))
+
+    def _cancel_active(self):
+        """Stop the active solves that were cancelled; returns True if any."""
+        with self._lock:
+            if not self._cancel:
+                return False
+            gone = [sl for sl in self.active if sl.req.rid in self._cancel]
+            if gone:
+                self.active = [sl for sl in self.active if sl.req.rid not in self._cancel]
+        for sl in gone:
+            self._release_cancelled(sl, "active")
+        return bool(gone)
 
     def _fp(self, req: Request) -> int:
         return footprint_bytes(req.workload, self._sopts, self.use_weights and req.workload.toeplitz)
 
     def _admit(self, now: float, t0: float):
+        with self._lock:
+            self._drop_cancelled()
         while self.pending and len(self.active) < self.max_slots:
             req = self.pending[0]
             if req.arrival > now - t0:
@@ -201,6 +264,8 @@ class Server:
     def _reserve(self, now_rel: float):
         """Under the lock: the next request to build, its memory reserved, or
         None (none has arrived, no slot is free, or memory must free up)."""
+        while self.pending and self.pending[0].rid in self._cancel:
+            self.cancelled.append((self.pending.popleft().rid, "queued", now_rel))
         if not self.pending or len(self.active) + self._building + len(self._ready) >= self.max_slots:
             return None
         req = self.pending[0]
@@ -250,11 +315,13 @@ class Server:
                 r.arrival = 0.0
             self.submit(r)
         t0 = time.perf_counter()
+        self._t0 = t0
         if self.prefetch:
             return self._run_prefetch(t0, on_result)
         while self.pending or self.active:
             now = time.perf_counter()
             self._admit(now, t0)
+            self._cancel_active()
             if not self.active:
                 # nothing admitted yet: wait for the next arrival
                 nxt = self.pending[0].arrival - (time.perf_counter() - t0)
@@ -295,6 +362,11 @@ class Server:
                 with self._lock:
                     if self._err is not None:
                         raise self._err
+                    gone = self._drop_cancelled()
+                for sl in gone:
+                    self._release_cancelled(sl)
+                self._cancel_active()
+                with self._lock:
                     while self._ready:
                         self.active.append(self._ready.popleft())
                     self.peak_slots = max(self.peak_slots, len(self.active))

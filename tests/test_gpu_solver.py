@@ -175,6 +175,50 @@ def test_batched_serving_mix_equals_alone():
         serve.Server(DEV, max_slots=17, batched=True)
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_serving_cancel_frees_and_keeps_others(batched):
+    """A request cancelled while queued and one cancelled while active (its
+    chunks of iterations still in flight) are withdrawn: their device memory
+    is freed, and every other request still converges."""
+    import gc
+    import torch
+    from paper_2501_16122_amd import serve
+    reqs, _ = _serving_requests()
+    torch.cuda.synchronize()
+    gc.collect()
+    before = torch.cuda.memory_allocated(DEV)
+    srv = serve.Server(DEV, max_slots=3, k_chunk=8, tol=1e-12, max_outer=20, batched=batched)
+    srv.cancel(6)  # still queued when the run starts
+    asked = []
+
+    def on_result(res):
+        if asked:
+            return
+        for sl in list(srv.active):
+            if sl.req.rid not in (res.rid, 6):
+                asked.append(sl.req.rid)
+                srv.cancel(sl.req.rid)
+                break
+
+    res = srv.run(reqs, realtime=False, on_result=on_result)
+    stages = {rid: stage for rid, stage, _ in srv.cancelled}
+    print(f"batched={batched}: cancelled {stages}, asked {asked}", flush=True)
+    assert stages[6] == "queued"
+    assert asked
+    # a solve that finished in the tick its cancel arrived is a result
+    if asked[0] in stages:
+        assert stages[asked[0]] == "active"
+    done = {r.rid for r in res}
+    assert done | set(stages) == set(range(7)) and not (done & set(stages))
+    for r in res:
+        assert r.info["converged"] == 1 and r.info["true_rel_resid"] <= 1e-12, r.rid
+    assert srv.in_use == 0
+    del srv, res
+    torch.cuda.synchronize()
+    gc.collect()
+    assert torch.cuda.memory_allocated(DEV) <= before + (1 << 20)
+
+
 def test_serving_respects_memory_budget():
     from paper_2501_16122_amd import serve
     reqs, _ = _serving_requests()

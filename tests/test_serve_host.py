@@ -1,7 +1,8 @@
 """Host logic of the server's admission, with fake solves (no device work):
 the memory budget and slot limit hold with the builder threads and without,
 in both scheduling modes; arrivals gate admission; a failed build is raised
-by the scheduler loop."""
+by the scheduler loop; a request cancelled while queued, being built or
+active is withdrawn and its memory freed."""
 import threading
 import time
 
@@ -46,7 +47,7 @@ class _FakeSolver:
         return {"maps": [torch.zeros(3 * self.n_pix, dtype=torch.float64)], "info": [{"converged": 1}]}
 
 
-def _install(monkeypatch, build_s=0.002, fail_rid=None):
+def _install(monkeypatch, build_s=0.002, fail_rid=None, on_build=None, forever=()):
     tr = _Tracker()
     monkeypatch.setattr(torch.cuda, "Stream", lambda *a, **k: object())
     # the footprint of a request: its sample count
@@ -57,9 +58,13 @@ def _install(monkeypatch, build_s=0.002, fail_rid=None):
             if req.rid == fail_rid:
                 raise RuntimeError(f"build of request {req.rid} failed")
             time.sleep(build_s)
+            if on_build:
+                on_build(req.rid)
             self.req = req
             self.admitted = now
-            self.solver = _FakeSolver(1 + req.rid % 3, req.workload.n_pix, 10 * build_s)
+            # a request in ``forever`` never finishes unless cancelled
+            self.solver = _FakeSolver(10 ** 9 if req.rid in forever else 1 + req.rid % 3, req.workload.n_pix,
+                                      10 * build_s)
             with tr.lock:
                 tr.live += 1
                 tr.peak_live = max(tr.peak_live, tr.live)
@@ -129,3 +134,30 @@ def test_request_larger_than_budget_is_refused(monkeypatch):
     srv = serve.Server("cpu", hbm_budget=10, max_slots=2, k_chunk=8, prefetch=True)
     with pytest.raises(MemoryError):
         srv.run(reqs, realtime=False)
+
+
+@pytest.mark.timeout(60)
+@pytest.mark.parametrize("batched", [False, True])
+@pytest.mark.parametrize("prefetch", [True, False])
+def test_cancel_at_every_stage(monkeypatch, prefetch, batched):
+    srv_box = []
+    # request 5 is cancelled from inside its own build; request 7 never
+    # finishes and is cancelled once it is active
+    tr = _install(monkeypatch, on_build=lambda rid: srv_box[0].cancel(rid) if rid == 5 else None, forever=(7,))
+    reqs = _requests(n=12)
+    srv = serve.Server("cpu", hbm_budget=10 ** 9, max_slots=3, k_chunk=8, batched=batched, prefetch=prefetch)
+    srv_box.append(srv)
+    srv.cancel(0)  # still queued when the run starts
+
+    def on_result(res):
+        if any(sl.req.rid == 7 for sl in list(srv.active)):
+            srv.cancel(7)
+
+    res = srv.run(reqs, realtime=False, on_result=on_result)
+    stages = {rid: stage for rid, stage, _ in srv.cancelled}
+    assert stages == {0: "queued", 5: stages[5], 7: "active"}
+    assert stages[5] in ("built", "active")
+    assert sorted(r.rid for r in res) == sorted(set(range(12)) - {0, 5, 7})
+    assert all(r.info["converged"] == 1 for r in res)
+    # every slot released, cancelled ones included
+    assert tr.live == 0 and tr.bytes == 0 and srv.in_use == 0
