@@ -650,6 +650,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gls", choices=["gls", "shard", "binned"])
+    ap.add_argument("--config", default=None,
+                    help="workload file (a path, or a name under paper_2501_16122_amd/configs/); overrides --workload")
     ap.add_argument("--fp32-steps", type=int, default=3, help="timed FP32-refined steps (0 = skip)")
     ap.add_argument("--cpu-det", type=int, default=4, help="detectors in the oracle sample (0 = skip)")
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
@@ -677,7 +679,10 @@ def main():
     b.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
-    w = {"gls": synth.C2_GLS, "shard": synth.C2_SHARD, "binned": synth.C1_BINNED}[args.workload]
+    if args.config:
+        w, _ = synth.load_config(args.config)
+    else:
+        w = {"gls": synth.C2_GLS, "shard": synth.C2_SHARD, "binned": synth.C1_BINNED}[args.workload]
     log(f"workload {w.name}: {w.n_samples} samples, {w.n_pix} pixels")
 
     t0 = time.perf_counter()

@@ -418,6 +418,35 @@ int mm_solver_destroy(mm_solver_t sv);
  * not timed (opts.timing). */
 int mm_batch_step(mm_solver_t* solvers, int32_t n, int32_t k);
 
+/* ------------------------------------------------------------------------
+ * The autotuner's choices (opts.autotune).  The process keeps one cache of
+ * them keyed by problem class; a later problem of a cached class takes the
+ * choice without timing.  These calls copy the cache out and add to it, so
+ * that a caller can keep the choices across processes.  Host memory only;
+ * no device work.  The calls are thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct mm_tune_entry {
+  int32_t device;       /* HIP device ordinal the choice was timed on         */
+  int32_t log2_samples; /* floor(log2(n_samples))                             */
+  int32_t dtype;        /* timeline storage: MM_F64 or MM_F32                  */
+  int32_t arith;        /* operator arithmetic: MM_F64 or MM_F32               */
+  int32_t n_rhs;        /* right-hand sides per solve, >= 1                    */
+  int32_t ncomp;        /* values per pixel (map form): 1, 2 or 3              */
+  int32_t lambda;       /* band of N^-1 (lags), 1 to 4096                      */
+  int32_t noise_kind;   /* 1 = band-Toeplitz, 2 = circulant                    */
+  int32_t op_variant;   /* the chosen operator variant, 0 <= op_variant < 32   */
+} mm_tune_entry;
+
+/* *n = the number of cached choices; the first min(cap, *n) of them are
+ * copied to out (may be null when cap is 0).  MM_EINVAL for a null n, a
+ * negative cap, or a null out with cap > 0. */
+int mm_tune_cache_get(mm_tune_entry* out, int32_t cap, int32_t* n);
+
+/* Add n choices from `in`; a choice whose class is cached already replaces
+ * the cached one.  MM_EINVAL, with nothing added, for n < 0, a null `in`
+ * with n > 0, or any entry outside the ranges above. */
+int mm_tune_cache_put(const mm_tune_entry* in, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,6 +36,11 @@ class SolveOpts(_c.Structure):
                 ("autotune", _i32), ("op_variant", _i32), ("graph", _i32), ("x0", _vp), ("bj_start", _i32)]
 
 
+class TuneEntry(_c.Structure):
+    _fields_ = [("device", _i32), ("log2_samples", _i32), ("dtype", _i32), ("arith", _i32), ("n_rhs", _i32),
+                ("ncomp", _i32), ("lambda_", _i32), ("noise_kind", _i32), ("op_variant", _i32)]
+
+
 class SolveInfo(_c.Structure):
     _fields_ = [("iters", _i32), ("outer_iters", _i32), ("converged", _i32), ("breakdown", _i32),
                 ("rel_resid", _f64), ("true_rel_resid", _f64), ("op_ms", _f64), ("op_launches", _i32),
@@ -92,7 +97,13 @@ SIGNATURES = {
     "mm_solver_restore": (_c.c_int, [_vp, _vp, _sz]),
     "mm_solver_destroy": (_c.c_int, [_vp]),
     "mm_batch_step": (_c.c_int, [_c.POINTER(_vp), _i32, _i32]),
+    "mm_tune_cache_get": (_c.c_int, [_c.POINTER(TuneEntry), _i32, _pi32]),
+    "mm_tune_cache_put": (_c.c_int, [_c.POINTER(TuneEntry), _i32]),
 }
+
+# A JSON file of the autotuner's choices: read when the library is loaded
+# and written when the process exits, if this variable names one.
+TUNE_CACHE_ENV = "MM_TUNE_CACHE"
 
 _lib = None
 
@@ -110,6 +121,12 @@ def load(path: str = LIB_PATH):
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    cache = os.environ.get(TUNE_CACHE_ENV)
+    if cache:
+        import atexit
+        if os.path.exists(cache):
+            tune_cache_load(cache)
+        atexit.register(tune_cache_save, cache)
     return lib
 
 
@@ -499,6 +516,46 @@ def batch_step(solvers, k=8):
     launches; poll and finish each one as usual."""
     arr = (_vp * len(solvers))(*[sv.handle for sv in solvers])
     _check(load().mm_batch_step(arr, len(solvers), int(k)))
+
+
+_TUNE_KEYS = ("device", "log2_samples", "dtype", "arith", "n_rhs", "ncomp", "lambda", "noise_kind", "op_variant")
+
+
+def tune_cache_get() -> list:
+    """The autotuner's cached choices, one dict per problem class."""
+    lib = load()
+    n = _c.c_int32()
+    _check(lib.mm_tune_cache_get(None, 0, _c.byref(n)))
+    arr = (TuneEntry * max(n.value, 1))()
+    _check(lib.mm_tune_cache_get(arr, n.value, _c.byref(n)))
+    return [{k: getattr(e, "lambda_" if k == "lambda" else k) for k in _TUNE_KEYS} for e in arr[:n.value]]
+
+
+def tune_cache_put(entries) -> None:
+    """Add choices (dicts with the keys of tune_cache_get); a cached class
+    takes the new choice."""
+    entries = list(entries)
+    arr = (TuneEntry * max(len(entries), 1))()
+    for e, d in zip(arr, entries):
+        for k in _TUNE_KEYS:
+            setattr(e, "lambda_" if k == "lambda" else k, int(d[k]))
+    _check(load().mm_tune_cache_put(arr, len(entries)))
+
+
+def tune_cache_save(path: str) -> None:
+    """Write the cached choices to a JSON file (atomically replaced)."""
+    import json
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump({"keys": list(_TUNE_KEYS), "entries": tune_cache_get()}, f, indent=1)
+    os.replace(tmp, path)
+
+
+def tune_cache_load(path: str) -> None:
+    """Add the choices of a JSON file written by tune_cache_save."""
+    import json
+    with open(path) as f:
+        tune_cache_put(json.load(f)["entries"])
 
 
 class AsyncSolver:

@@ -845,6 +845,48 @@ int mm_solve(mm_pointing_t pt, mm_noise_t nz, const void* tod, double* map_out, 
 
 }  // extern "C"
 
+// The autotuner's class cache, copied out and added to by the caller.
+extern "C" {
+
+int mm_tune_cache_get(mm_tune_entry* out, int32_t cap, int32_t* n) {
+  if (n == nullptr || cap < 0 || (cap > 0 && out == nullptr)) return fail(MM_EINVAL, "bad tune cache query");
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  *n = (int32_t)g_tune_cache.size();
+  for (int32_t i = 0; i < cap && i < *n; ++i) {
+    const TuneClass& c = g_tune_cache[i].first;
+    out[i] = mm_tune_entry{c.device, c.log2n, c.dtype, c.arith, c.nrhs, c.ncomp, c.lambda, c.kind,
+                           g_tune_cache[i].second};
+  }
+  return MM_OK;
+}
+
+int mm_tune_cache_put(const mm_tune_entry* in, int32_t n) {
+  if (n < 0 || (n > 0 && in == nullptr)) return fail(MM_EINVAL, "bad tune cache entries");
+  auto dt = [](int32_t d) { return d == MM_F64 || d == MM_F32; };
+  for (int32_t i = 0; i < n; ++i) {
+    const mm_tune_entry& e = in[i];
+    if (e.device < 0 || e.log2_samples < 0 || e.log2_samples > 62 || !dt(e.dtype) || !dt(e.arith) || e.n_rhs < 1 ||
+        e.ncomp < 1 || e.ncomp > 3 || e.lambda < 1 || e.lambda > kMaxLambda || (e.noise_kind != 1 && e.noise_kind != 2) ||
+        e.op_variant < 0 || e.op_variant >= kOpVariants)
+      return fail(MM_EINVAL, "tune cache entry out of range");
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (int32_t i = 0; i < n; ++i) {
+    const mm_tune_entry& e = in[i];
+    const TuneClass c{e.device, e.log2_samples, e.dtype, e.arith, e.n_rhs, e.ncomp, e.lambda, e.noise_kind};
+    bool have = false;
+    for (auto& kv : g_tune_cache)
+      if (kv.first == c) {
+        kv.second = e.op_variant;
+        have = true;
+      }
+    if (!have) g_tune_cache.emplace_back(c, e.op_variant);
+  }
+  return MM_OK;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
 // Allocation-free blocking solve (mm_solve_noalloc).  The solver's vectors,
 // partial sums, states and histories live in `scratch`, a file-scope device

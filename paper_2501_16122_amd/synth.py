@@ -8,8 +8,8 @@ testing or timing; the pieces it needs (pixel indices, angles, the input map,
 the noise realisation and the band-Toeplitz coefficients of N^-1) all come
 from here, identically for every consumer.
 
-Scan law and noise recipe (the paper fixes none of them; the experiment is a
-"generic CMB polarization experiment", abstract and Sec. III-B):
+Scan law and noise recipe (the paper fixes none of them; it simulates an
+unnamed CMB polarization experiment, abstract and Sec. III-B):
 
 * detector d, sample t = 0..n_samp-1 (integer sample index, detector-major
   layout, so detector d owns samples [d*n_samp, (d+1)*n_samp));
@@ -98,6 +98,49 @@ C4_MULTI = Workload("multirhs_512x512_32x2^22_x8_1overf_toeplitz4096_f32", 4, 51
                     t_psi=6000.0, noise="oneoverf", chunk=1 << 20, lam=4096, precision="f32")
 
 CONFIGS = {w.name: w for w in (C1_BINNED, C2_GLS, C3_PRECISION, C2_SHARD, C4_MULTI)}
+
+# The same workloads as JSON files (configs/), with the solve options they
+# are run with and a reference to the readings file, which lists every point
+# the paper leaves open and the fields that carry its value.
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+SOLVE_KEYS = ("tol", "max_iter", "check_every", "autotune", "mixed", "bj_start", "inner_tol", "max_outer")
+
+
+def config_path(name_or_path: str) -> str:
+    """A workload file by path, or by name under configs/ (with or without
+    the .json suffix)."""
+    if os.path.isfile(name_or_path):
+        return name_or_path
+    p = os.path.join(CONFIG_DIR, name_or_path if name_or_path.endswith(".json") else name_or_path + ".json")
+    if not os.path.isfile(p):
+        raise FileNotFoundError(f"no workload file {name_or_path!r} (looked in {CONFIG_DIR})")
+    return p
+
+
+def load_config(name_or_path: str):
+    """(Workload, solve options) from a workload file: "workload" holds every
+    field of Workload and no other, "solve" only names of the solve options."""
+    import json
+    with open(config_path(name_or_path)) as f:
+        d = json.load(f)
+    wl = d.get("workload")
+    if not isinstance(wl, dict):
+        raise ValueError("a workload file needs a 'workload' object")
+    names = {f.name for f in dataclasses.fields(Workload)}
+    missing, extra = sorted(names - set(wl)), sorted(set(wl) - names)
+    if missing or extra:
+        raise ValueError(f"workload fields missing {missing}, unknown {extra}")
+    solve = dict(d.get("solve", {}))
+    bad = sorted(set(solve) - set(SOLVE_KEYS))
+    if bad:
+        raise ValueError(f"unknown solve options {bad}")
+    return Workload(**wl), solve
+
+
+def config_dict(w: Workload, solve: dict, description: str = "") -> dict:
+    """The JSON form of a workload and its solve options (load_config's inverse)."""
+    return {"name": w.name, "description": description, "workload": dataclasses.asdict(w), "solve": dict(solve),
+            "readings": "readings.json"}
 
 
 def batch_workloads(n: int = 16, config_id: int = 4, det=(8, 128), samples=(1 << 20, 1 << 23),

@@ -69,6 +69,22 @@ int main() {
   CHECK(mm_solver_workspace_bound(100, 3, 0, &o, &sz) == MM_EINVAL);
   CHECK(mm_solver_workspace_bound(-1, 3, 1, &o, &sz) == MM_EINVAL);
 
+  // the tuner's choice cache: round trip, replacement, malformed entries
+  int32_t nt = -1;
+  CHECK(mm_tune_cache_get(nullptr, 0, &nt) == MM_OK && nt == 0);
+  mm_tune_entry te[2] = {{0, 28, MM_F64, MM_F64, 1, 3, 4096, 1, 16}, {0, 28, MM_F64, MM_F32, 1, 3, 4096, 1, 8}};
+  CHECK(mm_tune_cache_put(te, 2) == MM_OK);
+  mm_tune_entry back[4];
+  CHECK(mm_tune_cache_get(back, 4, &nt) == MM_OK && nt == 2 && back[1].op_variant == 8);
+  te[0].op_variant = 5;
+  CHECK(mm_tune_cache_put(te, 1) == MM_OK);
+  CHECK(mm_tune_cache_get(back, 1, &nt) == MM_OK && nt == 2 && back[0].op_variant == 5);
+  te[1].op_variant = 32;
+  CHECK(mm_tune_cache_put(te, 2) == MM_EINVAL);
+  CHECK(mm_tune_cache_get(nullptr, 0, &nt) == MM_OK && nt == 2);
+  CHECK(mm_tune_cache_get(nullptr, 1, &nt) == MM_EINVAL);
+  CHECK(mm_tune_cache_put(nullptr, 1) == MM_EINVAL);
+
   // null handles and bad arguments are refused before any device work
   CHECK(mm_apply_A(nullptr, nullptr, nullptr, nullptr, MM_F64, nullptr) == MM_EINVAL);
   CHECK(mm_rhs(nullptr, nullptr, nullptr, nullptr, MM_F64, nullptr) == MM_EINVAL);

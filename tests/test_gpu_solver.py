@@ -350,3 +350,23 @@ def test_start_vector_matches_oracle(white):
     x_ref1, _ = oracle.pcg(lambda v: oracle.apply_A(opt, noise, v), lambda v: oracle.apply_M(opt, v),
                            oracle.rhs(opt, noise, ds[1]), fixed_iters=k)
     assert np.all(oracle.rel_l2_per_stokes(res["x"][1].cpu().numpy(), x_ref1) < 1e-10)
+
+
+def test_autotuner_takes_a_cached_choice():
+    """A choice put into the tuner's class cache decides the variant of a
+    later autotuned solve of that class, and the solve is still right."""
+    b = _b()
+    w = SMALL_T
+    pt, nz, opt, noise, ds = _device_problem(w)
+    td = torch.from_numpy(ds[0]).to(DEV)
+    ref = b.Solver(pt, nz, tol=1e-10).solve(td)
+    cls = {"device": 0, "log2_samples": (w.n_samples).bit_length() - 1, "dtype": b.MM_F64, "arith": b.MM_F64,
+           "n_rhs": 1, "ncomp": 3, "lambda": w.lam, "noise_kind": 1}
+    for forced in (1, 9):
+        b.tune_cache_put([dict(cls, op_variant=forced)])
+        nz2 = b.Noise.toeplitz(synth.toeplitz_coeff(w), synth.chunk_offsets(w), DEV)  # no per-handle choice yet
+        out = b.Solver(pt, nz2, tol=1e-10, autotune=1).solve(td)
+        assert out["info"]["op_variant"] == forced
+        assert dict(cls, op_variant=forced) in b.tune_cache_get()
+        err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), ref["x"].cpu().numpy())
+        assert np.all(err < 1e-8), (forced, err)
