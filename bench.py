@@ -59,11 +59,27 @@ def source_commit() -> str:
     return (sha + ("+dirty" if dirty else "")) if sha else "unknown"
 
 
+def machine_info() -> dict:
+    """The host (CPU model, cores) and the GPU the run used (name and
+    architecture, if torch sees one; nothing here initialises the GPU)."""
+    info = {"host": {"cpu_model": cpu_model(), "cores": os.cpu_count()}, "gpu": None}
+    try:
+        import torch
+        if torch.cuda.is_initialized():
+            p = torch.cuda.get_device_properties(0)
+            info["gpu"] = {"name": p.name, "arch": getattr(p, "gcnArchName", ""),
+                           "memory_gib": round(p.total_memory / 2 ** 30, 1)}
+    except Exception:  # no torch or no GPU: host only
+        pass
+    return info
+
+
 def append_record(path: str, result: dict) -> None:
     """One JSONL line per run: the result line, the source commit, the kernel
-    sources' hash and the time (UTC)."""
+    sources' hash, the time (UTC) and the machine (host, GPU)."""
     rec = {"time_utc": time.strftime("%Y-%m-%dT%H:%M:%SZ", time.gmtime()), "commit": source_commit(),
-           "kernel_source_hash": kernel_source_hash(), "argv": sys.argv[1:], "result": result}
+           "kernel_source_hash": kernel_source_hash(), "argv": sys.argv[1:], "machine": machine_info(),
+           "result": result}
     with open(path, "a") as f:
         f.write(json.dumps(rec) + "\n")
 

@@ -34,6 +34,7 @@ def test_record_appends_one_line_per_run(tmp_path):
         assert r["kernel_source_hash"] == bench.kernel_source_hash()
         assert r["commit"] == "unknown" or len(r["commit"].split("+")[0]) == 40
         assert r["time_utc"].endswith("Z")
+        assert r["machine"]["host"]["cores"] == os.cpu_count() and r["machine"]["host"]["cpu_model"]
 
 
 def test_stored_traffic_only_for_its_kernel_and_sources():
