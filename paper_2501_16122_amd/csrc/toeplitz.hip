@@ -1306,7 +1306,7 @@ struct HPlanL64 {
   static constexpr int N = kFftN32, T = 1024, kROut = 16, kFft = 3;
   static constexpr bool kKeepIdx = true;
   static constexpr int kGatherBatch = 2;
-  static constexpr int kScatterBatch = 2;
+  static constexpr int kScatterBatch = 4;
   static constexpr int kWavesPerEU = 4;
   static constexpr int kKeepW0 = 0, kKeepW1 = 0;
   static constexpr bool kPairMerge = true;
