@@ -1622,11 +1622,17 @@ int launch_t(const mm_pointing_s* pt, const mm_noise_s* nz, const double* x, con
              double* q, const RhsBatch& rb, hipStream_t s, int32_t variant) {
   const int a = std::is_same<C, double>::value ? 0 : 1;
   if (nz->n_tiles[a] == 0) return MM_OK;
-  // the right-hand side P^T N^-1 d: plain tiles through the half buffer,
-  // two workgroups per CU
-  if constexpr (kIn == 0 && kOut == 1)
-    return launch_half<S, C, kW, NC, HPlan<C>, 0>(pt, nz, nz->tiles[a], nz->n_tiles[a], nz->abr[a], nz->tw[a], nullptr,
-                                                  q, rb, s, variant, tod_in);
+  // the right-hand side P^T N^-1 d: plain tiles through the half buffer;
+  // in FP64 the 16384-point four-step plan (its windows keep 75 % of their
+  // samples at lambda = 4096 against 50 %), in FP32 the two-per-CU plan
+  if constexpr (kIn == 0 && kOut == 1) {
+    if constexpr (std::is_same<C, double>::value)
+      return launch_half<S, C, kW, NC, HPlanL64, 0>(pt, nz, nz->tiles[1], nz->n_tiles[1], nz->ab64l, nz->tw64l,
+                                                     nullptr, q, rb, s, variant, tod_in);
+    else
+      return launch_half<S, C, kW, NC, HPlan<C>, 0>(pt, nz, nz->tiles[a], nz->n_tiles[a], nz->abr[a], nz->tw[a],
+                                                    nullptr, q, rb, s, variant, tod_in);
+  }
   // the longer plan of the arithmetic (bit kOpLongPlan) before any other bit
   if constexpr (kIn == 1 && kOut == 1) {
     if (variant & kOpLongPlan) {
