@@ -83,7 +83,9 @@ def test_multi_rhs_solve_equals_single_solves(mixed):
     pt, nz, opt, noise, ds = _device_problem(w, n_rhs=4)
     pt.attach_weights()
     tods = torch.from_numpy(np.stack(ds)).to(DEV)
-    multi = b.AsyncSolver(pt, nz, tods, tol=1e-11, mixed=mixed, max_outer=20)
+    # solved to 1e-13, so that the map is within about kappa * 1e-13 of the
+    # exact one and the oracle comparison below can use 1e-10
+    multi = b.AsyncSolver(pt, nz, tods, tol=1e-13, mixed=mixed, max_outer=20)
     while True:
         multi.step()
         multi.stream.synchronize()
@@ -92,14 +94,14 @@ def test_multi_rhs_solve_equals_single_solves(mixed):
             break
     out = multi.finish()
     for r in range(4):
-        single = b.Solver(pt, nz, tol=1e-11, mixed=mixed, max_outer=20).solve(tods[r].contiguous())
+        single = b.Solver(pt, nz, tol=1e-13, mixed=mixed, max_outer=20).solve(tods[r].contiguous())
         err = oracle.rel_l2_per_stokes(out["x"][r].cpu().numpy(), single["x"].cpu().numpy())
         assert np.all(err < 1e-10), (r, err)
         assert out["info"][r]["converged"] == 1
     # one right-hand side against the oracle on the same (rounded) inputs
     _, _, x_ref = oracle.solve(opt, noise, ds[1].astype(np.float64), tol=1e-13)
     err = oracle.rel_l2_per_stokes(out["x"][1].cpu().numpy(), x_ref)
-    assert np.all(err < 1e-7), err
+    assert np.all(err < 1e-10), err
 
 
 def _serving_requests():
@@ -304,11 +306,11 @@ def test_carry_variant_mixed_precision():
     w = LONG4096.replace(precision="f32")
     pt, nz, opt, noise, ds = _device_problem(w)
     pt.attach_weights()
-    out = b.Solver(pt, nz, tol=1e-12, mixed=1, max_outer=20, op_variant=5).solve(torch.from_numpy(ds[0]).to(DEV))
+    out = b.Solver(pt, nz, tol=1e-13, mixed=1, max_outer=20, op_variant=5).solve(torch.from_numpy(ds[0]).to(DEV))
     assert out["info"]["converged"] == 1
     _, _, x_ref = oracle.solve(opt, noise, ds[0].astype(np.float64), tol=1e-13)
     err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref)
-    assert np.all(err < 1e-9), err
+    assert np.all(err < 1e-10), err
 
 
 @pytest.mark.parametrize("white", [False, True])
@@ -329,13 +331,13 @@ def test_start_vector_matches_oracle(white):
     x_ref, info = oracle.pcg(lambda v: oracle.apply_A(opt, noise, v), lambda v: oracle.apply_M(opt, v), bb,
                              fixed_iters=k, x0=x0)
     assert np.all(oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref) < 1e-10)
-    conv = b.Solver(pt, nz, tol=1e-11).solve(td)
+    conv = b.Solver(pt, nz, tol=1e-13).solve(td)
     again = b.Solver(pt, nz, tol=1e-10).solve(td, x0=conv["x"].clone())
     assert again["info"]["iters"] == 0 and again["info"]["converged"] == 1
     assert torch.equal(again["x"], conv["x"])
-    mixed = b.Solver(pt, nz, tol=1e-10, mixed=1).solve(td, x0=tx0)
-    assert mixed["info"]["converged"] == 1 and mixed["info"]["true_rel_resid"] <= 1e-10
-    assert np.all(oracle.rel_l2_per_stokes(mixed["x"].cpu().numpy(), conv["x"].cpu().numpy()) < 1e-7)
+    mixed = b.Solver(pt, nz, tol=1e-13, mixed=1, max_outer=20).solve(td, x0=tx0)
+    assert mixed["info"]["converged"] == 1 and mixed["info"]["true_rel_resid"] <= 1e-13
+    assert np.all(oracle.rel_l2_per_stokes(mixed["x"].cpu().numpy(), conv["x"].cpu().numpy()) < 1e-10)
     # two right-hand sides, two start vectors
     X0 = torch.stack([tx0, torch.zeros_like(tx0)]).contiguous()
     two = torch.stack([torch.from_numpy(ds[0]), torch.from_numpy(ds[1])]).to(DEV).contiguous()

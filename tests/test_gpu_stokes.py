@@ -137,12 +137,12 @@ def test_toeplitz_solve_fixed_iterations(form):
 def test_mixed_precision_solve(form):
     b = _b()
     f = Form(form.opt.stokes, precision="f32")
-    out = b.Solver(f.pt, f.nz, tol=1e-10, mixed=1, autotune=1).solve(f.t_d)
-    assert out["info"]["converged"] == 1 and out["info"]["true_rel_resid"] <= 1e-10
+    out = b.Solver(f.pt, f.nz, tol=1e-13, mixed=1, max_outer=20, autotune=1).solve(f.t_d)
+    assert out["info"]["converged"] == 1 and out["info"]["true_rel_resid"] <= 1e-13
     _, info, x_ref = oracle.solve(f.opt, f.noise, f.d, tol=1e-13)
-    # a 1e-10 residual pins the map to about kappa * 1e-10
+    # both solved to 1e-13: each map is within about kappa * 1e-13 of the exact one
     err = oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref, ncomp=f.nc)
-    assert np.all(err < 1e-7), err
+    assert np.all(err < 1e-10), err
 
 
 def test_batched_steps_match_alone(form):

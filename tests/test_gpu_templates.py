@@ -127,10 +127,11 @@ def test_baselines_removed_from_noiseless_data():
 def test_mixed_precision_solve():
     b = _b()
     s = Setup("QU", precision="f32")
-    out = b.Solver(s.pt, s.nz, tol=1e-10, mixed=1).solve(s.t_d)
-    assert out["info"]["converged"] == 1 and out["info"]["true_rel_resid"] <= 1e-10
+    # both solved to 1e-13: each map is within about kappa * 1e-13 of the exact one
+    out = b.Solver(s.pt, s.nz, tol=1e-13, mixed=1, max_outer=20).solve(s.t_d)
+    assert out["info"]["converged"] == 1 and out["info"]["true_rel_resid"] <= 1e-13
     _, _, x_ref = oracle.solve(s.opt, s.noise, s.d, tol=1e-13)
-    assert np.all(oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref, ncomp=2) < 1e-7)
+    assert np.all(oracle.rel_l2_per_stokes(out["x"].cpu().numpy(), x_ref, ncomp=2) < 1e-10)
 
 
 def test_argument_checks(setup):
