@@ -200,6 +200,7 @@ class Server:
         keep = collections.deque()
         for r in self.pending:
             if r.rid in self._cancel:
+                self._cancel.discard(r.rid)
                 self.cancelled.append((r.rid, "queued", now))
             else:
                 keep.append(r)
@@ -209,6 +210,7 @@ class Server:
             (gone if sl.req.rid in self._cancel else ready).append(sl)
         self._ready = ready
         for sl in gone:
+            self._cancel.discard(sl.req.rid)
             self.cancelled.append((sl.req.rid, "built", now))
         return gone
 
@@ -232,6 +234,7 @@ class Server:
             gone = [sl for sl in self.active if sl.req.rid in self._cancel]
             if gone:
                 self.active = [sl for sl in self.active if sl.req.rid not in self._cancel]
+                self._cancel.difference_update(sl.req.rid for sl in gone)
         for sl in gone:
             self._release_cancelled(sl, "active")
         return bool(gone)
@@ -265,7 +268,9 @@ class Server:
         """Under the lock: the next request to build, its memory reserved, or
         None (none has arrived, no slot is free, or memory must free up)."""
         while self.pending and self.pending[0].rid in self._cancel:
-            self.cancelled.append((self.pending.popleft().rid, "queued", now_rel))
+            rid = self.pending.popleft().rid
+            self._cancel.discard(rid)
+            self.cancelled.append((rid, "queued", now_rel))
         if not self.pending or len(self.active) + self._building + len(self._ready) >= self.max_slots:
             return None
         req = self.pending[0]
@@ -412,6 +417,7 @@ class Server:
                      slot.req.arrival, slot.admitted, time.perf_counter() - t0)
         with self._lock:
             self.in_use -= slot.fp
+            self._cancel.discard(slot.req.rid)  # finished before its cancel was seen
         slot.release()
         self.results.append(res)
         if on_result:

@@ -159,5 +159,6 @@ def test_cancel_at_every_stage(monkeypatch, prefetch, batched):
     assert stages[5] in ("built", "active")
     assert sorted(r.rid for r in res) == sorted(set(range(12)) - {0, 5, 7})
     assert all(r.info["converged"] == 1 for r in res)
-    # every slot released, cancelled ones included
+    # every slot released, cancelled ones included; no cancel left pending
     assert tr.live == 0 and tr.bytes == 0 and srv.in_use == 0
+    assert not srv._cancel
