@@ -1281,7 +1281,7 @@ struct HPlan<float> {
   static constexpr int N = Plan<float>::N, T = Plan<float>::T, kROut = Plan<float>::kROut, kFft = 3;
   static constexpr bool kKeepIdx = false;
   static constexpr int kGatherBatch = 4;
-  static constexpr int kScatterBatch = 4;
+  static constexpr int kScatterBatch = 2;
   static constexpr int kWavesPerEU = 4;
   static constexpr int kKeepW0 = 0, kKeepW1 = 0;
   static constexpr bool kPairMerge = Plan<float>::kPairMerge;
