@@ -125,7 +125,12 @@ def load(path: str = LIB_PATH):
     if cache:
         import atexit
         if os.path.exists(cache):
-            tune_cache_load(cache)
+            try:
+                tune_cache_load(cache)
+            except (OSError, ValueError, KeyError, TypeError, MapMakerError) as e:
+                # a broken file costs only the cached choices (the tuner times again)
+                import warnings
+                warnings.warn(f"{TUNE_CACHE_ENV}={cache}: not loaded ({e})")
         atexit.register(tune_cache_save, cache)
     return lib
 

@@ -78,3 +78,18 @@ def test_file_carries_choices_across_processes(tmp_path):
     r = subprocess.run([sys.executable, "-c", get], env=env, check=True, timeout=120, capture_output=True, text=True)
     got = json.loads(r.stdout.strip().splitlines()[-1])
     assert E1 in got and E2 in got
+
+
+@pytest.mark.parametrize("content", ["{not json", '{"entries": [{"device": 0}]}',
+                                     '{"entries": [{"device": 0, "log2_samples": 28, "dtype": 0, "arith": 0, '
+                                     '"n_rhs": 1, "ncomp": 3, "lambda": 4096, "noise_kind": 1, "op_variant": 99}]}'])
+def test_broken_file_is_skipped_with_a_warning(tmp_path, content):
+    _b()
+    path = tmp_path / "tune.json"
+    path.write_text(content)
+    env = dict(os.environ, MM_TUNE_CACHE=str(path), PYTHONPATH=ROOT)
+    code = ("import warnings; warnings.simplefilter('always'); "
+            "from paper_2501_16122_amd import binding as b; lib = b.load(); print('abi', lib.mm_abi_version())")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "abi 5" in r.stdout and "not loaded" in r.stderr
